@@ -1,0 +1,204 @@
+"""FP64 CPU oracle for the D3Q19 central-moment LBM (arXiv 2010.01628).
+
+TEST INFRASTRUCTURE ONLY: this package is the reference the GPU library is
+checked against.  Only the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import it.  It shares no code with the
+GPU path (``paper_2010_01628_amd``) and never imports it.
+
+The arithmetic lives in plain C (``d3q19_oracle.c`` and friends), compiled
+with gcc and OpenMP into ``liboracle.so``; this module only marshals numpy
+arrays.  Each C function cites the paper passage it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["d3q19_oracle.c"]
+
+DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
+CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
+
+Q = 19
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no HIP, no GPU headers)."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    tmp = _SO + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        i32, f64 = ctypes.c_int, ctypes.c_double
+        L.orc19_tables.argtypes = [ip, dp, ip]
+        L.orc19_feq.argtypes = [f64, f64, f64, f64, dp]
+        L.orc19_T.argtypes = [f64, f64, f64, dp]
+        L.orc19_keq.argtypes = [f64, dp]
+        L.orc19_Rcm.argtypes = [f64, f64, f64, dp]
+        L.orc19_rstar.argtypes = [f64, f64, f64, f64, dp, dp]
+        L.orc19_fstar.argtypes = [dp, dp]
+        L.orc19_collide.argtypes = [dp, dp, dp, i32, dp, dp, dp, dp]
+        L.orc19_collide.restype = i32
+        L.orc19_K.argtypes = [f64, f64, dp, dp]
+        L.orc19_step.argtypes = [i32, i32, i32, i32, dp, dp, dp, dp, i32, i32]
+        L.orc19_step.restype = i32
+        L.orc19_init.argtypes = [i32, i32, i32, dp, dp, dp]
+        L.orc19_moments.argtypes = [i32, i32, i32, dp, dp, dp, dp]
+        L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
+
+
+def tables():
+    """(c[19,3] int, w[19], opp[19]) in the paper's velocity order."""
+    c = np.zeros((Q, 3), dtype=np.int32)
+    w = np.zeros(Q)
+    opp = np.zeros(Q, dtype=np.int32)
+    lib().orc19_tables(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(w),
+                       opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return c, w, opp
+
+
+def feq(rho, u):
+    out = np.zeros(Q)
+    lib().orc19_feq(float(rho), float(u[0]), float(u[1]), float(u[2]), _p(out))
+    return out
+
+
+def T(u):
+    out = np.zeros((Q, Q))
+    lib().orc19_T(float(u[0]), float(u[1]), float(u[2]), _p(out))
+    return out
+
+
+def keq(rho):
+    out = np.zeros(Q)
+    lib().orc19_keq(float(rho), _p(out))
+    return out
+
+
+def Rcm(F):
+    out = np.zeros(Q)
+    lib().orc19_Rcm(float(F[0]), float(F[1]), float(F[2]), _p(out))
+    return out
+
+
+def rstar(rho, u, kstar):
+    out = np.zeros(Q)
+    lib().orc19_rstar(float(rho), float(u[0]), float(u[1]), float(u[2]), _p(_f64(kstar)), _p(out))
+    return out
+
+
+def fstar(rstar_):
+    out = np.zeros(Q)
+    lib().orc19_fstar(_p(_f64(rstar_)), _p(out))
+    return out
+
+
+def K(omega, omega_bulk=1.0, omega_hi=None):
+    out = np.zeros(Q)
+    hi = None if omega_hi is None else _f64(omega_hi)
+    lib().orc19_K(float(omega), float(omega_bulk), _p(hi), _p(out))
+    return out
+
+
+def collide(f, F=(0.0, 0.0, 0.0), Kdiag=None, mode=CLOSED_FORM):
+    """One node.  Returns (f*, k, rho, u)."""
+    f = _f64(f)
+    F = _f64(F)
+    Kd = _f64(Kdiag if Kdiag is not None else K(1.0))
+    fs = np.zeros(Q)
+    k = np.zeros(Q)
+    rho = np.zeros(1)
+    u = np.zeros(3)
+    rc = lib().orc19_collide(_p(f), _p(F), _p(Kd), int(mode), _p(fs), _p(k), _p(rho), _p(u))
+    if rc != 0:
+        raise ArithmeticError("singular collision system")
+    return fs, k, float(rho[0]), u
+
+
+def init(rho, u):
+    """f = f_eq(rho, u) at every node.  rho: (nz,ny,nx); u: (3,nz,ny,nx)."""
+    rho = _f64(rho)
+    u = _f64(u)
+    nz, ny, nx = rho.shape
+    f = np.zeros((Q, nz, ny, nx))
+    lib().orc19_init(nx, ny, nz, _p(rho), _p(u), _p(f))
+    return f
+
+
+def step(f, Kdiag, F=None, walls_y=False, mode=CLOSED_FORM, out=None):
+    """One collide-and-stream step.  f: (19,nz,ny,nx).  Kdiag: (19,) or (19,nz,ny,nx)."""
+    f = _f64(f)
+    _, nz, ny, nx = f.shape
+    Kd = _f64(Kdiag)
+    per_node = 1 if Kd.ndim == 4 else 0
+    Fa = None if F is None else _f64(F)
+    if out is None:
+        out = np.empty_like(f)
+    rc = lib().orc19_step(nx, ny, nz, int(bool(walls_y)), _p(f), _p(out), _p(Fa), _p(Kd), per_node, int(mode))
+    if rc != 0:
+        raise ArithmeticError("singular collision system")
+    return out
+
+
+def run(f, nsteps, Kdiag, F=None, walls_y=False, mode=CLOSED_FORM):
+    a = _f64(f).copy()
+    b = np.empty_like(a)
+    for _ in range(int(nsteps)):
+        step(a, Kdiag, F=F, walls_y=walls_y, mode=mode, out=b)
+        a, b = b, a
+    return a
+
+
+def moments(f, F=None):
+    """(rho (nz,ny,nx), u (3,nz,ny,nx)) with the force-shifted velocity."""
+    f = _f64(f)
+    _, nz, ny, nx = f.shape
+    rho = np.zeros((nz, ny, nx))
+    u = np.zeros((3, nz, ny, nx))
+    Fa = None if F is None else _f64(F)
+    lib().orc19_moments(nx, ny, nz, _p(f), _p(Fa), _p(rho), _p(u))
+    return rho, u
