@@ -1,0 +1,151 @@
+/*
+ * lbm.h -- C ABI of liblbm.so, an MI355X (gfx950) implementation of the D3Q19
+ * central-moment (CM) multiple-relaxation-time lattice Boltzmann method of
+ * A. De Rosis & C. Coreixas, "Multiphysics flow simulations using D3Q19
+ * lattice Boltzmann methods based on central moments" (arXiv 2010.01628).
+ *
+ * What one step computes (Sec. II.B, eqs. "lbe", "posColl0", "system",
+ * "streaming_f"): at every node, rho = sum_i f_i and the force-shifted
+ * velocity u = (sum_i f_i c_i + F/2)/rho; the CMs k = T(u) f; the relaxation
+ * k* = (I - K) k + K k_eq + (I - K/2) R with the Galilean-invariant k_eq and
+ * the forcing CMs R of App. B; f* = T(u)^-1 k*; then streaming
+ * f_i(x + c_i, t+1) = f*_i(x, t).  Velocities and their order are those of
+ * Sec. II.A (opposite(i) = i +- 9).
+ *
+ * Conventions shared by every entry point:
+ *   - Node index n = x + nx*(y + ny*z).  Per-node fields are structure of
+ *     arrays: a scalar field is double[N]; a vector field is double[3*N] with
+ *     component d at [d*N + n].  Population arrays are double[19*N] with
+ *     population i at [i*N + n].
+ *   - Pointers marked "host or device" are device pointers when on_device is
+ *     non-zero (they must then be device memory of the handle's GPU), host
+ *     pointers otherwise.  The caller owns every pointer it passes; the library
+ *     never frees or retains caller memory past the call.
+ *   - Every call is ordered on the HIP stream given to lbm_create.  Calls that
+ *     write host memory synchronize that stream before returning; calls that
+ *     read or write only device memory do not.
+ *   - Errors: a negative lbm_status is returned and lbm_last_error() gives a
+ *     message (thread-local).  Nothing is printed.  A handle on which a call
+ *     failed with LBM_EDEVICE should be destroyed.
+ *   - One handle must not be used from two threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,       /* bad argument or parameter */
+    LBM_ENOMEM = -2,       /* device allocation failed */
+    LBM_EDEVICE = -3,      /* HIP runtime error */
+    LBM_EUNSTABLE = -4,    /* a stability check found a non-finite or non-positive density */
+    LBM_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} lbm_status;
+
+/* Storage precision of the populations.  Collision arithmetic is FP64 for
+ * LBM_FP64 and FP32 otherwise.  Populations are stored as deviations
+ * s_i = f_i - w_i rho0 from the rest equilibrium at the reference density. */
+typedef enum {
+    LBM_FP64 = 0,
+    LBM_FP32 = 1,
+    LBM_FP16_SHIFTED = 2,
+    LBM_BF16_SHIFTED = 3
+} lbm_precision;
+
+/* Streaming pattern: two buffers (pull from the neighbours into the other
+ * buffer) or one buffer updated in place (AA pattern, even/odd steps). */
+typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_streaming;
+
+typedef enum {
+    LBM_FORCE_NONE = 0,
+    LBM_FORCE_UNIFORM = 1,    /* F = force[0..2] at every node */
+    LBM_FORCE_FIELD = 2,      /* F read from force_field (device, double[3*N]) */
+    LBM_FORCE_KOLMOGOROV = 3  /* F_x = kolmogorov_amp * sin(2 pi y / ny), F_y = F_z = 0 */
+} lbm_force_mode;
+
+typedef struct {
+    uint32_t abi_version;     /* must be LBM_ABI_VERSION */
+    int32_t nx, ny, nz;       /* lattice nodes; periodic in x and z, and in y unless walls_y */
+    int32_t q;                /* 19 */
+    int32_t precision;        /* lbm_precision */
+    int32_t streaming;        /* lbm_streaming */
+    double omega;             /* shear rate of k5..k9, 1/(nu/cs^2 + 1/2), in (0, 2) (Sec. II.B) */
+    double omega_bulk;        /* rate of k4; the paper's choice is 1 */
+    double omega_hi[9];       /* rates of k10..k18; the paper's choice is 1 */
+    double rho0;              /* reference density of the stored deviations (usually 1) */
+    int32_t force_mode;       /* lbm_force_mode */
+    double force[3];          /* LBM_FORCE_UNIFORM */
+    double kolmogorov_amp;    /* LBM_FORCE_KOLMOGOROV */
+    const double *force_field;/* LBM_FORCE_FIELD: device pointer, double[3*N], must stay valid
+                                 while steps run */
+    int32_t walls_y;          /* 1: stationary no-slip walls half a link outside y = 0 and
+                                 y = ny - 1 (halfway bounce-back) */
+    int32_t check_every;      /* > 0: every that many steps lbm_step checks that the density
+                                 is finite and positive everywhere (FP64 reduction) */
+    int32_t block_x, block_y; /* work-group shape of the step kernels; 0 = library default */
+} lbm_params;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Fill *p with defaults: 32^3, q = 19, FP32, A-B, omega = 1, all other rates
+ * 1, rho0 = 1, no force, periodic, no checks. */
+void lbm_params_default(lbm_params *p);
+
+/* Create a lattice on the current HIP device.  stream: a hipStream_t (NULL =
+ * the default stream) on which all later calls of this handle are ordered.
+ * Allocates the population buffer(s): 19*N elements each (two for LBM_AB).
+ * Returns LBM_EINVAL for bad parameters, LBM_ENOMEM if the device is full. */
+int lbm_create(const lbm_params *p, void *stream, lbm_handle **out);
+
+/* Initialise at equilibrium from macroscopic fields (Sec. III: populations
+ * start at the equilibrium of the initial fields, eq. EqQ19RM):
+ * f_i(x, 0) = f_i^eq(rho(x), u(x)).  rho: double[N], u: double[3*N] (host or
+ * device).  Resets the step counter to 0. */
+int lbm_init(lbm_handle *h, const double *rho, const double *u, int on_device);
+
+/* Advance nsteps >= 0 time steps.  Returns LBM_EUNSTABLE at the first failed
+ * stability check (state left readable, step counter at the failed check). */
+int lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Macroscopic fields at the current time: rho = sum_i f_i (double[N]) and the
+ * force-shifted u = (sum_i f_i c_i + F/2)/rho (double[3*N]); either may be
+ * NULL.  diag (host, may be NULL) receives FP64 totals
+ * [sum rho, sum rho u_x, sum rho u_y, sum rho u_z, 1/2 sum rho |u|^2,
+ *  max |u|] over all nodes. */
+int lbm_moments(lbm_handle *h, double *rho, double *u, double *diag, int on_device);
+
+/* Copy the populations f_i(x, t) at the current time (before collision, the
+ * state the paper's algorithm starts a step from) into f (double[19*N], host
+ * or device), converting from the storage precision. */
+int lbm_get_populations(lbm_handle *h, double *f, int on_device);
+
+/* Replace the state by the populations f (double[19*N], host or device),
+ * rounded to the storage precision.  The step counter is kept. */
+int lbm_set_populations(lbm_handle *h, const double *f, int on_device);
+
+/* Number of steps taken since lbm_init. */
+int64_t lbm_step_count(const lbm_handle *h);
+
+/* Device bytes held by the handle (population buffers and tables). */
+int64_t lbm_device_bytes(const lbm_handle *h);
+
+int lbm_destroy(lbm_handle *h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* LBM_ABI_VERSION of the loaded library. */
+int lbm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -66,6 +66,9 @@ def lib():
         L.orc19_step.restype = i32
         L.orc19_init.argtypes = [i32, i32, i32, dp, dp, dp]
         L.orc19_moments.argtypes = [i32, i32, i32, dp, dp, dp, dp]
+        L.orc19_step_at.argtypes = [i32, i32, i32, i32, dp, dp, dp, i32, i32,
+                                    ctypes.POINTER(ctypes.c_int64), i32, dp]
+        L.orc19_step_at.restype = i32
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
         _lib = L
@@ -191,6 +194,22 @@ def run(f, nsteps, Kdiag, F=None, walls_y=False, mode=CLOSED_FORM):
         step(a, Kdiag, F=F, walls_y=walls_y, mode=mode, out=b)
         a, b = b, a
     return a
+
+
+def step_at(f, nodes, Kdiag, F=None, walls_y=False, mode=CLOSED_FORM):
+    """f_i(x, t+1) (shape (len(nodes), 19)) at the given node indices only."""
+    f = _f64(f)
+    _, nz, ny, nx = f.shape
+    Kd = _f64(Kdiag)
+    per_node = 1 if Kd.ndim == 4 else 0
+    Fa = None if F is None else _f64(F)
+    nd = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros((len(nd), Q))
+    rc = lib().orc19_step_at(nx, ny, nz, int(bool(walls_y)), _p(f), _p(Fa), _p(Kd), per_node, int(mode),
+                             nd.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(nd), _p(out))
+    if rc != 0:
+        raise ArithmeticError("singular collision system")
+    return out
 
 
 def moments(f, F=None):

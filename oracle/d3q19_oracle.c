@@ -416,3 +416,42 @@ void orc_set_num_threads(int n)
     (void)n;
 #endif
 }
+
+/*
+ * f_i(x, t+1) at selected nodes only, from the full state f at time t: by the
+ * streaming rule f_i(x, t+1) = f*_i(x - c_i, t), or f*_opp(i)(x, t) when
+ * x - c_i lies beyond a y wall; each f* from one collision (the function
+ * above) at the node it comes from.  out[s*19 + i] for sample s.  Lets a test
+ * check single outputs of a lattice too large for a full oracle step.
+ */
+int orc19_step_at(int nx, int ny, int nz, int walls_y, const double *f, const double *F, const double *Krates,
+                  int per_node_K, int mode, const int64_t *nodes, int nsample, double *out)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    int err = 0;
+#pragma omp parallel for schedule(static) reduction(| : err)
+    for (int s = 0; s < nsample; ++s) {
+        const int64_t n = nodes[s];
+        const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+        for (int i = 0; i < Q; ++i) {
+            int src_x = x, src_y = y, src_z = z, comp = i;
+            const int ys = y - CY[i];
+            if (walls_y && (ys < 0 || ys >= ny)) {
+                comp = opposite(i);
+            } else {
+                src_x = wrap(x - CX[i], nx);
+                src_y = wrap(ys, ny);
+                src_z = wrap(z - CZ[i], nz);
+            }
+            const int64_t m = node(src_x, src_y, src_z, nx, ny);
+            double fl[Q], fs[Q], Fl[3] = {0.0, 0.0, 0.0}, Kl[Q];
+            for (int j = 0; j < Q; ++j) fl[j] = f[(int64_t)j * N + m];
+            if (F)
+                for (int d = 0; d < 3; ++d) Fl[d] = F[(int64_t)d * N + m];
+            for (int r = 0; r < Q; ++r) Kl[r] = per_node_K ? Krates[(int64_t)r * N + m] : Krates[r];
+            if (orc19_collide(fl, Fl, Kl, mode, fs, NULL, NULL, NULL) != 0) err |= 1;
+            out[(int64_t)s * Q + i] = fs[comp];
+        }
+    }
+    return err ? -1 : 0;
+}

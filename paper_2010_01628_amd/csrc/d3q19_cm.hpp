@@ -1,0 +1,384 @@
+// D3Q19 central-moment collision for gfx950 -- device functions.
+//
+// The method is the D3Q19-CM-LBM of De Rosis & Coreixas (arXiv 2010.01628),
+// Sec. II.B: k = T(u) f, k* = (I - K) k + K k_eq + (I - K/2) R, f* = T(u)^-1 k*.
+// This file evaluates that map in a form chosen for FP32 accuracy and low
+// operation count, not the paper's closed forms:
+//
+//   * every quantity is carried as a deviation: populations are stored as
+//     s_i = f_i - w_i rho0, raw moments as m - rho0 W (W the raw moments of the
+//     rest weights), and the collision works on non-equilibrium moments
+//     m - m_eq(rho, u), so no step subtracts two O(1) numbers;
+//   * raw moments come from +-1 sums over the three face-diagonal groups and
+//     the three axes (the monomial set of the paper's basis is closed under
+//     lowering any exponent, so each central moment is reached by three 1-D
+//     binomial sweeps, one per axis: T = N M of App. C with N applied as
+//     x-, y- and z-shifts);
+//   * relaxation happens in the paper's basis rows (trace k4, deviators
+//     k5..k9, third order k10..k15, fourth order k16..k18) and the result is
+//     swept back with +u and mapped to populations by the inverse of M written
+//     per velocity group.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int Q19 = 19;
+
+// Sec. II.A velocity order.
+__host__ __device__ constexpr int cx19(int i)
+{
+    constexpr int v[19] = {0, -1, 0, 0, -1, -1, -1, -1, 0, 0, 1, 0, 0, 1, 1, 1, 1, 0, 0};
+    return v[i];
+}
+__host__ __device__ constexpr int cy19(int i)
+{
+    constexpr int v[19] = {0, 0, -1, 0, -1, 1, 0, 0, -1, -1, 0, 1, 0, 1, -1, 0, 0, 1, 1};
+    return v[i];
+}
+__host__ __device__ constexpr int cz19(int i)
+{
+    constexpr int v[19] = {0, 0, 0, -1, 0, 0, -1, 1, -1, 1, 0, 0, 1, 0, 0, 1, -1, 1, -1};
+    return v[i];
+}
+__host__ __device__ constexpr int opp19(int i) { return i == 0 ? 0 : (i <= 9 ? i + 9 : i - 9); }
+__host__ __device__ constexpr double w19(int i)
+{
+    return i == 0 ? 1.0 / 3.0 : (((i >= 1 && i <= 3) || (i >= 10 && i <= 12)) ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  FP16 uses the hardware round-to-nearest-even conversion;
+// BF16 is rounded to nearest even on the bit pattern (NaN kept quiet).
+// ---------------------------------------------------------------------------
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <class S> struct Codec;
+template <> struct Codec<double> {
+    using R = double;
+    __device__ static inline double dec(double v) { return v; }
+    __device__ static inline double enc(double v) { return v; }
+};
+template <> struct Codec<float> {
+    using R = float;
+    __device__ static inline float dec(float v) { return v; }
+    __device__ static inline float enc(float v) { return v; }
+};
+template <> struct Codec<_Float16> {
+    using R = float;
+    __device__ static inline float dec(_Float16 v) { return (float)v; }
+    __device__ static inline _Float16 enc(float v) { return (_Float16)v; }
+};
+template <> struct Codec<bf16_t> {
+    using R = float;
+    __device__ static inline float dec(bf16_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
+    __device__ static inline bf16_t enc(float v)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return bf16_t{(uint16_t)((u >> 16) | 0x40u)};
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return bf16_t{(uint16_t)(u >> 16)};
+    }
+};
+
+// Relaxation rates of the non-conserved rows of K (Sec. II.B).
+template <class R> struct Rates {
+    R omega;      // k5..k9
+    R omega_bulk; // k4
+    R omega_hi[9];// k10..k18
+};
+
+// Output of a collision besides the new populations.
+template <class R> struct NodeMacro {
+    R rho, ux, uy, uz;
+};
+
+// Deviation raw moments S_pqr = sum_i s_i cx^p cy^q cz^r in the monomial set of
+// the paper's basis.
+template <class R> struct RawMoments {
+    R m000, m100, m010, m001;
+    R m200, m020, m002, m110, m101, m011;
+    R m210, m120, m201, m102, m021, m012;
+    R m220, m202, m022;
+};
+
+template <class R> __host__ __device__ inline void raw_from_pops(const R s[19], RawMoments<R>& m)
+{
+    // xy face diagonals 4(-,-) 5(-,+) 13(+,+) 14(+,-)
+    m.m220 = (s[4] + s[5]) + (s[13] + s[14]);
+    m.m110 = (s[4] - s[5]) + (s[13] - s[14]);
+    m.m210 = (s[5] - s[4]) + (s[13] - s[14]);
+    m.m120 = (s[13] + s[14]) - (s[4] + s[5]);
+    // xz face diagonals 6(-,-) 7(-,+) 15(+,+) 16(+,-)
+    m.m202 = (s[6] + s[7]) + (s[15] + s[16]);
+    m.m101 = (s[6] - s[7]) + (s[15] - s[16]);
+    m.m201 = (s[7] - s[6]) + (s[15] - s[16]);
+    m.m102 = (s[15] + s[16]) - (s[6] + s[7]);
+    // yz face diagonals 8(-,-) 9(-,+) 17(+,+) 18(+,-)
+    m.m022 = (s[8] + s[9]) + (s[17] + s[18]);
+    m.m011 = (s[8] - s[9]) + (s[17] - s[18]);
+    m.m021 = (s[9] - s[8]) + (s[17] - s[18]);
+    m.m012 = (s[17] + s[18]) - (s[8] + s[9]);
+    // axes
+    const R ax = s[1] + s[10], ay = s[2] + s[11], az = s[3] + s[12];
+    m.m200 = ax + m.m220 + m.m202;
+    m.m020 = ay + m.m220 + m.m022;
+    m.m002 = az + m.m202 + m.m022;
+    m.m100 = (s[10] - s[1]) + m.m120 + m.m102;
+    m.m010 = (s[11] - s[2]) + m.m210 + m.m012;
+    m.m001 = (s[12] - s[3]) + m.m201 + m.m021;
+    m.m000 = s[0] + (ax + ay + az) + (m.m220 + m.m202 + m.m022);
+}
+
+// Populations from deviation raw moments (inverse of raw_from_pops).
+template <class R> __host__ __device__ inline void pops_from_raw(const RawMoments<R>& m, R s[19])
+{
+    const R q = R(0.25), h = R(0.5);
+    s[13] = q * ((m.m220 + m.m110) + (m.m210 + m.m120));
+    s[4] = q * ((m.m220 + m.m110) - (m.m210 + m.m120));
+    s[5] = q * ((m.m220 - m.m110) + (m.m210 - m.m120));
+    s[14] = q * ((m.m220 - m.m110) - (m.m210 - m.m120));
+    s[15] = q * ((m.m202 + m.m101) + (m.m201 + m.m102));
+    s[6] = q * ((m.m202 + m.m101) - (m.m201 + m.m102));
+    s[7] = q * ((m.m202 - m.m101) + (m.m201 - m.m102));
+    s[16] = q * ((m.m202 - m.m101) - (m.m201 - m.m102));
+    s[17] = q * ((m.m022 + m.m011) + (m.m021 + m.m012));
+    s[8] = q * ((m.m022 + m.m011) - (m.m021 + m.m012));
+    s[9] = q * ((m.m022 - m.m011) + (m.m021 - m.m012));
+    s[18] = q * ((m.m022 - m.m011) - (m.m021 - m.m012));
+    const R ax = m.m200 - (m.m220 + m.m202), dx = m.m100 - (m.m120 + m.m102);
+    const R ay = m.m020 - (m.m220 + m.m022), dy = m.m010 - (m.m210 + m.m012);
+    const R az = m.m002 - (m.m202 + m.m022), dz = m.m001 - (m.m201 + m.m021);
+    s[10] = h * (ax + dx);
+    s[1] = h * (ax - dx);
+    s[11] = h * (ay + dy);
+    s[2] = h * (ay - dy);
+    s[12] = h * (az + dz);
+    s[3] = h * (az - dz);
+    s[0] = m.m000 - (ax + ay + az) - (m.m220 + m.m202 + m.m022);
+}
+
+// Equilibrium raw moments minus the rest ones: m_eq(rho, u) - rho0 W, with
+// m_eq the raw moments of the extended equilibrium (those of T^-1 k_eq).
+template <class R>
+__host__ __device__ inline void eq_raw_deviation(R drho, R rho, R ux, R uy, R uz, RawMoments<R>& d)
+{
+    const R t = R(1) / R(3), n = R(1) / R(9);
+    const R x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+    const R rx = rho * ux, ry = rho * uy, rz = rho * uz;
+    d.m000 = drho;
+    d.m100 = rx;
+    d.m010 = ry;
+    d.m001 = rz;
+    d.m200 = drho * t + rho * x2;
+    d.m020 = drho * t + rho * y2;
+    d.m002 = drho * t + rho * z2;
+    d.m110 = rx * uy;
+    d.m101 = rx * uz;
+    d.m011 = ry * uz;
+    d.m210 = ry * (x2 + t);
+    d.m120 = rx * (y2 + t);
+    d.m201 = rz * (x2 + t);
+    d.m102 = rx * (z2 + t);
+    d.m021 = rz * (y2 + t);
+    d.m012 = ry * (z2 + t);
+    d.m220 = drho * n + rho * (x2 * y2 + (x2 + y2) * t);
+    d.m202 = drho * n + rho * (x2 * z2 + (x2 + z2) * t);
+    d.m022 = drho * n + rho * (y2 * z2 + (y2 + z2) * t);
+}
+
+// 1-D binomial shift of a chain (v0, v1, v2) of moments with exponents 0,1,2
+// along one axis by a: v_p <- sum_k C(p,k) a^(p-k) v_k.
+template <class R> __host__ __device__ inline void shift3(R v0, R& v1, R& v2, R a)
+{
+    const R n2 = v2 + a * (R(2) * v1 + a * v0);
+    v1 = v1 + a * v0;
+    v2 = n2;
+}
+template <class R> __host__ __device__ inline void shift2(R v0, R& v1, R a) { v1 = v1 + a * v0; }
+
+// Shift every moment of the monomial set by (a, b, c): central moments from raw
+// ones with (a,b,c) = -u, raw from central with +u.  m000 is left unchanged.
+template <class R> __host__ __device__ inline void shift_all(RawMoments<R>& m, R a, R b, R c)
+{
+    // x sweeps along chains with fixed (q, r)
+    shift3(m.m000, m.m100, m.m200, a);
+    shift3(m.m010, m.m110, m.m210, a);
+    shift3(m.m001, m.m101, m.m201, a);
+    shift3(m.m020, m.m120, m.m220, a);
+    shift3(m.m002, m.m102, m.m202, a);
+    // y sweeps along chains with fixed (p, r)
+    shift3(m.m000, m.m010, m.m020, b);
+    shift3(m.m100, m.m110, m.m120, b);
+    shift3(m.m200, m.m210, m.m220, b);
+    shift3(m.m001, m.m011, m.m021, b);
+    shift3(m.m002, m.m012, m.m022, b);
+    // z sweeps along chains with fixed (p, q)
+    shift3(m.m000, m.m001, m.m002, c);
+    shift3(m.m100, m.m101, m.m102, c);
+    shift3(m.m010, m.m011, m.m012, c);
+    shift3(m.m200, m.m201, m.m202, c);
+    shift3(m.m020, m.m021, m.m022, c);
+}
+
+// Pre-collision non-equilibrium central moments in the paper's basis rows,
+// divided into what the relaxation needs.  k[0..3] are not stored (k0 neq = 0,
+// k1..3 = -F/2); kn[4..18] = k_r - k_eq_r.
+template <class R> struct NeqCM {
+    R k[19];
+};
+
+// The collision of Sec. II.B eq. (posColl0) applied to deviations s (in place).
+// GENERAL = false assumes the paper's rates (omega_bulk = 1, omega_hi = 1) and
+// skips every moment those rates discard.  If kneq is non-null it receives the
+// pre-collision non-equilibrium CMs (rows 4..18).
+template <class R, bool GENERAL>
+__host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, const Rates<R>& rt, NodeMacro<R>& mac,
+                                  NeqCM<R>* kneq = nullptr)
+{
+    const R third = R(1) / R(3), ninth = R(1) / R(9), cs2 = third;
+    RawMoments<R> m;
+    raw_from_pops(s, m);
+    const R drho = m.m000;
+    const R rho = rho0 + drho;
+    const R irho = R(1) / rho;
+    const R ux = (m.m100 + R(0.5) * Fx) * irho;
+    const R uy = (m.m010 + R(0.5) * Fy) * irho;
+    const R uz = (m.m001 + R(0.5) * Fz) * irho;
+    mac.rho = rho;
+    mac.ux = ux;
+    mac.uy = uy;
+    mac.uz = uz;
+
+    // non-equilibrium raw moments n = (S + rho0 W) - m_eq(rho, u)
+    RawMoments<R> e;
+    eq_raw_deviation(drho, rho, ux, uy, uz, e);
+    RawMoments<R> n;
+    n.m000 = R(0);
+    n.m100 = R(-0.5) * Fx;
+    n.m010 = R(-0.5) * Fy;
+    n.m001 = R(-0.5) * Fz;
+    n.m200 = m.m200 - e.m200;
+    n.m020 = m.m020 - e.m020;
+    n.m002 = m.m002 - e.m002;
+    n.m110 = m.m110 - e.m110;
+    n.m101 = m.m101 - e.m101;
+    n.m011 = m.m011 - e.m011;
+    if constexpr (GENERAL) {
+        n.m210 = m.m210 - e.m210;
+        n.m120 = m.m120 - e.m120;
+        n.m201 = m.m201 - e.m201;
+        n.m102 = m.m102 - e.m102;
+        n.m021 = m.m021 - e.m021;
+        n.m012 = m.m012 - e.m012;
+        n.m220 = m.m220 - e.m220;
+        n.m202 = m.m202 - e.m202;
+        n.m022 = m.m022 - e.m022;
+    } else {
+        n.m210 = n.m120 = n.m201 = n.m102 = n.m021 = n.m012 = n.m220 = n.m202 = n.m022 = R(0);
+    }
+    // central non-equilibrium moments (shift by -u)
+    shift_all(n, -ux, -uy, -uz);
+
+    const R k4 = n.m200 + n.m020 + n.m002;
+    const R k5 = n.m200 - n.m020;
+    const R k6 = n.m020 - n.m002;
+    if (kneq) {
+        kneq->k[0] = R(0);
+        kneq->k[1] = n.m100;
+        kneq->k[2] = n.m010;
+        kneq->k[3] = n.m001;
+        kneq->k[4] = k4;
+        kneq->k[5] = k5;
+        kneq->k[6] = k6;
+        kneq->k[7] = n.m110;
+        kneq->k[8] = n.m101;
+        kneq->k[9] = n.m011;
+        kneq->k[10] = n.m210;
+        kneq->k[11] = n.m120;
+        kneq->k[12] = n.m201;
+        kneq->k[13] = n.m102;
+        kneq->k[14] = n.m021;
+        kneq->k[15] = n.m012;
+        kneq->k[16] = n.m220;
+        kneq->k[17] = n.m202;
+        kneq->k[18] = n.m022;
+    }
+
+    // relaxation + forcing (post-collision non-equilibrium CMs)
+    const R w1 = R(1) - rt.omega;
+    const R s5 = w1 * k5, s6 = w1 * k6;
+    R s4 = R(0);
+    RawMoments<R> p;
+    p.m000 = R(0);
+    p.m100 = R(0.5) * Fx;
+    p.m010 = R(0.5) * Fy;
+    p.m001 = R(0.5) * Fz;
+    p.m110 = w1 * n.m110;
+    p.m101 = w1 * n.m101;
+    p.m011 = w1 * n.m011;
+    if constexpr (GENERAL) {
+        s4 = (R(1) - rt.omega_bulk) * k4;
+        const R* oh = rt.omega_hi;
+        p.m210 = (R(1) - oh[0]) * n.m210 + (R(1) - R(0.5) * oh[0]) * cs2 * Fy;
+        p.m120 = (R(1) - oh[1]) * n.m120 + (R(1) - R(0.5) * oh[1]) * cs2 * Fx;
+        p.m201 = (R(1) - oh[2]) * n.m201 + (R(1) - R(0.5) * oh[2]) * cs2 * Fz;
+        p.m102 = (R(1) - oh[3]) * n.m102 + (R(1) - R(0.5) * oh[3]) * cs2 * Fx;
+        p.m021 = (R(1) - oh[4]) * n.m021 + (R(1) - R(0.5) * oh[4]) * cs2 * Fz;
+        p.m012 = (R(1) - oh[5]) * n.m012 + (R(1) - R(0.5) * oh[5]) * cs2 * Fy;
+        p.m220 = (R(1) - oh[6]) * n.m220;
+        p.m202 = (R(1) - oh[7]) * n.m202;
+        p.m022 = (R(1) - oh[8]) * n.m022;
+    } else {
+        const R hf = R(0.5) * cs2;
+        p.m210 = hf * Fy;
+        p.m120 = hf * Fx;
+        p.m201 = hf * Fz;
+        p.m102 = hf * Fx;
+        p.m021 = hf * Fz;
+        p.m012 = hf * Fy;
+        p.m220 = p.m202 = p.m022 = R(0);
+    }
+    p.m200 = third * (s4 + R(2) * s5 + s6);
+    p.m020 = third * (s4 - s5 + s6);
+    p.m002 = third * (s4 - s5 - R(2) * s6);
+    (void)ninth;
+
+    // back to raw moments (shift by +u) and add the equilibrium deviation
+    shift_all(p, ux, uy, uz);
+    p.m000 = e.m000;
+    p.m100 += e.m100;
+    p.m010 += e.m010;
+    p.m001 += e.m001;
+    p.m200 += e.m200;
+    p.m020 += e.m020;
+    p.m002 += e.m002;
+    p.m110 += e.m110;
+    p.m101 += e.m101;
+    p.m011 += e.m011;
+    p.m210 += e.m210;
+    p.m120 += e.m120;
+    p.m201 += e.m201;
+    p.m102 += e.m102;
+    p.m021 += e.m021;
+    p.m012 += e.m012;
+    p.m220 += e.m220;
+    p.m202 += e.m202;
+    p.m022 += e.m022;
+    pops_from_raw(p, s);
+}
+
+// Deviations of the extended equilibrium f_eq(rho, u) - w rho0 (eq. EqQ19RM),
+// through its raw moments.
+template <class R> __host__ __device__ inline void equilibrium_deviation(R rho, R rho0, R ux, R uy, R uz, R s[19])
+{
+    RawMoments<R> e;
+    eq_raw_deviation(rho - rho0, rho, ux, uy, uz, e);
+    pops_from_raw(e, s);
+}
+
+} // namespace lbm

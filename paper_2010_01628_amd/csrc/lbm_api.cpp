@@ -1,0 +1,388 @@
+// Host side of the C ABI declared in include/lbm.h.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "lbm_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                 \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s: %s (%s:%d)", #expr, \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                                   \
+    } while (0)
+
+int elem_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2); }
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+} // namespace
+
+struct lbm_handle {
+    lbm_params p;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    lbm::Geom g{};
+    lbm::Phys ph{};
+    void* buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t steps = 0;
+    double* row_table = nullptr;
+    double* partials = nullptr;
+    double* diag_dev = nullptr;
+    double* diag_host = nullptr;
+    dim3 grid, block;
+    bool walls = false, general = false;
+    int64_t bytes = 0;
+    int nblocks = 0;
+};
+
+namespace {
+
+int pattern_of(const lbm_handle* h)
+{
+    if (h->p.streaming == LBM_AB) return 0;
+    return (h->steps & 1) ? 2 : 1;
+}
+
+int validate(const lbm_params* p)
+{
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (p->abi_version != LBM_ABI_VERSION)
+        return fail(LBM_EINVAL, "abi_version %u != %d", p->abi_version, LBM_ABI_VERSION);
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "lattice size must be positive");
+    if ((int64_t)p->nx * p->ny * p->nz > 0x7fffffffLL) return fail(LBM_EINVAL, "more than 2^31-1 nodes");
+    if (p->nz > 65535) return fail(LBM_EINVAL, "nz > 65535");
+    if (p->q != 19) return fail(p->q == 27 ? LBM_EUNSUPPORTED : LBM_EINVAL, "q must be 19 (got %d)", p->q);
+    if (p->precision < LBM_FP64 || p->precision > LBM_BF16_SHIFTED) return fail(LBM_EINVAL, "bad precision");
+    if (p->streaming != LBM_AB && p->streaming != LBM_AA) return fail(LBM_EINVAL, "bad streaming");
+    auto rate_ok = [](double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; };
+    if (!rate_ok(p->omega)) return fail(LBM_EINVAL, "omega must be in (0,2) (got %g)", p->omega);
+    if (!rate_ok(p->omega_bulk)) return fail(LBM_EINVAL, "omega_bulk must be in (0,2)");
+    for (int j = 0; j < 9; ++j)
+        if (!(std::isfinite(p->omega_hi[j]) && p->omega_hi[j] > 0.0 && p->omega_hi[j] <= 2.0))
+            return fail(LBM_EINVAL, "omega_hi[%d] must be in (0,2]", j);
+    if (!(std::isfinite(p->rho0) && p->rho0 > 0.0)) return fail(LBM_EINVAL, "rho0 must be positive");
+    if (p->force_mode < LBM_FORCE_NONE || p->force_mode > LBM_FORCE_KOLMOGOROV) return fail(LBM_EINVAL, "bad force_mode");
+    if (p->force_mode == LBM_FORCE_FIELD && !p->force_field) return fail(LBM_EINVAL, "force_field is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p->force[d])) return fail(LBM_EINVAL, "force must be finite");
+    if (!std::isfinite(p->kolmogorov_amp)) return fail(LBM_EINVAL, "kolmogorov_amp must be finite");
+    if (p->walls_y != 0 && p->walls_y != 1) return fail(LBM_EINVAL, "walls_y must be 0 or 1");
+    if (p->walls_y && p->ny < 2) return fail(LBM_EINVAL, "walls need ny >= 2");
+    if (p->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+    if (p->block_x < 0 || p->block_y < 0) return fail(LBM_EINVAL, "negative block shape");
+    const int bx = p->block_x ? p->block_x : 64, by = p->block_y ? p->block_y : 1;
+    if (bx * by > 256 || (bx * by) % 64 != 0)
+        return fail(LBM_EINVAL, "block_x*block_y must be a multiple of 64 and at most 256");
+    return LBM_OK;
+}
+
+int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Default work-group shape: 64 x-values per wave, 4 rows per block (256
+// threads); narrow lattices pack more rows.
+void default_block(const lbm_params* p, int& bx, int& by)
+{
+    if (p->block_x && p->block_y) {
+        bx = p->block_x;
+        by = p->block_y;
+        return;
+    }
+    bx = p->nx >= 64 ? 64 : next_pow2(p->nx);
+    if (bx < 8) bx = 8;
+    by = 256 / bx;
+    const int ny2 = next_pow2(p->ny);
+    while (by > 1 && by / 2 >= ny2 && bx * (by / 2) >= 64) by /= 2;
+}
+
+int64_t pad_stride(int64_t N, int eb)
+{
+    // Separate the starts of consecutive population arrays by a non-power-of-two
+    // number of 256-byte blocks so the streams of one step spread over channels.
+    const char* env = std::getenv("LBM_PAD_BYTES");
+    int64_t pad_bytes = env ? std::atoll(env) : 4352;  // 17 * 256 B
+    int64_t base = round_up(N * eb, 4096);
+    return (base + pad_bytes) / eb;
+}
+
+int run_check(lbm_handle* h)
+{
+    lbm::launch_moments(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, nullptr, nullptr,
+                        h->partials, h->grid, h->block, h->stream);
+    lbm::launch_reduce(h->partials, h->nblocks, h->diag_dev, h->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h->diag_host, h->diag_dev, lbm::NDIAG_OUT * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+void lbm_params_default(lbm_params* p)
+{
+    std::memset(p, 0, sizeof *p);
+    p->abi_version = LBM_ABI_VERSION;
+    p->nx = p->ny = p->nz = 32;
+    p->q = 19;
+    p->precision = LBM_FP32;
+    p->streaming = LBM_AB;
+    p->omega = 1.0;
+    p->omega_bulk = 1.0;
+    for (int j = 0; j < 9; ++j) p->omega_hi[j] = 1.0;
+    p->rho0 = 1.0;
+    p->force_mode = LBM_FORCE_NONE;
+}
+
+int lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+const char* lbm_last_error(void) { return g_err; }
+
+int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    lbm_handle* h = new lbm_handle();
+    h->p = *p;
+    h->stream = (hipStream_t)stream;
+    auto cleanup = [&](int code) {
+        lbm_destroy(h);
+        return code;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) return cleanup(fail(LBM_EDEVICE, "no HIP device"));
+    const int eb = elem_bytes(p->precision);
+    h->g.nx = p->nx;
+    h->g.ny = p->ny;
+    h->g.nz = p->nz;
+    h->g.nxy = p->nx * p->ny;
+    h->g.N = p->nx * p->ny * p->nz;
+    h->g.stride = pad_stride(h->g.N, eb);
+    h->walls = p->walls_y != 0;
+    h->general = p->omega_bulk != 1.0;
+    for (int j = 0; j < 9; ++j) h->general = h->general || p->omega_hi[j] != 1.0;
+
+    h->ph.omega = p->omega;
+    h->ph.omega_bulk = p->omega_bulk;
+    for (int j = 0; j < 9; ++j) h->ph.omega_hi[j] = p->omega_hi[j];
+    h->ph.rho0 = p->rho0;
+    h->ph.force_mode = lbm::FORCE_NONE;
+    for (int d = 0; d < 3; ++d) h->ph.force[d] = p->force[d];
+    h->ph.force_field = nullptr;
+    h->ph.row_table = nullptr;
+
+    int bx, by;
+    default_block(p, bx, by);
+    h->block = dim3(bx, by, 1);
+    h->grid = dim3((p->nx + bx - 1) / bx, (p->ny + by - 1) / by, p->nz);
+    h->nblocks = h->grid.x * h->grid.y * h->grid.z;
+
+    const int64_t pop_bytes = (int64_t)19 * h->g.stride * eb;
+    const int nbuf = p->streaming == LBM_AB ? 2 : 1;
+    for (int b = 0; b < nbuf; ++b) {
+        hipError_t e = hipMalloc(&h->buf[b], pop_bytes);
+        if (e != hipSuccess)
+            return cleanup(fail(LBM_ENOMEM, "population buffer of %lld bytes: %s", (long long)pop_bytes, hipGetErrorString(e)));
+        h->bytes += pop_bytes;
+    }
+    if (hipMalloc((void**)&h->partials, (int64_t)h->nblocks * lbm::NDIAG_OUT * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&h->diag_dev, lbm::NDIAG_OUT * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&h->diag_host, lbm::NDIAG_OUT * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(LBM_ENOMEM, "diagnostic buffers"));
+    h->bytes += (int64_t)(h->nblocks + 1) * lbm::NDIAG_OUT * sizeof(double);
+
+    switch (p->force_mode) {
+    case LBM_FORCE_UNIFORM: h->ph.force_mode = lbm::FORCE_UNIFORM; break;
+    case LBM_FORCE_FIELD:
+        h->ph.force_mode = lbm::FORCE_FIELD;
+        h->ph.force_field = p->force_field;
+        break;
+    case LBM_FORCE_KOLMOGOROV: {
+        h->ph.force_mode = lbm::FORCE_ROW_TABLE;
+        double* tab = (double*)std::malloc(sizeof(double) * p->ny);
+        const double two_pi = 6.283185307179586476925286766559;
+        for (int y = 0; y < p->ny; ++y) tab[y] = p->kolmogorov_amp * std::sin(two_pi * y / p->ny);
+        hipError_t e = hipMalloc((void**)&h->row_table, sizeof(double) * p->ny);
+        if (e == hipSuccess) e = hipMemcpy(h->row_table, tab, sizeof(double) * p->ny, hipMemcpyHostToDevice);
+        std::free(tab);
+        if (e != hipSuccess) return cleanup(fail(LBM_EDEVICE, "force table: %s", hipGetErrorString(e)));
+        h->ph.row_table = h->row_table;
+        h->bytes += sizeof(double) * p->ny;
+        break;
+    }
+    default: break;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_handle* h)
+{
+    if (!h) return LBM_OK;
+    if (h->stream || h->buf[0]) hipStreamSynchronize(h->stream);
+    for (int b = 0; b < 2; ++b)
+        if (h->buf[b]) hipFree(h->buf[b]);
+    if (h->row_table) hipFree(h->row_table);
+    if (h->partials) hipFree(h->partials);
+    if (h->diag_dev) hipFree(h->diag_dev);
+    if (h->diag_host) hipHostFree(h->diag_host);
+    delete h;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_handle* h, const double* rho, const double* u, int on_device)
+{
+    if (!h || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+    const int64_t N = h->g.N;
+    const double* drho = rho;
+    const double* du = u;
+    double* staging = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc((void**)&staging, sizeof(double) * 4 * N));
+        HIP_TRY(hipMemcpyAsync(staging, rho, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(staging + N, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice, h->stream));
+        drho = staging;
+        du = staging + N;
+    }
+    h->steps = 0;
+    h->cur = 0;
+    lbm::launch_init(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, drho, du, h->grid,
+                     h->block, h->stream);
+    hipError_t e = hipGetLastError();
+    if (staging) {
+        hipStreamSynchronize(h->stream);
+        hipFree(staging);
+    }
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "init kernel: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int64_t nsteps)
+{
+    if (!h) return fail(LBM_EINVAL, "NULL handle");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int pat = pattern_of(h);
+        const int src = h->cur;
+        const int dst = h->p.streaming == LBM_AB ? 1 - h->cur : h->cur;
+        lbm::launch_step(h->p.precision, pat, h->walls, h->general, h->buf[src], h->buf[dst], h->g, h->ph, h->grid,
+                         h->block, h->stream);
+        h->cur = dst;
+        h->steps++;
+        if (h->p.check_every > 0 && h->steps % h->p.check_every == 0) {
+            int rc = run_check(h);
+            if (rc) return rc;
+            const double* d = h->diag_host;
+            if (!(d[6] == 0.0 && std::isfinite(d[0]) && d[7] > 0.0))
+                return fail(LBM_EUNSTABLE, "unstable at step %lld: %g bad nodes, sum rho = %g, min rho = %g",
+                            (long long)h->steps, d[6], d[0], d[7]);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_device)
+{
+    if (!h) return fail(LBM_EINVAL, "NULL handle");
+    const int64_t N = h->g.N;
+    double* drho = rho;
+    double* du = u;
+    double* staging = nullptr;
+    if (!on_device && (rho || u)) {
+        HIP_TRY(hipMalloc((void**)&staging, sizeof(double) * 4 * N));
+        drho = rho ? staging : nullptr;
+        du = u ? staging + N : nullptr;
+    }
+    lbm::launch_moments(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, drho, du, h->partials,
+                        h->grid, h->block, h->stream);
+    if (diag) lbm::launch_reduce(h->partials, h->nblocks, h->diag_dev, h->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && staging) {
+        if (rho) e = hipMemcpyAsync(rho, staging, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && u) e = hipMemcpyAsync(u, staging + N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, h->stream);
+    }
+    if (e == hipSuccess && diag)
+        e = hipMemcpyAsync(h->diag_host, h->diag_dev, lbm::NDIAG_OUT * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && (diag || staging)) e = hipStreamSynchronize(h->stream);
+    if (staging) hipFree(staging);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "moments: %s", hipGetErrorString(e));
+    if (diag)
+        for (int k = 0; k < 6; ++k) diag[k] = h->diag_host[k];
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle* h, double* f, int on_device)
+{
+    if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+    const int64_t bytes = sizeof(double) * 19 * (int64_t)h->g.N;
+    double* dst = f;
+    if (!on_device) HIP_TRY(hipMalloc((void**)&dst, bytes));
+    lbm::launch_get_pops(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, dst, h->grid,
+                         h->block, h->stream);
+    hipError_t e = hipGetLastError();
+    if (!on_device) {
+        if (e == hipSuccess) e = hipMemcpyAsync(f, dst, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        hipFree(dst);
+    }
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "get_populations: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_handle* h, const double* f, int on_device)
+{
+    if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+    const int64_t bytes = sizeof(double) * 19 * (int64_t)h->g.N;
+    const double* src = f;
+    double* staging = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc((void**)&staging, bytes));
+        HIP_TRY(hipMemcpyAsync(staging, f, bytes, hipMemcpyHostToDevice, h->stream));
+        src = staging;
+    }
+    lbm::launch_set_pops(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, src, h->grid,
+                         h->block, h->stream);
+    hipError_t e = hipGetLastError();
+    if (staging) {
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        hipFree(staging);
+    }
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "set_populations: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }
+
+int64_t lbm_device_bytes(const lbm_handle* h) { return h ? h->bytes : -1; }
+
+} // extern "C"

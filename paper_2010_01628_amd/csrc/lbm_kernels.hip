@@ -1,0 +1,463 @@
+// D3Q19 CM-LBM kernels for gfx950: fused gather + collide + store.
+//
+// Data layout in HBM: populations are structure of arrays, one array per
+// direction, stored as deviations s_i = f_i - w_i rho0 in the storage type S.
+// Element (i, n) sits at buf[i * stride + n], n = x + nx (y + ny z); stride >=
+// N is padded so that the 19 (or 38) streams of a step do not start on the
+// same HBM channel.
+//
+// Streaming patterns (Sec. II.B eq. "streaming_f", f_i(x + c_i, t+1) = f_i*(x, t)):
+//   A-B pull:  src holds post-collision values of the previous step at their
+//              own nodes.  Node x gathers f_i(x) = src_i(x - c_i) (or, when
+//              x - c_i lies beyond a wall, src_opp(i)(x): halfway bounce-back),
+//              collides and writes f_i*(x) to dst_i(x): reads shifted, writes
+//              aligned and coalesced.
+//   AA even:   node x reads slot i at x (= f_i(x)), writes f_i* to slot opp(i)
+//              at x.  All accesses local.
+//   AA odd:    node x reads slot opp(i) at x - c_i (wall: slot i at x) and
+//              writes f_i* to slot i at x + c_i (wall: slot opp(i) at x).  Each
+//              node writes exactly the locations it read, so the update is in
+//              place and race free.
+#include "d3q19_cm.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+enum Pattern { AB = 0, AA_EVEN = 1, AA_ODD = 2 };
+
+struct NodeIdx {
+    int x, y, z;
+    int ox[3], oy[3], oz[3]; // offsets of x-1,x,x+1 (and y, z rows/planes)
+    bool ylo, yhi;           // y-1 / y+1 beyond a wall
+};
+
+__device__ inline void node_idx(const Geom& g, int x, int y, int z, NodeIdx& d)
+{
+    d.x = x;
+    d.y = y;
+    d.z = z;
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    d.ox[0] = xm;
+    d.ox[1] = x;
+    d.ox[2] = xp;
+    d.oy[0] = ym * g.nx;
+    d.oy[1] = y * g.nx;
+    d.oy[2] = yp * g.nx;
+    d.oz[0] = zm * g.nxy;
+    d.oz[1] = z * g.nxy;
+    d.oz[2] = zp * g.nxy;
+    d.ylo = y == 0;
+    d.yhi = y == g.ny - 1;
+}
+
+// index of node x + (dx, dy, dz), dx etc. in {-1, 0, 1}
+__device__ inline int nb(const NodeIdx& d, int dx, int dy, int dz) { return d.ox[1 + dx] + d.oy[1 + dy] + d.oz[1 + dz]; }
+
+// Is x + (0, dy, 0) beyond a y wall?
+template <bool WALLS> __device__ inline bool beyond(const NodeIdx& d, int dy)
+{
+    if constexpr (!WALLS) return false;
+    return (dy < 0 && d.ylo) || (dy > 0 && d.yhi);
+}
+
+// Where f_i(x, t) lives in the buffer for pattern P (slot, node index).
+template <Pattern P, bool WALLS>
+__device__ inline void state_loc(const NodeIdx& d, int i, int& slot, int& idx)
+{
+    const int cx = cx19(i), cy = cy19(i), cz = cz19(i);
+    if constexpr (P == AA_EVEN) {
+        slot = i;
+        idx = nb(d, 0, 0, 0);
+    } else {
+        if (beyond<WALLS>(d, -cy)) {
+            // population i arriving from beyond a wall: bounce-back of opp(i)
+            slot = (P == AB) ? opp19(i) : i;
+            idx = nb(d, 0, 0, 0);
+        } else {
+            slot = (P == AB) ? i : opp19(i);
+            idx = nb(d, -cx, -cy, -cz);
+        }
+    }
+}
+
+// Load f_i(x, t) (as deviations) for the current pattern.
+template <class S, Pattern P, bool WALLS>
+__device__ inline void gather(const S* __restrict__ buf, int64_t stride, const NodeIdx& d, typename Codec<S>::R s[19])
+{
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        int slot, idx;
+        state_loc<P, WALLS>(d, i, slot, idx);
+        s[i] = Codec<S>::dec(buf[(int64_t)slot * stride + idx]);
+    }
+}
+
+// Store f_i*(x, t) (deviations) for the current pattern.
+template <class S, Pattern P, bool WALLS>
+__device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeIdx& d, const typename Codec<S>::R s[19])
+{
+    const int n = nb(d, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const int cx = cx19(i), cy = cy19(i), cz = cz19(i);
+        int slot, idx;
+        if constexpr (P == AB) {
+            slot = i;
+            idx = n;
+        } else if constexpr (P == AA_EVEN) {
+            slot = opp19(i);
+            idx = n;
+        } else {
+            if (beyond<WALLS>(d, cy)) {
+                slot = opp19(i);
+                idx = n;
+            } else {
+                slot = i;
+                idx = nb(d, cx, cy, cz);
+            }
+        }
+        buf[(int64_t)slot * stride + idx] = Codec<S>::enc(s[i]);
+    }
+}
+
+template <class R> __device__ inline void node_force(const Phys& ph, const Geom& g, int n, int y, R& Fx, R& Fy, R& Fz)
+{
+    switch (ph.force_mode) {
+    case FORCE_UNIFORM:
+        Fx = (R)ph.force[0];
+        Fy = (R)ph.force[1];
+        Fz = (R)ph.force[2];
+        break;
+    case FORCE_FIELD:
+        Fx = (R)ph.force_field[n];
+        Fy = (R)ph.force_field[g.N + n];
+        Fz = (R)ph.force_field[2 * g.N + n];
+        break;
+    case FORCE_ROW_TABLE:
+        Fx = (R)ph.row_table[y];
+        Fy = R(0);
+        Fz = R(0);
+        break;
+    default:
+        Fx = Fy = Fz = R(0);
+    }
+}
+
+template <class R> __device__ inline Rates<R> rates_of(const Phys& ph)
+{
+    Rates<R> rt;
+    rt.omega = (R)ph.omega;
+    rt.omega_bulk = (R)ph.omega_bulk;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) rt.omega_hi[j] = (R)ph.omega_hi[j];
+    return rt;
+}
+
+// One fused step at every node.  Block (bx, by, 1) covers bx x-values of by
+// rows; blockIdx.z is the z plane.
+template <class S, Pattern P, bool WALLS, bool GENERAL>
+__global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    R s[19];
+    gather<S, P, WALLS>(src, g.stride, d, s);
+    R Fx, Fy, Fz;
+    node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
+    NodeMacro<R> mac;
+    collide_cm<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
+    scatter<S, P, WALLS>(dst, g.stride, d, s);
+}
+
+// Write given deviations s_i(x) where the next step of pattern P reads them as
+// f_i(x, t) (the locations of state_loc; a bijection over all (node, i)).
+template <class S, Pattern P, bool WALLS>
+__device__ inline void place_state(S* __restrict__ buf, int64_t stride, const NodeIdx& d, const typename Codec<S>::R s[19])
+{
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        int slot, idx;
+        state_loc<P, WALLS>(d, i, slot, idx);
+        buf[(int64_t)slot * stride + idx] = Codec<S>::enc(s[i]);
+    }
+}
+
+// Initialisation at equilibrium from rho, u (double, device).
+template <class S, Pattern P, bool WALLS>
+__global__ __launch_bounds__(256) void k_init(S* __restrict__ buf, Geom g, double rho0, const double* __restrict__ rho,
+                                             const double* __restrict__ u)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int n = nb(d, 0, 0, 0);
+    R s[19];
+    equilibrium_deviation<R>((R)rho[n], (R)rho0, (R)u[n], (R)u[g.N + n], (R)u[2 * g.N + n], s);
+    place_state<S, P, WALLS>(buf, g.stride, d, s);
+}
+
+// Populations f = w rho0 + s from double[19 N] (device) into the state.
+template <class S, Pattern P, bool WALLS>
+__global__ __launch_bounds__(256) void k_set_pops(S* __restrict__ buf, Geom g, double rho0, const double* __restrict__ f)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int n = nb(d, 0, 0, 0);
+    R s[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) s[i] = (R)(f[(int64_t)i * g.N + n] - w19(i) * rho0);
+    place_state<S, P, WALLS>(buf, g.stride, d, s);
+}
+
+template <class S, Pattern P, bool WALLS>
+__global__ __launch_bounds__(256) void k_get_pops(const S* __restrict__ buf, Geom g, double rho0, double* __restrict__ f)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int n = nb(d, 0, 0, 0);
+    R s[19];
+    gather<S, P, WALLS>(buf, g.stride, d, s);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) f[(int64_t)i * g.N + n] = w19(i) * rho0 + (double)s[i];
+}
+
+// ---------------------------------------------------------------------------
+// Macroscopic fields and FP64 diagnostics.  Each block reduces its nodes with
+// wavefront shuffles then LDS, and writes one partial; k_reduce_partials sums
+// the partials in a fixed order (deterministic).
+// partial layout: [sum rho, sum rho ux, sum rho uy, sum rho uz, KE, max|u|,
+//                  bad count, min rho]
+// ---------------------------------------------------------------------------
+constexpr int NDIAG = 8;
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline void block_reduce_store(double v[NDIAG], double* __restrict__ out)
+{
+    __shared__ double lds[NDIAG][16];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int nthreads = blockDim.x * blockDim.y;
+    const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < NDIAG; ++k) {
+        double r = (k == 5) ? wave_max(v[k]) : (k == 7 ? wave_min(v[k]) : wave_sum(v[k]));
+        if (lane == 0) lds[k][wid] = r;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int nw = (nthreads + 63) / 64;
+        for (int k = 0; k < NDIAG; ++k) {
+            double r = lds[k][0];
+            for (int w = 1; w < nw; ++w) r = (k == 5) ? fmax(r, lds[k][w]) : (k == 7 ? fmin(r, lds[k][w]) : r + lds[k][w]);
+            out[k] = r;
+        }
+    }
+}
+
+template <class S, Pattern P, bool WALLS>
+__global__ __launch_bounds__(256) void k_moments(const S* __restrict__ buf, Geom g, Phys ph, double* __restrict__ rho_out,
+                                                double* __restrict__ u_out, double* __restrict__ partials)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double v[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 1e300};
+    if (x < g.nx && y < g.ny) {
+        NodeIdx d;
+        node_idx(g, x, y, z, d);
+        const int n = nb(d, 0, 0, 0);
+        R s[19];
+        gather<S, P, WALLS>(buf, g.stride, d, s);
+        RawMoments<R> m;
+        raw_from_pops(s, m);
+        R Fx, Fy, Fz;
+        node_force(ph, g, n, y, Fx, Fy, Fz);
+        const double rho = ph.rho0 + (double)m.m000;
+        const double ux = ((double)m.m100 + 0.5 * (double)Fx) / rho;
+        const double uy = ((double)m.m010 + 0.5 * (double)Fy) / rho;
+        const double uz = ((double)m.m001 + 0.5 * (double)Fz) / rho;
+        if (rho_out) rho_out[n] = rho;
+        if (u_out) {
+            u_out[n] = ux;
+            u_out[g.N + n] = uy;
+            u_out[2 * (int64_t)g.N + n] = uz;
+        }
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        v[0] = rho;
+        v[1] = rho * ux;
+        v[2] = rho * uy;
+        v[3] = rho * uz;
+        v[4] = 0.5 * rho * u2;
+        v[5] = sqrt(u2);
+        v[6] = (isfinite(rho) && isfinite(u2) && rho > 0.0) ? 0.0 : 1.0;
+        v[7] = rho;
+    }
+    const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_reduce_store(v, partials + (int64_t)bid * NDIAG);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int nblocks, double* __restrict__ out)
+{
+    // one block; thread t sums partials t, t+256, ... in order, then a fixed tree
+    __shared__ double lds[NDIAG][256];
+    const int t = threadIdx.x;
+    double v[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 1e300};
+    for (int b = t; b < nblocks; b += 256) {
+        const double* p = partials + (int64_t)b * NDIAG;
+        for (int k = 0; k < NDIAG; ++k) v[k] = (k == 5) ? fmax(v[k], p[k]) : (k == 7 ? fmin(v[k], p[k]) : v[k] + p[k]);
+    }
+    for (int k = 0; k < NDIAG; ++k) lds[k][t] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < NDIAG; ++k)
+                lds[k][t] = (k == 5) ? fmax(lds[k][t], lds[k][t + w])
+                                     : (k == 7 ? fmin(lds[k][t], lds[k][t + w]) : lds[k][t] + lds[k][t + w]);
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < NDIAG; ++k) out[k] = lds[k][0];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (dispatch on storage type, pattern, walls, rates).
+// ---------------------------------------------------------------------------
+template <class S> struct Launch {
+    static void step(int pattern, bool walls, bool general, const void* src, void* dst, const Geom& g, const Phys& ph,
+                     dim3 grid, dim3 block, hipStream_t st)
+    {
+        const S* a = (const S*)src;
+        S* b = (S*)dst;
+#define LBM_STEP(P, W, G) hipLaunchKernelGGL((k_step<S, P, W, G>), grid, block, 0, st, a, b, g, ph)
+#define LBM_STEP_G(P, W) \
+    if (general) LBM_STEP(P, W, true); else LBM_STEP(P, W, false)
+#define LBM_STEP_W(P) \
+    if (walls) { LBM_STEP_G(P, true); } else { LBM_STEP_G(P, false); }
+        switch (pattern) {
+        case AB: LBM_STEP_W(AB); break;
+        case AA_EVEN: LBM_STEP_W(AA_EVEN); break;
+        default: LBM_STEP_W(AA_ODD); break;
+        }
+#undef LBM_STEP_W
+#undef LBM_STEP_G
+#undef LBM_STEP
+    }
+
+#define LBM_DISPATCH_PW(KERNEL, ...)                                                         \
+    switch (pattern) {                                                                       \
+    case AB:                                                                                 \
+        if (walls) hipLaunchKernelGGL((KERNEL<S, AB, true>), grid, block, 0, st, __VA_ARGS__); \
+        else hipLaunchKernelGGL((KERNEL<S, AB, false>), grid, block, 0, st, __VA_ARGS__);      \
+        break;                                                                               \
+    case AA_EVEN:                                                                            \
+        if (walls) hipLaunchKernelGGL((KERNEL<S, AA_EVEN, true>), grid, block, 0, st, __VA_ARGS__); \
+        else hipLaunchKernelGGL((KERNEL<S, AA_EVEN, false>), grid, block, 0, st, __VA_ARGS__);      \
+        break;                                                                               \
+    default:                                                                                 \
+        if (walls) hipLaunchKernelGGL((KERNEL<S, AA_ODD, true>), grid, block, 0, st, __VA_ARGS__); \
+        else hipLaunchKernelGGL((KERNEL<S, AA_ODD, false>), grid, block, 0, st, __VA_ARGS__);      \
+    }
+
+    static void init(int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* rho, const double* u,
+                     dim3 grid, dim3 block, hipStream_t st)
+    {
+        LBM_DISPATCH_PW(k_init, (S*)buf, g, rho0, rho, u);
+    }
+    static void set_pops(int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* f, dim3 grid,
+                         dim3 block, hipStream_t st)
+    {
+        LBM_DISPATCH_PW(k_set_pops, (S*)buf, g, rho0, f);
+    }
+    static void get_pops(int pattern, bool walls, const void* buf, const Geom& g, double rho0, double* f, dim3 grid,
+                         dim3 block, hipStream_t st)
+    {
+        LBM_DISPATCH_PW(k_get_pops, (const S*)buf, g, rho0, f);
+    }
+    static void moments(int pattern, bool walls, const void* buf, const Geom& g, const Phys& ph, double* rho, double* u,
+                        double* partials, dim3 grid, dim3 block, hipStream_t st)
+    {
+        LBM_DISPATCH_PW(k_moments, (const S*)buf, g, ph, rho, u, partials);
+    }
+#undef LBM_DISPATCH_PW
+};
+
+template <class F> static void by_precision(int precision, F&& f)
+{
+    switch (precision) {
+    case PREC_FP64: f(Launch<double>{}); break;
+    case PREC_FP32: f(Launch<float>{}); break;
+    case PREC_FP16: f(Launch<_Float16>{}); break;
+    default: f(Launch<bf16_t>{}); break;
+    }
+}
+
+void launch_step(int precision, int pattern, bool walls, bool general, const void* src, void* dst, const Geom& g,
+                 const Phys& ph, dim3 grid, dim3 block, hipStream_t st)
+{
+    by_precision(precision, [&](auto L) { L.step(pattern, walls, general, src, dst, g, ph, grid, block, st); });
+}
+void launch_init(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* rho,
+                 const double* u, dim3 grid, dim3 block, hipStream_t st)
+{
+    by_precision(precision, [&](auto L) { L.init(pattern, walls, buf, g, rho0, rho, u, grid, block, st); });
+}
+void launch_set_pops(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* f,
+                     dim3 grid, dim3 block, hipStream_t st)
+{
+    by_precision(precision, [&](auto L) { L.set_pops(pattern, walls, buf, g, rho0, f, grid, block, st); });
+}
+void launch_get_pops(int precision, int pattern, bool walls, const void* buf, const Geom& g, double rho0, double* f,
+                     dim3 grid, dim3 block, hipStream_t st)
+{
+    by_precision(precision, [&](auto L) { L.get_pops(pattern, walls, buf, g, rho0, f, grid, block, st); });
+}
+void launch_moments(int precision, int pattern, bool walls, const void* buf, const Geom& g, const Phys& ph, double* rho,
+                    double* u, double* partials, dim3 grid, dim3 block, hipStream_t st)
+{
+    by_precision(precision, [&](auto L) { L.moments(pattern, walls, buf, g, ph, rho, u, partials, grid, block, st); });
+}
+void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+}
+
+} // namespace lbm

@@ -1,0 +1,244 @@
+"""ctypes binding of liblbm.so (the C ABI in include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the ABI.  Loading fails loudly if the library has not been built; there
+is no CPU fallback.
+
+The ``lbm_*`` functions mirror the C entry points one to one.  ``Lattice``
+wraps a handle for convenience: device memory for inputs and outputs is torch
+tensors on the handle's GPU; the handle's stream is torch's current stream at
+creation unless another is given.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+ABI_VERSION = 1
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+LBM_FP64, LBM_FP32, LBM_FP16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3
+LBM_AB, LBM_AA = 0, 1
+LBM_FORCE_NONE, LBM_FORCE_UNIFORM, LBM_FORCE_FIELD, LBM_FORCE_KOLMOGOROV = 0, 1, 2, 3
+
+PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16_SHIFTED, "bf16": LBM_BF16_SHIFTED}
+STREAMING = {"ab": LBM_AB, "aa": LBM_AA}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("streaming", ctypes.c_int32),
+        ("omega", ctypes.c_double),
+        ("omega_bulk", ctypes.c_double),
+        ("omega_hi", ctypes.c_double * 9),
+        ("rho0", ctypes.c_double),
+        ("force_mode", ctypes.c_int32),
+        ("force", ctypes.c_double * 3),
+        ("kolmogorov_amp", ctypes.c_double),
+        ("force_field", ctypes.c_void_p),
+        ("walls_y", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbm.so (raises if it is missing: no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2010_01628_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        P = ctypes.POINTER(lbm_params)
+        L.lbm_params_default.argtypes = [P]
+        L.lbm_params_default.restype = None
+        L.lbm_create.argtypes = [P, vp, ctypes.POINTER(vp)]
+        L.lbm_init.argtypes = [vp, vp, vp, i32]
+        L.lbm_step.argtypes = [vp, i64]
+        L.lbm_moments.argtypes = [vp, vp, vp, vp, i32]
+        L.lbm_get_populations.argtypes = [vp, vp, i32]
+        L.lbm_set_populations.argtypes = [vp, vp, i32]
+        L.lbm_step_count.argtypes = [vp]
+        L.lbm_step_count.restype = i64
+        L.lbm_device_bytes.argtypes = [vp]
+        L.lbm_device_bytes.restype = i64
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_last_error.restype = ctypes.c_char_p
+        L.lbm_abi_version.restype = i32
+        for name in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_get_populations",
+                     "lbm_set_populations", "lbm_destroy"):
+            getattr(L, name).restype = i32
+        if L.lbm_abi_version() != ABI_VERSION:
+            raise ImportError("liblbm.so ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != LBM_OK:
+        raise LbmError(rc, lib().lbm_last_error().decode())
+    return rc
+
+
+# -- one-to-one entry points -------------------------------------------------
+def lbm_params_default() -> lbm_params:
+    p = lbm_params()
+    lib().lbm_params_default(ctypes.byref(p))
+    return p
+
+
+def lbm_create(p: lbm_params, stream: int | None = None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().lbm_create(ctypes.byref(p), ctypes.c_void_p(stream or 0), ctypes.byref(h)))
+    return h.value
+
+
+def lbm_init(h: int, rho_ptr: int, u_ptr: int, on_device: bool) -> None:
+    _check(lib().lbm_init(h, rho_ptr, u_ptr, int(on_device)))
+
+
+def lbm_step(h: int, nsteps: int) -> None:
+    _check(lib().lbm_step(h, int(nsteps)))
+
+
+def lbm_moments(h: int, rho_ptr, u_ptr, diag_ptr, on_device: bool) -> None:
+    _check(lib().lbm_moments(h, rho_ptr, u_ptr, diag_ptr, int(on_device)))
+
+
+def lbm_get_populations(h: int, f_ptr: int, on_device: bool) -> None:
+    _check(lib().lbm_get_populations(h, f_ptr, int(on_device)))
+
+
+def lbm_set_populations(h: int, f_ptr: int, on_device: bool) -> None:
+    _check(lib().lbm_set_populations(h, f_ptr, int(on_device)))
+
+
+def lbm_step_count(h: int) -> int:
+    return lib().lbm_step_count(h)
+
+
+def lbm_device_bytes(h: int) -> int:
+    return lib().lbm_device_bytes(h)
+
+
+def lbm_destroy(h: int) -> None:
+    _check(lib().lbm_destroy(h))
+
+
+# -- convenience wrapper -----------------------------------------------------
+def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
+                rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
+                force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0)) -> lbm_params:
+    p = lbm_params_default()
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.streaming = STREAMING[streaming] if isinstance(streaming, str) else int(streaming)
+    p.omega = float(omega)
+    p.omega_bulk = float(omega_bulk)
+    hi = [1.0] * 9 if omega_hi is None else [float(v) for v in omega_hi]
+    for j in range(9):
+        p.omega_hi[j] = hi[j]
+    p.rho0 = float(rho0)
+    p.force_mode = int(force_mode)
+    for d in range(3):
+        p.force[d] = float(force[d])
+    p.kolmogorov_amp = float(kolmogorov_amp)
+    p.force_field = force_field_ptr
+    p.walls_y = int(bool(walls_y))
+    p.check_every = int(check_every)
+    p.block_x, p.block_y = int(block[0]), int(block[1])
+    return p
+
+
+class Lattice:
+    """Owns one lbm handle.  Fields are (nz, ny, nx) / (3, nz, ny, nx) float64."""
+
+    def __init__(self, params: lbm_params, stream=None, force_field=None):
+        import torch
+
+        self.torch = torch
+        self.params = params
+        self.shape = (params.nz, params.ny, params.nx)
+        self.N = params.nx * params.ny * params.nz
+        self._force_field = force_field  # keep the tensor alive
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.h = lbm_create(params, stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(device="cuda", dtype=t.float64).contiguous()
+        return t.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+    def init(self, rho, u):
+        r = self._dev(rho)
+        v = self._dev(u)
+        assert r.numel() == self.N and v.numel() == 3 * self.N
+        lbm_init(self.h, r.data_ptr(), v.data_ptr(), True)
+        self.stream.synchronize()
+
+    def step(self, n: int):
+        lbm_step(self.h, n)
+
+    def moments(self, want_fields=True):
+        t = self.torch
+        diag = np.zeros(6)
+        if want_fields:
+            rho = t.empty(self.shape, dtype=t.float64, device="cuda")
+            u = t.empty((3,) + self.shape, dtype=t.float64, device="cuda")
+            lbm_moments(self.h, rho.data_ptr(), u.data_ptr(), diag.ctypes.data, True)
+            return rho, u, diag
+        lbm_moments(self.h, None, None, diag.ctypes.data, True)
+        return None, None, diag
+
+    def get_populations(self):
+        t = self.torch
+        f = t.empty((19,) + self.shape, dtype=t.float64, device="cuda")
+        lbm_get_populations(self.h, f.data_ptr(), True)
+        self.stream.synchronize()
+        return f
+
+    def set_populations(self, f):
+        ff = self._dev(f)
+        assert ff.numel() == 19 * self.N
+        lbm_set_populations(self.h, ff.data_ptr(), True)
+        self.stream.synchronize()
+
+    @property
+    def step_count(self):
+        return lbm_step_count(self.h)
+
+    @property
+    def device_bytes(self):
+        return lbm_device_bytes(self.h)

@@ -1,0 +1,97 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/*.h declares, its parameter struct matches the ctypes mirror, and
+parameter validation fails cleanly before any device call."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INCLUDE = os.path.join(ROOT, "include")
+
+
+def declared_symbols():
+    names = set()
+    for hdr in glob.glob(os.path.join(INCLUDE, "*.h")):
+        text = open(hdr).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(lbm\w*)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2010_01628_amd import lbm as L
+
+    L.lib()
+    return L
+
+
+def test_header_declares_entry_points():
+    names = declared_symbols()
+    for must in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lbm):
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = declared_symbols() - exported
+    assert not missing, f"declared but not exported: {sorted(missing)}"
+    for name in declared_symbols():
+        getattr(lbm.lib(), name)  # resolvable through ctypes
+
+
+def test_params_struct_layout_matches_header(lbm, tmp_path):
+    """Compile a C probe against include/lbm.h and compare sizeof/offsetof
+    with the ctypes mirror used by the binding."""
+    fields = [f for f, _ in lbm.lbm_params._fields_]
+    src = tmp_path / "probe.c"
+    body = "\n".join(f'printf("{f} %zu\\n", offsetof(lbm_params, {f}));' for f in fields)
+    src.write_text(
+        "#include <stddef.h>\n#include <stdio.h>\n#include \"lbm.h\"\n"
+        "int main(void){" + body + 'printf("sizeof %zu\\n", sizeof(lbm_params)); return 0;}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for f in fields:
+        assert int(got[f]) == getattr(lbm.lbm_params, f).offset, f
+    assert int(got["sizeof"]) == ctypes.sizeof(lbm.lbm_params)
+
+
+def test_defaults(lbm):
+    p = lbm.lbm_params_default()
+    assert p.abi_version == lbm.ABI_VERSION
+    assert (p.nx, p.ny, p.nz, p.q) == (32, 32, 32, 19)
+    assert p.omega == 1.0 and p.omega_bulk == 1.0 and list(p.omega_hi) == [1.0] * 9
+    assert p.rho0 == 1.0 and p.precision == lbm.LBM_FP32 and p.streaming == lbm.LBM_AB
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("omega", 2.0, -1), ("omega", 0.0, -1), ("omega", float("nan"), -1),
+    ("omega_bulk", 2.5, -1), ("nx", 0, -1), ("q", 27, -5), ("q", 15, -1),
+    ("precision", 7, -1), ("streaming", 3, -1), ("rho0", -1.0, -1),
+    ("force_mode", 2, -1),  # FIELD without a pointer
+    ("check_every", -3, -1), ("abi_version", 99, -1),
+])
+def test_invalid_params_rejected_before_device_use(lbm, field, value, code):
+    p = lbm.lbm_params_default()
+    setattr(p, field, value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, None)
+    assert e.value.code == code
+    assert lbm.lib().lbm_last_error().decode()
+
+
+def test_block_shape_validation(lbm):
+    p = lbm.lbm_params_default()
+    p.block_x, p.block_y = 48, 1
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_create(p, None)
+    p.block_x, p.block_y = 512, 1
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_create(p, None)

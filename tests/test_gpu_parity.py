@@ -1,0 +1,205 @@
+"""GPU (HIP, gfx950) parity with the FP64 oracle, through the C ABI.
+
+Tolerances (relative L2 on rho and u after the stated steps): 1e-12 for FP64
+storage, 1e-5 for FP32, 1e-3 for FP16/BF16 shifted storage; populations are
+also compared element by element where the precision allows.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_run, oracle_run, rel_l2, rel_l2_fluct, say
+from paper_2010_01628_amd import inputs
+from paper_2010_01628_amd import lbm as L
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+
+
+@pytest.mark.parametrize("streaming", ["ab", "aa"])
+def test_config1_shear_wave_fp64(orc, streaming):
+    """32^3 shear wave, FP64, nu = 1/6, 200 steps: GPU = oracle to 1e-12 and the
+    u_x amplitude decays as ((2 + cos k)/3)^t."""
+    n, A0, steps = 32, 0.01, 200
+    say(f"config1 fp64 {streaming}")
+    rho, u = inputs.shear_wave(n, A0)
+    g = gpu_run(n, n, n, rho, u, steps, "fp64", streaming)
+    o = oracle_run(orc, rho, u, steps)
+    assert rel_l2(g["u"], o["u"]) < 1e-12
+    assert rel_l2(g["rho"], o["rho"]) < 1e-12
+    assert np.abs(g["f"] - o["f"]).max() < 1e-13
+    k = 2 * np.pi / n
+    z = np.arange(n)
+    A = 2.0 / n * np.sum(g["u"][0].mean(axis=(1, 2)) * np.sin(k * z))
+    assert abs(A / (A0 * ((2 + np.cos(k)) / 3) ** steps) - 1) < 1e-12
+    assert abs(g["diag"][0] - n ** 3) < 1e-9  # sum rho
+
+
+CASES = [
+    # nx, ny, nz, walls, streaming, steps
+    (16, 16, 16, False, "ab", 9),
+    (16, 16, 16, False, "aa", 9),
+    (13, 7, 5, True, "ab", 11),   # ragged: nothing a multiple of the block
+    (13, 7, 5, True, "aa", 11),
+    (70, 3, 2, False, "aa", 6),   # x spans two wavefronts plus a tail
+    (1, 1, 8, False, "ab", 5),    # degenerate x, y (every x/y link wraps to itself)
+    (2, 9, 1, True, "aa", 7),
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,walls,streaming,steps", CASES)
+def test_random_forced_fp64_elementwise(orc, nx, ny, nz, walls, streaming, steps):
+    """Random fields, random force field, general rates: every population
+    equal to the oracle's within 1e-13 after an odd number of steps."""
+    say(f"random fp64 {nx}x{ny}x{nz} walls={walls} {streaming} steps={steps}")
+    rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=nx * 131 + ny * 7 + nz, umax=0.06, fmax=2e-3)
+    rng = np.random.default_rng(nx + ny + nz)
+    om, ob, oh = rng.uniform(0.5, 1.95), rng.uniform(0.5, 1.9), rng.uniform(0.6, 1.9, 9)
+    g = gpu_run(nx, ny, nz, rho, u, steps, "fp64", streaming, omega=om, omega_bulk=ob, omega_hi=oh, force=F,
+                walls=walls)
+    o = oracle_run(orc, rho, u, steps, om, ob, oh, F=F, walls=walls)
+    assert np.abs(g["f"] - o["f"]).max() < 1e-13
+    assert rel_l2(g["u"], o["u"]) < 1e-12
+    assert rel_l2_fluct(g["rho"], o["rho"]) < 1e-11
+
+
+@pytest.mark.parametrize("mode", ["uniform", "kolmogorov"])
+def test_force_modes_fp64(orc, mode):
+    nx, ny, nz, steps = 12, 20, 6, 10
+    say(f"force mode {mode}")
+    rho, u = inputs.taylor_green_noise(nx, 0.05, 1e-4, seed=3, shape=(nx, ny, nz))
+    if mode == "uniform":
+        Fv = (1e-4, -2e-4, 5e-5)
+        F = inputs.uniform_force(nx, ny, nz, Fv)
+        g = gpu_run(nx, ny, nz, rho, u, steps, "fp64", "ab", omega=1.7, force_mode=L.LBM_FORCE_UNIFORM, uniform=Fv)
+    else:
+        F = inputs.kolmogorov_force(nx, ny, nz, 1e-3)
+        g = gpu_run(nx, ny, nz, rho, u, steps, "fp64", "ab", omega=1.7, force_mode=L.LBM_FORCE_KOLMOGOROV,
+                    kolmogorov_amp=1e-3)
+    o = oracle_run(orc, rho, u, steps, 1.7, F=F)
+    assert np.abs(g["f"] - o["f"]).max() < 1e-13
+    assert rel_l2(g["u"], o["u"]) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ab_equals_aa_bitwise(precision):
+    """Same arithmetic per node in both patterns: results are bit-identical."""
+    nx, ny, nz, steps = 24, 10, 6, 13
+    rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=77, umax=0.05, fmax=1e-3)
+    a = gpu_run(nx, ny, nz, rho, u, steps, precision, "ab", omega=1.9, omega_hi=[1.3] * 9, force=F, walls=True)
+    b = gpu_run(nx, ny, nz, rho, u, steps, precision, "aa", omega=1.9, omega_hi=[1.3] * 9, force=F, walls=True)
+    assert np.array_equal(a["f"], b["f"])
+    assert np.array_equal(a["u"], b["u"])
+
+
+@pytest.mark.parametrize("streaming", ["ab", "aa"])
+def test_fp32_parity_config2_recipe(orc, streaming):
+    """Config-2 recipe at 32^3 (Taylor-Green U0 = 0.05 + seeded noise, nu = 1e-3,
+    Kolmogorov force), FP32: relative L2 on u below 1e-5 after 200 steps."""
+    n, steps, nu = 32, 200, 1e-3
+    om = inputs.omega_from_nu(nu)
+    say(f"fp32 config2 recipe {streaming}")
+    rho, u = inputs.taylor_green_noise(n, 0.05, 1e-4, seed=20101628)
+    F = inputs.kolmogorov_force(n, n, n, 1e-6)
+    g = gpu_run(n, n, n, rho, u, steps, "fp32", streaming, omega=om, force_mode=L.LBM_FORCE_KOLMOGOROV,
+                kolmogorov_amp=1e-6, want_pops=False)
+    o = oracle_run(orc, rho, u, steps, om, F=F)
+    err_u = rel_l2(g["u"], o["u"])
+    say(f"  fp32 rel L2 u = {err_u:.3e}, rho-fluct {rel_l2_fluct(g['rho'], o['rho']):.3e}")
+    assert err_u < 1e-5
+    assert rel_l2(g["rho"], o["rho"]) < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_half_storage_error_vs_oracle(orc, precision):
+    """FP16 / BF16 shifted storage with FP32 collision, config-2 recipe at 32^3,
+    200 steps: relative L2 on u and rho against the FP64 oracle within 1e-3."""
+    n, steps, nu = 32, 200, 1e-3
+    om = inputs.omega_from_nu(nu)
+    say(f"{precision} config2 recipe")
+    rho, u = inputs.taylor_green_noise(n, 0.05, 1e-4, seed=20101628)
+    F = inputs.kolmogorov_force(n, n, n, 1e-6)
+    g = gpu_run(n, n, n, rho, u, steps, precision, "ab", omega=om, force_mode=L.LBM_FORCE_KOLMOGOROV,
+                kolmogorov_amp=1e-6, want_pops=False)
+    o = oracle_run(orc, rho, u, steps, om, F=F)
+    err_u = rel_l2(g["u"], o["u"])
+    err_r = rel_l2(g["rho"], o["rho"])
+    say(f"  {precision} rel L2 u = {err_u:.3e}, rho = {err_r:.3e}, rho-fluct = {rel_l2_fluct(g['rho'], o['rho']):.3e}")
+    assert err_r < 1e-3
+    assert err_u < 1e-3
+
+
+@pytest.mark.parametrize("streaming", ["ab", "aa"])
+def test_checkpoint_resume_bitwise(streaming):
+    """n steps, save populations, restore into a fresh lattice, m more steps ==
+    n + m steps uninterrupted, bit for bit (odd n exercises the AA parity)."""
+    import torch
+
+    nx, ny, nz = 20, 12, 8
+    rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=5, umax=0.05, fmax=0.0)
+    ref = gpu_run(nx, ny, nz, rho, u, 12, "fp32", streaming, omega=1.8)
+    p = L.make_params(nx, ny, nz, precision="fp32", streaming=streaming, omega=1.8)
+    a = L.Lattice(p)
+    a.init(rho, u)
+    a.step(5)
+    saved = a.get_populations().clone()
+    a.close()
+    b = L.Lattice(p)
+    b.init(rho, u)
+    b.step(5)  # same parity as the saved state
+    b.set_populations(saved)
+    b.step(7)
+    f = b.get_populations().cpu().numpy()
+    assert b.step_count == 12
+    b.close()
+    torch.cuda.synchronize()
+    assert np.array_equal(f, ref["f"])
+
+
+def test_set_get_roundtrip_fp64():
+    nx, ny, nz = 9, 5, 4
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=2)
+    for streaming in ("ab", "aa"):
+        for walls in (False, True):
+            p = L.make_params(nx, ny, nz, precision="fp64", streaming=streaming, walls_y=walls)
+            lat = L.Lattice(p)
+            lat.init(rho, u)
+            lat.step(3)
+            f = lat.get_populations()
+            f2 = f.clone() * 1.0001
+            lat.set_populations(f2)
+            assert lat.get_populations().equal(f2)
+            lat.close()
+
+
+def test_instability_is_reported():
+    """A non-finite density makes lbm_step fail with LBM_EUNSTABLE at the next check."""
+    nx = ny = nz = 8
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=1)
+    rho[3, 4, 5] = np.nan
+    p = L.make_params(nx, ny, nz, precision="fp32", check_every=2)
+    lat = L.Lattice(p)
+    lat.init(rho, u)
+    with pytest.raises(L.LbmError) as e:
+        lat.step(10)
+    assert e.value.code == L.LBM_EUNSTABLE
+    assert lat.step_count == 2
+    lat.close()
+
+
+def test_stable_run_passes_checks():
+    nx = ny = nz = 8
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=1)
+    p = L.make_params(nx, ny, nz, precision="fp32", check_every=3)
+    lat = L.Lattice(p)
+    lat.init(rho, u)
+    lat.step(10)
+    assert lat.step_count == 10
+    lat.close()

@@ -175,3 +175,16 @@ def test_halfway_bounce_back_poiseuille(orc):
     # steady: one more step changes nothing (to the decay of the slowest mode)
     g = orc.step(f, Kd, F=F, walls_y=True)
     assert np.abs(g - f).max() < 1e-12
+
+
+def test_step_at_matches_full_step(orc):
+    """The sampled single-step routine equals the full lattice step at every node."""
+    nx, ny, nz = 5, 6, 4
+    rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=21, umax=0.05, fmax=1e-3)
+    Kd = orc.K(1.6, 1.1, np.linspace(0.9, 1.2, 9))
+    for walls in (False, True):
+        f = orc.run(orc.init(rho, u), 3, Kd, F=F, walls_y=walls)
+        full = orc.step(f, Kd, F=F, walls_y=walls)
+        nodes = np.arange(nx * ny * nz)
+        got = orc.step_at(f, nodes, Kd, F=F, walls_y=walls)
+        assert np.array_equal(got, full.reshape(19, -1).T)
