@@ -137,7 +137,8 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--streaming", default="aa", choices=["ab", "aa"])
-    ap.add_argument("--variants", default="fp16,bf16", help="extra storage precisions to time ('' = none)")
+    ap.add_argument("--variants", default="fp16:aa,bf16:aa,fp32:ab,fp64:aa",
+                    help="extra precision:streaming pairs to time ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM counters)")
@@ -178,12 +179,14 @@ def main(argv=None):
     log(f"bench: timing {args.precision}/{args.streaming} {args.steps} steps")
     head = time_variant(L, inputs, torch, size, args.precision, args.streaming, args.steps, args.warmup, fields)
     variants = {}
-    for prec in [v for v in args.variants.split(",") if v]:
-        if prec == args.precision:
+    for spec in [v for v in args.variants.split(",") if v]:
+        prec, _, strm = spec.partition(":")
+        strm = strm or args.streaming
+        if (prec, strm) == (args.precision, args.streaming):
             continue
-        log(f"bench: timing variant {prec}")
-        variants[prec] = time_variant(L, inputs, torch, size, prec, args.streaming, max(20, args.steps // 4),
-                                      max(5, args.warmup // 4), fields)
+        log(f"bench: timing variant {prec}/{strm}")
+        variants[f"{prec}_{strm}"] = time_variant(L, inputs, torch, size, prec, strm, max(20, args.steps // 4),
+                                                  max(5, args.warmup // 4), fields)
     del fields
     torch.cuda.empty_cache()
 

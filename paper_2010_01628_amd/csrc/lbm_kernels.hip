@@ -155,10 +155,10 @@ template <class R> __device__ inline Rates<R> rates_of(const Phys& ph)
     return rt;
 }
 
-// One fused step at every node.  Block (bx, by, 1) covers bx x-values of by
+// One fused step at one node.  Block (bx, by, 1) covers bx x-values of by
 // rows; blockIdx.z is the z plane.
 template <class S, Pattern P, bool WALLS, bool GENERAL>
-__global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
+__device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys& ph)
 {
     using R = typename Codec<S>::R;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -174,6 +174,20 @@ __global__ __launch_bounds__(256) void k_step(const S* __restrict__ src, S* __re
     NodeMacro<R> mac;
     collide_cm<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
     scatter<S, P, WALLS>(dst, g.stride, d, s);
+}
+
+// A-B: two distinct buffers.
+template <class S, bool WALLS, bool GENERAL>
+__global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
+{
+    step_node<S, AB, WALLS, GENERAL>(src, dst, g, ph);
+}
+
+// AA: one buffer, each node rewrites exactly the locations it read.
+template <class S, Pattern P, bool WALLS, bool GENERAL>
+__global__ __launch_bounds__(256) void k_step_aa(S* buf, Geom g, Phys ph)
+{
+    step_node<S, P, WALLS, GENERAL>(buf, buf, g, ph);
 }
 
 // Write given deviations s_i(x) where the next step of pattern P reads them as
@@ -367,7 +381,11 @@ template <class S> struct Launch {
     {
         const S* a = (const S*)src;
         S* b = (S*)dst;
-#define LBM_STEP(P, W, G) hipLaunchKernelGGL((k_step<S, P, W, G>), grid, block, 0, st, a, b, g, ph)
+#define LBM_STEP(P, W, G)                                                                     \
+    do {                                                                                      \
+        if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<S, W, G>), grid, block, 0, st, a, b, g, ph); \
+        else hipLaunchKernelGGL((k_step_aa<S, P, W, G>), grid, block, 0, st, b, g, ph);       \
+    } while (0)
 #define LBM_STEP_G(P, W) \
     if (general) LBM_STEP(P, W, true); else LBM_STEP(P, W, false)
 #define LBM_STEP_W(P) \
