@@ -136,8 +136,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
-    ap.add_argument("--streaming", default="aa", choices=["ab", "aa"])
-    ap.add_argument("--variants", default="fp16:aa,bf16:aa,fp32:ab,fp64:aa",
+    ap.add_argument("--streaming", default="ab", choices=["ab", "aa"])
+    ap.add_argument("--variants", default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,fp64:ab",
                     help="extra precision:streaming pairs to time ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",

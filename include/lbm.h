@@ -90,6 +90,8 @@ typedef struct {
     int32_t check_every;      /* > 0: every that many steps lbm_step checks that the density
                                  is finite and positive everywhere (FP64 reduction) */
     int32_t block_x, block_y; /* work-group shape of the step kernels; 0 = library default */
+    int32_t cache_policy;     /* population loads/stores: 0 = library default, 1 = non-temporal
+                                 (streaming) hints, 2 = ordinary cached accesses */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

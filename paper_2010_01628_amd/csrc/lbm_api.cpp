@@ -52,7 +52,7 @@ struct lbm_handle {
     double* diag_dev = nullptr;
     double* diag_host = nullptr;
     dim3 grid, block;
-    bool walls = false, general = false;
+    bool walls = false, general = false, nt = true;
     int64_t bytes = 0;
     int nblocks = 0;
 };
@@ -92,6 +92,7 @@ int validate(const lbm_params* p)
     if (p->walls_y && p->ny < 2) return fail(LBM_EINVAL, "walls need ny >= 2");
     if (p->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
     if (p->block_x < 0 || p->block_y < 0) return fail(LBM_EINVAL, "negative block shape");
+    if (p->cache_policy < 0 || p->cache_policy > 2) return fail(LBM_EINVAL, "cache_policy must be 0, 1 or 2");
     const int bx = p->block_x ? p->block_x : 64, by = p->block_y ? p->block_y : 1;
     if (bx * by > 256 || (bx * by) % 64 != 0)
         return fail(LBM_EINVAL, "block_x*block_y must be a multiple of 64 and at most 256");
@@ -105,8 +106,8 @@ int next_pow2(int v)
     return p;
 }
 
-// Default work-group shape: 64 x-values per wave, 4 rows per block (256
-// threads); narrow lattices pack more rows.
+// Default work-group shape: 256 threads covering whole x-rows where possible;
+// narrow lattices pack several rows per block.
 void default_block(const lbm_params* p, int& bx, int& by)
 {
     if (p->block_x && p->block_y) {
@@ -114,7 +115,8 @@ void default_block(const lbm_params* p, int& bx, int& by)
         by = p->block_y;
         return;
     }
-    bx = p->nx >= 64 ? 64 : next_pow2(p->nx);
+    // one block per x-row (up to 256 nodes): measured fastest at 256^3
+    bx = p->nx >= 256 ? 256 : next_pow2(p->nx);
     if (bx < 8) bx = 8;
     by = 256 / bx;
     const int ny2 = next_pow2(p->ny);
@@ -126,7 +128,7 @@ int64_t pad_stride(int64_t N, int eb)
     // Separate the starts of consecutive population arrays by a non-power-of-two
     // number of 256-byte blocks so the streams of one step spread over channels.
     const char* env = std::getenv("LBM_PAD_BYTES");
-    int64_t pad_bytes = env ? std::atoll(env) : 4352;  // 17 * 256 B
+    int64_t pad_bytes = env ? std::atoll(env) : 17408;  // 68 * 256 B
     int64_t base = round_up(N * eb, 4096);
     return (base + pad_bytes) / eb;
 }
@@ -188,6 +190,13 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
     h->g.N = p->nx * p->ny * p->nz;
     h->g.stride = pad_stride(h->g.N, eb);
     h->walls = p->walls_y != 0;
+    // default: streaming hints for A-B with 4- and 8-byte storage, ordinary
+    // accesses for AA (in place) and 16-bit storage -- the faster choice of
+    // each pair measured at 256^3
+    if (p->cache_policy == 0)
+        h->nt = p->streaming == LBM_AB && eb >= 4;
+    else
+        h->nt = p->cache_policy == 1;
     h->general = p->omega_bulk != 1.0;
     for (int j = 0; j < 9; ++j) h->general = h->general || p->omega_hi[j] != 1.0;
 
@@ -294,8 +303,8 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
         const int pat = pattern_of(h);
         const int src = h->cur;
         const int dst = h->p.streaming == LBM_AB ? 1 - h->cur : h->cur;
-        lbm::launch_step(h->p.precision, pat, h->walls, h->general, h->buf[src], h->buf[dst], h->g, h->ph, h->grid,
-                         h->block, h->stream);
+        lbm::launch_step(h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g, h->ph,
+                         h->grid, h->block, h->stream);
         h->cur = dst;
         h->steps++;
         if (h->p.check_every > 0 && h->steps % h->p.check_every == 0) {

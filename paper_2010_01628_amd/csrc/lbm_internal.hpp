@@ -24,8 +24,8 @@ struct Phys {
     const double* row_table;   // device, double[ny]: F_x per y row
 };
 
-void launch_step(int precision, int pattern, bool walls, bool general, const void* src, void* dst, const Geom& g,
-                 const Phys& ph, dim3 grid, dim3 block, hipStream_t st);
+void launch_step(int precision, int pattern, bool walls, bool general, bool nt, const void* src, void* dst,
+                 const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st);
 void launch_init(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* rho,
                  const double* u, dim3 grid, dim3 block, hipStream_t st);
 void launch_set_pops(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* f,

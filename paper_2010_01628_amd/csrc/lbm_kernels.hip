@@ -62,6 +62,35 @@ template <bool WALLS> __device__ inline bool beyond(const NodeIdx& d, int dy)
     return (dy < 0 && d.ylo) || (dy > 0 && d.yhi);
 }
 
+// Population loads and stores, with or without the non-temporal (streaming)
+// hint.  Each population value is touched once per step, so the hint keeps it
+// from displacing reusable lines.
+template <class S, bool NT> __device__ inline S ld(const S* p)
+{
+    if constexpr (!NT) {
+        return *p;
+    } else if constexpr (sizeof(S) == 2) {
+        const uint16_t v = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
+        S out;
+        __builtin_memcpy(&out, &v, 2);
+        return out;
+    } else {
+        return __builtin_nontemporal_load(p);
+    }
+}
+template <class S, bool NT> __device__ inline void st(S* p, S v)
+{
+    if constexpr (!NT) {
+        *p = v;
+    } else if constexpr (sizeof(S) == 2) {
+        uint16_t u;
+        __builtin_memcpy(&u, &v, 2);
+        __builtin_nontemporal_store(u, reinterpret_cast<uint16_t*>(p));
+    } else {
+        __builtin_nontemporal_store(v, p);
+    }
+}
+
 // Where f_i(x, t) lives in the buffer for pattern P (slot, node index).
 template <Pattern P, bool WALLS>
 __device__ inline void state_loc(const NodeIdx& d, int i, int& slot, int& idx)
@@ -83,19 +112,19 @@ __device__ inline void state_loc(const NodeIdx& d, int i, int& slot, int& idx)
 }
 
 // Load f_i(x, t) (as deviations) for the current pattern.
-template <class S, Pattern P, bool WALLS>
+template <class S, Pattern P, bool WALLS, bool NT = false>
 __device__ inline void gather(const S* __restrict__ buf, int64_t stride, const NodeIdx& d, typename Codec<S>::R s[19])
 {
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         int slot, idx;
         state_loc<P, WALLS>(d, i, slot, idx);
-        s[i] = Codec<S>::dec(buf[(int64_t)slot * stride + idx]);
+        s[i] = Codec<S>::dec(ld<S, NT>(buf + (int64_t)slot * stride + idx));
     }
 }
 
 // Store f_i*(x, t) (deviations) for the current pattern.
-template <class S, Pattern P, bool WALLS>
+template <class S, Pattern P, bool WALLS, bool NT>
 __device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeIdx& d, const typename Codec<S>::R s[19])
 {
     const int n = nb(d, 0, 0, 0);
@@ -118,7 +147,7 @@ __device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeId
                 idx = nb(d, cx, cy, cz);
             }
         }
-        buf[(int64_t)slot * stride + idx] = Codec<S>::enc(s[i]);
+        st<S, NT>(buf + (int64_t)slot * stride + idx, Codec<S>::enc(s[i]));
     }
 }
 
@@ -157,7 +186,7 @@ template <class R> __device__ inline Rates<R> rates_of(const Phys& ph)
 
 // One fused step at one node.  Block (bx, by, 1) covers bx x-values of by
 // rows; blockIdx.z is the z plane.
-template <class S, Pattern P, bool WALLS, bool GENERAL>
+template <class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
 __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys& ph)
 {
     using R = typename Codec<S>::R;
@@ -168,26 +197,26 @@ __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R s[19];
-    gather<S, P, WALLS>(src, g.stride, d, s);
+    gather<S, P, WALLS, NT>(src, g.stride, d, s);
     R Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
     collide_cm<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
-    scatter<S, P, WALLS>(dst, g.stride, d, s);
+    scatter<S, P, WALLS, NT>(dst, g.stride, d, s);
 }
 
 // A-B: two distinct buffers.
-template <class S, bool WALLS, bool GENERAL>
+template <class S, bool WALLS, bool GENERAL, bool NT>
 __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
 {
-    step_node<S, AB, WALLS, GENERAL>(src, dst, g, ph);
+    step_node<S, AB, WALLS, GENERAL, NT>(src, dst, g, ph);
 }
 
 // AA: one buffer, each node rewrites exactly the locations it read.
-template <class S, Pattern P, bool WALLS, bool GENERAL>
+template <class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
 __global__ __launch_bounds__(256) void k_step_aa(S* buf, Geom g, Phys ph)
 {
-    step_node<S, P, WALLS, GENERAL>(buf, buf, g, ph);
+    step_node<S, P, WALLS, GENERAL, NT>(buf, buf, g, ph);
 }
 
 // Write given deviations s_i(x) where the next step of pattern P reads them as
@@ -376,15 +405,24 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
 // Host-side launchers (dispatch on storage type, pattern, walls, rates).
 // ---------------------------------------------------------------------------
 template <class S> struct Launch {
-    static void step(int pattern, bool walls, bool general, const void* src, void* dst, const Geom& g, const Phys& ph,
-                     dim3 grid, dim3 block, hipStream_t st)
+    static void step(int pattern, bool walls, bool general, bool nt, const void* src, void* dst, const Geom& g,
+                     const Phys& ph, dim3 grid, dim3 block, hipStream_t st)
     {
         const S* a = (const S*)src;
         S* b = (S*)dst;
-#define LBM_STEP(P, W, G)                                                                     \
-    do {                                                                                      \
-        if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<S, W, G>), grid, block, 0, st, a, b, g, ph); \
-        else hipLaunchKernelGGL((k_step_aa<S, P, W, G>), grid, block, 0, st, b, g, ph);       \
+        if (nt)
+            step_nt<true>(pattern, walls, general, a, b, g, ph, grid, block, st);
+        else
+            step_nt<false>(pattern, walls, general, a, b, g, ph, grid, block, st);
+    }
+    template <bool NT>
+    static void step_nt(int pattern, bool walls, bool general, const S* a, S* b, const Geom& g, const Phys& ph,
+                        dim3 grid, dim3 block, hipStream_t st)
+    {
+#define LBM_STEP(P, W, G)                                                                                     \
+    do {                                                                                                      \
+        if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<S, W, G, NT>), grid, block, 0, st, a, b, g, ph); \
+        else hipLaunchKernelGGL((k_step_aa<S, P, W, G, NT>), grid, block, 0, st, b, g, ph);                   \
     } while (0)
 #define LBM_STEP_G(P, W) \
     if (general) LBM_STEP(P, W, true); else LBM_STEP(P, W, false)
@@ -448,10 +486,10 @@ template <class F> static void by_precision(int precision, F&& f)
     }
 }
 
-void launch_step(int precision, int pattern, bool walls, bool general, const void* src, void* dst, const Geom& g,
-                 const Phys& ph, dim3 grid, dim3 block, hipStream_t st)
+void launch_step(int precision, int pattern, bool walls, bool general, bool nt, const void* src, void* dst,
+                 const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st)
 {
-    by_precision(precision, [&](auto L) { L.step(pattern, walls, general, src, dst, g, ph, grid, block, st); });
+    by_precision(precision, [&](auto L) { L.step(pattern, walls, general, nt, src, dst, g, ph, grid, block, st); });
 }
 void launch_init(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* rho,
                  const double* u, dim3 grid, dim3 block, hipStream_t st)

@@ -53,6 +53,7 @@ class lbm_params(ctypes.Structure):
         ("walls_y", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
         ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+        ("cache_policy", ctypes.c_int32),
     ]
 
 
@@ -146,7 +147,7 @@ def lbm_destroy(h: int) -> None:
 # -- convenience wrapper -----------------------------------------------------
 def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
                 rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
-                force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0)) -> lbm_params:
+                force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0) -> lbm_params:
     p = lbm_params_default()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -165,6 +166,7 @@ def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_b
     p.walls_y = int(bool(walls_y))
     p.check_every = int(check_every)
     p.block_x, p.block_y = int(block[0]), int(block[1])
+    p.cache_policy = int(cache_policy)
     return p
 
 
