@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["d3q19_oracle.c"]
+_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c"]
 
 DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
 CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
@@ -69,6 +69,18 @@ def lib():
         L.orc19_step_at.argtypes = [i32, i32, i32, i32, dp, dp, dp, i32, i32,
                                     ctypes.POINTER(ctypes.c_int64), i32, dp]
         L.orc19_step_at.restype = i32
+        L.orc27_tables.argtypes = [ip, dp, ip]
+        L.orc27_feq.argtypes = [f64, f64, f64, f64, dp]
+        L.orc27_T.argtypes = [f64, f64, f64, dp]
+        L.orc27_keq.argtypes = [f64, dp]
+        L.orc27_Rcm.argtypes = [f64, f64, f64, dp]
+        L.orc27_K.argtypes = [f64, dp]
+        L.orc27_collide.argtypes = [dp, dp, dp, dp, dp, dp]
+        L.orc27_collide.restype = i32
+        L.orc27_step.argtypes = [i32, i32, i32, i32, dp, dp, dp, dp]
+        L.orc27_step.restype = i32
+        L.orc27_init.argtypes = [i32, i32, i32, dp, dp, dp]
+        L.orc27_moments.argtypes = [i32, i32, i32, dp, dp, dp, dp]
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
         _lib = L
@@ -221,3 +233,101 @@ def moments(f, F=None):
     Fa = None if F is None else _f64(F)
     lib().orc19_moments(nx, ny, nz, _p(f), _p(Fa), _p(rho), _p(u))
     return rho, u
+
+
+# --------------------------------------------------------------------------
+# D3Q27 (App. D; readings Q1-Q4 in d3q27_oracle.c)
+# --------------------------------------------------------------------------
+Q27 = 27
+
+
+class d3q27:
+    @staticmethod
+    def tables():
+        c = np.zeros((Q27, 3), dtype=np.int32)
+        w = np.zeros(Q27)
+        opp = np.zeros(Q27, dtype=np.int32)
+        lib().orc27_tables(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(w),
+                           opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        return c, w, opp
+
+    @staticmethod
+    def feq(rho, u):
+        out = np.zeros(Q27)
+        lib().orc27_feq(float(rho), float(u[0]), float(u[1]), float(u[2]), _p(out))
+        return out
+
+    @staticmethod
+    def T(u):
+        out = np.zeros((Q27, Q27))
+        lib().orc27_T(float(u[0]), float(u[1]), float(u[2]), _p(out))
+        return out
+
+    @staticmethod
+    def keq(rho):
+        out = np.zeros(Q27)
+        lib().orc27_keq(float(rho), _p(out))
+        return out
+
+    @staticmethod
+    def Rcm(F):
+        out = np.zeros(Q27)
+        lib().orc27_Rcm(float(F[0]), float(F[1]), float(F[2]), _p(out))
+        return out
+
+    @staticmethod
+    def K(omega):
+        out = np.zeros(Q27)
+        lib().orc27_K(float(omega), _p(out))
+        return out
+
+    @staticmethod
+    def collide(f, F=(0.0, 0.0, 0.0), Kdiag=None):
+        f = _f64(f)
+        F = _f64(F)
+        Kd = _f64(Kdiag if Kdiag is not None else d3q27.K(1.0))
+        fs = np.zeros(Q27)
+        rho = np.zeros(1)
+        u = np.zeros(3)
+        if lib().orc27_collide(_p(f), _p(F), _p(Kd), _p(fs), _p(rho), _p(u)) != 0:
+            raise ArithmeticError("singular collision system")
+        return fs, float(rho[0]), u
+
+    @staticmethod
+    def init(rho, u):
+        rho = _f64(rho)
+        u = _f64(u)
+        nz, ny, nx = rho.shape
+        f = np.zeros((Q27, nz, ny, nx))
+        lib().orc27_init(nx, ny, nz, _p(rho), _p(u), _p(f))
+        return f
+
+    @staticmethod
+    def step(f, Kdiag, F=None, walls_y=False, out=None):
+        f = _f64(f)
+        _, nz, ny, nx = f.shape
+        if out is None:
+            out = np.empty_like(f)
+        Fa = None if F is None else _f64(F)
+        if lib().orc27_step(nx, ny, nz, int(bool(walls_y)), _p(f), _p(out), _p(Fa), _p(_f64(Kdiag))) != 0:
+            raise ArithmeticError("singular collision system")
+        return out
+
+    @staticmethod
+    def run(f, nsteps, Kdiag, F=None, walls_y=False):
+        a = _f64(f).copy()
+        b = np.empty_like(a)
+        for _ in range(int(nsteps)):
+            d3q27.step(a, Kdiag, F=F, walls_y=walls_y, out=b)
+            a, b = b, a
+        return a
+
+    @staticmethod
+    def moments(f, F=None):
+        f = _f64(f)
+        _, nz, ny, nx = f.shape
+        rho = np.zeros((nz, ny, nx))
+        u = np.zeros((3, nz, ny, nx))
+        Fa = None if F is None else _f64(F)
+        lib().orc27_moments(nx, ny, nz, _p(f), _p(Fa), _p(rho), _p(u))
+        return rho, u
