@@ -73,7 +73,8 @@ typedef enum {
 typedef struct {
     uint32_t abi_version;     /* must be LBM_ABI_VERSION */
     int32_t nx, ny, nz;       /* lattice nodes; periodic in x and z, and in y unless walls_y */
-    int32_t q;                /* 19 */
+    int32_t q;                /* 19, or 27 for the D3Q27 CM lattice of App. D (FP64/FP32 storage,
+                                 omega on the deviatoric moments, 1 elsewhere) */
     int32_t precision;        /* lbm_precision */
     int32_t streaming;        /* lbm_streaming */
     double omega;             /* shear rate of k5..k9, 1/(nu/cs^2 + 1/2), in (0, 2) (Sec. II.B) */

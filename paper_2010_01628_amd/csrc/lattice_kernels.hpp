@@ -1,10 +1,11 @@
-// D3Q19 CM-LBM kernels for gfx950: fused gather + collide + store.
+// Lattice-generic kernels for gfx950: fused gather + collide + store, init,
+// macroscopic moments with FP64 reductions, population import/export.
 //
 // Data layout in HBM: populations are structure of arrays, one array per
 // direction, stored as deviations s_i = f_i - w_i rho0 in the storage type S.
 // Element (i, n) sits at buf[i * stride + n], n = x + nx (y + ny z); stride >=
-// N is padded so that the 19 (or 38) streams of a step do not start on the
-// same HBM channel.
+// N is padded so that the streams of a step do not start on the same HBM
+// channel.
 //
 // Streaming patterns (Sec. II.B eq. "streaming_f", f_i(x + c_i, t+1) = f_i*(x, t)):
 //   A-B pull:  src holds post-collision values of the previous step at their
@@ -18,13 +19,64 @@
 //              writes f_i* to slot i at x + c_i (wall: slot opp(i) at x).  Each
 //              node writes exactly the locations it read, so the update is in
 //              place and race free.
+#pragma once
+
 #include "d3q19_cm.hpp"
+#include "d3q27_cm.hpp"
 #include "lbm_internal.hpp"
 
 namespace lbm {
 
 enum Pattern { AB = 0, AA_EVEN = 1, AA_ODD = 2 };
 
+template <class R> __device__ inline Rates<R> rates_of(const Phys& ph)
+{
+    Rates<R> rt;
+    rt.omega = (R)ph.omega;
+    rt.omega_bulk = (R)ph.omega_bulk;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) rt.omega_hi[j] = (R)ph.omega_hi[j];
+    return rt;
+}
+
+// Lattice traits ------------------------------------------------------------
+struct LatD3Q19 {
+    static constexpr int Q = 19;
+    __host__ __device__ static constexpr int cx(int i) { return cx19(i); }
+    __host__ __device__ static constexpr int cy(int i) { return cy19(i); }
+    __host__ __device__ static constexpr int cz(int i) { return cz19(i); }
+    __host__ __device__ static constexpr int opp(int i) { return opp19(i); }
+    __host__ __device__ static constexpr double w(int i) { return w19(i); }
+    template <class R, bool GENERAL>
+    __device__ static void collide(R* s, R rho0, R Fx, R Fy, R Fz, const Phys& ph, NodeMacro<R>& mac)
+    {
+        collide_cm<R, GENERAL>(s, rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
+    }
+    template <class R> __device__ static void eq(R rho, R rho0, R ux, R uy, R uz, R* s)
+    {
+        equilibrium_deviation<R>(rho, rho0, ux, uy, uz, s);
+    }
+};
+
+struct LatD3Q27 {
+    static constexpr int Q = 27;
+    __host__ __device__ static constexpr int cx(int i) { return cx27(i); }
+    __host__ __device__ static constexpr int cy(int i) { return cy27(i); }
+    __host__ __device__ static constexpr int cz(int i) { return cz27(i); }
+    __host__ __device__ static constexpr int opp(int i) { return opp27(i); }
+    __host__ __device__ static constexpr double w(int i) { return w27(i); }
+    template <class R, bool GENERAL>
+    __device__ static void collide(R* s, R rho0, R Fx, R Fy, R Fz, const Phys& ph, NodeMacro<R>& mac)
+    {
+        collide_cm27<R>(s, rho0, Fx, Fy, Fz, (R)ph.omega, mac);
+    }
+    template <class R> __device__ static void eq(R rho, R rho0, R ux, R uy, R uz, R* s)
+    {
+        equilibrium_deviation27<R>(rho, rho0, ux, uy, uz, s);
+    }
+};
+
+// Node indexing -------------------------------------------------------------
 struct NodeIdx {
     int x, y, z;
     int ox[3], oy[3], oz[3]; // offsets of x-1,x,x+1 (and y, z rows/planes)
@@ -92,55 +144,55 @@ template <class S, bool NT> __device__ inline void st(S* p, S v)
 }
 
 // Where f_i(x, t) lives in the buffer for pattern P (slot, node index).
-template <Pattern P, bool WALLS>
+template <class L, Pattern P, bool WALLS>
 __device__ inline void state_loc(const NodeIdx& d, int i, int& slot, int& idx)
 {
-    const int cx = cx19(i), cy = cy19(i), cz = cz19(i);
+    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
     if constexpr (P == AA_EVEN) {
         slot = i;
         idx = nb(d, 0, 0, 0);
     } else {
         if (beyond<WALLS>(d, -cy)) {
             // population i arriving from beyond a wall: bounce-back of opp(i)
-            slot = (P == AB) ? opp19(i) : i;
+            slot = (P == AB) ? L::opp(i) : i;
             idx = nb(d, 0, 0, 0);
         } else {
-            slot = (P == AB) ? i : opp19(i);
+            slot = (P == AB) ? i : L::opp(i);
             idx = nb(d, -cx, -cy, -cz);
         }
     }
 }
 
 // Load f_i(x, t) (as deviations) for the current pattern.
-template <class S, Pattern P, bool WALLS, bool NT = false>
-__device__ inline void gather(const S* __restrict__ buf, int64_t stride, const NodeIdx& d, typename Codec<S>::R s[19])
+template <class L, class S, Pattern P, bool WALLS, bool NT = false>
+__device__ inline void gather(const S* __restrict__ buf, int64_t stride, const NodeIdx& d, typename Codec<S>::R* s)
 {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < L::Q; ++i) {
         int slot, idx;
-        state_loc<P, WALLS>(d, i, slot, idx);
+        state_loc<L, P, WALLS>(d, i, slot, idx);
         s[i] = Codec<S>::dec(ld<S, NT>(buf + (int64_t)slot * stride + idx));
     }
 }
 
 // Store f_i*(x, t) (deviations) for the current pattern.
-template <class S, Pattern P, bool WALLS, bool NT>
-__device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeIdx& d, const typename Codec<S>::R s[19])
+template <class L, class S, Pattern P, bool WALLS, bool NT>
+__device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeIdx& d, const typename Codec<S>::R* s)
 {
     const int n = nb(d, 0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const int cx = cx19(i), cy = cy19(i), cz = cz19(i);
+    for (int i = 0; i < L::Q; ++i) {
+        const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
         int slot, idx;
         if constexpr (P == AB) {
             slot = i;
             idx = n;
         } else if constexpr (P == AA_EVEN) {
-            slot = opp19(i);
+            slot = L::opp(i);
             idx = n;
         } else {
             if (beyond<WALLS>(d, cy)) {
-                slot = opp19(i);
+                slot = L::opp(i);
                 idx = n;
             } else {
                 slot = i;
@@ -148,6 +200,19 @@ __device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeId
             }
         }
         st<S, NT>(buf + (int64_t)slot * stride + idx, Codec<S>::enc(s[i]));
+    }
+}
+
+// Write given deviations s_i(x) where the next step of pattern P reads them as
+// f_i(x, t) (the locations of state_loc; a bijection over all (node, i)).
+template <class L, class S, Pattern P, bool WALLS>
+__device__ inline void place_state(S* __restrict__ buf, int64_t stride, const NodeIdx& d, const typename Codec<S>::R* s)
+{
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        int slot, idx;
+        state_loc<L, P, WALLS>(d, i, slot, idx);
+        buf[(int64_t)slot * stride + idx] = Codec<S>::enc(s[i]);
     }
 }
 
@@ -162,7 +227,7 @@ template <class R> __device__ inline void node_force(const Phys& ph, const Geom&
     case FORCE_FIELD:
         Fx = (R)ph.force_field[n];
         Fy = (R)ph.force_field[g.N + n];
-        Fz = (R)ph.force_field[2 * g.N + n];
+        Fz = (R)ph.force_field[2 * (int64_t)g.N + n];
         break;
     case FORCE_ROW_TABLE:
         Fx = (R)ph.row_table[y];
@@ -174,19 +239,9 @@ template <class R> __device__ inline void node_force(const Phys& ph, const Geom&
     }
 }
 
-template <class R> __device__ inline Rates<R> rates_of(const Phys& ph)
-{
-    Rates<R> rt;
-    rt.omega = (R)ph.omega;
-    rt.omega_bulk = (R)ph.omega_bulk;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) rt.omega_hi[j] = (R)ph.omega_hi[j];
-    return rt;
-}
-
 // One fused step at one node.  Block (bx, by, 1) covers bx x-values of by
 // rows; blockIdx.z is the z plane.
-template <class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
+template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
 __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys& ph)
 {
     using R = typename Codec<S>::R;
@@ -196,44 +251,31 @@ __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys
     if (x >= g.nx || y >= g.ny) return;
     NodeIdx d;
     node_idx(g, x, y, z, d);
-    R s[19];
-    gather<S, P, WALLS, NT>(src, g.stride, d, s);
+    R s[L::Q];
+    gather<L, S, P, WALLS, NT>(src, g.stride, d, s);
     R Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
-    collide_cm<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
-    scatter<S, P, WALLS, NT>(dst, g.stride, d, s);
+    L::template collide<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    scatter<L, S, P, WALLS, NT>(dst, g.stride, d, s);
 }
 
 // A-B: two distinct buffers.
-template <class S, bool WALLS, bool GENERAL, bool NT>
+template <class L, class S, bool WALLS, bool GENERAL, bool NT>
 __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
 {
-    step_node<S, AB, WALLS, GENERAL, NT>(src, dst, g, ph);
+    step_node<L, S, AB, WALLS, GENERAL, NT>(src, dst, g, ph);
 }
 
 // AA: one buffer, each node rewrites exactly the locations it read.
-template <class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
+template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
 __global__ __launch_bounds__(256) void k_step_aa(S* buf, Geom g, Phys ph)
 {
-    step_node<S, P, WALLS, GENERAL, NT>(buf, buf, g, ph);
-}
-
-// Write given deviations s_i(x) where the next step of pattern P reads them as
-// f_i(x, t) (the locations of state_loc; a bijection over all (node, i)).
-template <class S, Pattern P, bool WALLS>
-__device__ inline void place_state(S* __restrict__ buf, int64_t stride, const NodeIdx& d, const typename Codec<S>::R s[19])
-{
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        int slot, idx;
-        state_loc<P, WALLS>(d, i, slot, idx);
-        buf[(int64_t)slot * stride + idx] = Codec<S>::enc(s[i]);
-    }
+    step_node<L, S, P, WALLS, GENERAL, NT>(buf, buf, g, ph);
 }
 
 // Initialisation at equilibrium from rho, u (double, device).
-template <class S, Pattern P, bool WALLS>
+template <class L, class S, Pattern P, bool WALLS>
 __global__ __launch_bounds__(256) void k_init(S* __restrict__ buf, Geom g, double rho0, const double* __restrict__ rho,
                                              const double* __restrict__ u)
 {
@@ -245,13 +287,13 @@ __global__ __launch_bounds__(256) void k_init(S* __restrict__ buf, Geom g, doubl
     NodeIdx d;
     node_idx(g, x, y, z, d);
     const int n = nb(d, 0, 0, 0);
-    R s[19];
-    equilibrium_deviation<R>((R)rho[n], (R)rho0, (R)u[n], (R)u[g.N + n], (R)u[2 * g.N + n], s);
-    place_state<S, P, WALLS>(buf, g.stride, d, s);
+    R s[L::Q];
+    L::template eq<R>((R)rho[n], (R)rho0, (R)u[n], (R)u[g.N + n], (R)u[2 * (int64_t)g.N + n], s);
+    place_state<L, S, P, WALLS>(buf, g.stride, d, s);
 }
 
-// Populations f = w rho0 + s from double[19 N] (device) into the state.
-template <class S, Pattern P, bool WALLS>
+// Populations f = w rho0 + s from double[Q N] (device) into the state.
+template <class L, class S, Pattern P, bool WALLS>
 __global__ __launch_bounds__(256) void k_set_pops(S* __restrict__ buf, Geom g, double rho0, const double* __restrict__ f)
 {
     using R = typename Codec<S>::R;
@@ -262,13 +304,13 @@ __global__ __launch_bounds__(256) void k_set_pops(S* __restrict__ buf, Geom g, d
     NodeIdx d;
     node_idx(g, x, y, z, d);
     const int n = nb(d, 0, 0, 0);
-    R s[19];
+    R s[L::Q];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) s[i] = (R)(f[(int64_t)i * g.N + n] - w19(i) * rho0);
-    place_state<S, P, WALLS>(buf, g.stride, d, s);
+    for (int i = 0; i < L::Q; ++i) s[i] = (R)(f[(int64_t)i * g.N + n] - L::w(i) * rho0);
+    place_state<L, S, P, WALLS>(buf, g.stride, d, s);
 }
 
-template <class S, Pattern P, bool WALLS>
+template <class L, class S, Pattern P, bool WALLS>
 __global__ __launch_bounds__(256) void k_get_pops(const S* __restrict__ buf, Geom g, double rho0, double* __restrict__ f)
 {
     using R = typename Codec<S>::R;
@@ -279,10 +321,10 @@ __global__ __launch_bounds__(256) void k_get_pops(const S* __restrict__ buf, Geo
     NodeIdx d;
     node_idx(g, x, y, z, d);
     const int n = nb(d, 0, 0, 0);
-    R s[19];
-    gather<S, P, WALLS>(buf, g.stride, d, s);
+    R s[L::Q];
+    gather<L, S, P, WALLS>(buf, g.stride, d, s);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) f[(int64_t)i * g.N + n] = w19(i) * rho0 + (double)s[i];
+    for (int i = 0; i < L::Q; ++i) f[(int64_t)i * g.N + n] = L::w(i) * rho0 + (double)s[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -313,6 +355,8 @@ __device__ inline double wave_min(double v)
     return v;
 }
 
+__device__ inline double combine(int k, double a, double b) { return k == 5 ? fmax(a, b) : (k == 7 ? fmin(a, b) : a + b); }
+
 __device__ inline void block_reduce_store(double v[NDIAG], double* __restrict__ out)
 {
     __shared__ double lds[NDIAG][16];
@@ -329,13 +373,13 @@ __device__ inline void block_reduce_store(double v[NDIAG], double* __restrict__ 
         const int nw = (nthreads + 63) / 64;
         for (int k = 0; k < NDIAG; ++k) {
             double r = lds[k][0];
-            for (int w = 1; w < nw; ++w) r = (k == 5) ? fmax(r, lds[k][w]) : (k == 7 ? fmin(r, lds[k][w]) : r + lds[k][w]);
+            for (int w = 1; w < nw; ++w) r = combine(k, r, lds[k][w]);
             out[k] = r;
         }
     }
 }
 
-template <class S, Pattern P, bool WALLS>
+template <class L, class S, Pattern P, bool WALLS>
 __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ buf, Geom g, Phys ph, double* __restrict__ rho_out,
                                                 double* __restrict__ u_out, double* __restrict__ partials)
 {
@@ -348,16 +392,23 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ buf, Geom
         NodeIdx d;
         node_idx(g, x, y, z, d);
         const int n = nb(d, 0, 0, 0);
-        R s[19];
-        gather<S, P, WALLS>(buf, g.stride, d, s);
-        RawMoments<R> m;
-        raw_from_pops(s, m);
+        R s[L::Q];
+        gather<L, S, P, WALLS>(buf, g.stride, d, s);
+        double m0 = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const double si = (double)s[i];
+            m0 += si;
+            if (L::cx(i)) jx += L::cx(i) * si;
+            if (L::cy(i)) jy += L::cy(i) * si;
+            if (L::cz(i)) jz += L::cz(i) * si;
+        }
         R Fx, Fy, Fz;
         node_force(ph, g, n, y, Fx, Fy, Fz);
-        const double rho = ph.rho0 + (double)m.m000;
-        const double ux = ((double)m.m100 + 0.5 * (double)Fx) / rho;
-        const double uy = ((double)m.m010 + 0.5 * (double)Fy) / rho;
-        const double uz = ((double)m.m001 + 0.5 * (double)Fz) / rho;
+        const double rho = ph.rho0 + m0;
+        const double ux = (jx + 0.5 * (double)Fx) / rho;
+        const double uy = (jy + 0.5 * (double)Fy) / rho;
+        const double uz = (jz + 0.5 * (double)Fz) / rho;
         if (rho_out) rho_out[n] = rho;
         if (u_out) {
             u_out[n] = ux;
@@ -378,33 +429,10 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ buf, Geom
     block_reduce_store(v, partials + (int64_t)bid * NDIAG);
 }
 
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int nblocks, double* __restrict__ out)
-{
-    // one block; thread t sums partials t, t+256, ... in order, then a fixed tree
-    __shared__ double lds[NDIAG][256];
-    const int t = threadIdx.x;
-    double v[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 1e300};
-    for (int b = t; b < nblocks; b += 256) {
-        const double* p = partials + (int64_t)b * NDIAG;
-        for (int k = 0; k < NDIAG; ++k) v[k] = (k == 5) ? fmax(v[k], p[k]) : (k == 7 ? fmin(v[k], p[k]) : v[k] + p[k]);
-    }
-    for (int k = 0; k < NDIAG; ++k) lds[k][t] = v[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w)
-            for (int k = 0; k < NDIAG; ++k)
-                lds[k][t] = (k == 5) ? fmax(lds[k][t], lds[k][t + w])
-                                     : (k == 7 ? fmin(lds[k][t], lds[k][t + w]) : lds[k][t] + lds[k][t + w]);
-        __syncthreads();
-    }
-    if (t == 0)
-        for (int k = 0; k < NDIAG; ++k) out[k] = lds[k][0];
-}
-
 // ---------------------------------------------------------------------------
-// Host-side launchers (dispatch on storage type, pattern, walls, rates).
+// Host-side launchers for one lattice and storage type.
 // ---------------------------------------------------------------------------
-template <class S> struct Launch {
+template <class L, class S> struct Launch {
     static void step(int pattern, bool walls, bool general, bool nt, const void* src, void* dst, const Geom& g,
                      const Phys& ph, dim3 grid, dim3 block, hipStream_t st)
     {
@@ -419,13 +447,20 @@ template <class S> struct Launch {
     static void step_nt(int pattern, bool walls, bool general, const S* a, S* b, const Geom& g, const Phys& ph,
                         dim3 grid, dim3 block, hipStream_t st)
     {
-#define LBM_STEP(P, W, G)                                                                                     \
-    do {                                                                                                      \
-        if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<S, W, G, NT>), grid, block, 0, st, a, b, g, ph); \
-        else hipLaunchKernelGGL((k_step_aa<S, P, W, G, NT>), grid, block, 0, st, b, g, ph);                   \
+        // D3Q27 has fixed rates: no general-rate variant
+        if (L::Q == 27) general = false;
+#define LBM_STEP(P, W, G)                                                                                        \
+    do {                                                                                                         \
+        if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT>), grid, block, 0, st, a, b, g, ph); \
+        else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT>), grid, block, 0, st, b, g, ph);                   \
     } while (0)
-#define LBM_STEP_G(P, W) \
-    if (general) LBM_STEP(P, W, true); else LBM_STEP(P, W, false)
+#define LBM_STEP_G(P, W)                                 \
+    if constexpr (L::Q == 19) {                          \
+        if (general) LBM_STEP(P, W, true);               \
+        else LBM_STEP(P, W, false);                      \
+    } else {                                             \
+        LBM_STEP(P, W, false);                           \
+    }
 #define LBM_STEP_W(P) \
     if (walls) { LBM_STEP_G(P, true); } else { LBM_STEP_G(P, false); }
         switch (pattern) {
@@ -438,19 +473,19 @@ template <class S> struct Launch {
 #undef LBM_STEP
     }
 
-#define LBM_DISPATCH_PW(KERNEL, ...)                                                         \
-    switch (pattern) {                                                                       \
-    case AB:                                                                                 \
-        if (walls) hipLaunchKernelGGL((KERNEL<S, AB, true>), grid, block, 0, st, __VA_ARGS__); \
-        else hipLaunchKernelGGL((KERNEL<S, AB, false>), grid, block, 0, st, __VA_ARGS__);      \
-        break;                                                                               \
-    case AA_EVEN:                                                                            \
-        if (walls) hipLaunchKernelGGL((KERNEL<S, AA_EVEN, true>), grid, block, 0, st, __VA_ARGS__); \
-        else hipLaunchKernelGGL((KERNEL<S, AA_EVEN, false>), grid, block, 0, st, __VA_ARGS__);      \
-        break;                                                                               \
-    default:                                                                                 \
-        if (walls) hipLaunchKernelGGL((KERNEL<S, AA_ODD, true>), grid, block, 0, st, __VA_ARGS__); \
-        else hipLaunchKernelGGL((KERNEL<S, AA_ODD, false>), grid, block, 0, st, __VA_ARGS__);      \
+#define LBM_DISPATCH_PW(KERNEL, ...)                                                                     \
+    switch (pattern) {                                                                                   \
+    case AB:                                                                                             \
+        if (walls) hipLaunchKernelGGL((KERNEL<L, S, AB, true>), grid, block, 0, st, __VA_ARGS__);          \
+        else hipLaunchKernelGGL((KERNEL<L, S, AB, false>), grid, block, 0, st, __VA_ARGS__);               \
+        break;                                                                                           \
+    case AA_EVEN:                                                                                        \
+        if (walls) hipLaunchKernelGGL((KERNEL<L, S, AA_EVEN, true>), grid, block, 0, st, __VA_ARGS__);     \
+        else hipLaunchKernelGGL((KERNEL<L, S, AA_EVEN, false>), grid, block, 0, st, __VA_ARGS__);          \
+        break;                                                                                           \
+    default:                                                                                             \
+        if (walls) hipLaunchKernelGGL((KERNEL<L, S, AA_ODD, true>), grid, block, 0, st, __VA_ARGS__);      \
+        else hipLaunchKernelGGL((KERNEL<L, S, AA_ODD, false>), grid, block, 0, st, __VA_ARGS__);           \
     }
 
     static void init(int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* rho, const double* u,
@@ -475,45 +510,5 @@ template <class S> struct Launch {
     }
 #undef LBM_DISPATCH_PW
 };
-
-template <class F> static void by_precision(int precision, F&& f)
-{
-    switch (precision) {
-    case PREC_FP64: f(Launch<double>{}); break;
-    case PREC_FP32: f(Launch<float>{}); break;
-    case PREC_FP16: f(Launch<_Float16>{}); break;
-    default: f(Launch<bf16_t>{}); break;
-    }
-}
-
-void launch_step(int precision, int pattern, bool walls, bool general, bool nt, const void* src, void* dst,
-                 const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st)
-{
-    by_precision(precision, [&](auto L) { L.step(pattern, walls, general, nt, src, dst, g, ph, grid, block, st); });
-}
-void launch_init(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* rho,
-                 const double* u, dim3 grid, dim3 block, hipStream_t st)
-{
-    by_precision(precision, [&](auto L) { L.init(pattern, walls, buf, g, rho0, rho, u, grid, block, st); });
-}
-void launch_set_pops(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* f,
-                     dim3 grid, dim3 block, hipStream_t st)
-{
-    by_precision(precision, [&](auto L) { L.set_pops(pattern, walls, buf, g, rho0, f, grid, block, st); });
-}
-void launch_get_pops(int precision, int pattern, bool walls, const void* buf, const Geom& g, double rho0, double* f,
-                     dim3 grid, dim3 block, hipStream_t st)
-{
-    by_precision(precision, [&](auto L) { L.get_pops(pattern, walls, buf, g, rho0, f, grid, block, st); });
-}
-void launch_moments(int precision, int pattern, bool walls, const void* buf, const Geom& g, const Phys& ph, double* rho,
-                    double* u, double* partials, dim3 grid, dim3 block, hipStream_t st)
-{
-    by_precision(precision, [&](auto L) { L.moments(pattern, walls, buf, g, ph, rho, u, partials, grid, block, st); });
-}
-void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nblocks, out);
-}
 
 } // namespace lbm

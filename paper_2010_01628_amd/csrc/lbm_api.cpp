@@ -73,7 +73,7 @@ int validate(const lbm_params* p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "lattice size must be positive");
     if ((int64_t)p->nx * p->ny * p->nz > 0x7fffffffLL) return fail(LBM_EINVAL, "more than 2^31-1 nodes");
     if (p->nz > 65535) return fail(LBM_EINVAL, "nz > 65535");
-    if (p->q != 19) return fail(p->q == 27 ? LBM_EUNSUPPORTED : LBM_EINVAL, "q must be 19 (got %d)", p->q);
+    if (p->q != 19 && p->q != 27) return fail(LBM_EINVAL, "q must be 19 or 27 (got %d)", p->q);
     if (p->precision < LBM_FP64 || p->precision > LBM_BF16_SHIFTED) return fail(LBM_EINVAL, "bad precision");
     if (p->streaming != LBM_AB && p->streaming != LBM_AA) return fail(LBM_EINVAL, "bad streaming");
     auto rate_ok = [](double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; };
@@ -93,6 +93,14 @@ int validate(const lbm_params* p)
     if (p->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
     if (p->block_x < 0 || p->block_y < 0) return fail(LBM_EINVAL, "negative block shape");
     if (p->cache_policy < 0 || p->cache_policy > 2) return fail(LBM_EINVAL, "cache_policy must be 0, 1 or 2");
+    if (p->q == 27) {
+        if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
+            return fail(LBM_EUNSUPPORTED, "D3Q27 supports FP64 and FP32 storage");
+        bool paper_rates = p->omega_bulk == 1.0;
+        for (int j = 0; j < 9; ++j) paper_rates = paper_rates && p->omega_hi[j] == 1.0;
+        if (!paper_rates)
+            return fail(LBM_EUNSUPPORTED, "D3Q27 relaxes every non-shear moment at rate 1 (omega_bulk/omega_hi)");
+    }
     const int bx = p->block_x ? p->block_x : 64, by = p->block_y ? p->block_y : 1;
     if (bx * by > 256 || (bx * by) % 64 != 0)
         return fail(LBM_EINVAL, "block_x*block_y must be a multiple of 64 and at most 256");
@@ -135,7 +143,7 @@ int64_t pad_stride(int64_t N, int eb)
 
 int run_check(lbm_handle* h)
 {
-    lbm::launch_moments(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, nullptr, nullptr,
+    lbm::launch_moments(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, nullptr, nullptr,
                         h->partials, h->grid, h->block, h->stream);
     lbm::launch_reduce(h->partials, h->nblocks, h->diag_dev, h->stream);
     HIP_TRY(hipGetLastError());
@@ -215,7 +223,7 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
     h->grid = dim3((p->nx + bx - 1) / bx, (p->ny + by - 1) / by, p->nz);
     h->nblocks = h->grid.x * h->grid.y * h->grid.z;
 
-    const int64_t pop_bytes = (int64_t)19 * h->g.stride * eb;
+    const int64_t pop_bytes = (int64_t)p->q * h->g.stride * eb;
     const int nbuf = p->streaming == LBM_AB ? 2 : 1;
     for (int b = 0; b < nbuf; ++b) {
         hipError_t e = hipMalloc(&h->buf[b], pop_bytes);
@@ -284,7 +292,7 @@ int lbm_init(lbm_handle* h, const double* rho, const double* u, int on_device)
     }
     h->steps = 0;
     h->cur = 0;
-    lbm::launch_init(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, drho, du, h->grid,
+    lbm::launch_init(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, drho, du, h->grid,
                      h->block, h->stream);
     hipError_t e = hipGetLastError();
     if (staging) {
@@ -303,7 +311,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
         const int pat = pattern_of(h);
         const int src = h->cur;
         const int dst = h->p.streaming == LBM_AB ? 1 - h->cur : h->cur;
-        lbm::launch_step(h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g, h->ph,
+        lbm::launch_step(h->p.q, h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g, h->ph,
                          h->grid, h->block, h->stream);
         h->cur = dst;
         h->steps++;
@@ -332,7 +340,7 @@ int lbm_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_devi
         drho = rho ? staging : nullptr;
         du = u ? staging + N : nullptr;
     }
-    lbm::launch_moments(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, drho, du, h->partials,
+    lbm::launch_moments(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, drho, du, h->partials,
                         h->grid, h->block, h->stream);
     if (diag) lbm::launch_reduce(h->partials, h->nblocks, h->diag_dev, h->stream);
     hipError_t e = hipGetLastError();
@@ -353,10 +361,10 @@ int lbm_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_devi
 int lbm_get_populations(lbm_handle* h, double* f, int on_device)
 {
     if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
-    const int64_t bytes = sizeof(double) * 19 * (int64_t)h->g.N;
+    const int64_t bytes = sizeof(double) * h->p.q * (int64_t)h->g.N;
     double* dst = f;
     if (!on_device) HIP_TRY(hipMalloc((void**)&dst, bytes));
-    lbm::launch_get_pops(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, dst, h->grid,
+    lbm::launch_get_pops(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, dst, h->grid,
                          h->block, h->stream);
     hipError_t e = hipGetLastError();
     if (!on_device) {
@@ -371,7 +379,7 @@ int lbm_get_populations(lbm_handle* h, double* f, int on_device)
 int lbm_set_populations(lbm_handle* h, const double* f, int on_device)
 {
     if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
-    const int64_t bytes = sizeof(double) * 19 * (int64_t)h->g.N;
+    const int64_t bytes = sizeof(double) * h->p.q * (int64_t)h->g.N;
     const double* src = f;
     double* staging = nullptr;
     if (!on_device) {
@@ -379,7 +387,7 @@ int lbm_set_populations(lbm_handle* h, const double* f, int on_device)
         HIP_TRY(hipMemcpyAsync(staging, f, bytes, hipMemcpyHostToDevice, h->stream));
         src = staging;
     }
-    lbm::launch_set_pops(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, src, h->grid,
+    lbm::launch_set_pops(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, src, h->grid,
                          h->block, h->stream);
     hipError_t e = hipGetLastError();
     if (staging) {

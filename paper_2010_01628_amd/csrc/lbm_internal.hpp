@@ -24,16 +24,54 @@ struct Phys {
     const double* row_table;   // device, double[ny]: F_x per y row
 };
 
-void launch_step(int precision, int pattern, bool walls, bool general, bool nt, const void* src, void* dst,
-                 const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st);
-void launch_init(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* rho,
-                 const double* u, dim3 grid, dim3 block, hipStream_t st);
-void launch_set_pops(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0, const double* f,
-                     dim3 grid, dim3 block, hipStream_t st);
-void launch_get_pops(int precision, int pattern, bool walls, const void* buf, const Geom& g, double rho0, double* f,
-                     dim3 grid, dim3 block, hipStream_t st);
-void launch_moments(int precision, int pattern, bool walls, const void* buf, const Geom& g, const Phys& ph, double* rho,
-                    double* u, double* partials, dim3 grid, dim3 block, hipStream_t st);
+#define LBM_DECLARE_LAUNCHERS(SUFFIX)                                                                              \
+    void launch_step_##SUFFIX(int precision, int pattern, bool walls, bool general, bool nt, const void* src,        \
+                              void* dst, const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st);     \
+    void launch_init_##SUFFIX(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0,         \
+                              const double* rho, const double* u, dim3 grid, dim3 block, hipStream_t st);           \
+    void launch_set_pops_##SUFFIX(int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0,     \
+                                  const double* f, dim3 grid, dim3 block, hipStream_t st);                          \
+    void launch_get_pops_##SUFFIX(int precision, int pattern, bool walls, const void* buf, const Geom& g,           \
+                                  double rho0, double* f, dim3 grid, dim3 block, hipStream_t st);                   \
+    void launch_moments_##SUFFIX(int precision, int pattern, bool walls, const void* buf, const Geom& g,            \
+                                 const Phys& ph, double* rho, double* u, double* partials, dim3 grid, dim3 block,   \
+                                 hipStream_t st);
+LBM_DECLARE_LAUNCHERS(q19)
+LBM_DECLARE_LAUNCHERS(q27)
+#undef LBM_DECLARE_LAUNCHERS
+
+// Dispatch on the lattice (q = 19 or 27).
+inline void launch_step(int q, int precision, int pattern, bool walls, bool general, bool nt, const void* src,
+                        void* dst, const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (q == 27) launch_step_q27(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
+    else launch_step_q19(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
+}
+inline void launch_init(int q, int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0,
+                        const double* rho, const double* u, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (q == 27) launch_init_q27(precision, pattern, walls, buf, g, rho0, rho, u, grid, block, st);
+    else launch_init_q19(precision, pattern, walls, buf, g, rho0, rho, u, grid, block, st);
+}
+inline void launch_set_pops(int q, int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0,
+                            const double* f, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (q == 27) launch_set_pops_q27(precision, pattern, walls, buf, g, rho0, f, grid, block, st);
+    else launch_set_pops_q19(precision, pattern, walls, buf, g, rho0, f, grid, block, st);
+}
+inline void launch_get_pops(int q, int precision, int pattern, bool walls, const void* buf, const Geom& g, double rho0,
+                            double* f, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (q == 27) launch_get_pops_q27(precision, pattern, walls, buf, g, rho0, f, grid, block, st);
+    else launch_get_pops_q19(precision, pattern, walls, buf, g, rho0, f, grid, block, st);
+}
+inline void launch_moments(int q, int precision, int pattern, bool walls, const void* buf, const Geom& g,
+                           const Phys& ph, double* rho, double* u, double* partials, dim3 grid, dim3 block,
+                           hipStream_t st)
+{
+    if (q == 27) launch_moments_q27(precision, pattern, walls, buf, g, ph, rho, u, partials, grid, block, st);
+    else launch_moments_q19(precision, pattern, walls, buf, g, ph, rho, u, partials, grid, block, st);
+}
 void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
 
 constexpr int NDIAG_OUT = 8;

@@ -147,8 +147,10 @@ def lbm_destroy(h: int) -> None:
 # -- convenience wrapper -----------------------------------------------------
 def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
                 rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
-                force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0) -> lbm_params:
+                force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0,
+                q=19) -> lbm_params:
     p = lbm_params_default()
+    p.q = int(q)
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.streaming = STREAMING[streaming] if isinstance(streaming, str) else int(streaming)
@@ -180,6 +182,7 @@ class Lattice:
         self.params = params
         self.shape = (params.nz, params.ny, params.nx)
         self.N = params.nx * params.ny * params.nz
+        self.q = params.q
         self._force_field = force_field  # keep the tensor alive
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -226,14 +229,14 @@ class Lattice:
 
     def get_populations(self):
         t = self.torch
-        f = t.empty((19,) + self.shape, dtype=t.float64, device="cuda")
+        f = t.empty((self.q,) + self.shape, dtype=t.float64, device="cuda")
         lbm_get_populations(self.h, f.data_ptr(), True)
         self.stream.synchronize()
         return f
 
     def set_populations(self, f):
         ff = self._dev(f)
-        assert ff.numel() == 19 * self.N
+        assert ff.numel() == self.q * self.N
         lbm_set_populations(self.h, ff.data_ptr(), True)
         self.stream.synchronize()
 

@@ -73,7 +73,7 @@ def test_defaults(lbm):
 
 @pytest.mark.parametrize("field,value,code", [
     ("omega", 2.0, -1), ("omega", 0.0, -1), ("omega", float("nan"), -1),
-    ("omega_bulk", 2.5, -1), ("nx", 0, -1), ("q", 27, -5), ("q", 15, -1),
+    ("omega_bulk", 2.5, -1), ("nx", 0, -1), ("q", 15, -1),
     ("precision", 7, -1), ("streaming", 3, -1), ("rho0", -1.0, -1),
     ("force_mode", 2, -1),  # FIELD without a pointer
     ("check_every", -3, -1), ("abi_version", 99, -1),
@@ -85,6 +85,20 @@ def test_invalid_params_rejected_before_device_use(lbm, field, value, code):
         lbm.lbm_create(p, None)
     assert e.value.code == code
     assert lbm.lib().lbm_last_error().decode()
+
+
+def test_d3q27_restrictions(lbm):
+    p = lbm.lbm_params_default()
+    p.q = 27
+    p.precision = lbm.LBM_FP16_SHIFTED
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, None)
+    assert e.value.code == lbm.LBM_EUNSUPPORTED
+    p.precision = lbm.LBM_FP32
+    p.omega_bulk = 1.2
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, None)
+    assert e.value.code == lbm.LBM_EUNSUPPORTED
 
 
 def test_block_shape_validation(lbm):
