@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c"]
+_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c"]
 
 DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
 CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
@@ -81,6 +81,18 @@ def lib():
         L.orc27_step.restype = i32
         L.orc27_init.argtypes = [i32, i32, i32, dp, dp, dp]
         L.orc27_moments.argtypes = [i32, i32, i32, dp, dp, dp, dp]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.orc_mlp_nparam.restype = i32
+        L.orc_bf16.argtypes = [f64]
+        L.orc_bf16.restype = f64
+        L.orc_mlp_features.argtypes = [f64, dp, dp, dp]
+        L.orc_mlp_forward.argtypes = [dp, dp, i32, dp, dp, dp, dp]
+        L.orc_mlp_rates.argtypes = [dp, dp]
+        L.orc_mlp_rates.restype = i32
+        L.orc19_step_mlp.argtypes = [i32, i32, i32, i32, dp, dp, dp, f64, dp, dp, i32]
+        L.orc19_step_mlp.restype = ctypes.c_int64
+        L.orc19_mlp_loss_grad.argtypes = [i32, i32, i32, dp, dp, f64, dp, dp, dp, i32, dp, i64p]
+        L.orc19_mlp_loss_grad.restype = f64
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
         _lib = L
@@ -331,3 +343,83 @@ class d3q27:
         Fa = None if F is None else _f64(F)
         lib().orc27_moments(nx, ny, nz, _p(f), _p(Fa), _p(rho), _p(u))
         return rho, u
+
+
+# --------------------------------------------------------------------------
+# Learned higher-order rates (readings L1-L5 in mlp_oracle.c)
+# --------------------------------------------------------------------------
+MLP_NIN, MLP_NH, MLP_NOUT = 11, 32, 9
+
+
+class mlp:
+    @staticmethod
+    def nparam():
+        return lib().orc_mlp_nparam()
+
+    @staticmethod
+    def unpack(P):
+        P = _f64(P)
+        o = 0
+        out = {}
+        for name, shape in (("W1", (32, 11)), ("b1", (32,)), ("W2", (32, 32)), ("b2", (32,)), ("W3", (9, 32)),
+                            ("b3", (9,))):
+            size = int(np.prod(shape))
+            out[name] = P[o:o + size].reshape(shape)
+            o += size
+        return out
+
+    @staticmethod
+    def bf16(v):
+        return lib().orc_bf16(float(v))
+
+    @staticmethod
+    def features(rho, k, scales):
+        x = np.zeros(MLP_NIN)
+        lib().orc_mlp_features(float(rho), _p(_f64(k)), _p(_f64(scales)), _p(x))
+        return x
+
+    @staticmethod
+    def forward(P, x, bf16=False):
+        xq, h1, h2, z = np.zeros(MLP_NIN), np.zeros(MLP_NH), np.zeros(MLP_NH), np.zeros(MLP_NOUT)
+        lib().orc_mlp_forward(_p(_f64(P)), _p(_f64(x)), int(bf16), _p(xq), _p(h1), _p(h2), _p(z))
+        return z, (xq, h1, h2)
+
+    @staticmethod
+    def rates(z):
+        r = np.zeros(MLP_NOUT)
+        fb = lib().orc_mlp_rates(_p(_f64(z)), _p(r))
+        return r, bool(fb)
+
+    @staticmethod
+    def step(f, omega, P, scales, F=None, walls_y=False, bf16=False, out=None):
+        f = _f64(f)
+        _, nz, ny, nx = f.shape
+        if out is None:
+            out = np.empty_like(f)
+        Fa = None if F is None else _f64(F)
+        fb = lib().orc19_step_mlp(nx, ny, nz, int(bool(walls_y)), _p(f), _p(out), _p(Fa), float(omega),
+                                  _p(_f64(P)), _p(_f64(scales)), int(bf16))
+        if fb < 0:
+            raise ArithmeticError("singular collision system")
+        return out, int(fb)
+
+    @staticmethod
+    def run(f, nsteps, omega, P, scales, F=None, walls_y=False, bf16=False):
+        a = _f64(f).copy()
+        b = np.empty_like(a)
+        total = 0
+        for _ in range(int(nsteps)):
+            _, fb = mlp.step(a, omega, P, scales, F=F, walls_y=walls_y, bf16=bf16, out=b)
+            total += fb
+            a, b = b, a
+        return a, total
+
+    @staticmethod
+    def loss_grad(f, target, omega, P, scales, sigma, bf16=False, want_grad=True):
+        f = _f64(f)
+        _, nz, ny, nx = f.shape
+        g = np.zeros(mlp.nparam()) if want_grad else None
+        fb = ctypes.c_int64(0)
+        loss = lib().orc19_mlp_loss_grad(nx, ny, nz, _p(f), _p(_f64(target)), float(omega), _p(_f64(P)),
+                                         _p(_f64(scales)), _p(_f64(sigma)), int(bf16), _p(g), ctypes.byref(fb))
+        return loss, g, int(fb.value)
