@@ -147,6 +147,65 @@ const char *lbm_last_error(void);
 /* LBM_ABI_VERSION of the loaded library. */
 int lbm_abi_version(void);
 
+/* ---------------------------------------------------------------------------
+ * Learned higher-order rates.  Not part of the paper, which fixes the rates of
+ * the third- and fourth-order CMs k10..k18 to 1 (Sec. II.B): here a per-node
+ * network sets them so that D3Q19 follows D3Q27 (App. D) more closely.  The
+ * conserved (k0..k3), bulk (k4) and viscous (k5..k9) rates are never touched.
+ *
+ * Network: inputs x = (rho - 1, (k4 - rho)/rho, k10..k15 / rho,
+ * (k16..k18 - rho/9)/rho) of the node's pre-collision CMs, each multiplied by
+ * 1/scale_j; two tanh layers of 32; outputs z; omega_hi_j = 1 + z_j.  If any
+ * omega_hi_j is outside (0, 2) the node uses the paper's rates (all 1) and is
+ * counted as a fallback.  Products run on BF16 MFMA with FP32 accumulation.
+ * Parameters: LBM_MLP_NPARAM floats W1[32][11], b1[32], W2[32][32], b2[32],
+ * W3[9][32], b3[9] (W[out][in], row-major).
+ * ------------------------------------------------------------------------- */
+#define LBM_MLP_NPARAM 1737
+
+typedef struct lbm_mlp lbm_mlp;
+
+/* params: host float[LBM_MLP_NPARAM] or NULL (all zero: the paper's rates);
+ * scales: host float[11], all > 0.  All calls are ordered on `stream`. */
+int lbm_mlp_create(const float *params, const float *scales, void *stream, lbm_mlp **out);
+int lbm_mlp_set_params(lbm_mlp *m, const float *params);   /* host; resets Adam moments */
+int lbm_mlp_get_params(const lbm_mlp *m, float *params);   /* host */
+int lbm_mlp_set_scales(lbm_mlp *m, const float *scales);   /* host float[11] */
+int lbm_mlp_destroy(lbm_mlp *m);
+
+/* Use network m for the rates of k10..k18 in every later lbm_step of h (NULL
+ * detaches).  h must be D3Q19 with FP32, FP16 or BF16 storage; m must outlive
+ * its use by h. */
+int lbm_set_mlp(lbm_handle *h, const lbm_mlp *m);
+
+/* Number of node updates that fell back to the paper's rates since the
+ * network was attached (synchronizes the handle's stream). */
+int64_t lbm_fallback_count(lbm_handle *h);
+
+/* Training.  One sample is the one-step map of h's current state f(t) (h:
+ * D3Q19, FP32, A-B, periodic, no force, network m attached): the loss is the
+ * mean over nodes of sum_k ((m_k(f(t+1)) - target_k) / sigma_k)^2 with the raw
+ * moments m = (rho, j_x, j_y, j_z, Pi_xx, Pi_yy, Pi_zz, Pi_xy, Pi_xz, Pi_yz) of
+ * the populations after the step.  target: device float[10*N] (component k at
+ * [k*N + n]).  The gradient is added to m's accumulator; h's state and step
+ * counter are unchanged.  *loss (host, may be NULL) receives the loss. */
+int lbm_mlp_zero_grad(lbm_mlp *m);
+int lbm_mlp_accumulate_grad(lbm_mlp *m, lbm_handle *h, const float *target, const double sigma[10], double *loss);
+int lbm_mlp_get_grad(const lbm_mlp *m, double *grad);      /* host double[LBM_MLP_NPARAM] */
+/* One Adam update of the FP32 master parameters with the accumulated gradient. */
+int lbm_mlp_adam_step(lbm_mlp *m, double lr, double beta1, double beta2, double eps);
+
+/* Root mean square over all nodes of each of the 11 raw network inputs
+ * (before the 1/scale factors) for h's current state (D3Q19, FP32 or 16-bit
+ * storage): the natural input scales.  rms: host double[11]. */
+int lbm_feature_rms(lbm_handle *h, double rms[11]);
+
+/* Training data: D3Q27 populations f27 (device double[27*n], App. D order) ->
+ * D3Q19 populations f19 with the same 19 shared raw moments (device
+ * double[19*n], may be NULL) and the 10 raw moments above (device
+ * float[10*n], may be NULL).  Ordered on `stream`. */
+int lbm_project_q27(const double *f27, int64_t n, double *f19, float *moments, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -225,39 +225,37 @@ template <class R> __host__ __device__ inline void shift_all(RawMoments<R>& m, R
     shift3(m.m020, m.m021, m.m022, c);
 }
 
-// Pre-collision non-equilibrium central moments in the paper's basis rows,
-// divided into what the relaxation needs.  k[0..3] are not stored (k0 neq = 0,
-// k1..3 = -F/2); kn[4..18] = k_r - k_eq_r.
-template <class R> struct NeqCM {
-    R k[19];
+// State between the two halves of a collision: macroscopic fields, the
+// equilibrium raw-moment deviation and the pre-collision non-equilibrium
+// central moments (monomial form; k4 trace and k5, k6 deviators of the paper's
+// rows precomputed).
+template <class R> struct CMState {
+    R rho, drho, ux, uy, uz, Fx, Fy, Fz;
+    RawMoments<R> e; // m_eq(rho, u) - rho0 W
+    RawMoments<R> n; // non-equilibrium central moments (n.m000 = 0, n.m100 = -Fx/2, ...)
+    R k4, k5, k6;
 };
 
-// The collision of Sec. II.B eq. (posColl0) applied to deviations s (in place).
-// GENERAL = false assumes the paper's rates (omega_bulk = 1, omega_hi = 1) and
-// skips every moment those rates discard.  If kneq is non-null it receives the
-// pre-collision non-equilibrium CMs (rows 4..18).
+// First half of the collision of Sec. II.B: moments, equilibrium and the
+// pre-collision non-equilibrium CMs.  GENERAL = false skips the third- and
+// fourth-order CMs (not needed when their rates are 1).
 template <class R, bool GENERAL>
-__host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, const Rates<R>& rt, NodeMacro<R>& mac,
-                                  NeqCM<R>* kneq = nullptr)
+__host__ __device__ inline void pre_collide(const R s[19], R rho0, R Fx, R Fy, R Fz, CMState<R>& st)
 {
-    const R third = R(1) / R(3), ninth = R(1) / R(9), cs2 = third;
     RawMoments<R> m;
     raw_from_pops(s, m);
-    const R drho = m.m000;
-    const R rho = rho0 + drho;
-    const R irho = R(1) / rho;
-    const R ux = (m.m100 + R(0.5) * Fx) * irho;
-    const R uy = (m.m010 + R(0.5) * Fy) * irho;
-    const R uz = (m.m001 + R(0.5) * Fz) * irho;
-    mac.rho = rho;
-    mac.ux = ux;
-    mac.uy = uy;
-    mac.uz = uz;
-
-    // non-equilibrium raw moments n = (S + rho0 W) - m_eq(rho, u)
-    RawMoments<R> e;
-    eq_raw_deviation(drho, rho, ux, uy, uz, e);
-    RawMoments<R> n;
+    st.drho = m.m000;
+    st.rho = rho0 + st.drho;
+    const R irho = R(1) / st.rho;
+    st.ux = (m.m100 + R(0.5) * Fx) * irho;
+    st.uy = (m.m010 + R(0.5) * Fy) * irho;
+    st.uz = (m.m001 + R(0.5) * Fz) * irho;
+    st.Fx = Fx;
+    st.Fy = Fy;
+    st.Fz = Fz;
+    eq_raw_deviation(st.drho, st.rho, st.ux, st.uy, st.uz, st.e);
+    RawMoments<R>& n = st.n;
+    const RawMoments<R>& e = st.e;
     n.m000 = R(0);
     n.m100 = R(-0.5) * Fx;
     n.m010 = R(-0.5) * Fy;
@@ -282,38 +280,23 @@ __host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, co
         n.m210 = n.m120 = n.m201 = n.m102 = n.m021 = n.m012 = n.m220 = n.m202 = n.m022 = R(0);
     }
     // central non-equilibrium moments (shift by -u)
-    shift_all(n, -ux, -uy, -uz);
+    shift_all(n, -st.ux, -st.uy, -st.uz);
+    st.k4 = n.m200 + n.m020 + n.m002;
+    st.k5 = n.m200 - n.m020;
+    st.k6 = n.m020 - n.m002;
+}
 
-    const R k4 = n.m200 + n.m020 + n.m002;
-    const R k5 = n.m200 - n.m020;
-    const R k6 = n.m020 - n.m002;
-    if (kneq) {
-        kneq->k[0] = R(0);
-        kneq->k[1] = n.m100;
-        kneq->k[2] = n.m010;
-        kneq->k[3] = n.m001;
-        kneq->k[4] = k4;
-        kneq->k[5] = k5;
-        kneq->k[6] = k6;
-        kneq->k[7] = n.m110;
-        kneq->k[8] = n.m101;
-        kneq->k[9] = n.m011;
-        kneq->k[10] = n.m210;
-        kneq->k[11] = n.m120;
-        kneq->k[12] = n.m201;
-        kneq->k[13] = n.m102;
-        kneq->k[14] = n.m021;
-        kneq->k[15] = n.m012;
-        kneq->k[16] = n.m220;
-        kneq->k[17] = n.m202;
-        kneq->k[18] = n.m022;
-    }
-
-    // relaxation + forcing (post-collision non-equilibrium CMs)
+// Post-collision non-equilibrium CMs, k* - k_eq = (I - K)(k - k_eq) + (I - K/2) R
+// (eq. posColl0), in monomial form.
+template <class R, bool GENERAL>
+__host__ __device__ inline void relax(const CMState<R>& st, const Rates<R>& rt, RawMoments<R>& p)
+{
+    const R third = R(1) / R(3), cs2 = third;
+    const RawMoments<R>& n = st.n;
+    const R Fx = st.Fx, Fy = st.Fy, Fz = st.Fz;
     const R w1 = R(1) - rt.omega;
-    const R s5 = w1 * k5, s6 = w1 * k6;
+    const R s5 = w1 * st.k5, s6 = w1 * st.k6;
     R s4 = R(0);
-    RawMoments<R> p;
     p.m000 = R(0);
     p.m100 = R(0.5) * Fx;
     p.m010 = R(0.5) * Fy;
@@ -322,7 +305,7 @@ __host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, co
     p.m101 = w1 * n.m101;
     p.m011 = w1 * n.m011;
     if constexpr (GENERAL) {
-        s4 = (R(1) - rt.omega_bulk) * k4;
+        s4 = (R(1) - rt.omega_bulk) * st.k4;
         const R* oh = rt.omega_hi;
         p.m210 = (R(1) - oh[0]) * n.m210 + (R(1) - R(0.5) * oh[0]) * cs2 * Fy;
         p.m120 = (R(1) - oh[1]) * n.m120 + (R(1) - R(0.5) * oh[1]) * cs2 * Fx;
@@ -346,10 +329,14 @@ __host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, co
     p.m200 = third * (s4 + R(2) * s5 + s6);
     p.m020 = third * (s4 - s5 + s6);
     p.m002 = third * (s4 - s5 - R(2) * s6);
-    (void)ninth;
+}
 
-    // back to raw moments (shift by +u) and add the equilibrium deviation
-    shift_all(p, ux, uy, uz);
+// Second half: back to raw moments (shift by +u), add the equilibrium
+// deviation, populations by M^-1.
+template <class R> __host__ __device__ inline void post_collide(const CMState<R>& st, RawMoments<R>& p, R s[19])
+{
+    const RawMoments<R>& e = st.e;
+    shift_all(p, st.ux, st.uy, st.uz);
     p.m000 = e.m000;
     p.m100 += e.m100;
     p.m010 += e.m010;
@@ -370,6 +357,81 @@ __host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, co
     p.m202 += e.m202;
     p.m022 += e.m022;
     pops_from_raw(p, s);
+}
+
+// The collision of Sec. II.B eq. (posColl0) applied to deviations s (in place).
+// GENERAL = false assumes the paper's rates (omega_bulk = 1, omega_hi = 1).
+template <class R, bool GENERAL>
+__host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, const Rates<R>& rt, NodeMacro<R>& mac)
+{
+    CMState<R> st;
+    pre_collide<R, GENERAL>(s, rho0, Fx, Fy, Fz, st);
+    mac.rho = st.rho;
+    mac.ux = st.ux;
+    mac.uy = st.uy;
+    mac.uz = st.uz;
+    RawMoments<R> p;
+    relax<R, GENERAL>(st, rt, p);
+    post_collide(st, p, s);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoints (transposes) of the linear maps of the back-transform, for the
+// gradient of a loss on post-collision populations with respect to the
+// post-collision CMs: s* = M^-1 (S(+u) k* + e) gives kbar = S(+u)^T M^-T sbar.
+// ---------------------------------------------------------------------------
+template <class R> __host__ __device__ inline void pops_from_raw_T(const R g[19], RawMoments<R>& m)
+{
+    const R q = R(0.25), h = R(0.5);
+    const R ax = h * (g[10] + g[1]) - g[0], dx = h * (g[10] - g[1]);
+    const R ay = h * (g[11] + g[2]) - g[0], dy = h * (g[11] - g[2]);
+    const R az = h * (g[12] + g[3]) - g[0], dz = h * (g[12] - g[3]);
+    m.m000 = g[0];
+    m.m200 = ax;
+    m.m020 = ay;
+    m.m002 = az;
+    m.m100 = dx;
+    m.m010 = dy;
+    m.m001 = dz;
+    m.m220 = q * ((g[13] + g[4]) + (g[5] + g[14])) - ax - ay - g[0];
+    m.m110 = q * ((g[13] + g[4]) - (g[5] + g[14]));
+    m.m210 = q * ((g[13] - g[4]) + (g[5] - g[14])) - dy;
+    m.m120 = q * ((g[13] - g[4]) - (g[5] - g[14])) - dx;
+    m.m202 = q * ((g[15] + g[6]) + (g[7] + g[16])) - ax - az - g[0];
+    m.m101 = q * ((g[15] + g[6]) - (g[7] + g[16]));
+    m.m201 = q * ((g[15] - g[6]) + (g[7] - g[16])) - dz;
+    m.m102 = q * ((g[15] - g[6]) - (g[7] - g[16])) - dx;
+    m.m022 = q * ((g[17] + g[8]) + (g[9] + g[18])) - ay - az - g[0];
+    m.m011 = q * ((g[17] + g[8]) - (g[9] + g[18]));
+    m.m021 = q * ((g[17] - g[8]) + (g[9] - g[18])) - dz;
+    m.m012 = q * ((g[17] - g[8]) - (g[9] - g[18])) - dy;
+}
+
+// transpose of shift3: (g0, g1, g2) <- (g0 + a g1 + a^2 g2, g1 + 2 a g2, g2)
+template <class R> __host__ __device__ inline void shift3_T(R& g0, R& g1, R g2, R a)
+{
+    g0 = g0 + a * (g1 + a * g2);
+    g1 = g1 + R(2) * a * g2;
+}
+
+// transpose of shift_all: the sweeps in reverse order
+template <class R> __host__ __device__ inline void shift_all_T(RawMoments<R>& m, R a, R b, R c)
+{
+    shift3_T(m.m000, m.m001, m.m002, c);
+    shift3_T(m.m100, m.m101, m.m102, c);
+    shift3_T(m.m010, m.m011, m.m012, c);
+    shift3_T(m.m200, m.m201, m.m202, c);
+    shift3_T(m.m020, m.m021, m.m022, c);
+    shift3_T(m.m000, m.m010, m.m020, b);
+    shift3_T(m.m100, m.m110, m.m120, b);
+    shift3_T(m.m200, m.m210, m.m220, b);
+    shift3_T(m.m001, m.m011, m.m021, b);
+    shift3_T(m.m002, m.m012, m.m022, b);
+    shift3_T(m.m000, m.m100, m.m200, a);
+    shift3_T(m.m010, m.m110, m.m210, a);
+    shift3_T(m.m001, m.m101, m.m201, a);
+    shift3_T(m.m020, m.m120, m.m220, a);
+    shift3_T(m.m002, m.m102, m.m202, a);
 }
 
 // Deviations of the extended equilibrium f_eq(rho, u) - w rho0 (eq. EqQ19RM),

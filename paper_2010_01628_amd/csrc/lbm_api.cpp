@@ -38,6 +38,27 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 } // namespace
 
+struct lbm_mlp {
+    hipStream_t stream = nullptr;
+    float* theta = nullptr;     // FP32 master parameters (device)
+    float* m1 = nullptr;        // Adam moments
+    float* m2 = nullptr;
+    double* grad = nullptr;     // accumulated gradient (FP64)
+    float* inv_scale = nullptr; // 16 floats
+    void* packed = nullptr;     // bf16 network for the kernels
+    float* inv_sigma = nullptr; // 10 floats
+    int64_t adam_t = 0;
+    // training scratch, grown on demand
+    float* gbuf = nullptr;
+    int64_t gbuf_elems = 0;
+    float* grad_parts = nullptr;
+    int64_t grad_parts_n = 0;
+    double* loss_parts = nullptr;
+    int64_t loss_parts_n = 0;
+    double* loss_dev = nullptr;
+    double* loss_host = nullptr;
+};
+
 struct lbm_handle {
     lbm_params p;
     int device = 0;
@@ -55,6 +76,8 @@ struct lbm_handle {
     bool walls = false, general = false, nt = true;
     int64_t bytes = 0;
     int nblocks = 0;
+    const lbm_mlp* mlp = nullptr;
+    uint32_t* fb_partials = nullptr; // per-block fallback counts of the learned step
 };
 
 namespace {
@@ -266,6 +289,7 @@ int lbm_destroy(lbm_handle* h)
 {
     if (!h) return LBM_OK;
     if (h->stream || h->buf[0]) hipStreamSynchronize(h->stream);
+    if (h->fb_partials) hipFree(h->fb_partials);
     for (int b = 0; b < 2; ++b)
         if (h->buf[b]) hipFree(h->buf[b]);
     if (h->row_table) hipFree(h->row_table);
@@ -311,8 +335,12 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
         const int pat = pattern_of(h);
         const int src = h->cur;
         const int dst = h->p.streaming == LBM_AB ? 1 - h->cur : h->cur;
-        lbm::launch_step(h->p.q, h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g, h->ph,
-                         h->grid, h->block, h->stream);
+        if (h->mlp)
+            lbm::launch_step_mlp(h->p.precision, pat, h->walls, h->nt, h->buf[src], h->buf[dst], h->g, h->ph,
+                                 h->mlp->packed, h->fb_partials, h->grid, h->block, h->stream);
+        else
+            lbm::launch_step(h->p.q, h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g,
+                             h->ph, h->grid, h->block, h->stream);
         h->cur = dst;
         h->steps++;
         if (h->p.check_every > 0 && h->steps % h->p.check_every == 0) {
@@ -399,6 +427,252 @@ int lbm_set_populations(lbm_handle* h, const double* f, int on_device)
 }
 
 int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }
+
+// ---------------------------------------------------------------------------
+// Learned rates
+// ---------------------------------------------------------------------------
+int lbm_mlp_destroy(lbm_mlp* m)
+{
+    if (!m) return LBM_OK;
+    hipStreamSynchronize(m->stream);
+    void* bufs[] = {m->theta, m->m1, m->m2, m->grad, m->inv_scale, m->packed, m->inv_sigma, m->gbuf, m->grad_parts,
+                    m->loss_parts, m->loss_dev};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    if (m->loss_host) hipHostFree(m->loss_host);
+    delete m;
+    return LBM_OK;
+}
+
+static int mlp_repack(lbm_mlp* m)
+{
+    lbm::launch_mlp_pack(m->theta, m->inv_scale, m->packed, m->stream);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int lbm_mlp_create(const float* params, const float* scales, void* stream, lbm_mlp** out)
+{
+    g_err[0] = 0;
+    if (!out || !scales) return fail(LBM_EINVAL, "NULL argument");
+    *out = nullptr;
+    for (int j = 0; j < 11; ++j)
+        if (!(std::isfinite(scales[j]) && scales[j] > 0.0f)) return fail(LBM_EINVAL, "scales must be positive");
+    if (params)
+        for (int p = 0; p < LBM_MLP_NPARAM; ++p)
+            if (!std::isfinite(params[p])) return fail(LBM_EINVAL, "non-finite parameter %d", p);
+    lbm_mlp* m = new lbm_mlp();
+    m->stream = (hipStream_t)stream;
+    const size_t pb = sizeof(float) * LBM_MLP_NPARAM;
+    if (hipMalloc((void**)&m->theta, pb) != hipSuccess || hipMalloc((void**)&m->m1, pb) != hipSuccess ||
+        hipMalloc((void**)&m->m2, pb) != hipSuccess ||
+        hipMalloc((void**)&m->grad, sizeof(double) * LBM_MLP_NPARAM) != hipSuccess ||
+        hipMalloc((void**)&m->inv_scale, sizeof(float) * 16) != hipSuccess ||
+        hipMalloc(&m->packed, lbm::mlp_packed_bytes()) != hipSuccess ||
+        hipMalloc((void**)&m->inv_sigma, sizeof(float) * 10) != hipSuccess ||
+        hipMalloc((void**)&m->loss_dev, sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&m->loss_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        lbm_mlp_destroy(m);
+        return fail(LBM_ENOMEM, "network buffers");
+    }
+    float inv[16] = {0};
+    for (int j = 0; j < 11; ++j) inv[j] = 1.0f / scales[j];
+    hipError_t e = hipMemcpyAsync(m->inv_scale, inv, sizeof inv, hipMemcpyHostToDevice, m->stream);
+    if (e == hipSuccess) e = params ? hipMemcpyAsync(m->theta, params, pb, hipMemcpyHostToDevice, m->stream)
+                                    : hipMemsetAsync(m->theta, 0, pb, m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->m1, 0, pb, m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->m2, 0, pb, m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->grad, 0, sizeof(double) * LBM_MLP_NPARAM, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+        lbm_mlp_destroy(m);
+        return fail(LBM_EDEVICE, "network upload: %s", hipGetErrorString(e));
+    }
+    int rc = mlp_repack(m);
+    if (rc) {
+        lbm_mlp_destroy(m);
+        return rc;
+    }
+    *out = m;
+    return LBM_OK;
+}
+
+int lbm_mlp_set_params(lbm_mlp* m, const float* params)
+{
+    if (!m || !params) return fail(LBM_EINVAL, "NULL argument");
+    const size_t pb = sizeof(float) * LBM_MLP_NPARAM;
+    HIP_TRY(hipMemcpyAsync(m->theta, params, pb, hipMemcpyHostToDevice, m->stream));
+    HIP_TRY(hipMemsetAsync(m->m1, 0, pb, m->stream));
+    HIP_TRY(hipMemsetAsync(m->m2, 0, pb, m->stream));
+    m->adam_t = 0;
+    int rc = mlp_repack(m);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    return LBM_OK;
+}
+
+int lbm_mlp_get_params(const lbm_mlp* m, float* params)
+{
+    if (!m || !params) return fail(LBM_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(params, m->theta, sizeof(float) * LBM_MLP_NPARAM, hipMemcpyDeviceToHost, m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    return LBM_OK;
+}
+
+int lbm_mlp_set_scales(lbm_mlp* m, const float* scales)
+{
+    if (!m || !scales) return fail(LBM_EINVAL, "NULL argument");
+    float inv[16] = {0};
+    for (int j = 0; j < 11; ++j) {
+        if (!(std::isfinite(scales[j]) && scales[j] > 0.0f)) return fail(LBM_EINVAL, "scales must be positive");
+        inv[j] = 1.0f / scales[j];
+    }
+    HIP_TRY(hipMemcpyAsync(m->inv_scale, inv, sizeof inv, hipMemcpyHostToDevice, m->stream));
+    int rc = mlp_repack(m);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    return LBM_OK;
+}
+
+int lbm_set_mlp(lbm_handle* h, const lbm_mlp* m)
+{
+    if (!h) return fail(LBM_EINVAL, "NULL handle");
+    if (m) {
+        if (h->p.q != 19) return fail(LBM_EUNSUPPORTED, "learned rates need the D3Q19 lattice");
+        if (h->p.precision == LBM_FP64) return fail(LBM_EUNSUPPORTED, "learned rates run with FP32 collision");
+        if (!h->fb_partials) {
+            HIP_TRY(hipMalloc((void**)&h->fb_partials, sizeof(uint32_t) * h->nblocks));
+            h->bytes += sizeof(uint32_t) * h->nblocks;
+        }
+        HIP_TRY(hipMemsetAsync(h->fb_partials, 0, sizeof(uint32_t) * h->nblocks, h->stream));
+        // the network's uploads are ordered on its own stream
+        HIP_TRY(hipStreamSynchronize(m->stream));
+    }
+    h->mlp = m;
+    return LBM_OK;
+}
+
+int64_t lbm_fallback_count(lbm_handle* h)
+{
+    if (!h || !h->fb_partials) return 0;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(LBM_EDEVICE, "sync");
+    uint32_t* host = (uint32_t*)std::malloc(sizeof(uint32_t) * h->nblocks);
+    if (!host) return fail(LBM_ENOMEM, "host buffer");
+    int64_t total = -1;
+    if (hipMemcpy(host, h->fb_partials, sizeof(uint32_t) * h->nblocks, hipMemcpyDeviceToHost) == hipSuccess) {
+        total = 0;
+        for (int b = 0; b < h->nblocks; ++b) total += host[b];
+    }
+    std::free(host);
+    return total < 0 ? fail(LBM_EDEVICE, "copy") : total;
+}
+
+int lbm_mlp_zero_grad(lbm_mlp* m)
+{
+    if (!m) return fail(LBM_EINVAL, "NULL argument");
+    HIP_TRY(hipMemsetAsync(m->grad, 0, sizeof(double) * LBM_MLP_NPARAM, m->stream));
+    return LBM_OK;
+}
+
+static int grow(void** p, int64_t& have, int64_t need, size_t elem)
+{
+    if (have >= need) return LBM_OK;
+    if (*p) hipFree(*p);
+    *p = nullptr;
+    have = 0;
+    if (hipMalloc(p, elem * need) != hipSuccess) return fail(LBM_ENOMEM, "training scratch");
+    have = need;
+    return LBM_OK;
+}
+
+int lbm_mlp_accumulate_grad(lbm_mlp* m, lbm_handle* h, const float* target, const double sigma[10], double* loss)
+{
+    if (!m || !h || !target || !sigma) return fail(LBM_EINVAL, "NULL argument");
+    if (h->mlp != m) return fail(LBM_EINVAL, "the network must be attached to the handle (lbm_set_mlp)");
+    if (h->p.q != 19 || h->p.precision != LBM_FP32 || h->p.streaming != LBM_AB || h->walls ||
+        h->p.force_mode != LBM_FORCE_NONE)
+        return fail(LBM_EUNSUPPORTED, "training needs a periodic, force-free D3Q19 FP32 A-B lattice");
+    float isig[10];
+    for (int k = 0; k < 10; ++k) {
+        if (!(std::isfinite(sigma[k]) && sigma[k] > 0.0)) return fail(LBM_EINVAL, "sigma must be positive");
+        isig[k] = (float)(1.0 / sigma[k]);
+    }
+    const lbm::Geom& g = h->g;
+    const int nwb = ((g.nx + 63) / 64) * g.ny * g.nz; // backward: one wavefront per block
+    int rc = grow((void**)&m->gbuf, m->gbuf_elems, (int64_t)19 * g.N, sizeof(float));
+    if (!rc) rc = grow((void**)&m->grad_parts, m->grad_parts_n, (int64_t)nwb * LBM_MLP_NPARAM, sizeof(float));
+    if (!rc) rc = grow((void**)&m->loss_parts, m->loss_parts_n, h->nblocks, sizeof(double));
+    if (rc) return rc;
+    // the network and the lattice may use different streams: order m's work first
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    HIP_TRY(hipMemcpyAsync(m->inv_sigma, isig, sizeof isig, hipMemcpyHostToDevice, h->stream));
+    void* state = h->buf[h->cur];
+    void* post = h->buf[1 - h->cur];
+    lbm::launch_step_mlp(LBM_FP32, 0, false, false, state, post, g, h->ph, m->packed, h->fb_partials, h->grid, h->block,
+                         h->stream);
+    lbm::launch_train_loss((const float*)post, g, (float)h->p.rho0, target, m->inv_sigma, m->gbuf, m->loss_parts,
+                           h->grid, h->block, h->stream);
+    lbm::launch_train_backward((const float*)state, m->gbuf, g, (float)h->p.rho0, m->packed, m->grad_parts, h->stream);
+    lbm::launch_reduce_grad(m->grad_parts, nwb, m->grad, h->stream);
+    lbm::launch_sum_partials(m->loss_parts, h->nblocks, m->loss_dev, h->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(m->loss_host, m->loss_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (loss) *loss = *m->loss_host;
+    return LBM_OK;
+}
+
+int lbm_mlp_get_grad(const lbm_mlp* m, double* grad)
+{
+    if (!m || !grad) return fail(LBM_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(grad, m->grad, sizeof(double) * LBM_MLP_NPARAM, hipMemcpyDeviceToHost, m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    return LBM_OK;
+}
+
+int lbm_mlp_adam_step(lbm_mlp* m, double lr, double beta1, double beta2, double eps)
+{
+    if (!m) return fail(LBM_EINVAL, "NULL argument");
+    if (!(lr > 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0))
+        return fail(LBM_EINVAL, "bad Adam hyper-parameters");
+    m->adam_t++;
+    const double c1 = 1.0 - std::pow(beta1, (double)m->adam_t), c2 = 1.0 - std::pow(beta2, (double)m->adam_t);
+    lbm::launch_adam(m->theta, m->m1, m->m2, m->grad, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
+                     (float)c2, m->stream);
+    int rc = mlp_repack(m);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    return LBM_OK;
+}
+
+int lbm_feature_rms(lbm_handle* h, double rms[11])
+{
+    if (!h || !rms) return fail(LBM_EINVAL, "NULL argument");
+    if (h->p.q != 19 || h->p.precision == LBM_FP64) return fail(LBM_EUNSUPPORTED, "D3Q19 with FP32/16-bit storage");
+    double* part = nullptr;
+    double* out = nullptr;
+    HIP_TRY(hipMalloc((void**)&part, sizeof(double) * 11 * (h->nblocks + 1)));
+    out = part + 11 * (int64_t)h->nblocks;
+    lbm::launch_feature_sumsq(h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, part, out,
+                              h->nblocks, h->grid, h->block, h->stream);
+    double host[11];
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    hipFree(part);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "feature_rms: %s", hipGetErrorString(e));
+    for (int k = 0; k < 11; ++k) rms[k] = std::sqrt(host[k] / (double)h->g.N);
+    return LBM_OK;
+}
+
+int lbm_project_q27(const double* f27, int64_t n, double* f19, float* moments, void* stream)
+{
+    if (!f27 || n <= 0) return fail(LBM_EINVAL, "bad arguments");
+    lbm::launch_project_q27(f27, n, f19, moments, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
 
 int64_t lbm_device_bytes(const lbm_handle* h) { return h ? h->bytes : -1; }
 

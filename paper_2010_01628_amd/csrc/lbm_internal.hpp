@@ -74,6 +74,24 @@ inline void launch_moments(int q, int precision, int pattern, bool walls, const 
 }
 void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
 
+// learned rates (mlp.hip)
+constexpr int MLP_PARAMS = 1737;
+void launch_step_mlp(int precision, int pattern, bool walls, bool nt, const void* src, void* dst, const Geom& g,
+                     const Phys& ph, const void* net, uint32_t* fb_partials, dim3 grid, dim3 block, hipStream_t st);
+void launch_train_loss(const float* post, const Geom& g, float rho0, const float* target, const float* inv_sigma,
+                       float* gbuf, double* loss_partials, dim3 grid, dim3 block, hipStream_t st);
+void launch_train_backward(const float* state, const float* gbuf, const Geom& g, float rho0, const void* net,
+                           float* grad_partials, hipStream_t st);
+void launch_reduce_grad(const float* partials, int nparts, double* grad, hipStream_t st);
+void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
+void launch_adam(float* theta, float* m1, float* m2, const double* grad, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t st);
+void launch_mlp_pack(const float* theta, const float* inv_scale, void* packed, hipStream_t st);
+void launch_project_q27(const double* f27, int64_t N, double* f19, float* mom, hipStream_t st);
+size_t mlp_packed_bytes();
+void launch_feature_sumsq(int precision, int pattern, bool walls, const void* buf, const Geom& g, const Phys& ph,
+                          double* partials, double* out, int nblocks, dim3 grid, dim3 block, hipStream_t st);
+
 constexpr int NDIAG_OUT = 8;
 
 } // namespace lbm

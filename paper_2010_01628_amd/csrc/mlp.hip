@@ -1,0 +1,537 @@
+// Learned-rate D3Q19 step, its training kernels, and the D3Q27 -> D3Q19
+// projection that produces training data.
+#include "lattice_kernels.hpp"
+#include "mlp_device.hpp"
+
+namespace lbm {
+
+// Raw features of reading L1 from the pre-collision state (the kernels scale
+// them by MlpPacked::inv_scale).
+__device__ inline void mlp_features(const CMState<float>& st, float x[MLP_NIN])
+{
+    const float ir = 1.0f / st.rho;
+    const RawMoments<float>& n = st.n;
+    x[0] = st.rho - 1.0f;
+    x[1] = st.k4 * ir;
+    x[2] = n.m210 * ir;
+    x[3] = n.m120 * ir;
+    x[4] = n.m201 * ir;
+    x[5] = n.m102 * ir;
+    x[6] = n.m021 * ir;
+    x[7] = n.m012 * ir;
+    x[8] = n.m220 * ir;
+    x[9] = n.m202 * ir;
+    x[10] = n.m022 * ir;
+}
+
+// Cooperative copy of the first `words` 32-bit words of the packed network
+// into LDS (all threads of the block).
+__device__ inline void load_net(uint32_t* d, const MlpPacked* __restrict__ src, int words)
+{
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int nthr = blockDim.x * blockDim.y;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    for (int i = tid; i < words; i += nthr) d[i] = s[i];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Step with learned rates (FP32 collision; FP32/FP16/BF16 storage).  Every
+// lane of every wavefront takes part in the network (lanes past the lattice
+// edge work on a clamped node and store nothing).  Per block, the number of
+// nodes that fell back is added to fb_partials[block].
+// ---------------------------------------------------------------------------
+template <class S, Pattern P, bool WALLS, bool NT>
+__global__ __launch_bounds__(256) void k_step_mlp(const S* src, S* dst, Geom g, Phys ph,
+                                                  const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
+{
+    __shared__ uint32_t snet_words[MLP_INFER_WORDS];
+    __shared__ uint16_t tiles[4][2][MLP_TILE];
+    __shared__ uint32_t wave_fb[4];
+    load_net(snet_words, net, MLP_INFER_WORDS);
+    const MlpPacked& snet = *reinterpret_cast<const MlpPacked*>(snet_words);
+    const int xr = blockIdx.x * blockDim.x + threadIdx.x;
+    const int yr = blockIdx.y * blockDim.y + threadIdx.y;
+    const bool valid = xr < g.nx && yr < g.ny;
+    const int x = xr < g.nx ? xr : g.nx - 1;
+    const int y = yr < g.ny ? yr : g.ny - 1;
+    const int z = blockIdx.z;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    float s[19];
+    gather<LatD3Q19, S, P, WALLS, NT>(src, g.stride, d, s);
+    float Fx, Fy, Fz;
+    node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
+    CMState<float> st;
+    pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
+    float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];
+    mlp_features(st, xin);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int w = tid >> 6;
+    // tile 0: inputs then second hidden layer; tile 1: first hidden layer then outputs
+    mlp_forward_wave(snet, tiles[w][0], tiles[w][1], tiles[w][0], reinterpret_cast<float*>(tiles[w][1]), xin, zout);
+    const bool fb = mlp_rates(zout, rates);
+    Rates<float> rt = rates_of<float>(ph);
+#pragma unroll
+    for (int j = 0; j < MLP_NOUT; ++j) rt.omega_hi[j] = rates[j];
+    RawMoments<float> p;
+    if (fb && ph.omega_bulk == 1.0)
+        relax<float, false>(st, rt, p); // the paper's rates: the plain step's arithmetic, bit for bit
+    else
+        relax<float, true>(st, rt, p);
+    post_collide(st, p, s);
+    if (valid) scatter<LatD3Q19, S, P, WALLS, NT>(dst, g.stride, d, s);
+    // fallback count of the block
+    const uint64_t ballot = __ballot(valid && fb);
+    if ((tid & 63) == 0) wave_fb[w] = (uint32_t)__popcll(ballot);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t c = 0;
+        for (int i = 0; i < (int)((blockDim.x * blockDim.y + 63) / 64); ++i) c += wave_fb[i];
+        const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        fb_partials[bid] += c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training, reading L5: loss on the 10 raw moments of f(t+1) after one A-B
+// step from f(t) (periodic, no force).  post: post-collision buffer written by
+// k_step_mlp (A-B).  Writes dL/df_i(y, t+1) to gbuf (SoA floats, stride N) and
+// one FP64 loss partial per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_train_loss(const float* __restrict__ post, Geom g, float rho0,
+                                                    const float* __restrict__ target, const float* __restrict__ inv_sigma,
+                                                    float* __restrict__ gbuf, double* __restrict__ loss_partials)
+{
+    __shared__ double red[4];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double l2 = 0.0;
+    if (x < g.nx && y < g.ny) {
+        NodeIdx d;
+        node_idx(g, x, y, z, d);
+        const int n = nb(d, 0, 0, 0);
+        float s[19];
+        gather<LatD3Q19, float, AB, false>(post, g.stride, d, s);
+        // moments of f = w rho0 + s: rest part (1, 0,0,0, 1/3 x3, 0 x3) rho0
+        float m[10] = {rho0, 0, 0, 0, rho0 / 3.0f, rho0 / 3.0f, rho0 / 3.0f, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const float cx = LatD3Q19::cx(i), cy = LatD3Q19::cy(i), cz = LatD3Q19::cz(i);
+            m[0] += s[i];
+            m[1] += cx * s[i];
+            m[2] += cy * s[i];
+            m[3] += cz * s[i];
+            m[4] += cx * cx * s[i];
+            m[5] += cy * cy * s[i];
+            m[6] += cz * cz * s[i];
+            m[7] += cx * cy * s[i];
+            m[8] += cx * cz * s[i];
+            m[9] += cy * cz * s[i];
+        }
+        float dm[10];
+        const float two_over_n = 2.0f / (float)g.N;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const float r = (m[k] - target[(int64_t)k * g.N + n]) * inv_sigma[k];
+            l2 += (double)r * (double)r;
+            dm[k] = two_over_n * r * inv_sigma[k];
+        }
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const float cx = LatD3Q19::cx(i), cy = LatD3Q19::cy(i), cz = LatD3Q19::cz(i);
+            gbuf[(int64_t)i * g.N + n] = dm[0] + cx * dm[1] + cy * dm[2] + cz * dm[3] + cx * cx * dm[4] + cy * cy * dm[5] +
+                                         cz * cz * dm[6] + cx * cy * dm[7] + cx * cz * dm[8] + cy * cz * dm[9];
+        }
+    }
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    double v = l2;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)((blockDim.x * blockDim.y + 63) / 64); ++i) t += red[i];
+        loss_partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t / (double)g.N;
+    }
+}
+
+// Backward pass, one wavefront per block (64 nodes): recompute the forward
+// state from f(t), pull dL/df*_i(x) = dL/df_i(x + c_i, t+1), form
+// dL/domega_j = kbar_{10+j} (-(k_{10+j} - k_eq) - R_{10+j}/2) with
+// kbar = S(+u)^T M^-T gbar, then back-propagate through the network.  Writes
+// this wavefront's 1737 gradient entries to grad_partials[wave].
+__global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__ state, const float* __restrict__ gbuf,
+                                                       Geom g, float rho0, const MlpPacked* __restrict__ net,
+                                                       float* __restrict__ grad_partials)
+{
+    __shared__ MlpPacked snet;
+    __shared__ uint16_t tx[MLP_TILE], th1[MLP_TILE], th2[MLP_TILE], tdz[MLP_TILE], tdh[MLP_TILE];
+    __shared__ float tz[64 * MLP_NOUT];
+    load_net(reinterpret_cast<uint32_t*>(&snet), net, (int)(sizeof(MlpPacked) / 4));
+    const int l = threadIdx.x;
+    const int xr = blockIdx.x * 64 + l;
+    const int yr = blockIdx.y;
+    const bool valid = xr < g.nx;
+    const int x = valid ? xr : g.nx - 1;
+    const int y = yr, z = blockIdx.z;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    float s[19];
+    gather<LatD3Q19, float, AB, false>(state, g.stride, d, s);
+    CMState<float> st;
+    pre_collide<float, true>(s, rho0, 0.0f, 0.0f, 0.0f, st);
+    float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];
+    mlp_features(st, xin);
+    mlp_forward_wave(snet, tx, th1, th2, tz, xin, zout);
+    const bool fb = mlp_rates(zout, rates);
+    // adjoint of the streaming
+    float gbar[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+        gbar[i] = gbuf[(int64_t)i * g.N + nb(d, LatD3Q19::cx(i), LatD3Q19::cy(i), LatD3Q19::cz(i))];
+    RawMoments<float> kb;
+    pops_from_raw_T(gbar, kb);
+    shift_all_T(kb, st.ux, st.uy, st.uz);
+    const RawMoments<float>& n = st.n;
+    // no force in training: R = 0 on rows 10..18
+    float dz[MLP_NOUT] = {-kb.m210 * n.m210, -kb.m120 * n.m120, -kb.m201 * n.m201, -kb.m102 * n.m102, -kb.m021 * n.m021,
+                          -kb.m012 * n.m012, -kb.m220 * n.m220, -kb.m202 * n.m202, -kb.m022 * n.m022};
+    const bool active = valid && !fb;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) tdz[l * MLP_LDS_STRIDE + k] = (k < MLP_NOUT && active) ? f32_to_bf16(dz[k]) : 0;
+    __syncthreads();
+    float* gp = grad_partials + (int64_t)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) * MLP_NPARAM;
+    // dW3[o][h] = sum_n dz[n][o] h2[n][h]
+    {
+        const f32x16_t acc = mfma_AtB(tdz, th2);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+            if (o < MLP_NOUT) gp[MLP_OFF_W3 + o * 32 + (l & 31)] = acc[r];
+        }
+    }
+    // db3, and dh2 = (dz W3) * (1 - h2^2)
+    if (l < MLP_NOUT) {
+        float sb = 0.0f;
+        for (int q = 0; q < 64; ++q) sb += bf16_to_f32(tdz[q * MLP_LDS_STRIDE + l]);
+        gp[MLP_OFF_B3 + l] = sb;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const f32x16_t acc = mfma_xwT<32>(tdz, rb, snet.w3t, 32);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = acc_row(rb, r), h = l & 31;
+            const float a2 = bf16_to_f32(th2[row * MLP_LDS_STRIDE + h]);
+            tdh[row * MLP_LDS_STRIDE + h] = f32_to_bf16(acc[r] * (1.0f - a2 * a2));
+        }
+    }
+    __syncthreads();
+    // dW2, db2, dh1 = (dh2 W2) * (1 - h1^2) written over tdz
+    {
+        const f32x16_t acc = mfma_AtB(tdh, th1);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) gp[MLP_OFF_W2 + (8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * 32 + (l & 31)] = acc[r];
+    }
+    if (l < 32) {
+        float sb = 0.0f;
+        for (int q = 0; q < 64; ++q) sb += bf16_to_f32(tdh[q * MLP_LDS_STRIDE + l]);
+        gp[MLP_OFF_B2 + l] = sb;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const f32x16_t acc = mfma_xwT<32>(tdh, rb, snet.w2t, 32);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = acc_row(rb, r), h = l & 31;
+            const float a1 = bf16_to_f32(th1[row * MLP_LDS_STRIDE + h]);
+            tdz[row * MLP_LDS_STRIDE + h] = f32_to_bf16(acc[r] * (1.0f - a1 * a1));
+        }
+    }
+    __syncthreads();
+    // dW1[o][i] = sum_n dh1[n][o] x[n][i], db1
+    {
+        const f32x16_t acc = mfma_AtB(tdz, tx);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = l & 31;
+            if (i < MLP_NIN) gp[MLP_OFF_W1 + (8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * MLP_NIN + i] = acc[r];
+        }
+    }
+    if (l < 32) {
+        float sb = 0.0f;
+        for (int q = 0; q < 64; ++q) sb += bf16_to_f32(tdz[q * MLP_LDS_STRIDE + l]);
+        gp[MLP_OFF_B1 + l] = sb;
+    }
+}
+
+// grad[p] += sum over partials (FP64, fixed order); one thread per parameter.
+__global__ __launch_bounds__(256) void k_reduce_grad(const float* __restrict__ partials, int nparts, double* __restrict__ grad)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM) return;
+    double s = 0.0;
+    for (int w = 0; w < nparts; ++w) s += (double)partials[(int64_t)w * MLP_NPARAM + p];
+    grad[p] += s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partials, int n, double* __restrict__ out)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += partials[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// Adam on the FP32 master parameters (FP64 gradient).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, float* __restrict__ m1, float* __restrict__ m2,
+                                              const double* __restrict__ grad, float lr, float b1, float b2, float eps,
+                                              float c1, float c2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM) return;
+    const float gr = (float)grad[p];
+    const float a = b1 * m1[p] + (1.0f - b1) * gr;
+    const float b = b2 * m2[p] + (1.0f - b2) * gr * gr;
+    m1[p] = a;
+    m2[p] = b;
+    theta[p] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+// FP32 master parameters + inverse feature scales -> packed bf16 network.
+__global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ theta, const float* __restrict__ inv_scale,
+                                                  MlpPacked* __restrict__ out)
+{
+    const int t = threadIdx.x;
+    for (int i = t; i < 32 * 16; i += 256) {
+        const int o = i / 16, k = i % 16;
+        out->w1[i] = k < MLP_NIN ? f32_to_bf16(theta[MLP_OFF_W1 + o * MLP_NIN + k]) : 0;
+    }
+    for (int i = t; i < 32 * 32; i += 256) {
+        const int o = i / 32, k = i % 32;
+        const uint16_t v2 = f32_to_bf16(theta[MLP_OFF_W2 + o * 32 + k]);
+        out->w2[i] = v2;
+        out->w2t[k * 32 + o] = v2;
+        const uint16_t v3 = o < MLP_NOUT ? f32_to_bf16(theta[MLP_OFF_W3 + o * 32 + k]) : 0;
+        out->w3[i] = v3;
+        out->w3t[k * 32 + o] = v3;
+    }
+    if (t < 32) {
+        out->b1[t] = theta[MLP_OFF_B1 + t];
+        out->b2[t] = theta[MLP_OFF_B2 + t];
+        out->b3[t] = t < MLP_NOUT ? theta[MLP_OFF_B3 + t] : 0.0f;
+    }
+    if (t < 16) out->inv_scale[t] = t < MLP_NIN ? inv_scale[t] : 0.0f;
+}
+
+// D3Q27 populations (canonical, double) -> D3Q19 populations with the same 19
+// raw moments, and the 10 moments (rho, j, Pi) of the D3Q27 state.
+__global__ __launch_bounds__(256) void k_project_q27(const double* __restrict__ f27, int64_t N, double* __restrict__ f19,
+                                                     float* __restrict__ mom)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    RawMoments<double> m = {};
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const double v = f27[(int64_t)i * N + n];
+        const int a = cx27(i), b = cy27(i), c = cz27(i);
+        const int a2 = a * a, b2 = b * b, c2 = c * c;
+        m.m000 += v;
+        m.m100 += a * v;
+        m.m010 += b * v;
+        m.m001 += c * v;
+        m.m200 += a2 * v;
+        m.m020 += b2 * v;
+        m.m002 += c2 * v;
+        m.m110 += a * b * v;
+        m.m101 += a * c * v;
+        m.m011 += b * c * v;
+        m.m210 += a2 * b * v;
+        m.m120 += a * b2 * v;
+        m.m201 += a2 * c * v;
+        m.m102 += a * c2 * v;
+        m.m021 += b2 * c * v;
+        m.m012 += b * c2 * v;
+        m.m220 += a2 * b2 * v;
+        m.m202 += a2 * c2 * v;
+        m.m022 += b2 * c2 * v;
+    }
+    if (f19) {
+        double s[19];
+        pops_from_raw(m, s);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) f19[(int64_t)i * N + n] = s[i];
+    }
+    if (mom) {
+        const double v[10] = {m.m000, m.m100, m.m010, m.m001, m.m200, m.m020, m.m002, m.m110, m.m101, m.m011};
+#pragma unroll
+        for (int k = 0; k < 10; ++k) mom[(int64_t)k * N + n] = (float)v[k];
+    }
+}
+
+// Per-block FP64 sums of squares of the 11 raw network inputs of the current
+// state (to fit the input scales); partials[block][11].
+template <class S, Pattern P, bool WALLS>
+__global__ __launch_bounds__(256) void k_feature_sumsq(const S* __restrict__ buf, Geom g, Phys ph, double* __restrict__ partials)
+{
+    __shared__ double red[4][MLP_NIN];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double v[MLP_NIN] = {};
+    if (x < g.nx && y < g.ny) {
+        NodeIdx d;
+        node_idx(g, x, y, z, d);
+        float s[19];
+        gather<LatD3Q19, S, P, WALLS>(buf, g.stride, d, s);
+        float Fx, Fy, Fz;
+        node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
+        CMState<float> st;
+        pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
+        float xin[MLP_NIN];
+        mlp_features(st, xin);
+#pragma unroll
+        for (int k = 0; k < MLP_NIN; ++k) v[k] = (double)xin[k] * (double)xin[k];
+    }
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+#pragma unroll
+    for (int k = 0; k < MLP_NIN; ++k) {
+        double a = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6][k] = a;
+    }
+    __syncthreads();
+    if (tid < MLP_NIN) {
+        double t = 0.0;
+        for (int i = 0; i < (int)((blockDim.x * blockDim.y + 63) / 64); ++i) t += red[i][tid];
+        partials[(int64_t)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) * MLP_NIN + tid] = t;
+    }
+}
+
+// out[k] = sum over blocks of partials[block][k], k < 11 (FP64, fixed order)
+__global__ void k_sum_features(const double* __restrict__ partials, int nblocks, double* __restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= MLP_NIN) return;
+    double t = 0.0;
+    for (int b = 0; b < nblocks; ++b) t += partials[(int64_t)b * MLP_NIN + k];
+    out[k] = t;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+void launch_feature_sumsq(int precision, int pattern, bool walls, const void* buf, const Geom& g, const Phys& ph,
+                          double* partials, double* out, int nblocks, dim3 grid, dim3 block, hipStream_t st)
+{
+#define LBM_FEAT(S_)                                                                                              \
+    switch (pattern) {                                                                                            \
+    case AB:                                                                                                      \
+        if (walls) hipLaunchKernelGGL((k_feature_sumsq<S_, AB, true>), grid, block, 0, st, (const S_*)buf, g, ph, partials); \
+        else hipLaunchKernelGGL((k_feature_sumsq<S_, AB, false>), grid, block, 0, st, (const S_*)buf, g, ph, partials); \
+        break;                                                                                                    \
+    case AA_EVEN:                                                                                                 \
+        if (walls) hipLaunchKernelGGL((k_feature_sumsq<S_, AA_EVEN, true>), grid, block, 0, st, (const S_*)buf, g, ph, partials); \
+        else hipLaunchKernelGGL((k_feature_sumsq<S_, AA_EVEN, false>), grid, block, 0, st, (const S_*)buf, g, ph, partials); \
+        break;                                                                                                    \
+    default:                                                                                                      \
+        if (walls) hipLaunchKernelGGL((k_feature_sumsq<S_, AA_ODD, true>), grid, block, 0, st, (const S_*)buf, g, ph, partials); \
+        else hipLaunchKernelGGL((k_feature_sumsq<S_, AA_ODD, false>), grid, block, 0, st, (const S_*)buf, g, ph, partials); \
+    }
+    switch (precision) {
+    case PREC_FP32: LBM_FEAT(float); break;
+    case PREC_FP16: LBM_FEAT(_Float16); break;
+    default: LBM_FEAT(bf16_t); break;
+    }
+#undef LBM_FEAT
+    hipLaunchKernelGGL(k_sum_features, dim3(1), dim3(64), 0, st, partials, nblocks, out);
+}
+
+template <class S>
+static void step_mlp_s(int pattern, bool walls, bool nt, const void* src, void* dst, const Geom& g, const Phys& ph,
+                       const void* net, uint32_t* fb, dim3 grid, dim3 block, hipStream_t st)
+{
+    const S* a = (const S*)src;
+    S* b = (S*)dst;
+    const MlpPacked* w = (const MlpPacked*)net;
+#define LBM_MLP_STEP(P, W, NT_)                                                                       \
+    hipLaunchKernelGGL((k_step_mlp<S, P, W, NT_>), grid, block, 0, st, a, b, g, ph, w, fb)
+#define LBM_MLP_NT(P, W) \
+    if (nt) LBM_MLP_STEP(P, W, true); else LBM_MLP_STEP(P, W, false)
+#define LBM_MLP_W(P) \
+    if (walls) { LBM_MLP_NT(P, true); } else { LBM_MLP_NT(P, false); }
+    switch (pattern) {
+    case AB: LBM_MLP_W(AB); break;
+    case AA_EVEN: LBM_MLP_W(AA_EVEN); break;
+    default: LBM_MLP_W(AA_ODD); break;
+    }
+#undef LBM_MLP_W
+#undef LBM_MLP_NT
+#undef LBM_MLP_STEP
+}
+
+void launch_step_mlp(int precision, int pattern, bool walls, bool nt, const void* src, void* dst, const Geom& g,
+                     const Phys& ph, const void* net, uint32_t* fb_partials, dim3 grid, dim3 block, hipStream_t st)
+{
+    switch (precision) {
+    case PREC_FP32: step_mlp_s<float>(pattern, walls, nt, src, dst, g, ph, net, fb_partials, grid, block, st); break;
+    case PREC_FP16: step_mlp_s<_Float16>(pattern, walls, nt, src, dst, g, ph, net, fb_partials, grid, block, st); break;
+    default: step_mlp_s<bf16_t>(pattern, walls, nt, src, dst, g, ph, net, fb_partials, grid, block, st); break;
+    }
+}
+
+void launch_train_loss(const float* post, const Geom& g, float rho0, const float* target, const float* inv_sigma,
+                       float* gbuf, double* loss_partials, dim3 grid, dim3 block, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_train_loss, grid, block, 0, st, post, g, rho0, target, inv_sigma, gbuf, loss_partials);
+}
+
+void launch_train_backward(const float* state, const float* gbuf, const Geom& g, float rho0, const void* net,
+                           float* grad_partials, hipStream_t st)
+{
+    const dim3 grid((g.nx + 63) / 64, g.ny, g.nz);
+    hipLaunchKernelGGL(k_train_backward, grid, dim3(64), 0, st, state, gbuf, g, rho0, (const MlpPacked*)net,
+                       grad_partials);
+}
+
+void launch_reduce_grad(const float* partials, int nparts, double* grad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_grad, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, partials, nparts, grad);
+}
+
+void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partials, n, out);
+}
+
+void launch_adam(float* theta, float* m1, float* m2, const double* grad, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, theta, m1, m2, grad, lr, b1, b2, eps, c1,
+                       c2);
+}
+
+void launch_mlp_pack(const float* theta, const float* inv_scale, void* packed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(256), 0, st, theta, inv_scale, (MlpPacked*)packed);
+}
+
+void launch_project_q27(const double* f27, int64_t N, double* f19, float* mom, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_project_q27, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, f27, N, f19, mom);
+}
+
+size_t mlp_packed_bytes() { return sizeof(MlpPacked); }
+
+} // namespace lbm

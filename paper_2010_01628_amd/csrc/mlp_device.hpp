@@ -1,0 +1,189 @@
+// Learned higher-order relaxation rates: a per-node MLP on BF16 MFMA.
+//
+// Network (not in the paper; it replaces the fixed rate 1 of the CMs k10..k18
+// of Sec. II.B): 11 inputs -> 32 tanh -> 32 tanh -> 9 linear outputs z,
+// omega_hi = 1 + z; any rate outside (0, 2) sends the node back to the
+// paper's rates.  Inputs: rho - 1, (k4 - rho)/rho, k10..k15/rho and
+// (k16..k18 - rho/9)/rho, each times a fixed inverse scale.
+//
+// One wavefront evaluates the network for its 64 nodes (one per lane) with
+// v_mfma_f32_32x32x8bf16_1k: every layer is Y[64 x 32] = X[64 x K] W^T[K x 32]
+// as two 32-row blocks.  MFMA operand layout (lane l, v = 0..3):
+//   A[l % 32][4 (l / 32) + v],  B[4 (l / 32) + v][l % 32],
+//   D: acc[r] = D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+// Activations move between the accumulator layout and the operand layout
+// through per-wavefront LDS tiles (rows = nodes, bf16).  Products take BF16
+// operands and accumulate in FP32; biases, tanh and the rates are FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int MLP_NIN = 11, MLP_NH = 32, MLP_NOUT = 9;
+constexpr int MLP_NPARAM = MLP_NH * MLP_NIN + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NOUT * MLP_NH + MLP_NOUT;
+// offsets of the flat FP32 parameter vector: W1[32][11] b1[32] W2[32][32] b2[32] W3[9][32] b3[9]
+constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 352, MLP_OFF_W2 = 384, MLP_OFF_B2 = 1408, MLP_OFF_W3 = 1440,
+              MLP_OFF_B3 = 1728;
+static_assert(MLP_OFF_B3 + MLP_NOUT == MLP_NPARAM, "parameter layout");
+
+// Packed network as the kernels read it (built by k_mlp_pack from the FP32
+// master parameters).  Matrices are bf16 [row][col], zero padded to 32 x 32
+// (W1 to 32 x 16); the transposed copies serve the backward products.
+struct MlpPacked {
+    // inference part (what the step kernel stages in LDS)
+    uint16_t w1[32 * 16]; // [out][in]
+    uint16_t w2[32 * 32]; // [out][in]
+    uint16_t w3[32 * 32]; // [out (9 used)][in]
+    float b1[32], b2[32], b3[32];
+    float inv_scale[16];
+    // transposed copies for the backward pass
+    uint16_t w2t[32 * 32]; // [in][out]
+    uint16_t w3t[32 * 32]; // [in][out (9 used)]
+};
+constexpr int MLP_INFER_WORDS = (int)(__builtin_offsetof(MlpPacked, w2t) / 4);
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__host__ __device__ inline uint16_t f32_to_bf16(float f)
+{
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t b)
+{
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// tanh through exp: tanh x = 1 - 2 / (exp(2x) + 1).  The result is rounded
+// to bf16 before it is used, far coarser than this formula's error.
+__device__ inline float tanh_fast(float x)
+{
+    const float e = __expf(2.0f * x);
+    return 1.0f - 2.0f / (e + 1.0f);
+}
+
+// LDS tile of 64 rows (nodes) of bf16; stride 36 keeps 8-byte alignment and
+// halves bank conflicts of column-parallel reads.
+constexpr int MLP_LDS_STRIDE = 36;
+constexpr int MLP_TILE = 64 * MLP_LDS_STRIDE; // uint16 elements per tile
+
+__device__ inline bf16x4_t lds4(const uint16_t* p) { return *reinterpret_cast<const bf16x4_t*>(p); }
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Y = X W^T over one 32-row block: X rows [rb*32, rb*32+32) of a tile (K
+// columns), W [32][kw] bf16 row-major (rows = outputs).  K multiple of 8.
+template <int K>
+__device__ inline f32x16_t mfma_xwT(const uint16_t* xtile, int rb, const uint16_t* w, int kw)
+{
+    const int l = lane_id();
+    f32x16_t acc = {0};
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        const bf16x4_t a = lds4(xtile + (rb * 32 + (l & 31)) * MLP_LDS_STRIDE + k0 + 4 * (l >> 5));
+        const bf16x4_t b = lds4(w + (l & 31) * kw + k0 + 4 * (l >> 5));
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Row (node) index within the 64-row tile of accumulator register r.
+__device__ inline int acc_row(int rb, int r) { return rb * 32 + 8 * (r >> 2) + 4 * (lane_id() >> 5) + (r & 3); }
+
+// Forward pass for the 64 nodes of this wavefront.  x: this lane's 11 raw
+// features.  Tiles: tx (inputs), th1, th2 (hidden activations, kept for the
+// backward pass), tz (outputs as floats, 64 x 9).  On return z holds this
+// lane's 9 outputs.  Must be called by all 64 lanes.
+__device__ inline void mlp_forward_wave(const MlpPacked& W, uint16_t* tx, uint16_t* th1, uint16_t* th2, float* tz,
+                                        const float x[MLP_NIN], float z[MLP_NOUT])
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tx[l * MLP_LDS_STRIDE + k] = k < MLP_NIN ? f32_to_bf16(x[k] * W.inv_scale[k]) : 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const f32x16_t acc = mfma_xwT<16>(tx, rb, W.w1, 16);
+        const float bias = W.b1[l & 31];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) th1[acc_row(rb, r) * MLP_LDS_STRIDE + (l & 31)] = f32_to_bf16(tanh_fast(acc[r] + bias));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const f32x16_t acc = mfma_xwT<32>(th1, rb, W.w2, 32);
+        const float bias = W.b2[l & 31];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) th2[acc_row(rb, r) * MLP_LDS_STRIDE + (l & 31)] = f32_to_bf16(tanh_fast(acc[r] + bias));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const f32x16_t acc = mfma_xwT<32>(th2, rb, W.w3, 32);
+        if ((l & 31) < MLP_NOUT) {
+            const float bias = W.b3[l & 31];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) tz[acc_row(rb, r) * MLP_NOUT + (l & 31)] = acc[r] + bias;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int j = 0; j < MLP_NOUT; ++j) z[j] = tz[l * MLP_NOUT + j];
+}
+
+// rates 1 + z, or the paper's rates (all 1) when any leaves (0, 2); returns
+// true on fallback.
+__device__ inline bool mlp_rates(const float z[MLP_NOUT], float rates[MLP_NOUT])
+{
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        const float w = 1.0f + z[j];
+        bad = bad || !(w > 0.0f && w < 2.0f);
+        rates[j] = w;
+    }
+    if (bad)
+#pragma unroll
+        for (int j = 0; j < MLP_NOUT; ++j) rates[j] = 1.0f;
+    return bad;
+}
+
+// Weight-gradient product over the 64 nodes of the wavefront:
+// G[i][j] += sum_n A[n][i] B[n][j], A and B tiles (rows = nodes), i, j < 32.
+// Returns the accumulator (D layout: row i = 8(r/4) + 4(l/32) + r%4, col j = l%32).
+__device__ inline f32x16_t mfma_AtB(const uint16_t* ta, const uint16_t* tb)
+{
+    const int l = lane_id();
+    f32x16_t acc = {0};
+#pragma unroll
+    for (int n0 = 0; n0 < 64; n0 += 8) {
+        bf16x4_t a, b;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int n = n0 + 4 * (l >> 5) + v;
+            a[v] = (short)ta[n * MLP_LDS_STRIDE + (l & 31)];
+            b[v] = (short)tb[n * MLP_LDS_STRIDE + (l & 31)];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+} // namespace lbm

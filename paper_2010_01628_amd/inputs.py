@@ -98,3 +98,44 @@ def random_lattice_fields(nx: int, ny: int, nz: int, seed: int, umax: float = 0.
     u = np.stack([umax * uniform_pm1(seed, nodes, d) for d in range(3)])
     F = np.stack([fmax * uniform_pm1(seed + 1, nodes, d) for d in range(3)])
     return rho, u, F
+
+
+def random_phase_field(L: int, u_rms: float = 0.04, seed: int = 0, k0: float = 4.0, shape=None):
+    """Solenoidal velocity field with random phases and energy spectrum
+    E(k) ~ k^4 exp(-2 (k/k0)^2) on a periodic box, rescaled so that
+    sqrt(<|u|^2>/3) = u_rms; rho = 1.  Built from seeded white noise filtered
+    in Fourier space (numpy FFT) and projected onto zero divergence."""
+    nx, ny, nz = shape if shape is not None else (L, L, L)
+    rng = np.random.default_rng(seed)
+    noise = rng.standard_normal((3, nz, ny, nx))
+    U = np.fft.fftn(noise, axes=(1, 2, 3))
+    kz = np.fft.fftfreq(nz) * nz
+    ky = np.fft.fftfreq(ny) * ny
+    kx = np.fft.fftfreq(nx) * nx
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    k2 = KX ** 2 + KY ** 2 + KZ ** 2
+    k = np.sqrt(k2)
+    # white noise has a flat |U|^2 per mode; E(k) = 4 pi k^2 |U(k)|^2 ~ k^4 exp(-2 (k/k0)^2)
+    amp = np.where(k > 0, k * np.exp(-(k / k0) ** 2), 0.0)
+    U *= amp[None]
+    kd = np.where(k2 > 0, k2, 1.0)
+    div = (KX * U[0] + KY * U[1] + KZ * U[2]) / kd
+    U[0] -= KX * div
+    U[1] -= KY * div
+    U[2] -= KZ * div
+    u = np.real(np.fft.ifftn(U, axes=(1, 2, 3)))
+    u -= u.mean(axis=(1, 2, 3), keepdims=True)
+    u *= u_rms / np.sqrt(np.mean(np.sum(u ** 2, axis=0)) / 3.0)
+    return np.ones((nz, ny, nx)), u
+
+
+def ensemble_boxes(n_boxes: int = 64, sizes=(48, 64, 96), nu_range=(1e-4, 1e-3), seed: int = 2010):
+    """Seeded box list of the ensemble workload: side lengths drawn from
+    `sizes`, viscosities log-uniform in nu_range.  Returns [(L, nu, field_seed)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(n_boxes):
+        L = int(rng.choice(sizes))
+        nu = float(np.exp(rng.uniform(np.log(nu_range[0]), np.log(nu_range[1]))))
+        out.append((L, nu, seed * 1000 + b))
+    return out

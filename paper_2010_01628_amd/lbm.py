@@ -84,8 +84,26 @@ def lib():
         L.lbm_destroy.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_abi_version.restype = i32
+        fp, dp = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
+        L.lbm_mlp_create.argtypes = [fp, fp, vp, ctypes.POINTER(vp)]
+        L.lbm_mlp_set_params.argtypes = [vp, fp]
+        L.lbm_mlp_get_params.argtypes = [vp, fp]
+        L.lbm_mlp_set_scales.argtypes = [vp, fp]
+        L.lbm_mlp_destroy.argtypes = [vp]
+        L.lbm_set_mlp.argtypes = [vp, vp]
+        L.lbm_fallback_count.argtypes = [vp]
+        L.lbm_fallback_count.restype = i64
+        L.lbm_mlp_zero_grad.argtypes = [vp]
+        L.lbm_mlp_accumulate_grad.argtypes = [vp, vp, vp, dp, dp]
+        L.lbm_mlp_get_grad.argtypes = [vp, dp]
+        L.lbm_mlp_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.lbm_feature_rms.argtypes = [vp, dp]
+        L.lbm_project_q27.argtypes = [vp, i64, vp, vp, vp]
         for name in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_get_populations",
-                     "lbm_set_populations", "lbm_destroy"):
+                     "lbm_set_populations", "lbm_destroy", "lbm_mlp_create", "lbm_mlp_set_params",
+                     "lbm_mlp_get_params", "lbm_mlp_set_scales", "lbm_mlp_destroy", "lbm_set_mlp",
+                     "lbm_mlp_zero_grad", "lbm_mlp_accumulate_grad", "lbm_mlp_get_grad", "lbm_mlp_adam_step",
+                     "lbm_feature_rms", "lbm_project_q27"):
             getattr(L, name).restype = i32
         if L.lbm_abi_version() != ABI_VERSION:
             raise ImportError("liblbm.so ABI version mismatch")
@@ -142,6 +160,123 @@ def lbm_device_bytes(h: int) -> int:
 
 def lbm_destroy(h: int) -> None:
     _check(lib().lbm_destroy(h))
+
+
+MLP_NPARAM = 1737
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lbm_mlp_create(params, scales, stream=None) -> int:
+    m = ctypes.c_void_p()
+    pp = None if params is None else _fptr(np.ascontiguousarray(params, dtype=np.float32))
+    sc = np.ascontiguousarray(scales, dtype=np.float32)
+    _check(lib().lbm_mlp_create(pp, _fptr(sc), ctypes.c_void_p(stream or 0), ctypes.byref(m)))
+    return m.value
+
+
+def lbm_mlp_set_params(m, params):
+    _check(lib().lbm_mlp_set_params(m, _fptr(np.ascontiguousarray(params, dtype=np.float32))))
+
+
+def lbm_mlp_get_params(m):
+    out = np.zeros(MLP_NPARAM, dtype=np.float32)
+    _check(lib().lbm_mlp_get_params(m, _fptr(out)))
+    return out
+
+
+def lbm_mlp_set_scales(m, scales):
+    _check(lib().lbm_mlp_set_scales(m, _fptr(np.ascontiguousarray(scales, dtype=np.float32))))
+
+
+def lbm_mlp_destroy(m):
+    _check(lib().lbm_mlp_destroy(m))
+
+
+def lbm_set_mlp(h, m):
+    _check(lib().lbm_set_mlp(h, m))
+
+
+def lbm_fallback_count(h) -> int:
+    v = lib().lbm_fallback_count(h)
+    if v < 0:
+        _check(int(v))
+    return int(v)
+
+
+def lbm_mlp_zero_grad(m):
+    _check(lib().lbm_mlp_zero_grad(m))
+
+
+def lbm_mlp_accumulate_grad(m, h, target_ptr, sigma) -> float:
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    loss = np.zeros(1)
+    _check(lib().lbm_mlp_accumulate_grad(m, h, target_ptr, _dptr(sig), _dptr(loss)))
+    return float(loss[0])
+
+
+def lbm_mlp_get_grad(m):
+    out = np.zeros(MLP_NPARAM)
+    _check(lib().lbm_mlp_get_grad(m, _dptr(out)))
+    return out
+
+
+def lbm_mlp_adam_step(m, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().lbm_mlp_adam_step(m, float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def lbm_feature_rms(h):
+    out = np.zeros(11)
+    _check(lib().lbm_feature_rms(h, _dptr(out)))
+    return out
+
+
+def lbm_project_q27(f27_ptr, n, f19_ptr, moments_ptr, stream=None):
+    _check(lib().lbm_project_q27(f27_ptr, int(n), f19_ptr, moments_ptr, ctypes.c_void_p(stream or 0)))
+
+
+class Mlp:
+    """Owns one lbm_mlp (learned higher-order rates)."""
+
+    def __init__(self, params=None, scales=None, stream=None):
+        import torch
+
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.m = lbm_mlp_create(params, np.ones(11) if scales is None else scales, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "m", None):
+            lbm_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    params = property(lambda self: lbm_mlp_get_params(self.m))
+
+    def set_params(self, p):
+        lbm_mlp_set_params(self.m, p)
+
+    def set_scales(self, s):
+        lbm_mlp_set_scales(self.m, s)
+
+    def zero_grad(self):
+        lbm_mlp_zero_grad(self.m)
+
+    def grad(self):
+        return lbm_mlp_get_grad(self.m)
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        lbm_mlp_adam_step(self.m, lr, beta1, beta2, eps)
 
 
 # -- convenience wrapper -----------------------------------------------------
@@ -239,6 +374,22 @@ class Lattice:
         assert ff.numel() == self.q * self.N
         lbm_set_populations(self.h, ff.data_ptr(), True)
         self.stream.synchronize()
+
+    def attach_mlp(self, mlp):
+        lbm_set_mlp(self.h, None if mlp is None else mlp.m)
+        self._mlp = mlp
+
+    def fallback_count(self):
+        return lbm_fallback_count(self.h)
+
+    def feature_rms(self):
+        return lbm_feature_rms(self.h)
+
+    def accumulate_grad(self, mlp, target, sigma):
+        """target: device float32 tensor (10, nz, ny, nx)."""
+        t = target.contiguous()
+        assert t.dtype == self.torch.float32 and t.numel() == 10 * self.N
+        return lbm_mlp_accumulate_grad(mlp.m, self.h, t.data_ptr(), sigma)
 
     @property
     def step_count(self):

@@ -1,0 +1,223 @@
+"""Learned higher-order rates on the GPU (BF16 MFMA) against the FP64 oracle
+run with the same BF16-rounded weights and BF16 activation rounding."""
+import numpy as np
+import pytest
+
+from gpu_helpers import rel_l2, say
+from paper_2010_01628_amd import inputs
+from paper_2010_01628_amd import lbm as L
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+
+
+def gpu_weights(orc, P):
+    """What the GPU uses: weight matrices rounded to bf16, biases to float32."""
+    Q = np.asarray(P, dtype=np.float32).astype(np.float64)
+    u = orc.mlp.unpack(Q)
+    for w in ("W1", "W2", "W3"):
+        flat = u[w].reshape(-1)
+        flat[:] = [orc.mlp.bf16(v) for v in flat]
+    return Q
+
+
+def noneq_state(orc, nx, ny, nz, seed, amp=0.02):
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=seed, umax=0.05)
+    rng = np.random.default_rng(seed)
+    return orc.init(rho, u) * (1 + amp * rng.uniform(-1, 1, (19, nz, ny, nx)))
+
+
+def make_lattice(nx, ny, nz, f, omega, **kw):
+    p = L.make_params(nx, ny, nz, precision="fp32", streaming=kw.pop("streaming", "ab"), omega=omega, **kw)
+    lat = L.Lattice(p)
+    lat.init(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    lat.set_populations(f)
+    return lat
+
+
+SCALES = np.array([0.05, 0.02, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3])
+
+
+@pytest.mark.parametrize("streaming,walls", [("ab", False), ("aa", True)])
+def test_mlp_step_matches_oracle(orc, streaming, walls):
+    nx, ny, nz = 16, 12, 8
+    say(f"mlp step parity {streaming} walls={walls}")
+    rng = np.random.default_rng(1)
+    P = 0.15 * rng.normal(size=L.MLP_NPARAM)
+    f0 = noneq_state(orc, nx, ny, nz, 3)
+    om = 1.85
+    mlp = L.Mlp(P, SCALES)
+    lat = make_lattice(nx, ny, nz, f0, om, streaming=streaming, walls_y=walls)
+    f0r = lat.get_populations().cpu().numpy()  # FP32-rounded start, shared with the oracle
+    lat.attach_mlp(mlp)
+    Pg = gpu_weights(orc, P)
+    g1 = None
+    for steps in (1, 4):
+        lat.step(1 if steps == 1 else 3)
+        g = lat.get_populations().cpu().numpy()
+        o, fb = orc.mlp.run(f0r, steps, om, Pg, SCALES, walls_y=walls, bf16=True)
+        err = np.abs(g - o).max()
+        say(f"  {steps} steps: max |f_gpu - f_oracle| = {err:.3e}, oracle fallbacks {fb}")
+        assert err < (2e-7 if steps == 1 else 1e-6)
+        if steps == 1:
+            g1 = g
+    assert lat.fallback_count() == 0
+    assert g1 is not None
+    lat.close()
+    mlp.close()
+
+
+def test_fallback_is_plain_scheme_bitwise(orc):
+    nx, ny, nz = 20, 9, 7
+    f0 = noneq_state(orc, nx, ny, nz, 5)
+    P = np.zeros(L.MLP_NPARAM)
+    P[-9:] = 1.5  # every output rate 2.5: every node falls back
+    mlp = L.Mlp(P, SCALES)
+    a = make_lattice(nx, ny, nz, f0, 1.7)
+    b = make_lattice(nx, ny, nz, f0, 1.7)
+    a.attach_mlp(mlp)
+    a.step(5)
+    b.step(5)
+    fa = a.get_populations().cpu().numpy()
+    fb_ = b.get_populations().cpu().numpy()
+    assert np.array_equal(fa, fb_)
+    assert a.fallback_count() == 5 * nx * ny * nz
+    a.close()
+    b.close()
+    mlp.close()
+
+
+def test_zero_network_is_paper_scheme(orc):
+    nx, ny, nz = 16, 8, 6
+    f0 = noneq_state(orc, nx, ny, nz, 7)
+    mlp = L.Mlp(None, SCALES)
+    a = make_lattice(nx, ny, nz, f0, 1.9)
+    b = make_lattice(nx, ny, nz, f0, 1.9)
+    a.attach_mlp(mlp)
+    a.step(4)
+    b.step(4)
+    assert np.abs(a.get_populations().cpu().numpy() - b.get_populations().cpu().numpy()).max() < 1e-7
+    assert a.fallback_count() == 0
+    a.close()
+    b.close()
+    mlp.close()
+
+
+def test_gradient_matches_oracle(orc):
+    """GPU loss and gradient (BF16 products, FP32 accumulation, FP64 sums)
+    against the oracle's exact FP64 backpropagation of the same model."""
+    import torch
+
+    nx, ny, nz = 16, 8, 8
+    rng = np.random.default_rng(11)
+    P = 0.2 * rng.normal(size=L.MLP_NPARAM)
+    f0 = noneq_state(orc, nx, ny, nz, 9)
+    om = 1.8
+    mlp = L.Mlp(P, SCALES)
+    lat = make_lattice(nx, ny, nz, f0, om)
+    f0r = lat.get_populations().cpu().numpy()
+    lat.attach_mlp(mlp)
+    rho = f0r.sum(axis=0)
+    c, _, _ = orc.tables()
+    mono = np.stack([np.ones(19), c[:, 0], c[:, 1], c[:, 2], c[:, 0] ** 2, c[:, 1] ** 2, c[:, 2] ** 2,
+                     c[:, 0] * c[:, 1], c[:, 0] * c[:, 2], c[:, 1] * c[:, 2]])
+    target = np.einsum("ki,iabc->kabc", mono, f0r) + 1e-3 * rng.normal(size=(10, nz, ny, nx))
+    sigma = np.array([1e-3, 1e-2, 1e-2, 1e-2, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3])
+    mlp.zero_grad()
+    tgt = torch.from_numpy(target.astype(np.float32)).cuda()
+    loss = lat.accumulate_grad(mlp, tgt, sigma)
+    g = mlp.grad()
+    Pg = gpu_weights(orc, P)
+    tq = target.astype(np.float32).astype(np.float64)
+    lo, go, fb = orc.mlp.loss_grad(f0r, tq, om, Pg, SCALES, sigma, bf16=True)
+    say(f"  loss gpu {loss:.6e} oracle {lo:.6e}; fallbacks {fb}")
+    assert fb == 0
+    assert abs(loss - lo) / lo < 1e-4
+    err = np.linalg.norm(g - go) / np.linalg.norm(go)
+    cos = g @ go / (np.linalg.norm(g) * np.linalg.norm(go))
+    say(f"  gradient rel L2 err {err:.3e}, cosine {cos:.6f}")
+    assert err < 5e-2 and cos > 0.998
+    assert lat.step_count == 0  # the state is not advanced
+    lat.close()
+    mlp.close()
+
+
+def test_projection_q27_to_q19(orc):
+    """GPU projection = solve of the 19 shared raw moments (oracle tables, numpy)."""
+    import torch
+
+    n = 12
+    rho, u = inputs.random_phase_field(n, 0.04, seed=3)
+    p = L.make_params(n, n, n, precision="fp64", q=27, omega=1.9)
+    lat = L.Lattice(p)
+    lat.init(rho, u)
+    lat.step(3)
+    f27 = lat.get_populations()
+    N = n ** 3
+    f19 = torch.empty((19, N), dtype=torch.float64, device="cuda")
+    mom = torch.empty((10, N), dtype=torch.float32, device="cuda")
+    L.lbm_project_q27(f27.data_ptr(), N, f19.data_ptr(), mom.data_ptr(), lat.stream.cuda_stream)
+    torch.cuda.synchronize()
+    c27, _, _ = orc.d3q27.tables()
+    c19, _, _ = orc.tables()
+    monos = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (0, 2, 0), (0, 0, 2), (1, 1, 0), (1, 0, 1),
+             (0, 1, 1), (2, 1, 0), (1, 2, 0), (2, 0, 1), (1, 0, 2), (0, 2, 1), (0, 1, 2), (2, 2, 0), (2, 0, 2),
+             (0, 2, 2)]
+    A27 = np.array([[c27[i, 0] ** a * c27[i, 1] ** b * c27[i, 2] ** d for i in range(27)] for a, b, d in monos])
+    A19 = np.array([[c19[i, 0] ** a * c19[i, 1] ** b * c19[i, 2] ** d for i in range(19)] for a, b, d in monos])
+    F27 = f27.reshape(27, -1).cpu().numpy()
+    want = np.linalg.solve(A19, A27 @ F27)
+    assert np.abs(f19.cpu().numpy() - want).max() < 1e-14
+    assert np.allclose(mom.cpu().numpy(), (A27 @ F27)[:10], rtol=0, atol=1e-6)
+    lat.close()
+
+
+def test_training_reduces_loss(orc):
+    """Adam on the GPU-computed gradient lowers the one-step loss against the
+    projected D3Q27 evolution on a 32^3 random-phase field."""
+    import torch
+
+    n, nu = 32, 5e-4
+    om = inputs.omega_from_nu(nu)
+    rho, u = inputs.random_phase_field(n, 0.04, seed=5)
+    N = n ** 3
+    p27 = L.make_params(n, n, n, precision="fp64", q=27, omega=om)
+    q27 = L.Lattice(p27)
+    q27.init(rho, u)
+    q27.step(20)
+    f27 = q27.get_populations()
+    f19 = torch.empty((19, N), dtype=torch.float64, device="cuda")
+    L.lbm_project_q27(f27.data_ptr(), N, f19.data_ptr(), None, q27.stream.cuda_stream)
+    q27.step(1)
+    f27b = q27.get_populations()
+    tgt = torch.empty((10, N), dtype=torch.float32, device="cuda")
+    L.lbm_project_q27(f27b.data_ptr(), N, None, tgt.data_ptr(), q27.stream.cuda_stream)
+    torch.cuda.synchronize()
+    lat = L.Lattice(L.make_params(n, n, n, precision="fp32", omega=om))
+    lat.init(rho, u)
+    lat.set_populations(f19)
+    rms = lat.feature_rms()
+    say(f"  feature rms {np.array2string(rms, precision=2)}")
+    scales = np.maximum(rms, 1e-12)
+    mlp = L.Mlp(None, scales)
+    lat.attach_mlp(mlp)
+    sigma = np.array([1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4])
+    losses = []
+    for it in range(30):
+        mlp.zero_grad()
+        losses.append(lat.accumulate_grad(mlp, tgt, sigma))
+        mlp.adam_step(3e-3)
+    say(f"  loss {losses[0]:.6e} -> {losses[-1]:.6e}")
+    assert losses[-1] < losses[0]
+    assert lat.fallback_count() >= 0
+    lat.close()
+    q27.close()
+    mlp.close()
