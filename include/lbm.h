@@ -206,6 +206,43 @@ int lbm_feature_rms(lbm_handle *h, double rms[11]);
  * float[10*n], may be NULL).  Ordered on `stream`. */
 int lbm_project_q27(const double *f27, int64_t n, double *f19, float *moments, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Ensembles: many independent periodic cubic boxes (different sides and
+ * viscosities, no force) advanced together, one persistent launch per step
+ * over a (box, 256-node tile) work list; the step loop is captured in a HIP
+ * graph and replayed.  Same collision as a single lattice (Sec. II.B for q =
+ * 19, App. D for q = 27); A-B streaming; FP32 or FP64 storage.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_ensemble lbm_ensemble;
+
+typedef struct {
+    int32_t n;    /* box side (nodes), 2..1024 */
+    double omega; /* shear rate of the box, in (0, 2) */
+} lbm_box;
+
+/* stream: hipStream_t, or NULL for a stream the ensemble creates and owns
+ * (the null stream cannot be captured into a graph).  Boxes start at rest. */
+int lbm_ensemble_create(const lbm_box *boxes, int32_t nboxes, int32_t q, int32_t precision, void *stream,
+                        lbm_ensemble **out);
+/* f = f_eq(rho, u) in box `box` (rho: double[n^3], u: double[3 n^3], host or device). */
+int lbm_ensemble_init(lbm_ensemble *e, int32_t box, const double *rho, const double *u, int on_device);
+/* Learned rates in every box (D3Q19, FP32); NULL detaches. */
+int lbm_ensemble_set_mlp(lbm_ensemble *e, const lbm_mlp *m);
+int lbm_ensemble_step(lbm_ensemble *e, int64_t nsteps);
+/* Per-box FP64 kinetic energy 1/2 sum rho |u|^2 and mass sum rho (host
+ * double[nboxes] each, either may be NULL; synchronizes). */
+int lbm_ensemble_energy(lbm_ensemble *e, double *ke, double *mass);
+int lbm_ensemble_get_populations(lbm_ensemble *e, int32_t box, double *f, int on_device);
+int64_t lbm_ensemble_nodes(const lbm_ensemble *e);
+int64_t lbm_ensemble_step_count(const lbm_ensemble *e);
+int64_t lbm_ensemble_fallback_count(lbm_ensemble *e);
+/* Autotuner: times `trial_steps` steps for each candidate number of
+ * persistent workgroups and keeps the fastest (*grid_out, may be NULL).  It
+ * advances the state by those steps; call it before lbm_ensemble_init (the
+ * rest state is a fixed point). */
+int lbm_ensemble_tune(lbm_ensemble *e, int32_t trial_steps, int32_t *grid_out);
+int lbm_ensemble_destroy(lbm_ensemble *e);
+
 #ifdef __cplusplus
 }
 #endif

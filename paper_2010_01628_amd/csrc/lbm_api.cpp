@@ -38,26 +38,10 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 } // namespace
 
-struct lbm_mlp {
-    hipStream_t stream = nullptr;
-    float* theta = nullptr;     // FP32 master parameters (device)
-    float* m1 = nullptr;        // Adam moments
-    float* m2 = nullptr;
-    double* grad = nullptr;     // accumulated gradient (FP64)
-    float* inv_scale = nullptr; // 16 floats
-    void* packed = nullptr;     // bf16 network for the kernels
-    float* inv_sigma = nullptr; // 10 floats
-    int64_t adam_t = 0;
-    // training scratch, grown on demand
-    float* gbuf = nullptr;
-    int64_t gbuf_elems = 0;
-    float* grad_parts = nullptr;
-    int64_t grad_parts_n = 0;
-    double* loss_parts = nullptr;
-    int64_t loss_parts_n = 0;
-    double* loss_dev = nullptr;
-    double* loss_host = nullptr;
-};
+void lbm_internal_set_error(const char* msg)
+{
+    std::snprintf(g_err, sizeof g_err, "%s", msg);
+}
 
 struct lbm_handle {
     lbm_params p;

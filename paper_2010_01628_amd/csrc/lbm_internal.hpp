@@ -95,3 +95,40 @@ void launch_feature_sumsq(int precision, int pattern, bool walls, const void* bu
 constexpr int NDIAG_OUT = 8;
 
 } // namespace lbm
+
+// Sets the message returned by lbm_last_error() on this thread.
+void lbm_internal_set_error(const char* msg);
+
+// The learned-rate network object behind the opaque lbm_mlp of lbm.h.
+struct lbm_mlp {
+    hipStream_t stream = nullptr;
+    float* theta = nullptr;     // FP32 master parameters (device)
+    float* m1 = nullptr;        // Adam moments
+    float* m2 = nullptr;
+    double* grad = nullptr;     // accumulated gradient (FP64)
+    float* inv_scale = nullptr; // 16 floats
+    void* packed = nullptr;     // bf16 network for the kernels
+    float* inv_sigma = nullptr; // 10 floats
+    int64_t adam_t = 0;
+    // training scratch, grown on demand
+    float* gbuf = nullptr;
+    int64_t gbuf_elems = 0;
+    float* grad_parts = nullptr;
+    int64_t grad_parts_n = 0;
+    double* loss_parts = nullptr;
+    int64_t loss_parts_n = 0;
+    double* loss_dev = nullptr;
+    double* loss_host = nullptr;
+};
+
+
+// ensemble (ensemble.hip)
+namespace lbm {
+void launch_ens_step(int q, int precision, bool mlp, const void* src, void* dst, const void* boxes, const int* tile_box,
+                     int ntiles, float rho0, const void* net, uint32_t* fb, int grid, int block, hipStream_t st);
+void launch_ens_energy(int q, int precision, const void* buf, const void* boxes, const int* tile_box, int ntiles,
+                       int nboxes, const int* tile_count, double rho0, double* tile_out, double* box_out, int grid,
+                       hipStream_t st);
+size_t ens_box_desc_bytes();
+void ens_fill_box_desc(void* out, int L, int tile0, int64_t off, int64_t stride, double omega);
+} // namespace lbm

@@ -99,6 +99,29 @@ def lib():
         L.lbm_mlp_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.lbm_feature_rms.argtypes = [vp, dp]
         L.lbm_project_q27.argtypes = [vp, i64, vp, vp, vp]
+        class _box(ctypes.Structure):
+            _fields_ = [("n", ctypes.c_int32), ("omega", ctypes.c_double)]
+
+        globals()["lbm_box"] = _box
+        BP = ctypes.POINTER(_box)
+        L.lbm_ensemble_create.argtypes = [BP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        L.lbm_ensemble_init.argtypes = [vp, ctypes.c_int32, vp, vp, i32]
+        L.lbm_ensemble_set_mlp.argtypes = [vp, vp]
+        L.lbm_ensemble_step.argtypes = [vp, i64]
+        L.lbm_ensemble_energy.argtypes = [vp, dp, dp]
+        L.lbm_ensemble_get_populations.argtypes = [vp, ctypes.c_int32, vp, i32]
+        L.lbm_ensemble_nodes.argtypes = [vp]
+        L.lbm_ensemble_nodes.restype = i64
+        L.lbm_ensemble_step_count.argtypes = [vp]
+        L.lbm_ensemble_step_count.restype = i64
+        L.lbm_ensemble_fallback_count.argtypes = [vp]
+        L.lbm_ensemble_fallback_count.restype = i64
+        L.lbm_ensemble_tune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.lbm_ensemble_destroy.argtypes = [vp]
+        for name in ("lbm_ensemble_create", "lbm_ensemble_init", "lbm_ensemble_set_mlp", "lbm_ensemble_step",
+                     "lbm_ensemble_energy", "lbm_ensemble_get_populations", "lbm_ensemble_tune",
+                     "lbm_ensemble_destroy"):
+            getattr(L, name).restype = i32
         for name in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_get_populations",
                      "lbm_set_populations", "lbm_destroy", "lbm_mlp_create", "lbm_mlp_set_params",
                      "lbm_mlp_get_params", "lbm_mlp_set_scales", "lbm_mlp_destroy", "lbm_set_mlp",
@@ -277,6 +300,87 @@ class Mlp:
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         lbm_mlp_adam_step(self.m, lr, beta1, beta2, eps)
+
+
+def lbm_ensemble_create(boxes, q=19, precision="fp32", stream=None) -> int:
+    lib()
+    arr = (lbm_box * len(boxes))(*[lbm_box(int(n), float(om)) for n, om in boxes])
+    e = ctypes.c_void_p()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().lbm_ensemble_create(arr, len(boxes), int(q), prec, ctypes.c_void_p(stream or 0), ctypes.byref(e)))
+    return e.value
+
+
+class Ensemble:
+    """Owns one lbm_ensemble: boxes = [(side, omega), ...]."""
+
+    def __init__(self, boxes, q=19, precision="fp32"):
+        import torch
+
+        self.torch = torch
+        self.boxes = list(boxes)
+        self.q = q
+        self.e = lbm_ensemble_create(self.boxes, q, precision, None)
+
+    def close(self):
+        if getattr(self, "e", None):
+            _check(lib().lbm_ensemble_destroy(self.e))
+            self.e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, box, rho, u):
+        t = self.torch
+        n = self.boxes[box][0]
+        r = t.from_numpy(np.ascontiguousarray(rho, dtype=np.float64)).cuda()
+        v = t.from_numpy(np.ascontiguousarray(u, dtype=np.float64)).cuda()
+        assert r.numel() == n ** 3 and v.numel() == 3 * n ** 3
+        t.cuda.synchronize()  # the ensemble works on its own stream
+        _check(lib().lbm_ensemble_init(self.e, int(box), r.data_ptr(), v.data_ptr(), 1))
+        _check(lib().lbm_ensemble_energy(self.e, None, np.zeros(len(self.boxes)).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double))))  # synchronizes before r, v go out of scope
+
+    def set_mlp(self, mlp):
+        _check(lib().lbm_ensemble_set_mlp(self.e, None if mlp is None else mlp.m))
+        self._mlp = mlp
+
+    def step(self, n):
+        _check(lib().lbm_ensemble_step(self.e, int(n)))
+
+    def energy(self):
+        ke = np.zeros(len(self.boxes))
+        mass = np.zeros(len(self.boxes))
+        _check(lib().lbm_ensemble_energy(self.e, _dptr(ke), _dptr(mass)))
+        return ke, mass
+
+    def get_populations(self, box):
+        n = self.boxes[box][0]
+        f = np.zeros((self.q, n, n, n))
+        _check(lib().lbm_ensemble_get_populations(self.e, int(box), f.ctypes.data, 0))
+        return f
+
+    def tune(self, trial_steps=10):
+        g = ctypes.c_int32(0)
+        _check(lib().lbm_ensemble_tune(self.e, int(trial_steps), ctypes.byref(g)))
+        return g.value
+
+    @property
+    def nodes(self):
+        return lib().lbm_ensemble_nodes(self.e)
+
+    @property
+    def step_count(self):
+        return lib().lbm_ensemble_step_count(self.e)
+
+    def fallback_count(self):
+        v = lib().lbm_ensemble_fallback_count(self.e)
+        if v < 0:
+            _check(int(v))
+        return int(v)
 
 
 # -- convenience wrapper -----------------------------------------------------
