@@ -14,7 +14,6 @@ CPU oracle timed on a bounded sample of the same workload on the host.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -25,13 +24,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2010_01628_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2010_01628_amd.traffic import kernel_source_hash as h
+
+    return h()
 
 
 def log(*a):
@@ -42,7 +37,7 @@ def elem_bytes(precision: str) -> int:
     return {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[precision]
 
 
-def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fields):
+def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fields, mlp=None):
     nu = 1e-3
     p = L.make_params(size, size, size, precision=precision, streaming=streaming,
                       omega=inputs.omega_from_nu(nu), force_mode=L.LBM_FORCE_KOLMOGOROV,
@@ -50,6 +45,8 @@ def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fi
     lat = L.Lattice(p)
     rho_d, u_d = fields
     lat.init(rho_d, u_d)
+    if mlp is not None:
+        lat.attach_mlp(mlp)
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = lat.stream
@@ -65,6 +62,7 @@ def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fi
     kernel_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
     _, _, diag = lat.moments(want_fields=False)
     nbytes = lat.device_bytes
+    fallbacks = lat.fallback_count() if mlp is not None else None
     lat.close()
     N = size ** 3
     kms = sorted(kernel_ms)
@@ -82,10 +80,59 @@ def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fi
         "device_bytes": nbytes,
         "sum_rho": diag[0],
         "finite": bool(all(x == x for x in diag)),
+        "fallbacks": fallbacks,
     }
 
 
-def cpu_baseline(inputs, size, seconds_target=20.0):
+def time_ensemble(L, inputs, torch, steps, warmup, mlp):
+    """The 64-box ensemble workload (sides 48/64/96, random-phase fields,
+    u_rms 0.04, nu log-uniform in [1e-4, 1e-3]): MLUPS of plain D3Q19, learned
+    D3Q19 and D3Q27, FP32 storage, one persistent launch per step replayed
+    from a HIP graph."""
+    spec = inputs.ensemble_boxes()
+    boxes = [(n, inputs.omega_from_nu(nu)) for n, nu, _ in spec]
+    fields = [inputs.random_phase_field(n, 0.04, seed=sd) for n, _, sd in spec]
+    out = {}
+    for name, q, net in (("q19", 19, None), ("q19_learned", 19, mlp), ("q27", 27, None)):
+        ens = L.Ensemble(boxes, q=q, precision="fp32")
+        for b, (rho, u) in enumerate(fields):
+            ens.init(b, rho, u)
+        if net is not None:
+            ens.set_mlp(net)
+        ens.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        bpn = 2 * q * 4
+        out[name] = {"mlups": round(ens.nodes * steps / wall / 1e6, 1),
+                     "achieved_GBs": round(ens.nodes * bpn * steps / wall / 1e9, 1),
+                     "algo_bytes_per_node": bpn}
+        if net is not None:
+            out[name]["fallback_rate"] = ens.fallback_count() / float(ens.nodes * (steps + warmup))
+        out["nodes"] = ens.nodes
+        ens.close()
+    out["boxes"] = len(boxes)
+    out["steps"] = steps
+    return out
+
+
+def bench_network(L):
+    """A fixed network for throughput runs: random hidden layers and a small
+    random output layer, so the rates spread around 1 without fallbacks (the
+    cost does not depend on the weights otherwise)."""
+    import numpy as np
+
+    from paper_2010_01628_amd import learned
+
+    P = learned.initial_params(seed=0)
+    P[1440:1728] = np.random.default_rng(1).normal(size=288) * 0.02
+    scales = np.array([0.05, 0.02, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3])
+    return L.Mlp(P, scales)
+
+
+def cpu_baseline(inputs, size, seconds_target=12.0):
     """FP64 oracle (closed-form mode, OpenMP on all host cores) on a bounded
     sample: whole-lattice steps of the same 256^3 workload."""
     import numpy as np
@@ -106,7 +153,7 @@ def cpu_baseline(inputs, size, seconds_target=20.0):
         f, out = out, f
         steps += 1
         el = time.perf_counter() - t0
-        if el > seconds_target / 2 or steps >= 4:
+        if el > seconds_target or steps >= 64:
             break
     N = size ** 3
     return {
@@ -137,8 +184,11 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--streaming", default="ab", choices=["ab", "aa"])
-    ap.add_argument("--variants", default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,fp64:ab",
-                    help="extra precision:streaming pairs to time ('' = none)")
+    ap.add_argument("--variants", default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,fp64:ab,fp32+mlp:ab,fp16+mlp:ab",
+                    help="extra precision[+mlp]:streaming pairs to time ('' = none); +mlp = learned rates")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble workload")
+    ap.add_argument("--mem-check", action="store_true",
+                    help="also run 512^3 AA FP32 and FP16 (device bytes and MLUPS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM counters)")
@@ -179,16 +229,40 @@ def main(argv=None):
     log(f"bench: timing {args.precision}/{args.streaming} {args.steps} steps")
     head = time_variant(L, inputs, torch, size, args.precision, args.streaming, args.steps, args.warmup, fields)
     variants = {}
+    mlp = None
     for spec in [v for v in args.variants.split(",") if v]:
         prec, _, strm = spec.partition(":")
         strm = strm or args.streaming
-        if (prec, strm) == (args.precision, args.streaming):
+        prec, plus, _ = prec.partition("+")
+        if (prec, strm) == (args.precision, args.streaming) and not plus:
             continue
-        log(f"bench: timing variant {prec}/{strm}")
-        variants[f"{prec}_{strm}"] = time_variant(L, inputs, torch, size, prec, strm, max(20, args.steps // 4),
-                                                  max(5, args.warmup // 4), fields)
+        if plus and mlp is None:
+            mlp = bench_network(L)
+        log(f"bench: timing variant {spec}")
+        variants[f"{prec}{'_learned' if plus else ''}_{strm}"] = time_variant(
+            L, inputs, torch, size, prec, strm, max(20, args.steps // 4), max(5, args.warmup // 4), fields,
+            mlp=mlp if plus else None)
     del fields
     torch.cuda.empty_cache()
+    ensemble = None
+    if not args.no_ensemble:
+        if mlp is None:
+            mlp = bench_network(L)
+        log("bench: ensemble workload")
+        ensemble = time_ensemble(L, inputs, torch, max(20, args.steps // 2), max(4, args.warmup // 2), mlp)
+    mem = None
+    if args.mem_check:
+        log("bench: 512^3 memory check")
+        rho, u = inputs.taylor_green_noise(512, 0.05, 1e-4, seed=20101628)
+        f512 = (torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+        del rho, u
+        mem = {}
+        for prec in ("fp32", "fp16"):
+            r = time_variant(L, inputs, torch, 512, prec, "aa", 20, 4, f512)
+            mem[f"{prec}_aa"] = {"mlups": round(r["mlups"], 1), "device_bytes": r["device_bytes"],
+                                 "achieved_GBs": round(r["achieved_GBs"], 1), "finite": r["finite"]}
+        del f512
+        torch.cuda.empty_cache()
 
     traffic = load_traffic(args.precision, args.streaming, size, head["algo_bytes_per_launch"])
     roof = {
@@ -198,7 +272,7 @@ def main(argv=None):
         "unit": "GB/s",
         "frac": round(head["achieved_GBs"] / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": "lbm::k_step (fused gather-collide-store)",
+        "kernel": f"lbm::k_step_{args.streaming} (fused gather-collide-store)",
         "kernel_ms_avg": round(head["kernel_ms_avg"], 5),
         "algo_bytes_per_launch": head["algo_bytes_per_launch"],
     }
@@ -232,7 +306,11 @@ def main(argv=None):
         "variants": {k: {"mlups": round(v["mlups"], 1), "achieved_GBs": round(v["achieved_GBs"], 1),
                          "frac": round(v["achieved_GBs"] / HBM_PEAK_GBS, 4),
                          "kernel_ms_avg": round(v["kernel_ms_avg"], 5),
-                         "speedup_vs_head": round(v["mlups"] / head["mlups"], 3)} for k, v in variants.items()},
+                         "speedup_vs_head": round(v["mlups"] / head["mlups"], 3),
+                         **({"fallbacks": v["fallbacks"]} if v["fallbacks"] is not None else {})}
+                     for k, v in variants.items()},
+        "ensemble": ensemble,
+        "mem_check_512": mem,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line), flush=True)
