@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c"]
+_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c"]
 
 DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
 CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
@@ -93,6 +93,16 @@ def lib():
         L.orc19_step_mlp.restype = ctypes.c_int64
         L.orc19_mlp_loss_grad.argtypes = [i32, i32, i32, dp, dp, f64, dp, dp, dp, i32, dp, i64p]
         L.orc19_mlp_loss_grad.restype = f64
+        L.orc_pf_tables7.argtypes = [ip, dp]
+        L.orc_pf_derivs.argtypes = [dp, dp, dp]
+        L.orc_pf_macro.argtypes = [dp, dp, dp, dp]
+        L.orc_pf_collide_g.argtypes = [f64, dp, f64, f64, dp, dp, dp, dp]
+        L.orc_pf_collide_g.restype = i32
+        L.orc_pf_collide_h.argtypes = [f64, f64, dp, dp, dp, dp]
+        L.orc_pf_step.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp]
+        L.orc_pf_step.restype = i32
+        L.orc_pf_init.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp, dp]
+        L.orc_pf_fields.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
         _lib = L
@@ -423,3 +433,94 @@ class mlp:
         loss = lib().orc19_mlp_loss_grad(nx, ny, nz, _p(f), _p(_f64(target)), float(omega), _p(_f64(P)),
                                          _p(_f64(scales)), _p(_f64(sigma)), int(bf16), _p(g), ctypes.byref(fb))
         return loss, g, int(fb.value)
+
+
+# --------------------------------------------------------------------------
+# Two-phase flow: conservative phase field on D3Q7 coupled to velocity-based
+# D3Q19 flow populations (readings P1-P6 in phase_oracle.c)
+# --------------------------------------------------------------------------
+class phase:
+    """prm = (rho_l, rho_h, sigma, W, M, omega)."""
+
+    @staticmethod
+    def params(rho_l=1.0, rho_h=10.0, sigma=1e-3, W=4.0, M=0.1, omega=1.25):
+        return np.array([rho_l, rho_h, sigma, W, M, omega], dtype=np.float64)
+
+    @staticmethod
+    def tables7():
+        c = np.zeros((7, 3), dtype=np.int32)
+        w = np.zeros(7)
+        lib().orc_pf_tables7(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(w))
+        return c, w
+
+    @staticmethod
+    def derivs(phin):
+        g = np.zeros(3)
+        lap = np.zeros(1)
+        lib().orc_pf_derivs(_p(_f64(phin)), _p(g), _p(lap))
+        return g, float(lap[0])
+
+    @staticmethod
+    def macro(prm, g, phin):
+        """dict of the node's Pi (= p/cs^2), rho, u, F, mu and S0."""
+        out = np.zeros(10)
+        lib().orc_pf_macro(_p(_f64(prm)), _p(_f64(g)), _p(_f64(phin)), _p(out))
+        return {"Pi": out[0], "rho": out[1], "u": out[2:5], "F": out[5:8], "mu": out[8], "S0": out[9]}
+
+    @staticmethod
+    def collide_g(omega, g, Pi, rho, u, F, grad_rho):
+        gs = np.zeros(19)
+        if lib().orc_pf_collide_g(float(omega), _p(_f64(g)), float(Pi), float(rho), _p(_f64(u)), _p(_f64(F)),
+                                  _p(_f64(grad_rho)), _p(gs)) != 0:
+            raise ArithmeticError("singular collision system")
+        return gs
+
+    @staticmethod
+    def collide_h(W, M, h, phin, u):
+        hs = np.zeros(7)
+        lib().orc_pf_collide_h(float(W), float(M), _p(_f64(h)), _p(_f64(phin)), _p(_f64(u)), _p(hs))
+        return hs
+
+    @staticmethod
+    def init(prm, phi, p, u):
+        phi = _f64(phi)
+        nz, ny, nx = phi.shape
+        g = np.zeros((19, nz, ny, nx))
+        h = np.zeros((7, nz, ny, nx))
+        lib().orc_pf_init(nx, ny, nz, _p(_f64(prm)), _p(phi), _p(_f64(p)), _p(_f64(u)), _p(g), _p(h))
+        return g, h
+
+    @staticmethod
+    def step(prm, g, h, gout=None, hout=None):
+        g = _f64(g)
+        h = _f64(h)
+        _, nz, ny, nx = g.shape
+        gout = np.empty_like(g) if gout is None else gout
+        hout = np.empty_like(h) if hout is None else hout
+        rc = lib().orc_pf_step(nx, ny, nz, _p(_f64(prm)), _p(g), _p(h), _p(gout), _p(hout))
+        if rc != 0:
+            raise ArithmeticError("phase-field step failed")
+        return gout, hout
+
+    @staticmethod
+    def run(prm, g, h, nsteps):
+        a, b = _f64(g).copy(), _f64(h).copy()
+        a2, b2 = np.empty_like(a), np.empty_like(b)
+        for _ in range(int(nsteps)):
+            phase.step(prm, a, b, a2, b2)
+            a, a2 = a2, a
+            b, b2 = b2, b
+        return a, b
+
+    @staticmethod
+    def fields(prm, g, h):
+        """(phi, p, rho, u): p = cs^2 Pi, u force-shifted."""
+        g = _f64(g)
+        h = _f64(h)
+        _, nz, ny, nx = g.shape
+        phi = np.zeros((nz, ny, nx))
+        p = np.zeros_like(phi)
+        rho = np.zeros_like(phi)
+        u = np.zeros((3, nz, ny, nx))
+        lib().orc_pf_fields(nx, ny, nz, _p(_f64(prm)), _p(g), _p(h), _p(phi), _p(p), _p(rho), _p(u))
+        return phi, p, rho, u

@@ -277,6 +277,9 @@ static int solve19(double *A, double *b, double *x)
     return 0;
 }
 
+/* The same elimination for the other oracle files (n <= 19; A, b overwritten). */
+int orc_solve19(double *A, double *b, double *x) { return solve19(A, b, x); }
+
 enum { ORC_DEFINITION = 0, ORC_CLOSED_FORM = 1 };
 
 /*

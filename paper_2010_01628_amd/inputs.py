@@ -139,3 +139,30 @@ def ensemble_boxes(n_boxes: int = 64, sizes=(48, 64, 96), nu_range=(1e-4, 1e-3),
         nu = float(np.exp(rng.uniform(np.log(nu_range[0]), np.log(nu_range[1]))))
         out.append((L, nu, seed * 1000 + b))
     return out
+
+
+def droplet(shape, R: float, W: float = 4.0, noise: float = 0.0, seed: int = 192, center=None):
+    """Phase field of a drop of radius R: phi = 1/2 + 1/2 tanh(2 (R - r)/W)
+    (phi = 1 inside), r the distance from `center` (default: the box centre
+    (nx/2, ny/2, nz/2); with nz = 1 the drop is a cylinder along z), plus
+    seeded uniform noise in [-noise, noise].  shape = (nx, ny, nz);
+    returns (nz, ny, nx)."""
+    nx, ny, nz = shape
+    cx, cy, cz = center if center is not None else (nx / 2, ny / 2, nz / 2 if nz > 1 else 0.0)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)
+    phi = 0.5 + 0.5 * np.tanh(2.0 * (R - r) / W)
+    if noise:
+        nodes = np.arange(nx * ny * nz, dtype=np.uint64).reshape(nz, ny, nx)
+        phi = phi + noise * uniform_pm1(seed, nodes, 0)
+    return phi
+
+
+def slab(shape, thickness: float, W: float = 4.0):
+    """Planar layer phi = 1 for |x - nx/2| < thickness/2 (tanh edges of width
+    W), uniform in y and z; (nz, ny, nx)."""
+    nx, ny, nz = shape
+    x = np.arange(nx, dtype=np.float64)
+    d = thickness / 2 - np.abs(x - nx / 2)
+    phi = 0.5 + 0.5 * np.tanh(2.0 * d / W)
+    return np.broadcast_to(phi[None, None, :], (nz, ny, nx)).copy()
