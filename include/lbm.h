@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 typedef enum {
     LBM_OK = 0,
@@ -70,6 +70,37 @@ typedef enum {
     LBM_FORCE_KOLMOGOROV = 3  /* F_x = kolmogorov_amp * sin(2 pi y / ny), F_y = F_z = 0 */
 } lbm_force_mode;
 
+/* Lattice coupled to the flow (Sec. III multiphysics cases). */
+typedef enum {
+    LBM_COUPLED_NONE = 0,
+    LBM_COUPLED_PHASE = 1,    /* two-phase flow with a conservative phase field (see below) */
+    LBM_COUPLED_MAGNETIC = 2  /* magnetohydrodynamics with a vector magnetic lattice (see below) */
+} lbm_coupling;
+
+/* Two-phase flow (not in the paper, whose multiphase models are Shan-Chen and
+ * the colour gradient): conservative Allen-Cahn phase field phi in [0, 1]
+ * (P.-H. Chiu & Y.-T. Lin, J. Comput. Phys. 230, 2011) carried by a D3Q7
+ * lattice in the form of A. Fakhari et al. (Phys. Rev. E 96, 2017), coupled
+ * to pressure-based D3Q19 flow populations (zeroth moment p/cs^2, first
+ * moment rho u; X. He, S. Chen & R. Zhang, J. Comput. Phys. 152, 1999;
+ * H. Liang et al., Phys. Rev. E 97, 2018) collided with the CM scheme of
+ * Sec. II.B.  rho = rho_light + phi (rho_heavy - rho_light); surface tension
+ * F = mu grad(phi), mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
+ * beta = 12 sigma / width, kappa = 3 sigma width / 2. */
+typedef struct {
+    double rho_light;         /* density where phi = 0, > 0 */
+    double rho_heavy;         /* density where phi = 1, > 0 */
+    double sigma;             /* surface tension, >= 0 */
+    double width;             /* interface width W (lattice units), > 0 */
+    double mobility;          /* M > 0; phase relaxation rate 1 / (4 M + 1/2) */
+} lbm_phase_params;
+
+/* Magnetohydrodynamics (Sec. III, Hartmann flow): vector magnetic lattice. */
+typedef struct {
+    double eta;               /* magnetic diffusivity, > 0 */
+    double b_wall[3];         /* field imposed at the y walls (walls_y = 1) */
+} lbm_magnetic_params;
+
 typedef struct {
     uint32_t abi_version;     /* must be LBM_ABI_VERSION */
     int32_t nx, ny, nz;       /* lattice nodes; periodic in x and z, and in y unless walls_y */
@@ -93,6 +124,11 @@ typedef struct {
     int32_t block_x, block_y; /* work-group shape of the step kernels; 0 = library default */
     int32_t cache_policy;     /* population loads/stores: 0 = library default, 1 = non-temporal
                                  (streaming) hints, 2 = ordinary cached accesses */
+    int32_t coupled;          /* lbm_coupling */
+    lbm_phase_params phase;   /* LBM_COUPLED_PHASE: q = 19, FP64 or FP32, A-B, periodic, no
+                                 external force, the paper's bulk and higher-order rates,
+                                 rho0 = 1 */
+    lbm_magnetic_params magnetic; /* LBM_COUPLED_MAGNETIC */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -132,6 +168,25 @@ int lbm_get_populations(lbm_handle *h, double *f, int on_device);
 /* Replace the state by the populations f (double[19*N], host or device),
  * rounded to the storage precision.  The step counter is kept. */
 int lbm_set_populations(lbm_handle *h, const double *f, int on_device);
+
+/* Two-phase lattices (coupled = LBM_COUPLED_PHASE) start from lbm_init_phase
+ * instead of lbm_init: phase populations at h_eq(phi, u), flow populations
+ * at the paper's equilibrium at density rho(phi) plus (p/cs^2 - rho(phi))
+ * times the rest weights.  phi, p: double[N]; u: double[3*N] (host or
+ * device).  Resets the step counter.  On such a handle lbm_moments reports
+ * rho(phi) and the force-shifted velocity, and lbm_get/set_populations the
+ * flow populations g (double[19*N], pull order as for the plain lattice). */
+int lbm_init_phase(lbm_handle *h, const double *phi, const double *p, const double *u, int on_device);
+
+/* phi = sum of the phase populations and the pressure p = cs^2 (sum g + S0/2)
+ * at the current time (double[N] each, host or device, either may be NULL). */
+int lbm_phase_fields(lbm_handle *h, double *phi, double *p, int on_device);
+
+/* Populations of the coupled lattice at the current time (double[q_c*N],
+ * population i at [i*N + n]; q_c = 7 for the phase field, order rest, -x,
+ * -y, -z, +x, +y, +z), host or device; set replaces them (step counter kept). */
+int lbm_get_coupled_populations(lbm_handle *h, double *out, int on_device);
+int lbm_set_coupled_populations(lbm_handle *h, const double *in, int on_device);
 
 /* Number of steps taken since lbm_init. */
 int64_t lbm_step_count(const lbm_handle *h);

@@ -1,0 +1,223 @@
+// Host side of the coupled lattices of include/lbm.h (two-phase phase field).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "coupled.hpp"
+#include "handle.hpp"
+
+namespace {
+
+#define CHIP(expr)                                                                                        \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess)                                                                             \
+            return lbm_fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s: %s", #expr,        \
+                            hipGetErrorString(e_));                                                       \
+    } while (0)
+
+int eb_of(int precision) { return precision == LBM_FP64 ? 8 : 4; }
+
+// Copy a host array to a fresh device buffer (or use the device pointer).
+struct Staged {
+    const double* ptr = nullptr;
+    double* owned = nullptr;
+    ~Staged()
+    {
+        if (owned) hipFree(owned);
+    }
+};
+
+int stage_in(const double* src, int64_t n, int on_device, hipStream_t st, Staged& out)
+{
+    if (!src) return LBM_OK;
+    if (on_device) {
+        out.ptr = src;
+        return LBM_OK;
+    }
+    CHIP(hipMalloc((void**)&out.owned, sizeof(double) * n));
+    CHIP(hipMemcpyAsync(out.owned, src, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    out.ptr = out.owned;
+    return LBM_OK;
+}
+
+} // namespace
+
+int coupled_validate(const lbm_params* p)
+{
+    if (p->coupled == LBM_COUPLED_MAGNETIC) return lbm_fail(LBM_EUNSUPPORTED, "magnetic coupling is not built yet");
+    const lbm_phase_params& q = p->phase;
+    if (p->q != 19) return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice is D3Q19");
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
+        return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice stores FP64 or FP32");
+    if (p->streaming != LBM_AB) return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice streams A-B");
+    if (p->walls_y) return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice is periodic");
+    if (p->force_mode != LBM_FORCE_NONE) return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice takes no external force");
+    bool paper = p->omega_bulk == 1.0;
+    for (int j = 0; j < 9; ++j) paper = paper && p->omega_hi[j] == 1.0;
+    if (!paper) return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice uses the paper's bulk and higher-order rates");
+    if (p->rho0 != 1.0) return lbm_fail(LBM_EINVAL, "the two-phase lattice stores deviations from rho0 = 1");
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(q.rho_light) || !pos(q.rho_heavy)) return lbm_fail(LBM_EINVAL, "phase densities must be positive");
+    if (!(std::isfinite(q.sigma) && q.sigma >= 0.0)) return lbm_fail(LBM_EINVAL, "sigma must be >= 0");
+    if (!pos(q.width)) return lbm_fail(LBM_EINVAL, "interface width must be positive");
+    if (!pos(q.mobility)) return lbm_fail(LBM_EINVAL, "mobility must be positive");
+    return LBM_OK;
+}
+
+int coupled_create(lbm_handle* h)
+{
+    const lbm_params& p = h->p;
+    lbm_coupled* c = new lbm_coupled();
+    h->cp = c;
+    c->q = 7;
+    const int eb = eb_of(p.precision);
+    const int64_t bytes = (int64_t)c->q * h->g.stride * eb;
+    for (int b = 0; b < 2; ++b) {
+        CHIP(hipMalloc(&c->buf[b], bytes));
+        h->bytes += bytes;
+    }
+    CHIP(hipMalloc(&c->scratch, (int64_t)h->g.N * eb));
+    h->bytes += (int64_t)h->g.N * eb;
+    const lbm_phase_params& q = p.phase;
+    c->pc.rho_l = q.rho_light;
+    c->pc.drho = q.rho_heavy - q.rho_light;
+    c->pc.beta = 12.0 * q.sigma / q.width;
+    c->pc.kappa = 1.5 * q.sigma * q.width;
+    c->pc.four_over_w = 4.0 / q.width;
+    c->pc.omega = p.omega;
+    c->pc.omega_phi = 1.0 / (q.mobility / 0.25 + 0.5);
+    return LBM_OK;
+}
+
+void coupled_destroy(lbm_handle* h)
+{
+    lbm_coupled* c = h->cp;
+    if (!c) return;
+    for (int b = 0; b < 2; ++b)
+        if (c->buf[b]) hipFree(c->buf[b]);
+    if (c->scratch) hipFree(c->scratch);
+    delete c;
+    h->cp = nullptr;
+}
+
+int coupled_step(lbm_handle* h)
+{
+    lbm_coupled* c = h->cp;
+    const int src = h->cur, dst = 1 - h->cur;
+    lbm::launch_phase_step(h->p.precision, h->nt, h->buf[src], h->buf[dst], c->buf[src], c->buf[dst], c->scratch, h->g,
+                           c->pc, h->grid, h->block, h->stream);
+    CHIP(hipGetLastError());
+    return LBM_OK;
+}
+
+int coupled_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_device)
+{
+    lbm_coupled* c = h->cp;
+    const int64_t N = h->g.N;
+    double* drho = rho;
+    double* du = u;
+    double* staging = nullptr;
+    if (!on_device && (rho || u)) {
+        CHIP(hipMalloc((void**)&staging, sizeof(double) * 4 * N));
+        drho = rho ? staging : nullptr;
+        du = u ? staging + N : nullptr;
+    }
+    lbm::launch_phase_fields(h->p.precision, h->buf[h->cur], c->buf[h->cur], c->scratch, h->g, c->pc, nullptr, nullptr,
+                             drho, du, h->partials, h->grid, h->block, h->stream);
+    if (diag) lbm::launch_reduce(h->partials, h->nblocks, h->diag_dev, h->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && staging) {
+        if (rho) e = hipMemcpyAsync(rho, staging, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && u) e = hipMemcpyAsync(u, staging + N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, h->stream);
+    }
+    if (e == hipSuccess && diag)
+        e = hipMemcpyAsync(h->diag_host, h->diag_dev, lbm::NDIAG_OUT * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && (diag || staging)) e = hipStreamSynchronize(h->stream);
+    if (staging) hipFree(staging);
+    if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "coupled moments: %s", hipGetErrorString(e));
+    if (diag)
+        for (int k = 0; k < 6; ++k) diag[k] = h->diag_host[k];
+    return LBM_OK;
+}
+
+extern "C" {
+
+int lbm_init_phase(lbm_handle* h, const double* phi, const double* p, const double* u, int on_device)
+{
+    if (!h || !phi || !p || !u) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (!h->cp || h->p.coupled != LBM_COUPLED_PHASE) return lbm_fail(LBM_EINVAL, "not a two-phase lattice");
+    const int64_t N = h->g.N;
+    Staged sphi, sp, su;
+    int rc = stage_in(phi, N, on_device, h->stream, sphi);
+    if (!rc) rc = stage_in(p, N, on_device, h->stream, sp);
+    if (!rc) rc = stage_in(u, 3 * N, on_device, h->stream, su);
+    if (rc) return rc;
+    h->steps = 0;
+    h->cur = 0;
+    lbm::launch_phase_init(h->p.precision, h->buf[0], h->cp->buf[0], h->g, h->cp->pc, sphi.ptr, sp.ptr, su.ptr, h->grid,
+                           h->block, h->stream);
+    CHIP(hipGetLastError());
+    if (!on_device) CHIP(hipStreamSynchronize(h->stream)); // staging buffers are freed on return
+    return LBM_OK;
+}
+
+int lbm_phase_fields(lbm_handle* h, double* phi, double* p, int on_device)
+{
+    if (!h) return lbm_fail(LBM_EINVAL, "NULL handle");
+    if (!h->cp || h->p.coupled != LBM_COUPLED_PHASE) return lbm_fail(LBM_EINVAL, "not a two-phase lattice");
+    const int64_t N = h->g.N;
+    double* dphi = phi;
+    double* dp = p;
+    double* staging = nullptr;
+    if (!on_device && (phi || p)) {
+        CHIP(hipMalloc((void**)&staging, sizeof(double) * 2 * N));
+        dphi = phi ? staging : nullptr;
+        dp = p ? staging + N : nullptr;
+    }
+    lbm::launch_phase_fields(h->p.precision, h->buf[h->cur], h->cp->buf[h->cur], h->cp->scratch, h->g, h->cp->pc, dphi,
+                             dp, nullptr, nullptr, h->partials, h->grid, h->block, h->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && staging) {
+        if (phi) e = hipMemcpyAsync(phi, staging, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && p) e = hipMemcpyAsync(p, staging + N, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    if (staging) hipFree(staging);
+    if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "phase fields: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_get_coupled_populations(lbm_handle* h, double* out, int on_device)
+{
+    if (!h || !out) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (!h->cp) return lbm_fail(LBM_EINVAL, "no coupled lattice");
+    const int64_t bytes = sizeof(double) * h->cp->q * (int64_t)h->g.N;
+    double* dst = out;
+    if (!on_device) CHIP(hipMalloc((void**)&dst, bytes));
+    lbm::launch_phase_get_h(h->p.precision, h->cp->buf[h->cur], h->g, dst, h->grid, h->block, h->stream);
+    hipError_t e = hipGetLastError();
+    if (!on_device) {
+        if (e == hipSuccess) e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        hipFree(dst);
+    }
+    if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "get_coupled_populations: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_set_coupled_populations(lbm_handle* h, const double* in, int on_device)
+{
+    if (!h || !in) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (!h->cp) return lbm_fail(LBM_EINVAL, "no coupled lattice");
+    Staged s;
+    int rc = stage_in(in, (int64_t)h->cp->q * h->g.N, on_device, h->stream, s);
+    if (rc) return rc;
+    lbm::launch_phase_set_h(h->p.precision, h->cp->buf[h->cur], h->g, s.ptr, h->grid, h->block, h->stream);
+    CHIP(hipGetLastError());
+    if (!on_device) CHIP(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+} // extern "C"

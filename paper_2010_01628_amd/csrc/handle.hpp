@@ -1,0 +1,49 @@
+// The lattice handle behind the opaque lbm_handle of include/lbm.h, shared by
+// the host-side sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm.h"
+#include "lbm_internal.hpp"
+#include "phase_cm.hpp"
+
+// State of a coupled lattice (lbm_params.coupled != LBM_COUPLED_NONE).
+struct lbm_coupled {
+    void* buf[2] = {nullptr, nullptr}; // its populations (A-B), same stride as the flow lattice
+    int q = 0;                         // populations per node (7 for the phase field)
+    void* scratch = nullptr;           // phase field phi (storage-precision arithmetic type)
+    lbm::PhaseConst pc{};
+};
+
+struct lbm_handle {
+    lbm_params p;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    lbm::Geom g{};
+    lbm::Phys ph{};
+    void* buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t steps = 0;
+    double* row_table = nullptr;
+    double* partials = nullptr;
+    double* diag_dev = nullptr;
+    double* diag_host = nullptr;
+    dim3 grid, block;
+    bool walls = false, general = false, nt = true;
+    int64_t bytes = 0;
+    int nblocks = 0;
+    const lbm_mlp* mlp = nullptr;
+    uint32_t* fb_partials = nullptr; // per-block fallback counts of the learned step
+    lbm_coupled* cp = nullptr;         // coupled lattice, if any
+};
+
+// Coupled-lattice parts of the entry points (coupled_api.cpp).
+int coupled_validate(const lbm_params* p);
+int coupled_create(lbm_handle* h);
+void coupled_destroy(lbm_handle* h);
+int coupled_step(lbm_handle* h);
+int coupled_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_device);
+// error reporting of lbm_api.cpp (message for lbm_last_error)
+int lbm_fail(int code, const char* fmt, ...);

@@ -9,7 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 
-#include "lbm_internal.hpp"
+#include "handle.hpp"
 
 namespace {
 
@@ -43,26 +43,15 @@ void lbm_internal_set_error(const char* msg)
     std::snprintf(g_err, sizeof g_err, "%s", msg);
 }
 
-struct lbm_handle {
-    lbm_params p;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    lbm::Geom g{};
-    lbm::Phys ph{};
-    void* buf[2] = {nullptr, nullptr};
-    int cur = 0;
-    int64_t steps = 0;
-    double* row_table = nullptr;
-    double* partials = nullptr;
-    double* diag_dev = nullptr;
-    double* diag_host = nullptr;
-    dim3 grid, block;
-    bool walls = false, general = false, nt = true;
-    int64_t bytes = 0;
-    int nblocks = 0;
-    const lbm_mlp* mlp = nullptr;
-    uint32_t* fb_partials = nullptr; // per-block fallback counts of the learned step
-};
+int lbm_fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
 
 namespace {
 
@@ -111,6 +100,8 @@ int validate(const lbm_params* p)
     const int bx = p->block_x ? p->block_x : 64, by = p->block_y ? p->block_y : 1;
     if (bx * by > 256 || (bx * by) % 64 != 0)
         return fail(LBM_EINVAL, "block_x*block_y must be a multiple of 64 and at most 256");
+    if (p->coupled < LBM_COUPLED_NONE || p->coupled > LBM_COUPLED_MAGNETIC) return fail(LBM_EINVAL, "bad coupled");
+    if (p->coupled != LBM_COUPLED_NONE) return coupled_validate(p);
     return LBM_OK;
 }
 
@@ -265,6 +256,10 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
     }
     default: break;
     }
+    if (p->coupled != LBM_COUPLED_NONE) {
+        const int crc = coupled_create(h);
+        if (crc) return cleanup(crc);
+    }
     *out = h;
     return LBM_OK;
 }
@@ -273,6 +268,7 @@ int lbm_destroy(lbm_handle* h)
 {
     if (!h) return LBM_OK;
     if (h->stream || h->buf[0]) hipStreamSynchronize(h->stream);
+    if (h->cp) coupled_destroy(h);
     if (h->fb_partials) hipFree(h->fb_partials);
     for (int b = 0; b < 2; ++b)
         if (h->buf[b]) hipFree(h->buf[b]);
@@ -287,6 +283,7 @@ int lbm_destroy(lbm_handle* h)
 int lbm_init(lbm_handle* h, const double* rho, const double* u, int on_device)
 {
     if (!h || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+    if (h->cp) return fail(LBM_EINVAL, "a coupled lattice starts from its own init call (lbm_init_phase)");
     const int64_t N = h->g.N;
     const double* drho = rho;
     const double* du = u;
@@ -319,6 +316,21 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
         const int pat = pattern_of(h);
         const int src = h->cur;
         const int dst = h->p.streaming == LBM_AB ? 1 - h->cur : h->cur;
+        if (h->cp) {
+            const int crc = coupled_step(h);
+            if (crc) return crc;
+            h->cur = dst;
+            h->steps++;
+            if (h->p.check_every > 0 && h->steps % h->p.check_every == 0) {
+                double d[6];
+                const int mrc = coupled_moments(h, nullptr, nullptr, d, 1);
+                if (mrc) return mrc;
+                if (!(h->diag_host[6] == 0.0 && std::isfinite(d[0]) && h->diag_host[7] > 0.0))
+                    return fail(LBM_EUNSTABLE, "unstable at step %lld: %g bad nodes", (long long)h->steps,
+                                h->diag_host[6]);
+            }
+            continue;
+        }
         if (h->mlp)
             lbm::launch_step_mlp(h->p.precision, pat, h->walls, h->nt, h->buf[src], h->buf[dst], h->g, h->ph,
                                  h->mlp->packed, h->fb_partials, h->grid, h->block, h->stream);
@@ -343,6 +355,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
 int lbm_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_device)
 {
     if (!h) return fail(LBM_EINVAL, "NULL handle");
+    if (h->cp) return coupled_moments(h, rho, u, diag, on_device);
     const int64_t N = h->g.N;
     double* drho = rho;
     double* du = u;
@@ -522,6 +535,7 @@ int lbm_set_mlp(lbm_handle* h, const lbm_mlp* m)
 {
     if (!h) return fail(LBM_EINVAL, "NULL handle");
     if (m) {
+        if (h->cp) return fail(LBM_EUNSUPPORTED, "learned rates apply to the single-phase lattice");
         if (h->p.q != 19) return fail(LBM_EUNSUPPORTED, "learned rates need the D3Q19 lattice");
         if (h->p.precision == LBM_FP64) return fail(LBM_EUNSUPPORTED, "learned rates run with FP32 collision");
         if (!h->fb_partials) {

@@ -1,0 +1,268 @@
+// Kernels of the two-phase (conservative phase-field) coupled lattice.
+//
+// One step is two launches over all nodes (A-B pull streaming on both
+// lattices, periodic):
+//   k_phase_sum:  phi(x) = sum_i h_i(x) with h_i(x) = h*_i(x - c_i) pulled from
+//                 the previous step's post-collision phase populations;
+//   k_phase_step: phi at the 19 stencil nodes (gradient, Laplacian, chemical
+//                 potential, force), flow populations pulled, collided and
+//                 stored, phase populations pulled, collided and stored.
+// Flow populations use the D3Q19 layout of the plain lattice (deviations
+// g_i - w_i, SoA with padded stride); phase populations are stored as is,
+// seven arrays with the same stride.
+#include "lattice_kernels.hpp"
+#include "phase_cm.hpp"
+#include "coupled.hpp"
+
+namespace lbm {
+
+template <class S> __device__ inline void gather7(const S* __restrict__ buf, int64_t stride, const NodeIdx& d,
+                                                   typename Codec<S>::R h[7])
+{
+#pragma unroll
+    for (int i = 0; i < 7; ++i) h[i] = Codec<S>::dec(buf[(int64_t)i * stride + nb(d, -cx7(i), -cy7(i), -cz7(i))]);
+}
+
+template <class S, bool NT> __device__ inline void store7(S* __restrict__ buf, int64_t stride, int n,
+                                                          const typename Codec<S>::R h[7])
+{
+#pragma unroll
+    for (int i = 0; i < 7; ++i) st<S, NT>(buf + (int64_t)i * stride + n, Codec<S>::enc(h[i]));
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_phase_sum(const S* __restrict__ hsrc, typename Codec<S>::R* __restrict__ phi,
+                                                  Geom g)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    R h[7];
+    gather7<S>(hsrc, g.stride, d, h);
+    R s = h[0];
+#pragma unroll
+    for (int i = 1; i < 7; ++i) s += h[i];
+    phi[nb(d, 0, 0, 0)] = s;
+}
+
+template <class R> __device__ inline void phi_stencil(const R* __restrict__ phi, const NodeIdx& d, R phin[19])
+{
+#pragma unroll
+    for (int i = 0; i < 19; ++i) phin[i] = phi[nb(d, cx19(i), cy19(i), cz19(i))];
+}
+
+template <class S, bool NT>
+__global__ __launch_bounds__(256) void k_phase_step(const S* __restrict__ gsrc, S* __restrict__ gdst,
+                                                   const S* __restrict__ hsrc, S* __restrict__ hdst,
+                                                   const typename Codec<S>::R* __restrict__ phi, Geom g, PhaseConst pc)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int n = nb(d, 0, 0, 0);
+    R phin[19];
+    phi_stencil(phi, d, phin);
+    R s[19];
+    gather<LatD3Q19, S, AB, false, NT>(gsrc, g.stride, d, s);
+    RawMoments<R> m;
+    raw_from_pops(s, m);
+    PhaseMacro<R> o;
+    R gx, gy, gz;
+    phase_macro(m, phin, pc, o, gx, gy, gz);
+    phase_collide_g(s, m, o, (R)pc.omega);
+    scatter<LatD3Q19, S, AB, false, NT>(gdst, g.stride, d, s);
+    R h[7];
+    gather7<S>(hsrc, g.stride, d, h);
+    phase_collide_h(h, phin[0], gx, gy, gz, o.ux, o.uy, o.uz, pc);
+    store7<S, NT>(hdst, g.stride, n, h);
+}
+
+// Equilibrium of the initial fields, written where the first step pulls it:
+// flow population i of node x at x - c_i, phase population likewise.
+template <class S>
+__global__ __launch_bounds__(256) void k_phase_init(S* __restrict__ gbuf, S* __restrict__ hbuf, Geom g, PhaseConst pc,
+                                                   const double* __restrict__ phi_in, const double* __restrict__ p_in,
+                                                   const double* __restrict__ u_in)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int n = nb(d, 0, 0, 0);
+    const R phi = (R)phi_in[n];
+    const R ux = (R)u_in[n], uy = (R)u_in[g.N + n], uz = (R)u_in[2 * (int64_t)g.N + n];
+    const R rho = (R)pc.rho_l + phi * (R)pc.drho;
+    const R Pi = (R)(3.0 * p_in[n]);
+    RawMoments<R> e;
+    eq_raw_deviation(Pi - R(1), rho, ux, uy, uz, e);
+    R s[19];
+    pops_from_raw(e, s);
+    place_state<LatD3Q19, S, AB, false>(gbuf, g.stride, d, s);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const R cu = R(cx7(i)) * ux + R(cy7(i)) * uy + R(cz7(i)) * uz;
+        hbuf[(int64_t)i * g.stride + nb(d, -cx7(i), -cy7(i), -cz7(i))] =
+            Codec<S>::enc(phi * R(w7(i)) * (R(1) + R(4) * cu));
+    }
+}
+
+// Macroscopic fields (double outputs, any may be NULL) and FP64 partial sums
+// [sum rho, sum rho u (3), 1/2 sum rho |u|^2, max |u|, bad count, min rho].
+template <class S>
+__global__ __launch_bounds__(256) void k_phase_fields(const S* __restrict__ gsrc,
+                                                     const typename Codec<S>::R* __restrict__ phi, Geom g, PhaseConst pc,
+                                                     double* __restrict__ phi_out, double* __restrict__ p_out,
+                                                     double* __restrict__ rho_out, double* __restrict__ u_out,
+                                                     double* __restrict__ partials)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double v[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 1e300};
+    if (x < g.nx && y < g.ny) {
+        NodeIdx d;
+        node_idx(g, x, y, z, d);
+        const int n = nb(d, 0, 0, 0);
+        R phin[19];
+        phi_stencil(phi, d, phin);
+        R s[19];
+        gather<LatD3Q19, S, AB, false>(gsrc, g.stride, d, s);
+        RawMoments<R> m;
+        raw_from_pops(s, m);
+        PhaseMacro<R> o;
+        R gx, gy, gz;
+        phase_macro(m, phin, pc, o, gx, gy, gz);
+        const double rho = (double)o.rho, ux = (double)o.ux, uy = (double)o.uy, uz = (double)o.uz;
+        if (phi_out) phi_out[n] = (double)phin[0];
+        if (p_out) p_out[n] = (1.0 + (double)o.dPi) / 3.0;
+        if (rho_out) rho_out[n] = rho;
+        if (u_out) {
+            u_out[n] = ux;
+            u_out[g.N + n] = uy;
+            u_out[2 * (int64_t)g.N + n] = uz;
+        }
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        v[0] = rho;
+        v[1] = rho * ux;
+        v[2] = rho * uy;
+        v[3] = rho * uz;
+        v[4] = 0.5 * rho * u2;
+        v[5] = sqrt(u2);
+        v[6] = (isfinite(rho) && isfinite(u2) && isfinite((double)o.dPi)) ? 0.0 : 1.0;
+        v[7] = rho;
+    }
+    const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_reduce_store(v, partials + (int64_t)bid * NDIAG);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_phase_get_h(const S* __restrict__ hbuf, Geom g, double* __restrict__ out)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    R h[7];
+    gather7<S>(hbuf, g.stride, d, h);
+    const int n = nb(d, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) out[(int64_t)i * g.N + n] = (double)h[i];
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_phase_set_h(S* __restrict__ hbuf, Geom g, const double* __restrict__ in)
+{
+    using R = typename Codec<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int n = nb(d, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        hbuf[(int64_t)i * g.stride + nb(d, -cx7(i), -cy7(i), -cz7(i))] = Codec<S>::enc((R)in[(int64_t)i * g.N + n]);
+}
+
+// ---------------------------------------------------------------------------
+void launch_phase_step(int precision, bool nt, const void* gsrc, void* gdst, const void* hsrc, void* hdst, void* phi,
+                       const Geom& g, const PhaseConst& pc, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (precision == PREC_FP64) {
+        hipLaunchKernelGGL(k_phase_sum<double>, grid, block, 0, st, (const double*)hsrc, (double*)phi, g);
+        if (nt)
+            hipLaunchKernelGGL((k_phase_step<double, true>), grid, block, 0, st, (const double*)gsrc, (double*)gdst,
+                               (const double*)hsrc, (double*)hdst, (const double*)phi, g, pc);
+        else
+            hipLaunchKernelGGL((k_phase_step<double, false>), grid, block, 0, st, (const double*)gsrc, (double*)gdst,
+                               (const double*)hsrc, (double*)hdst, (const double*)phi, g, pc);
+    } else {
+        hipLaunchKernelGGL(k_phase_sum<float>, grid, block, 0, st, (const float*)hsrc, (float*)phi, g);
+        if (nt)
+            hipLaunchKernelGGL((k_phase_step<float, true>), grid, block, 0, st, (const float*)gsrc, (float*)gdst,
+                               (const float*)hsrc, (float*)hdst, (const float*)phi, g, pc);
+        else
+            hipLaunchKernelGGL((k_phase_step<float, false>), grid, block, 0, st, (const float*)gsrc, (float*)gdst,
+                               (const float*)hsrc, (float*)hdst, (const float*)phi, g, pc);
+    }
+}
+
+void launch_phase_init(int precision, void* gbuf, void* hbuf, const Geom& g, const PhaseConst& pc, const double* phi,
+                       const double* p, const double* u, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (precision == PREC_FP64)
+        hipLaunchKernelGGL(k_phase_init<double>, grid, block, 0, st, (double*)gbuf, (double*)hbuf, g, pc, phi, p, u);
+    else
+        hipLaunchKernelGGL(k_phase_init<float>, grid, block, 0, st, (float*)gbuf, (float*)hbuf, g, pc, phi, p, u);
+}
+
+void launch_phase_fields(int precision, const void* gsrc, const void* hsrc, void* phi, const Geom& g,
+                         const PhaseConst& pc, double* phi_out, double* p_out, double* rho_out, double* u_out,
+                         double* partials, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (precision == PREC_FP64) {
+        hipLaunchKernelGGL(k_phase_sum<double>, grid, block, 0, st, (const double*)hsrc, (double*)phi, g);
+        hipLaunchKernelGGL(k_phase_fields<double>, grid, block, 0, st, (const double*)gsrc, (const double*)phi, g, pc,
+                           phi_out, p_out, rho_out, u_out, partials);
+    } else {
+        hipLaunchKernelGGL(k_phase_sum<float>, grid, block, 0, st, (const float*)hsrc, (float*)phi, g);
+        hipLaunchKernelGGL(k_phase_fields<float>, grid, block, 0, st, (const float*)gsrc, (const float*)phi, g, pc,
+                           phi_out, p_out, rho_out, u_out, partials);
+    }
+}
+
+void launch_phase_get_h(int precision, const void* hbuf, const Geom& g, double* out, dim3 grid, dim3 block,
+                        hipStream_t st)
+{
+    if (precision == PREC_FP64)
+        hipLaunchKernelGGL(k_phase_get_h<double>, grid, block, 0, st, (const double*)hbuf, g, out);
+    else
+        hipLaunchKernelGGL(k_phase_get_h<float>, grid, block, 0, st, (const float*)hbuf, g, out);
+}
+
+void launch_phase_set_h(int precision, void* hbuf, const Geom& g, const double* in, dim3 grid, dim3 block,
+                        hipStream_t st)
+{
+    if (precision == PREC_FP64)
+        hipLaunchKernelGGL(k_phase_set_h<double>, grid, block, 0, st, (double*)hbuf, g, in);
+    else
+        hipLaunchKernelGGL(k_phase_set_h<float>, grid, block, 0, st, (float*)hbuf, g, in);
+}
+
+} // namespace lbm

@@ -19,7 +19,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3
 LBM_AB, LBM_AA = 0, 1
@@ -33,6 +33,18 @@ class LbmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"lbm error {code}: {msg}")
         self.code = code
+
+
+class lbm_phase_params(ctypes.Structure):
+    _fields_ = [("rho_light", ctypes.c_double), ("rho_heavy", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("width", ctypes.c_double), ("mobility", ctypes.c_double)]
+
+
+class lbm_magnetic_params(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("b_wall", ctypes.c_double * 3)]
+
+
+LBM_COUPLED_NONE, LBM_COUPLED_PHASE, LBM_COUPLED_MAGNETIC = 0, 1, 2
 
 
 class lbm_params(ctypes.Structure):
@@ -54,6 +66,9 @@ class lbm_params(ctypes.Structure):
         ("check_every", ctypes.c_int32),
         ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
         ("cache_policy", ctypes.c_int32),
+        ("coupled", ctypes.c_int32),
+        ("phase", lbm_phase_params),
+        ("magnetic", lbm_magnetic_params),
     ]
 
 
@@ -121,6 +136,13 @@ def lib():
         for name in ("lbm_ensemble_create", "lbm_ensemble_init", "lbm_ensemble_set_mlp", "lbm_ensemble_step",
                      "lbm_ensemble_energy", "lbm_ensemble_get_populations", "lbm_ensemble_tune",
                      "lbm_ensemble_destroy"):
+            getattr(L, name).restype = i32
+        L.lbm_init_phase.argtypes = [vp, vp, vp, vp, i32]
+        L.lbm_phase_fields.argtypes = [vp, vp, vp, i32]
+        L.lbm_get_coupled_populations.argtypes = [vp, vp, i32]
+        L.lbm_set_coupled_populations.argtypes = [vp, vp, i32]
+        for name in ("lbm_init_phase", "lbm_phase_fields", "lbm_get_coupled_populations",
+                     "lbm_set_coupled_populations"):
             getattr(L, name).restype = i32
         for name in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_get_populations",
                      "lbm_set_populations", "lbm_destroy", "lbm_mlp_create", "lbm_mlp_set_params",
@@ -387,7 +409,9 @@ class Ensemble:
 def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
                 rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
                 force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0,
-                q=19) -> lbm_params:
+                q=19, phase=None) -> lbm_params:
+    """phase: dict(rho_light, rho_heavy, sigma, width, mobility) makes a
+    two-phase lattice (coupled = LBM_COUPLED_PHASE)."""
     p = lbm_params_default()
     p.q = int(q)
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -408,6 +432,10 @@ def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_b
     p.check_every = int(check_every)
     p.block_x, p.block_y = int(block[0]), int(block[1])
     p.cache_policy = int(cache_policy)
+    if phase is not None:
+        p.coupled = LBM_COUPLED_PHASE
+        for k in ("rho_light", "rho_heavy", "sigma", "width", "mobility"):
+            setattr(p.phase, k, float(phase[k]))
     return p
 
 
@@ -498,6 +526,34 @@ class Lattice:
     @property
     def step_count(self):
         return lbm_step_count(self.h)
+
+    # -- two-phase lattices ------------------------------------------------
+    def init_phase(self, phi, p, u):
+        a, b, c = self._dev(phi), self._dev(p), self._dev(u)
+        assert a.numel() == self.N and b.numel() == self.N and c.numel() == 3 * self.N
+        _check(lib().lbm_init_phase(self.h, a.data_ptr(), b.data_ptr(), c.data_ptr(), 1))
+        self.stream.synchronize()
+
+    def phase_fields(self):
+        """(phi, p) as device float64 tensors (nz, ny, nx)."""
+        t = self.torch
+        phi = t.empty(self.shape, dtype=t.float64, device="cuda")
+        p = t.empty(self.shape, dtype=t.float64, device="cuda")
+        _check(lib().lbm_phase_fields(self.h, phi.data_ptr(), p.data_ptr(), 1))
+        self.stream.synchronize()
+        return phi, p
+
+    def get_coupled_populations(self, q=7):
+        t = self.torch
+        f = t.empty((q,) + self.shape, dtype=t.float64, device="cuda")
+        _check(lib().lbm_get_coupled_populations(self.h, f.data_ptr(), 1))
+        self.stream.synchronize()
+        return f
+
+    def set_coupled_populations(self, f):
+        ff = self._dev(f)
+        _check(lib().lbm_set_coupled_populations(self.h, ff.data_ptr(), 1))
+        self.stream.synchronize()
 
     @property
     def device_bytes(self):

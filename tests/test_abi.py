@@ -61,6 +61,16 @@ def test_params_struct_layout_matches_header(lbm, tmp_path):
     for f in fields:
         assert int(got[f]) == getattr(lbm.lbm_params, f).offset, f
     assert int(got["sizeof"]) == ctypes.sizeof(lbm.lbm_params)
+    # nested parameter blocks of the coupled lattices
+    for sname, cls in (("lbm_phase_params", lbm.lbm_phase_params), ("lbm_magnetic_params", lbm.lbm_magnetic_params)):
+        body = "\n".join(f'printf("{f} %zu\\n", offsetof({sname}, {f}));' for f, _ in cls._fields_)
+        src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"lbm.h\"\n"
+                       "int main(void){" + body + f'printf("sizeof %zu\\n", sizeof({sname})); return 0;}}\n')
+        subprocess.run(["gcc", "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
+        got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+        for f, _ in cls._fields_:
+            assert int(got[f]) == getattr(cls, f).offset, (sname, f)
+        assert int(got["sizeof"]) == ctypes.sizeof(cls)
 
 
 def test_defaults(lbm):
@@ -109,3 +119,27 @@ def test_block_shape_validation(lbm):
     p.block_x, p.block_y = 512, 1
     with pytest.raises(lbm.LbmError):
         lbm.lbm_create(p, None)
+
+
+def _phase_params(lbm, **kw):
+    p = lbm.make_params(16, 16, 16, precision="fp32",
+                        phase=dict(rho_light=1.0, rho_heavy=10.0, sigma=1e-3, width=4.0, mobility=0.1))
+    for k, v in kw.items():
+        if k in ("rho_light", "rho_heavy", "sigma", "width", "mobility"):
+            setattr(p.phase, k, v)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(q=27), -5), (dict(precision=2), -5), (dict(streaming=1), -5), (dict(walls_y=1), -5),
+    (dict(force_mode=1), -5), (dict(omega_bulk=1.5), -5), (dict(rho0=2.0), -1),
+    (dict(width=0.0), -1), (dict(mobility=-0.1), -1), (dict(rho_light=0.0), -1), (dict(sigma=-1.0), -1),
+    (dict(coupled=7), -1),
+])
+def test_phase_lattice_validation(lbm, kw, code):
+    p = _phase_params(lbm, **kw)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, None)
+    assert e.value.code == code, lbm.lib().lbm_last_error().decode()
