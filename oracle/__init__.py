@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c"]
+_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c", "mhd_oracle.c"]
 
 DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
 CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
@@ -103,6 +103,12 @@ def lib():
         L.orc_pf_step.restype = i32
         L.orc_pf_init.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp, dp]
         L.orc_pf_fields.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_mhd_geq.argtypes = [dp, dp, dp]
+        L.orc_mhd_current.argtypes = [dp, dp, f64, dp, dp]
+        L.orc_mhd_step.argtypes = [i32, i32, i32, i32, dp, f64, dp, dp, dp, dp, dp]
+        L.orc_mhd_step.restype = i32
+        L.orc_mhd_init.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp]
+        L.orc_mhd_fields.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
         _lib = L
@@ -524,3 +530,78 @@ class phase:
         u = np.zeros((3, nz, ny, nx))
         lib().orc_pf_fields(nx, ny, nz, _p(_f64(prm)), _p(g), _p(h), _p(phi), _p(p), _p(rho), _p(u))
         return phi, p, rho, u
+
+
+# --------------------------------------------------------------------------
+# Magnetohydrodynamics: D3Q7 vector magnetic lattice coupled to the D3Q19 CM
+# flow (readings M1-M4 in mhd_oracle.c)
+# --------------------------------------------------------------------------
+class mhd:
+    """prm = (eta, b_wall_x, b_wall_y, b_wall_z)."""
+
+    @staticmethod
+    def params(eta=0.1, b_wall=(0.0, 0.0, 0.0)):
+        return np.array([eta, *b_wall], dtype=np.float64)
+
+    @staticmethod
+    def omega_m(eta):
+        return 1.0 / (eta / 0.25 + 0.5)
+
+    @staticmethod
+    def geq(b, u):
+        out = np.zeros(21)
+        lib().orc_mhd_geq(_p(_f64(b)), _p(_f64(u)), _p(out))
+        return out.reshape(3, 7)
+
+    @staticmethod
+    def current(g, u0, omega_m):
+        b = np.zeros(3)
+        j = np.zeros(3)
+        lib().orc_mhd_current(_p(_f64(g).reshape(-1)), _p(_f64(u0)), float(omega_m), _p(b), _p(j))
+        return b, j
+
+    @staticmethod
+    def init(rho, u, b):
+        rho = _f64(rho)
+        nz, ny, nx = rho.shape
+        f = np.zeros((19, nz, ny, nx))
+        g = np.zeros((21, nz, ny, nx))
+        lib().orc_mhd_init(nx, ny, nz, _p(rho), _p(_f64(u)), _p(_f64(b)), _p(f), _p(g))
+        return f, g
+
+    @staticmethod
+    def step(prm, omega, f, g, F=None, walls_y=False, fout=None, gout=None):
+        f = _f64(f)
+        g = _f64(g)
+        _, nz, ny, nx = f.shape
+        fout = np.empty_like(f) if fout is None else fout
+        gout = np.empty_like(g) if gout is None else gout
+        Fa = None if F is None else _f64(F)
+        if lib().orc_mhd_step(nx, ny, nz, int(bool(walls_y)), _p(_f64(prm)), float(omega), _p(f), _p(g), _p(Fa),
+                              _p(fout), _p(gout)) != 0:
+            raise ArithmeticError("collision failed")
+        return fout, gout
+
+    @staticmethod
+    def run(prm, omega, f, g, nsteps, F=None, walls_y=False):
+        a, b = _f64(f).copy(), _f64(g).copy()
+        a2, b2 = np.empty_like(a), np.empty_like(b)
+        for _ in range(int(nsteps)):
+            mhd.step(prm, omega, a, b, F=F, walls_y=walls_y, fout=a2, gout=b2)
+            a, a2 = a2, a
+            b, b2 = b2, b
+        return a, b
+
+    @staticmethod
+    def fields(prm, f, g, F=None):
+        """(rho, u, b, j): u force-shifted with the Lorentz force."""
+        f = _f64(f)
+        g = _f64(g)
+        _, nz, ny, nx = f.shape
+        rho = np.zeros((nz, ny, nx))
+        u = np.zeros((3, nz, ny, nx))
+        b = np.zeros_like(u)
+        j = np.zeros_like(u)
+        Fa = None if F is None else _f64(F)
+        lib().orc_mhd_fields(nx, ny, nz, _p(_f64(prm)), _p(f), _p(g), _p(Fa), _p(rho), _p(u), _p(b), _p(j))
+        return rho, u, b, j
