@@ -95,7 +95,14 @@ typedef struct {
     double mobility;          /* M > 0; phase relaxation rate 1 / (4 M + 1/2) */
 } lbm_phase_params;
 
-/* Magnetohydrodynamics (Sec. III, Hartmann flow): vector magnetic lattice. */
+/* Magnetohydrodynamics (Sec. III, Hartmann flow; the paper cites the magnetic
+ * lattice without writing it out): induction equation on a D3Q7 vector
+ * lattice in the form of P. J. Dellar (J. Comput. Phys. 179, 2002),
+ * g_eq_{i,a} = w_i (b_a + c_i.(u b_a - b u_a) / cs^2), cs^2 = 1/4, one
+ * relaxation rate 1 / (4 eta + 1/2); current j = curl b from the magnetic
+ * non-equilibrium; the Lorentz force j x b (mu0 = 1) joins the external
+ * force in the flow collision.  With walls_y, magnetic populations are
+ * anti-bounced back so that b = b_wall on the walls. */
 typedef struct {
     double eta;               /* magnetic diffusivity, > 0 */
     double b_wall[3];         /* field imposed at the y walls (walls_y = 1) */
@@ -128,7 +135,8 @@ typedef struct {
     lbm_phase_params phase;   /* LBM_COUPLED_PHASE: q = 19, FP64 or FP32, A-B, periodic, no
                                  external force, the paper's bulk and higher-order rates,
                                  rho0 = 1 */
-    lbm_magnetic_params magnetic; /* LBM_COUPLED_MAGNETIC */
+    lbm_magnetic_params magnetic; /* LBM_COUPLED_MAGNETIC: q = 19, FP64 or FP32, A-B, the paper's
+                                 bulk and higher-order rates; any external force mode */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -182,9 +190,22 @@ int lbm_init_phase(lbm_handle *h, const double *phi, const double *p, const doub
  * at the current time (double[N] each, host or device, either may be NULL). */
 int lbm_phase_fields(lbm_handle *h, double *phi, double *p, int on_device);
 
+/* Magnetic lattices (coupled = LBM_COUPLED_MAGNETIC) start from
+ * lbm_init_magnetic: flow at f_eq(rho, u), magnetic populations at
+ * g_eq(b, u).  rho: double[N]; u, b: double[3*N] (host or device).  Resets
+ * the step counter.  lbm_moments then reports the velocity shifted by half
+ * the total (external + Lorentz) force. */
+int lbm_init_magnetic(lbm_handle *h, const double *rho, const double *u, const double *b, int on_device);
+
+/* Magnetic field b = sum of the magnetic populations and current j (double[3*N]
+ * each, host or device, either may be NULL) at the current time. */
+int lbm_magnetic_fields(lbm_handle *h, double *b, double *j, int on_device);
+
 /* Populations of the coupled lattice at the current time (double[q_c*N],
- * population i at [i*N + n]; q_c = 7 for the phase field, order rest, -x,
- * -y, -z, +x, +y, +z), host or device; set replaces them (step counter kept). */
+ * population k at [k*N + n]; D3Q7 order rest, -x, -y, -z, +x, +y, +z;
+ * q_c = 7 for the phase field, 21 = 3 x 7 for the magnetic field with
+ * k = 7 a + i for component a), host or device; set replaces them (step
+ * counter kept). */
 int lbm_get_coupled_populations(lbm_handle *h, double *out, int on_device);
 int lbm_set_coupled_populations(lbm_handle *h, const double *in, int on_device);
 

@@ -9,6 +9,12 @@
 
 namespace lbm {
 
+// Constants of the magnetic lattice.
+struct MhdConst {
+    double omega_m;   // 1 / (eta / cs^2 + 1/2), cs^2 = 1/4
+    double b_wall[3]; // field imposed at the y walls
+};
+
 // One step of the two-phase lattice: phi = sum h into `phi`, then the fused
 // flow + phase collide-stream from (gsrc, hsrc) into (gdst, hdst).
 void launch_phase_step(int precision, bool nt, const void* gsrc, void* gdst, const void* hsrc, void* hdst, void* phi,
@@ -23,5 +29,18 @@ void launch_phase_get_h(int precision, const void* hbuf, const Geom& g, double* 
                         hipStream_t st);
 void launch_phase_set_h(int precision, void* hbuf, const Geom& g, const double* in, dim3 grid, dim3 block,
                         hipStream_t st);
+
+// One step of the magnetic coupling (flow + magnetic lattice, one launch).
+void launch_mhd_step(int precision, bool walls, bool nt, const void* fsrc, void* fdst, const void* gsrc, void* gdst,
+                     const Geom& g, const Phys& ph, const MhdConst& mc, dim3 grid, dim3 block, hipStream_t st);
+void launch_mhd_init(int precision, bool walls, void* fbuf, void* gbuf, const Geom& g, double rho0, const MhdConst& mc,
+                     const double* rho, const double* u, const double* b, dim3 grid, dim3 block, hipStream_t st);
+void launch_mhd_fields(int precision, bool walls, const void* fsrc, const void* gsrc, const Geom& g, const Phys& ph,
+                       const MhdConst& mc, double* rho, double* u, double* b, double* j, double* partials, dim3 grid,
+                       dim3 block, hipStream_t st);
+void launch_mhd_get_g(int precision, bool walls, const void* gbuf, const Geom& g, const MhdConst& mc, double* out,
+                      dim3 grid, dim3 block, hipStream_t st);
+void launch_mhd_set_g(int precision, bool walls, void* gbuf, const Geom& g, const MhdConst& mc, const double* in,
+                      dim3 grid, dim3 block, hipStream_t st);
 
 } // namespace lbm

@@ -1,4 +1,5 @@
-// Host side of the coupled lattices of include/lbm.h (two-phase phase field).
+// Host side of the coupled lattices of include/lbm.h (two-phase phase field,
+// magnetic field).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -44,9 +45,25 @@ int stage_in(const double* src, int64_t n, int on_device, hipStream_t st, Staged
 
 } // namespace
 
+static int magnetic_validate(const lbm_params* p)
+{
+    if (p->q != 19) return lbm_fail(LBM_EUNSUPPORTED, "the magnetic coupling runs on D3Q19");
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
+        return lbm_fail(LBM_EUNSUPPORTED, "the magnetic coupling stores FP64 or FP32");
+    if (p->streaming != LBM_AB) return lbm_fail(LBM_EUNSUPPORTED, "the magnetic coupling streams A-B");
+    bool paper = p->omega_bulk == 1.0;
+    for (int j = 0; j < 9; ++j) paper = paper && p->omega_hi[j] == 1.0;
+    if (!paper) return lbm_fail(LBM_EUNSUPPORTED, "the magnetic coupling uses the paper's bulk and higher-order rates");
+    const lbm_magnetic_params& m = p->magnetic;
+    if (!(std::isfinite(m.eta) && m.eta > 0.0)) return lbm_fail(LBM_EINVAL, "eta must be positive");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(m.b_wall[a])) return lbm_fail(LBM_EINVAL, "b_wall must be finite");
+    return LBM_OK;
+}
+
 int coupled_validate(const lbm_params* p)
 {
-    if (p->coupled == LBM_COUPLED_MAGNETIC) return lbm_fail(LBM_EUNSUPPORTED, "magnetic coupling is not built yet");
+    if (p->coupled == LBM_COUPLED_MAGNETIC) return magnetic_validate(p);
     const lbm_phase_params& q = p->phase;
     if (p->q != 19) return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice is D3Q19");
     if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
@@ -71,12 +88,17 @@ int coupled_create(lbm_handle* h)
     const lbm_params& p = h->p;
     lbm_coupled* c = new lbm_coupled();
     h->cp = c;
-    c->q = 7;
+    c->q = p.coupled == LBM_COUPLED_MAGNETIC ? 21 : 7;
     const int eb = eb_of(p.precision);
     const int64_t bytes = (int64_t)c->q * h->g.stride * eb;
     for (int b = 0; b < 2; ++b) {
         CHIP(hipMalloc(&c->buf[b], bytes));
         h->bytes += bytes;
+    }
+    if (p.coupled == LBM_COUPLED_MAGNETIC) {
+        c->mc.omega_m = 1.0 / (p.magnetic.eta / 0.25 + 0.5);
+        for (int a = 0; a < 3; ++a) c->mc.b_wall[a] = p.magnetic.b_wall[a];
+        return LBM_OK;
     }
     CHIP(hipMalloc(&c->scratch, (int64_t)h->g.N * eb));
     h->bytes += (int64_t)h->g.N * eb;
@@ -106,6 +128,12 @@ int coupled_step(lbm_handle* h)
 {
     lbm_coupled* c = h->cp;
     const int src = h->cur, dst = 1 - h->cur;
+    if (h->p.coupled == LBM_COUPLED_MAGNETIC) {
+        lbm::launch_mhd_step(h->p.precision, h->walls, h->nt, h->buf[src], h->buf[dst], c->buf[src], c->buf[dst], h->g,
+                             h->ph, c->mc, h->grid, h->block, h->stream);
+        CHIP(hipGetLastError());
+        return LBM_OK;
+    }
     lbm::launch_phase_step(h->p.precision, h->nt, h->buf[src], h->buf[dst], c->buf[src], c->buf[dst], c->scratch, h->g,
                            c->pc, h->grid, h->block, h->stream);
     CHIP(hipGetLastError());
@@ -124,8 +152,12 @@ int coupled_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_
         drho = rho ? staging : nullptr;
         du = u ? staging + N : nullptr;
     }
-    lbm::launch_phase_fields(h->p.precision, h->buf[h->cur], c->buf[h->cur], c->scratch, h->g, c->pc, nullptr, nullptr,
-                             drho, du, h->partials, h->grid, h->block, h->stream);
+    if (h->p.coupled == LBM_COUPLED_MAGNETIC)
+        lbm::launch_mhd_fields(h->p.precision, h->walls, h->buf[h->cur], c->buf[h->cur], h->g, h->ph, c->mc, drho, du,
+                               nullptr, nullptr, h->partials, h->grid, h->block, h->stream);
+    else
+        lbm::launch_phase_fields(h->p.precision, h->buf[h->cur], c->buf[h->cur], c->scratch, h->g, c->pc, nullptr,
+                                 nullptr, drho, du, h->partials, h->grid, h->block, h->stream);
     if (diag) lbm::launch_reduce(h->partials, h->nblocks, h->diag_dev, h->stream);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && staging) {
@@ -196,7 +228,11 @@ int lbm_get_coupled_populations(lbm_handle* h, double* out, int on_device)
     const int64_t bytes = sizeof(double) * h->cp->q * (int64_t)h->g.N;
     double* dst = out;
     if (!on_device) CHIP(hipMalloc((void**)&dst, bytes));
-    lbm::launch_phase_get_h(h->p.precision, h->cp->buf[h->cur], h->g, dst, h->grid, h->block, h->stream);
+    if (h->p.coupled == LBM_COUPLED_MAGNETIC)
+        lbm::launch_mhd_get_g(h->p.precision, h->walls, h->cp->buf[h->cur], h->g, h->cp->mc, dst, h->grid, h->block,
+                              h->stream);
+    else
+        lbm::launch_phase_get_h(h->p.precision, h->cp->buf[h->cur], h->g, dst, h->grid, h->block, h->stream);
     hipError_t e = hipGetLastError();
     if (!on_device) {
         if (e == hipSuccess) e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, h->stream);
@@ -214,9 +250,58 @@ int lbm_set_coupled_populations(lbm_handle* h, const double* in, int on_device)
     Staged s;
     int rc = stage_in(in, (int64_t)h->cp->q * h->g.N, on_device, h->stream, s);
     if (rc) return rc;
-    lbm::launch_phase_set_h(h->p.precision, h->cp->buf[h->cur], h->g, s.ptr, h->grid, h->block, h->stream);
+    if (h->p.coupled == LBM_COUPLED_MAGNETIC)
+        lbm::launch_mhd_set_g(h->p.precision, h->walls, h->cp->buf[h->cur], h->g, h->cp->mc, s.ptr, h->grid, h->block,
+                              h->stream);
+    else
+        lbm::launch_phase_set_h(h->p.precision, h->cp->buf[h->cur], h->g, s.ptr, h->grid, h->block, h->stream);
     CHIP(hipGetLastError());
     if (!on_device) CHIP(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_init_magnetic(lbm_handle* h, const double* rho, const double* u, const double* b, int on_device)
+{
+    if (!h || !rho || !u || !b) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (!h->cp || h->p.coupled != LBM_COUPLED_MAGNETIC) return lbm_fail(LBM_EINVAL, "not a magnetic lattice");
+    const int64_t N = h->g.N;
+    Staged sr, su, sb;
+    int rc = stage_in(rho, N, on_device, h->stream, sr);
+    if (!rc) rc = stage_in(u, 3 * N, on_device, h->stream, su);
+    if (!rc) rc = stage_in(b, 3 * N, on_device, h->stream, sb);
+    if (rc) return rc;
+    h->steps = 0;
+    h->cur = 0;
+    lbm::launch_mhd_init(h->p.precision, h->walls, h->buf[0], h->cp->buf[0], h->g, h->p.rho0, h->cp->mc, sr.ptr, su.ptr,
+                         sb.ptr, h->grid, h->block, h->stream);
+    CHIP(hipGetLastError());
+    if (!on_device) CHIP(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_magnetic_fields(lbm_handle* h, double* b, double* j, int on_device)
+{
+    if (!h) return lbm_fail(LBM_EINVAL, "NULL handle");
+    if (!h->cp || h->p.coupled != LBM_COUPLED_MAGNETIC) return lbm_fail(LBM_EINVAL, "not a magnetic lattice");
+    const int64_t N = h->g.N;
+    double* db = b;
+    double* dj = j;
+    double* staging = nullptr;
+    if (!on_device && (b || j)) {
+        CHIP(hipMalloc((void**)&staging, sizeof(double) * 6 * N));
+        db = b ? staging : nullptr;
+        dj = j ? staging + 3 * N : nullptr;
+    }
+    lbm::launch_mhd_fields(h->p.precision, h->walls, h->buf[h->cur], h->cp->buf[h->cur], h->g, h->ph, h->cp->mc, nullptr,
+                           nullptr, db, dj, h->partials, h->grid, h->block, h->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && staging) {
+        if (b) e = hipMemcpyAsync(b, staging, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && j) e = hipMemcpyAsync(j, staging + 3 * N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    if (staging) hipFree(staging);
+    if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "magnetic fields: %s", hipGetErrorString(e));
     return LBM_OK;
 }
 

@@ -7,14 +7,15 @@
 
 #include "lbm.h"
 #include "lbm_internal.hpp"
-#include "phase_cm.hpp"
+#include "coupled.hpp"
 
 // State of a coupled lattice (lbm_params.coupled != LBM_COUPLED_NONE).
 struct lbm_coupled {
     void* buf[2] = {nullptr, nullptr}; // its populations (A-B), same stride as the flow lattice
-    int q = 0;                         // populations per node (7 for the phase field)
+    int q = 0;                         // populations per node (7 phase, 21 magnetic)
     void* scratch = nullptr;           // phase field phi (storage-precision arithmetic type)
     lbm::PhaseConst pc{};
+    lbm::MhdConst mc{};
 };
 
 struct lbm_handle {

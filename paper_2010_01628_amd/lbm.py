@@ -137,6 +137,10 @@ def lib():
                      "lbm_ensemble_energy", "lbm_ensemble_get_populations", "lbm_ensemble_tune",
                      "lbm_ensemble_destroy"):
             getattr(L, name).restype = i32
+        L.lbm_init_magnetic.argtypes = [vp, vp, vp, vp, i32]
+        L.lbm_magnetic_fields.argtypes = [vp, vp, vp, i32]
+        L.lbm_init_magnetic.restype = i32
+        L.lbm_magnetic_fields.restype = i32
         L.lbm_init_phase.argtypes = [vp, vp, vp, vp, i32]
         L.lbm_phase_fields.argtypes = [vp, vp, vp, i32]
         L.lbm_get_coupled_populations.argtypes = [vp, vp, i32]
@@ -409,9 +413,10 @@ class Ensemble:
 def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
                 rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
                 force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0,
-                q=19, phase=None) -> lbm_params:
+                q=19, phase=None, magnetic=None) -> lbm_params:
     """phase: dict(rho_light, rho_heavy, sigma, width, mobility) makes a
-    two-phase lattice (coupled = LBM_COUPLED_PHASE)."""
+    two-phase lattice (coupled = LBM_COUPLED_PHASE); magnetic: dict(eta,
+    b_wall=(bx, by, bz)) a magnetic one (LBM_COUPLED_MAGNETIC)."""
     p = lbm_params_default()
     p.q = int(q)
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -432,6 +437,12 @@ def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_b
     p.check_every = int(check_every)
     p.block_x, p.block_y = int(block[0]), int(block[1])
     p.cache_policy = int(cache_policy)
+    if magnetic is not None:
+        p.coupled = LBM_COUPLED_MAGNETIC
+        p.magnetic.eta = float(magnetic["eta"])
+        bw = magnetic.get("b_wall", (0.0, 0.0, 0.0))
+        for d in range(3):
+            p.magnetic.b_wall[d] = float(bw[d])
     if phase is not None:
         p.coupled = LBM_COUPLED_PHASE
         for k in ("rho_light", "rho_heavy", "sigma", "width", "mobility"):
@@ -543,7 +554,25 @@ class Lattice:
         self.stream.synchronize()
         return phi, p
 
-    def get_coupled_populations(self, q=7):
+    # -- magnetic lattices ---------------------------------------------------
+    def init_magnetic(self, rho, u, b):
+        a, c, e = self._dev(rho), self._dev(u), self._dev(b)
+        assert a.numel() == self.N and c.numel() == 3 * self.N and e.numel() == 3 * self.N
+        _check(lib().lbm_init_magnetic(self.h, a.data_ptr(), c.data_ptr(), e.data_ptr(), 1))
+        self.stream.synchronize()
+
+    def magnetic_fields(self):
+        """(b, j) as device float64 tensors (3, nz, ny, nx)."""
+        t = self.torch
+        b = t.empty((3,) + self.shape, dtype=t.float64, device="cuda")
+        j = t.empty((3,) + self.shape, dtype=t.float64, device="cuda")
+        _check(lib().lbm_magnetic_fields(self.h, b.data_ptr(), j.data_ptr(), 1))
+        self.stream.synchronize()
+        return b, j
+
+    def get_coupled_populations(self, q=None):
+        if q is None:
+            q = 21 if self.params.coupled == LBM_COUPLED_MAGNETIC else 7
         t = self.torch
         f = t.empty((q,) + self.shape, dtype=t.float64, device="cuda")
         _check(lib().lbm_get_coupled_populations(self.h, f.data_ptr(), 1))

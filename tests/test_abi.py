@@ -143,3 +143,19 @@ def test_phase_lattice_validation(lbm, kw, code):
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_create(p, None)
     assert e.value.code == code, lbm.lib().lbm_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(q=27), -5), (dict(precision=3), -5), (dict(streaming=1), -5), (dict(omega_bulk=1.2), -5),
+    (dict(eta=0.0), -1), (dict(eta=float("nan")), -1),
+])
+def test_magnetic_lattice_validation(lbm, kw, code):
+    p = lbm.make_params(8, 8, 8, precision="fp32", magnetic=dict(eta=0.1, b_wall=(0.0, 0.01, 0.0)))
+    for k, v in kw.items():
+        if k == "eta":
+            p.magnetic.eta = v
+        else:
+            setattr(p, k, v)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, None)
+    assert e.value.code == code, lbm.lib().lbm_last_error().decode()
