@@ -241,13 +241,42 @@ template <class R> __device__ inline void node_force(const Phys& ph, const Geom&
 
 // One fused step at one node.  Block (bx, by, 1) covers bx x-values of by
 // rows; blockIdx.z is the z plane.
+// Block coordinates of this work-group.  A 3-D grid (ceil(nx/bx), ceil(ny/by),
+// nz) maps directly.  A 1-D grid of all those blocks (T of them, a multiple of
+// 8 * chunk) is read in the same x-then-y-then-z order after an XCD-aware
+// permutation: work-groups go to the eight XCDs round-robin by launch index
+// L, so XCD L % 8 takes its k-th block (k = L / 8) from block
+// (k / chunk) * 8 chunk + (L % 8) chunk + k % chunk, i.e. each XCD sweeps runs
+// of `chunk` consecutive blocks (rows), interleaved with the other XCDs'.
+__device__ inline void block_coords(const Geom& g, int chunk, int& bxi, int& byi, int& bz)
+{
+    if (gridDim.y == 1 && gridDim.z == 1) {
+        int L = blockIdx.x;
+        if (chunk > 1) {
+            const int k = L >> 3;
+            L = (k / chunk) * (8 * chunk) + (L & 7) * chunk + k % chunk;
+        }
+        const int gx = (g.nx + blockDim.x - 1) / blockDim.x;
+        const int gy = (g.ny + blockDim.y - 1) / blockDim.y;
+        bxi = L % gx;
+        const int t = L / gx;
+        byi = t % gy;
+        bz = t / gy;
+    } else {
+        bxi = blockIdx.x;
+        byi = blockIdx.y;
+        bz = blockIdx.z;
+    }
+}
+
 template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
 __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys& ph)
 {
     using R = typename Codec<S>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+    int bxi, byi, z;
+    block_coords(g, g.xcd_chunk, bxi, byi, z);
+    const int x = bxi * blockDim.x + threadIdx.x;
+    const int y = byi * blockDim.y + threadIdx.y;
     if (x >= g.nx || y >= g.ny) return;
     NodeIdx d;
     node_idx(g, x, y, z, d);

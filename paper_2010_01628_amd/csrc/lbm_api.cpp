@@ -220,6 +220,18 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
     h->block = dim3(bx, by, 1);
     h->grid = dim3((p->nx + bx - 1) / bx, (p->ny + by - 1) / by, p->nz);
     h->nblocks = h->grid.x * h->grid.y * h->grid.z;
+    // step kernels: LBM_XCD_CHUNK=c > 1 launches one 1-D grid of the same
+    // blocks permuted so that each XCD sweeps runs of c consecutive rows.
+    // Measured at 256^3 (A-B, c = 2..64 and one contiguous range per XCD):
+    // FP32 within +-0.5 %, FP16 shifted 12-17 % slower, so the default keeps
+    // the 3-D grid and the hardware's round-robin order.
+    {
+        const char* env = std::getenv("LBM_XCD_CHUNK");
+        const int chunk = env ? std::atoi(env) : 1;
+        const bool remap = chunk > 1 && h->nblocks % (8 * chunk) == 0;
+        h->g.xcd_chunk = remap ? chunk : 1;
+        h->step_grid = remap ? dim3(h->nblocks, 1, 1) : h->grid;
+    }
 
     const int64_t pop_bytes = (int64_t)p->q * h->g.stride * eb;
     const int nbuf = p->streaming == LBM_AB ? 2 : 1;
@@ -336,7 +348,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
                                  h->mlp->packed, h->fb_partials, h->grid, h->block, h->stream);
         else
             lbm::launch_step(h->p.q, h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g,
-                             h->ph, h->grid, h->block, h->stream);
+                             h->ph, h->step_grid, h->block, h->stream);
         h->cur = dst;
         h->steps++;
         if (h->p.check_every > 0 && h->steps % h->p.check_every == 0) {

@@ -13,6 +13,7 @@ struct Geom {
     int nx, ny, nz, nxy;
     int N;          // nodes
     int64_t stride; // elements between consecutive population arrays (>= N)
+    int xcd_chunk = 1; // 1-D step grids: rows per XCD run (1 = launch order)
 };
 
 struct Phys {
