@@ -118,6 +118,56 @@ def time_ensemble(L, inputs, torch, steps, warmup, mlp):
     return out
 
 
+def time_coupled(L, inputs, torch, steps, warmup):
+    """Coupled-lattice workloads: the two-phase droplet (192^3, R = 32,
+    density ratio 10, sigma = 1e-3, W = 4, FP32) and the Hartmann channel
+    (32 x 128 x 32, Ha = 10, FP32).  Algorithmic bytes per node and step:
+    two-phase 244 (flow 152, phase 56, phi 32 + 4), magnetic 320."""
+    import numpy as np
+
+    out = {}
+    n = 192
+    phi = inputs.droplet((n, n, n), 32.0, 4.0, noise=1e-3, seed=192)
+    par = L.make_params(n, n, n, precision="fp32", omega=1.25,
+                        phase=dict(rho_light=1.0, rho_heavy=10.0, sigma=1e-3, width=4.0, mobility=0.1))
+    lat = L.Lattice(par)
+    lat.init_phase(phi, np.full(phi.shape, 1.0 / 3.0), np.zeros((3,) + phi.shape))
+    del phi
+    out["phase_192"] = _time_lattice(lat, torch, steps, warmup, n ** 3, 244)
+    lat.close()
+    nx, ny, nz = 32, 128, 32
+    b0 = 10.0 * 2 * 0.1 / ny
+    F = 0.02 * b0 ** 2 * np.tanh(10.0) / (0.1 * 10.0 * (1 - 1 / np.cosh(10.0)))
+    par = L.make_params(nx, ny, nz, precision="fp32", omega=1.0 / 0.8, walls_y=True, force_mode=L.LBM_FORCE_UNIFORM,
+                        force=(F, 0.0, 0.0), magnetic=dict(eta=0.1, b_wall=(0.0, b0, 0.0)))
+    lat = L.Lattice(par)
+    b = np.zeros((3, nz, ny, nx))
+    b[1] = b0
+    lat.init_magnetic(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)), b)
+    out["hartmann_32x128x32"] = _time_lattice(lat, torch, 4 * steps, warmup, nx * ny * nz, 320)
+    lat.close()
+    return out
+
+
+def _time_lattice(lat, torch, steps, warmup, nodes, bytes_per_node):
+    lat.step(warmup)
+    st = lat.stream
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.record(st)
+    lat.step(steps)
+    b.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = a.elapsed_time(b) / steps
+    gbs = nodes * bytes_per_node / (ms * 1e-3) / 1e9
+    _, _, diag = lat.moments(want_fields=False)
+    return {"mlups": round(nodes * steps / wall / 1e6, 1), "ms_per_step": round(ms, 5),
+            "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "algo_bytes_per_node": bytes_per_node, "finite": all(x == x for x in diag)}
+
+
 def bench_network(L):
     """A fixed network for throughput runs: random hidden layers and a small
     random output layer, so the rates spread around 1 without fallbacks (the
@@ -187,6 +237,7 @@ def main(argv=None):
     ap.add_argument("--variants", default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,fp64:ab,fp32+mlp:ab,fp16+mlp:ab",
                     help="extra precision[+mlp]:streaming pairs to time ('' = none); +mlp = learned rates")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble workload")
+    ap.add_argument("--no-coupled", action="store_true", help="skip the two-phase and magnetic workloads")
     ap.add_argument("--mem-check", action="store_true",
                     help="also run 512^3 AA FP32 and FP16 (device bytes and MLUPS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -250,6 +301,10 @@ def main(argv=None):
             mlp = bench_network(L)
         log("bench: ensemble workload")
         ensemble = time_ensemble(L, inputs, torch, max(20, args.steps // 2), max(4, args.warmup // 2), mlp)
+    coupled = None
+    if not args.no_coupled:
+        log("bench: coupled-lattice workloads")
+        coupled = time_coupled(L, inputs, torch, max(20, args.steps // 2), max(4, args.warmup // 2))
     mem = None
     if args.mem_check:
         log("bench: 512^3 memory check")
@@ -310,6 +365,7 @@ def main(argv=None):
                          **({"fallbacks": v["fallbacks"]} if v["fallbacks"] is not None else {})}
                      for k, v in variants.items()},
         "ensemble": ensemble,
+        "coupled": coupled,
         "mem_check_512": mem,
         "kernel_source_hash": kernel_source_hash(),
     }

@@ -72,20 +72,12 @@ __global__ __launch_bounds__(256) void k_ens_step(const S* __restrict__ src_all,
 // Learned rates (D3Q19, FP32 collision): every thread of a block takes part in
 // the network each iteration (tiles past a box's end work on a clamped node).
 template <class S>
-__global__ __launch_bounds__(256) void k_ens_step_mlp(const S* __restrict__ src_all, S* __restrict__ dst_all,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ens_step_mlp(const S* __restrict__ src_all, S* __restrict__ dst_all,
                                                       const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
                                                       int ntiles, float rho0, const MlpPacked* __restrict__ net,
                                                       uint32_t* __restrict__ fb_counts)
 {
-    __shared__ uint32_t snet_words[MLP_INFER_WORDS];
-    __shared__ uint16_t tiles[4][2][MLP_TILE];
     __shared__ uint32_t wave_fb[4];
-    {
-        const uint32_t* s = reinterpret_cast<const uint32_t*>(net);
-        for (int i = threadIdx.x; i < MLP_INFER_WORDS; i += blockDim.x) snet_words[i] = s[i];
-        __syncthreads();
-    }
-    const MlpPacked& snet = *reinterpret_cast<const MlpPacked*>(snet_words);
     const int w = threadIdx.x >> 6;
     uint32_t my_fb = 0;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -100,25 +92,34 @@ __global__ __launch_bounds__(256) void k_ens_step_mlp(const S* __restrict__ src_
         node_idx(g, x, y, z, d);
         float s[19];
         gather<LatD3Q19, S, AB, false, true>(src_all + bd.off, g.stride, d, s);
-        CMState<float> st;
-        pre_collide<float, true>(s, rho0, 0.0f, 0.0f, 0.0f, st);
         float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];
         {
-            const float ir = 1.0f / st.rho;
-            xin[0] = st.rho - 1.0f;
-            xin[1] = st.k4 * ir;
-            xin[2] = st.n.m210 * ir;
-            xin[3] = st.n.m120 * ir;
-            xin[4] = st.n.m201 * ir;
-            xin[5] = st.n.m102 * ir;
-            xin[6] = st.n.m021 * ir;
-            xin[7] = st.n.m012 * ir;
-            xin[8] = st.n.m220 * ir;
-            xin[9] = st.n.m202 * ir;
-            xin[10] = st.n.m022 * ir;
+            CMState<float> st0;
+            pre_collide<float, true>(s, rho0, 0.0f, 0.0f, 0.0f, st0);
+            const float ir = 1.0f / st0.rho;
+            xin[0] = st0.rho - 1.0f;
+            xin[1] = st0.k4 * ir;
+            xin[2] = st0.n.m210 * ir;
+            xin[3] = st0.n.m120 * ir;
+            xin[4] = st0.n.m201 * ir;
+            xin[5] = st0.n.m102 * ir;
+            xin[6] = st0.n.m021 * ir;
+            xin[7] = st0.n.m012 * ir;
+            xin[8] = st0.n.m220 * ir;
+            xin[9] = st0.n.m202 * ir;
+            xin[10] = st0.n.m022 * ir;
         }
-        mlp_forward_wave(snet, tiles[w][0], tiles[w][1], tiles[w][0], reinterpret_cast<float*>(tiles[w][1]), xin, zout);
+        // the network is re-read every tile (L1/L2 hits) rather than held in
+        // registers across the loop: hoisting its loads costs ~70 registers
+        const MlpPacked* netp = net;
+        asm volatile("" : "+s"(netp));
+        mlp_forward_regs(*netp, xin, zout);
         const bool fb = mlp_rates(zout, rates);
+        // recomputed rather than kept live across the network (registers)
+#pragma unroll
+        for (int i = 0; i < 19; ++i) asm volatile("" : "+v"(s[i]));
+        CMState<float> st;
+        pre_collide<float, true>(s, rho0, 0.0f, 0.0f, 0.0f, st);
         Rates<float> rt;
         rt.omega = (float)bd.omega;
         rt.omega_bulk = 1.0f;

@@ -42,14 +42,10 @@ __device__ inline void load_net(uint32_t* d, const MlpPacked* __restrict__ src, 
 // nodes that fell back is added to fb_partials[block].
 // ---------------------------------------------------------------------------
 template <class S, Pattern P, bool WALLS, bool NT>
-__global__ __launch_bounds__(256) void k_step_mlp(const S* src, S* dst, Geom g, Phys ph,
-                                                  const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
+__device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const Phys& ph,
+                                     const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
 {
-    __shared__ uint32_t snet_words[MLP_INFER_WORDS];
-    __shared__ uint16_t tiles[4][2][MLP_TILE];
     __shared__ uint32_t wave_fb[4];
-    load_net(snet_words, net, MLP_INFER_WORDS);
-    const MlpPacked& snet = *reinterpret_cast<const MlpPacked*>(snet_words);
     const int xr = blockIdx.x * blockDim.x + threadIdx.x;
     const int yr = blockIdx.y * blockDim.y + threadIdx.y;
     const bool valid = xr < g.nx && yr < g.ny;
@@ -62,15 +58,23 @@ __global__ __launch_bounds__(256) void k_step_mlp(const S* src, S* dst, Geom g, 
     gather<LatD3Q19, S, P, WALLS, NT>(src, g.stride, d, s);
     float Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
-    CMState<float> st;
-    pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
     float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];
-    mlp_features(st, xin);
+    {
+        CMState<float> st0;
+        pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st0);
+        mlp_features(st0, xin);
+    }
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int w = tid >> 6;
-    // tile 0: inputs then second hidden layer; tile 1: first hidden layer then outputs
-    mlp_forward_wave(snet, tiles[w][0], tiles[w][1], tiles[w][0], reinterpret_cast<float*>(tiles[w][1]), xin, zout);
+    mlp_forward_regs(*net, xin, zout);
     const bool fb = mlp_rates(zout, rates);
+    // the collision state is recomputed rather than kept live across the
+    // network (register pressure); the empty asm keeps the compiler from
+    // reusing the first computation
+#pragma unroll
+    for (int i = 0; i < 19; ++i) asm volatile("" : "+v"(s[i]));
+    CMState<float> st;
+    pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
     Rates<float> rt = rates_of<float>(ph);
 #pragma unroll
     for (int j = 0; j < MLP_NOUT; ++j) rt.omega_hi[j] = rates[j];
@@ -91,6 +95,22 @@ __global__ __launch_bounds__(256) void k_step_mlp(const S* src, S* dst, Geom g, 
         const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
         fb_partials[bid] += c;
     }
+}
+
+// A-B fits four waves per SIMD without spilling (115 VGPRs); the AA variants
+// would spill under that limit and keep the compiler's choice.
+template <class S, bool WALLS, bool NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_step_mlp_ab(
+    const S* src, S* dst, Geom g, Phys ph, const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
+{
+    step_mlp_body<S, AB, WALLS, NT>(src, dst, g, ph, net, fb_partials);
+}
+
+template <class S, Pattern P, bool WALLS, bool NT>
+__global__ __launch_bounds__(256) void k_step_mlp(const S* src, S* dst, Geom g, Phys ph,
+                                                  const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
+{
+    step_mlp_body<S, P, WALLS, NT>(src, dst, g, ph, net, fb_partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -466,7 +486,10 @@ static void step_mlp_s(int pattern, bool walls, bool nt, const void* src, void* 
     S* b = (S*)dst;
     const MlpPacked* w = (const MlpPacked*)net;
 #define LBM_MLP_STEP(P, W, NT_)                                                                       \
-    hipLaunchKernelGGL((k_step_mlp<S, P, W, NT_>), grid, block, 0, st, a, b, g, ph, w, fb)
+    do {                                                                                              \
+        if constexpr (P == AB) hipLaunchKernelGGL((k_step_mlp_ab<S, W, NT_>), grid, block, 0, st, a, b, g, ph, w, fb); \
+        else hipLaunchKernelGGL((k_step_mlp<S, P, W, NT_>), grid, block, 0, st, a, b, g, ph, w, fb);    \
+    } while (0)
 #define LBM_MLP_NT(P, W) \
     if (nt) LBM_MLP_STEP(P, W, true); else LBM_MLP_STEP(P, W, false)
 #define LBM_MLP_W(P) \

@@ -64,12 +64,13 @@ __host__ __device__ inline float bf16_to_f32(uint16_t b)
 }
 
 // tanh for activations that are rounded to bf16 next: 1 - 2/(exp(2x) + 1)
-// for |x| >= 1/4, and the odd Taylor polynomial through x^7 below (its
-// truncation error, < 1e-7 there, avoids the cancellation of the exp form).
+// (hardware exp and reciprocal, ~1 ulp each) for |x| >= 1/4, and the odd
+// Taylor polynomial through x^7 below (its truncation error, < 1e-7 there,
+// avoids the cancellation of the exp form).
 __device__ inline float tanh_fast(float x)
 {
     const float e = __expf(2.0f * x);
-    const float big = 1.0f - 2.0f / (e + 1.0f);
+    const float big = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
     const float x2 = x * x;
     const float small = x * (1.0f + x2 * (-1.0f / 3.0f + x2 * (2.0f / 15.0f + x2 * (-17.0f / 315.0f))));
     return fabsf(x) < 0.25f ? small : big;
@@ -150,6 +151,135 @@ __device__ inline void mlp_forward_wave(const MlpPacked& W, uint16_t* tx, uint16
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
     for (int j = 0; j < MLP_NOUT; ++j) z[j] = tz[l * MLP_NOUT + j];
+}
+
+// ---------------------------------------------------------------------------
+// Inference with the activations kept in registers.  Each layer is computed
+// transposed, Y^T[out][node] = W[out][k] X^T[k][node], as two 32-node column
+// blocks.  With A = W (lane l: W[l % 32][k0 + 4 (l / 32) + v]) and B = X^T
+// (lane l: X^T[k0 + 4 (l / 32) + v][node l % 32]), the accumulator of one
+// layer, acc[r] = Y^T[8 (r / 4) + 4 (l / 32) + r % 4][l % 32], holds in
+// acc[4m .. 4m+3] exactly the B operand of k-step k0 = 8m of the next layer:
+// hidden layers chain without data movement.  Only the input (lane = node,
+// features split over the two half-waves) and the output (rates back to the
+// node's lane) cross half-waves, by v_permlane32_swap.
+// ---------------------------------------------------------------------------
+__device__ inline bf16x4_t pack_bf16(float a, float b, float c, float d)
+{
+    bf16x4_t r;
+    r[0] = __builtin_bit_cast(short, (__bf16)a);
+    r[1] = __builtin_bit_cast(short, (__bf16)b);
+    r[2] = __builtin_bit_cast(short, (__bf16)c);
+    r[3] = __builtin_bit_cast(short, (__bf16)d);
+    return r;
+}
+
+// swap: a <- [a.lo | b.lo], b <- [a.hi | b.hi] (half-waves of 32 lanes)
+__device__ inline void swap_halves(uint32_t& a, uint32_t& b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
+__device__ inline void swap_halves(bf16x4_t& a, bf16x4_t& b)
+{
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 ua = __builtin_bit_cast(u32x2, a), ub = __builtin_bit_cast(u32x2, b);
+    uint32_t a0 = ua[0], a1 = ua[1], b0 = ub[0], b1 = ub[1];
+    swap_halves(a0, b0);
+    swap_halves(a1, b1);
+    ua[0] = a0;
+    ua[1] = a1;
+    ub[0] = b0;
+    ub[1] = b1;
+    a = __builtin_bit_cast(bf16x4_t, ua);
+    b = __builtin_bit_cast(bf16x4_t, ub);
+}
+__device__ inline void swap_halves(float& a, float& b)
+{
+    uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
+    swap_halves(ua, ub);
+    a = __builtin_bit_cast(float, ua);
+    b = __builtin_bit_cast(float, ub);
+}
+
+// bias in accumulator layout: acc[r] = b[8 (r / 4) + 4 (l / 32) + r % 4] (rows < nrows)
+__device__ inline f32x16_t bias_acc(const float* b, int nrows)
+{
+    const int kh = 4 * (lane_id() >> 5);
+    f32x16_t acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = 8 * (r >> 2) + kh + (r & 3);
+        acc[r] = j < nrows ? b[j] : 0.0f;
+    }
+    return acc;
+}
+
+// tanh and bf16 of an accumulator: the next layer's four B operands
+__device__ inline void act_to_operands(const f32x16_t& acc, bf16x4_t op[4])
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        op[m] = pack_bf16(tanh_fast(acc[4 * m]), tanh_fast(acc[4 * m + 1]), tanh_fast(acc[4 * m + 2]),
+                          tanh_fast(acc[4 * m + 3]));
+}
+
+// One 32-node column block through the three layers; o[q] = accumulator
+// rows q (q < 5) of the output layer.
+__device__ inline void mlp_block_regs(const MlpPacked& W, const bf16x4_t in[2], float o[5])
+{
+    const int l = lane_id();
+    const int row = l & 31, kh = 4 * (l >> 5);
+    f32x16_t acc = bias_acc(W.b1, MLP_NH);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w1 + row * 16 + 8 * s + kh), in[s], acc, 0, 0, 0);
+    bf16x4_t h[4];
+    act_to_operands(acc, h);
+    acc = bias_acc(W.b2, MLP_NH);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w2 + row * 32 + 8 * m + kh), h[m], acc, 0, 0, 0);
+    act_to_operands(acc, h);
+    acc = bias_acc(W.b3, MLP_NOUT);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w3 + row * 32 + 8 * m + kh), h[m], acc, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) o[q] = acc[q];
+}
+
+// Forward pass for the 64 nodes of this wavefront (node = lane), network W in
+// global or LDS memory.  x: this lane's 11 raw features; z: its 9 outputs.
+// Must be called by all 64 lanes.
+__device__ inline void mlp_forward_regs(const MlpPacked& W, const float x[MLP_NIN], float z[MLP_NOUT])
+{
+    // layer-1 B operands: features scaled and rounded; after the swap, in0
+    // feeds block 0 (nodes 0..31) and in1 block 1 (nodes 32..63)
+    float xs[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xs[k] = k < MLP_NIN ? x[k] * W.inv_scale[k] : 0.0f;
+    bf16x4_t in0[2], in1[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        in0[s] = pack_bf16(xs[8 * s], xs[8 * s + 1], xs[8 * s + 2], xs[8 * s + 3]);
+        in1[s] = pack_bf16(xs[8 * s + 4], xs[8 * s + 5], xs[8 * s + 6], xs[8 * s + 7]);
+        swap_halves(in0[s], in1[s]);
+    }
+    // o_b[q]: output q (lanes < 32) or 4 + q (lanes >= 32) of node 32 b + l % 32;
+    // o_b[4]: output 8 (lanes < 32)
+    float o0[5], o1[5];
+    mlp_block_regs(W, in0, o0);
+    mlp_block_regs(W, in1, o1);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) swap_halves(o0[q], o1[q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        z[q] = o0[q];
+        z[4 + q] = o1[q];
+    }
+    z[8] = o0[4];
 }
 
 // rates 1 + z, or the paper's rates (all 1) when any leaves (0, 2); returns
