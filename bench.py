@@ -99,6 +99,7 @@ def time_ensemble(L, inputs, torch, steps, warmup, mlp):
             ens.init(b, rho, u)
         if net is not None:
             ens.set_mlp(net)
+        grid = ens.tune(10)  # work-groups of the persistent launch (times real steps)
         ens.step(warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -108,7 +109,7 @@ def time_ensemble(L, inputs, torch, steps, warmup, mlp):
         bpn = 2 * q * 4
         out[name] = {"mlups": round(ens.nodes * steps / wall / 1e6, 1),
                      "achieved_GBs": round(ens.nodes * bpn * steps / wall / 1e9, 1),
-                     "algo_bytes_per_node": bpn}
+                     "algo_bytes_per_node": bpn, "grid": grid}
         if net is not None:
             out[name]["fallback_rate"] = ens.fallback_count() / float(ens.nodes * (steps + warmup))
         out["nodes"] = ens.nodes

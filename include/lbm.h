@@ -312,10 +312,12 @@ int lbm_ensemble_get_populations(lbm_ensemble *e, int32_t box, double *f, int on
 int64_t lbm_ensemble_nodes(const lbm_ensemble *e);
 int64_t lbm_ensemble_step_count(const lbm_ensemble *e);
 int64_t lbm_ensemble_fallback_count(lbm_ensemble *e);
-/* Autotuner: times `trial_steps` steps for each candidate number of
- * persistent workgroups and keeps the fastest (*grid_out, may be NULL).  It
- * advances the state by those steps; call it before lbm_ensemble_init (the
- * rest state is a fixed point). */
+/* Autotuner: times `trial_steps` steps (rounded up to even) for each
+ * candidate launch -- 2, 4, 8, 16, 32 or 64 persistent work-groups per
+ * compute unit, or one work-group per tile -- and keeps the fastest
+ * (*grid_out, may be NULL).  It advances the state by those steps; call it
+ * before lbm_ensemble_init (the rest state is a fixed point) to leave the
+ * state untouched. */
 int lbm_ensemble_tune(lbm_ensemble *e, int32_t trial_steps, int32_t *grid_out);
 int lbm_ensemble_destroy(lbm_ensemble *e);
 

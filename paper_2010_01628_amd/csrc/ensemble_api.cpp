@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -59,7 +60,8 @@ struct lbm_ensemble {
     double* tile_out = nullptr;
     double* box_out = nullptr;
     const lbm_mlp* mlp = nullptr;
-    uint32_t* fb = nullptr;
+    uint32_t* fb = nullptr;  // fallback counts, one per work-group of the largest grid
+    int64_t fb_len = 0;
     int grid = 0;
     // captured step loop: `graph_steps` steps starting from buffer parity 0
     hipGraph_t graph = nullptr;
@@ -174,14 +176,15 @@ int lbm_ensemble_create(const lbm_box* boxes, int32_t nboxes, int32_t q, int32_t
         hipMalloc((void**)&e->tile_count_dev, sizeof(int) * nboxes) != hipSuccess ||
         hipMalloc((void**)&e->tile_out, sizeof(double) * 2 * tiles) != hipSuccess ||
         hipMalloc((void**)&e->box_out, sizeof(double) * 2 * nboxes) != hipSuccess ||
-        hipMalloc((void**)&e->fb, sizeof(uint32_t) * (size_t)ncu * 64) != hipSuccess)
+        hipMalloc((void**)&e->fb, sizeof(uint32_t) * (size_t)(e->fb_len = std::max<int64_t>((int64_t)ncu * 64, tiles))) !=
+            hipSuccess)
         return cleanup(efail(LBM_ENOMEM, "ensemble tables"));
     hipError_t err = hipMemcpy(e->boxes_dev, desc.data(), desc.size(), hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(e->tile_box_dev, tile_box.data(), sizeof(int) * tiles, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(e->tile_count_dev, e->tiles.data(), sizeof(int) * nboxes, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemset(e->buf[0], 0, elems * e->eb);
     if (err == hipSuccess) err = hipMemset(e->buf[1], 0, elems * e->eb);
-    if (err == hipSuccess) err = hipMemset(e->fb, 0, sizeof(uint32_t) * (size_t)ncu * 64);
+    if (err == hipSuccess) err = hipMemset(e->fb, 0, sizeof(uint32_t) * (size_t)e->fb_len);
     // the set-up above ran on the null stream; the ensemble's stream may not
     // be ordered with it
     if (err == hipSuccess) err = hipDeviceSynchronize();
@@ -336,8 +339,8 @@ int64_t lbm_ensemble_fallback_count(lbm_ensemble* e)
 {
     if (!e) return efail(LBM_EINVAL, "NULL ensemble");
     if (hipStreamSynchronize(e->stream) != hipSuccess) return efail(LBM_EDEVICE, "sync");
-    std::vector<uint32_t> host(e->grid);
-    if (hipMemcpy(host.data(), e->fb, sizeof(uint32_t) * e->grid, hipMemcpyDeviceToHost) != hipSuccess)
+    std::vector<uint32_t> host(e->fb_len);
+    if (hipMemcpy(host.data(), e->fb, sizeof(uint32_t) * e->fb_len, hipMemcpyDeviceToHost) != hipSuccess)
         return efail(LBM_EDEVICE, "copy");
     int64_t t = 0;
     for (uint32_t v : host) t += v;
@@ -352,7 +355,8 @@ int lbm_ensemble_tune(lbm_ensemble* e, int32_t trial_steps, int32_t* grid_out)
     EHIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     // Candidates: workgroups per CU.  Timing runs real steps on the current
     // state, then the buffers return to the same parity (even step counts).
-    const int mult[] = {2, 4, 8, 16, 32};
+    // (0: one work-group per tile, i.e. no persistence)
+    const int mult[] = {2, 4, 8, 16, 32, 64, 0};
     hipEvent_t a, b;
     EHIP(hipEventCreate(&a));
     EHIP(hipEventCreate(&b));
@@ -360,7 +364,7 @@ int lbm_ensemble_tune(lbm_ensemble* e, int32_t trial_steps, int32_t* grid_out)
     int best = e->grid;
     const int steps = trial_steps + (trial_steps & 1);
     for (int m : mult) {
-        int g = ncu * m;
+        int g = m ? ncu * m : e->ntiles;
         if (g > e->ntiles) g = e->ntiles;
         e->grid = g;
         launch_one(e);
