@@ -37,7 +37,7 @@ def elem_bytes(precision: str) -> int:
     return {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[precision]
 
 
-def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fields, mlp=None):
+def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fields, mlp=None, tune=True):
     nu = 1e-3
     p = L.make_params(size, size, size, precision=precision, streaming=streaming,
                       omega=inputs.omega_from_nu(nu), force_mode=L.LBM_FORCE_KOLMOGOROV,
@@ -45,8 +45,12 @@ def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fi
     lat = L.Lattice(p)
     rho_d, u_d = fields
     lat.init(rho_d, u_d)
+    launch = None
     if mlp is not None:
         lat.attach_mlp(mlp)
+    elif tune:
+        launch = lat.tune(10)  # work-group shape and cache hints, timed on real steps
+        lat.init(rho_d, u_d)
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = lat.stream
@@ -81,10 +85,11 @@ def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fi
         "sum_rho": diag[0],
         "finite": bool(all(x == x for x in diag)),
         "fallbacks": fallbacks,
+        "launch": launch,
     }
 
 
-def time_ensemble(L, inputs, torch, steps, warmup, mlp):
+def time_ensemble(L, inputs, torch, steps, warmup, mlp, tune=True):
     """The 64-box ensemble workload (sides 48/64/96, random-phase fields,
     u_rms 0.04, nu log-uniform in [1e-4, 1e-3]): MLUPS of plain D3Q19, learned
     D3Q19 and D3Q27, FP32 storage, one persistent launch per step replayed
@@ -99,7 +104,7 @@ def time_ensemble(L, inputs, torch, steps, warmup, mlp):
             ens.init(b, rho, u)
         if net is not None:
             ens.set_mlp(net)
-        grid = ens.tune(10)  # work-groups of the persistent launch (times real steps)
+        grid = ens.tune(10) if tune else None  # work-groups per launch (times real steps)
         ens.step(warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -239,6 +244,7 @@ def main(argv=None):
                     help="extra precision[+mlp]:streaming pairs to time ('' = none); +mlp = learned rates")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble workload")
     ap.add_argument("--no-coupled", action="store_true", help="skip the two-phase and magnetic workloads")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
     ap.add_argument("--mem-check", action="store_true",
                     help="also run 512^3 AA FP32 and FP16 (device bytes and MLUPS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -279,7 +285,8 @@ def main(argv=None):
         del a, b
 
     log(f"bench: timing {args.precision}/{args.streaming} {args.steps} steps")
-    head = time_variant(L, inputs, torch, size, args.precision, args.streaming, args.steps, args.warmup, fields)
+    head = time_variant(L, inputs, torch, size, args.precision, args.streaming, args.steps, args.warmup, fields,
+                        tune=not args.no_tune)
     variants = {}
     mlp = None
     for spec in [v for v in args.variants.split(",") if v]:
@@ -293,7 +300,7 @@ def main(argv=None):
         log(f"bench: timing variant {spec}")
         variants[f"{prec}{'_learned' if plus else ''}_{strm}"] = time_variant(
             L, inputs, torch, size, prec, strm, max(20, args.steps // 4), max(5, args.warmup // 4), fields,
-            mlp=mlp if plus else None)
+            mlp=mlp if plus else None, tune=not args.no_tune)
     del fields
     torch.cuda.empty_cache()
     ensemble = None
@@ -301,7 +308,8 @@ def main(argv=None):
         if mlp is None:
             mlp = bench_network(L)
         log("bench: ensemble workload")
-        ensemble = time_ensemble(L, inputs, torch, max(20, args.steps // 2), max(4, args.warmup // 2), mlp)
+        ensemble = time_ensemble(L, inputs, torch, max(20, args.steps // 2), max(4, args.warmup // 2), mlp,
+                                 tune=not args.no_tune)
     coupled = None
     if not args.no_coupled:
         log("bench: coupled-lattice workloads")
@@ -331,6 +339,7 @@ def main(argv=None):
         "kernel": f"lbm::k_step_{args.streaming} (fused gather-collide-store)",
         "kernel_ms_avg": round(head["kernel_ms_avg"], 5),
         "algo_bytes_per_launch": head["algo_bytes_per_launch"],
+        "launch": head["launch"],
     }
     cpu = None
     if not args.no_cpu_baseline:
@@ -362,7 +371,7 @@ def main(argv=None):
         "variants": {k: {"mlups": round(v["mlups"], 1), "achieved_GBs": round(v["achieved_GBs"], 1),
                          "frac": round(v["achieved_GBs"] / HBM_PEAK_GBS, 4),
                          "kernel_ms_avg": round(v["kernel_ms_avg"], 5),
-                         "speedup_vs_head": round(v["mlups"] / head["mlups"], 3),
+                         "speedup_vs_head": round(v["mlups"] / head["mlups"], 3), "launch": v["launch"],
                          **({"fallbacks": v["fallbacks"]} if v["fallbacks"] is not None else {})}
                      for k, v in variants.items()},
         "ensemble": ensemble,

@@ -209,6 +209,18 @@ int lbm_magnetic_fields(lbm_handle *h, double *b, double *j, int on_device);
 int lbm_get_coupled_populations(lbm_handle *h, double *out, int on_device);
 int lbm_set_coupled_populations(lbm_handle *h, const double *in, int on_device);
 
+/* Autotuner of the plain step kernel: runs 2 + trial_steps (rounded up to
+ * even) real steps for each work-group shape 256x1, 128x2, 64x4, 128x1, 64x2,
+ * 64x1 (those that fit the lattice) with and without non-temporal hints,
+ * keeps the fastest for later lbm_step calls and reports it (block_x,
+ * block_y, cache_policy 1 = non-temporal, 2 = cached; each may be NULL).  The
+ * state advances by the steps taken and the step counter counts them.  The
+ * choice is cached for the process per (GPU architecture, lattice size, q,
+ * precision, streaming, walls, general rates): a later call with the same key
+ * applies it without running steps.  Not for coupled lattices or attached
+ * networks (LBM_EUNSUPPORTED). */
+int lbm_tune(lbm_handle *h, int32_t trial_steps, int32_t *block_x, int32_t *block_y, int32_t *cache_policy);
+
 /* Number of steps taken since lbm_init. */
 int64_t lbm_step_count(const lbm_handle *h);
 
@@ -284,8 +296,10 @@ int lbm_project_q27(const double *f27, int64_t n, double *f19, float *moments, v
 
 /* ---------------------------------------------------------------------------
  * Ensembles: many independent periodic cubic boxes (different sides and
- * viscosities, no force) advanced together, one persistent launch per step
- * over a (box, 256-node tile) work list; the step loop is captured in a HIP
+ * viscosities, no force) advanced together, one launch per step over a
+ * (box, 256-node tile) work list, walked by a fixed number of work-groups
+ * (one per tile by default; lbm_ensemble_tune tries persistent grids of
+ * 2..64 work-groups per compute unit); the step loop is captured in a HIP
  * graph and replayed.  Same collision as a single lattice (Sec. II.B for q =
  * 19, App. D for q = 27); A-B streaming; FP32 or FP64 storage.
  * ------------------------------------------------------------------------- */

@@ -204,19 +204,34 @@ __global__ __launch_bounds__(256) void k_ens_tile_energy(const S* __restrict__ b
     }
 }
 
-__global__ void k_ens_box_sums(const double* __restrict__ tile_out, const BoxDesc* __restrict__ boxes, int nboxes,
-                               const int* __restrict__ tile_count, double* __restrict__ box_out)
+// One work-group per box: each thread sums a fixed strided subset of the
+// box's tile partials, then a fixed-order tree in LDS (deterministic).
+__global__ __launch_bounds__(256) void k_ens_box_sums(const double* __restrict__ tile_out,
+                                                      const BoxDesc* __restrict__ boxes, int nboxes,
+                                                      const int* __restrict__ tile_count, double* __restrict__ box_out)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nboxes) return;
+    __shared__ double red[2][256];
+    const int b = blockIdx.x;
     const BoxDesc bd = boxes[b];
     double ke = 0.0, mass = 0.0;
-    for (int t = bd.tile0; t < bd.tile0 + tile_count[b]; ++t) {
+    for (int t = bd.tile0 + threadIdx.x; t < bd.tile0 + tile_count[b]; t += blockDim.x) {
         ke += tile_out[2 * (int64_t)t];
         mass += tile_out[2 * (int64_t)t + 1];
     }
-    box_out[2 * b] = ke;
-    box_out[2 * b + 1] = mass;
+    red[0][threadIdx.x] = ke;
+    red[1][threadIdx.x] = mass;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        box_out[2 * b] = red[0][0];
+        box_out[2 * b + 1] = red[1][0];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -262,7 +277,7 @@ void launch_ens_energy(int q, int precision, const void* buf, const void* boxes,
         else LBM_ENS_E(LatD3Q19, float);
     }
 #undef LBM_ENS_E
-    hipLaunchKernelGGL(k_ens_box_sums, dim3((nboxes + 63) / 64), dim3(64), 0, st, tile_out, bd, nboxes, tile_count, box_out);
+    hipLaunchKernelGGL(k_ens_box_sums, dim3(nboxes), dim3(256), 0, st, tile_out, bd, nboxes, tile_count, box_out);
 }
 
 size_t ens_box_desc_bytes() { return sizeof(BoxDesc); }

@@ -167,8 +167,10 @@ int lbm_ensemble_create(const lbm_box* boxes, int32_t nboxes, int32_t q, int32_t
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return cleanup(efail(LBM_EDEVICE, "no HIP device"));
-    e->grid = ncu * 8; // default: 8 workgroups per CU; lbm_ensemble_tune may change it
-    if (e->grid > tiles) e->grid = tiles;
+    // default: one work-group per tile (the tuner's choice on MI355X for the
+    // 64-box workload); lbm_ensemble_tune also tries 2..64 persistent
+    // work-groups per CU
+    e->grid = tiles;
     for (int k = 0; k < 2; ++k)
         if (hipMalloc(&e->buf[k], elems * e->eb) != hipSuccess) return cleanup(efail(LBM_ENOMEM, "population buffers"));
     if (hipMalloc(&e->boxes_dev, desc.size()) != hipSuccess ||

@@ -32,7 +32,7 @@ struct lbm_handle {
     double* diag_dev = nullptr;
     double* diag_host = nullptr;
     dim3 grid, block;
-    dim3 step_grid;                    // grid of the step kernels (1-D XCD-aware, or = grid)
+    dim3 step_grid, step_block;        // launch shape of the plain step kernel (tunable)
     bool walls = false, general = false, nt = true;
     int64_t bytes = 0;
     int nblocks = 0;

@@ -8,6 +8,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "handle.hpp"
 
@@ -231,6 +234,7 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
         const bool remap = chunk > 1 && h->nblocks % (8 * chunk) == 0;
         h->g.xcd_chunk = remap ? chunk : 1;
         h->step_grid = remap ? dim3(h->nblocks, 1, 1) : h->grid;
+        h->step_block = h->block;
     }
 
     const int64_t pop_bytes = (int64_t)p->q * h->g.stride * eb;
@@ -348,7 +352,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
                                  h->mlp->packed, h->fb_partials, h->grid, h->block, h->stream);
         else
             lbm::launch_step(h->p.q, h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g,
-                             h->ph, h->step_grid, h->block, h->stream);
+                             h->ph, h->step_grid, h->step_block, h->stream);
         h->cur = dst;
         h->steps++;
         if (h->p.check_every > 0 && h->steps % h->p.check_every == 0) {
@@ -436,6 +440,94 @@ int lbm_set_populations(lbm_handle* h, const double* f, int on_device)
 }
 
 int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }
+
+// ---------------------------------------------------------------------------
+// Autotuner of the plain step: work-group shape x cache policy
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TuneEntry {
+    std::string arch;
+    int nx, ny, nz, q, precision, streaming, walls, general;
+    int bx, by, nt;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune_cache; // process-wide: (GPU arch, lattice, variant) -> launch
+
+void apply_launch(lbm_handle* h, int bx, int by, bool nt)
+{
+    h->step_block = dim3(bx, by, 1);
+    h->step_grid = dim3((h->g.nx + bx - 1) / bx, (h->g.ny + by - 1) / by, h->g.nz);
+    h->g.xcd_chunk = 1;
+    h->nt = nt;
+}
+
+} // namespace
+
+int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* block_y, int32_t* cache_policy)
+{
+    if (!h || trial_steps < 0) return fail(LBM_EINVAL, "bad arguments");
+    if (h->cp || h->mlp) return fail(LBM_EUNSUPPORTED, "the tuner sets up the plain step (no coupled lattice or network)");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, h->device));
+    TuneEntry key{prop.gcnArchName, h->g.nx, h->g.ny, h->g.nz, h->p.q, h->p.precision, h->p.streaming,
+                  h->walls ? 1 : 0, h->general ? 1 : 0, 0, 0, 0};
+    auto same = [&](const TuneEntry& e) {
+        return e.arch == key.arch && e.nx == key.nx && e.ny == key.ny && e.nz == key.nz && e.q == key.q &&
+               e.precision == key.precision && e.streaming == key.streaming && e.walls == key.walls &&
+               e.general == key.general;
+    };
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const TuneEntry& e : g_tune_cache)
+            if (same(e)) {
+                key = e;
+                cached = true;
+            }
+    }
+    if (!cached) {
+        const int steps = trial_steps + (trial_steps & 1);
+        const int shapes[][2] = {{256, 1}, {128, 2}, {64, 4}, {128, 1}, {64, 2}, {64, 1}};
+        const int nx2 = next_pow2(h->g.nx), ny2 = next_pow2(h->g.ny);
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        float best = 1e30f;
+        for (const auto& sh : shapes) {
+            // skip shapes that would leave most of a work-group idle
+            if ((sh[0] > 64 && sh[0] > nx2) || (sh[1] > 1 && sh[1] > ny2)) continue;
+            for (int nt = 1; nt >= 0; --nt) {
+                apply_launch(h, sh[0], sh[1], nt != 0);
+                int rc = lbm_step(h, 2);
+                if (rc) return rc;
+                HIP_TRY(hipEventRecord(a, h->stream));
+                rc = lbm_step(h, steps);
+                if (rc) return rc;
+                HIP_TRY(hipEventRecord(b, h->stream));
+                HIP_TRY(hipEventSynchronize(b));
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, a, b));
+                if (ms < best) {
+                    best = ms;
+                    key.bx = sh[0];
+                    key.by = sh[1];
+                    key.nt = nt;
+                }
+            }
+        }
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+        if (best == 1e30f) return fail(LBM_EINVAL, "no candidate work-group shape fits the lattice");
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache.push_back(key);
+    }
+    apply_launch(h, key.bx, key.by, key.nt != 0);
+    if (block_x) *block_x = key.bx;
+    if (block_y) *block_y = key.by;
+    if (cache_policy) *cache_policy = key.nt ? 1 : 2;
+    return LBM_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Learned rates

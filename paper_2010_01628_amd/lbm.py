@@ -137,6 +137,9 @@ def lib():
                      "lbm_ensemble_energy", "lbm_ensemble_get_populations", "lbm_ensemble_tune",
                      "lbm_ensemble_destroy"):
             getattr(L, name).restype = i32
+        ip32 = ctypes.POINTER(ctypes.c_int32)
+        L.lbm_tune.argtypes = [vp, ctypes.c_int32, ip32, ip32, ip32]
+        L.lbm_tune.restype = i32
         L.lbm_init_magnetic.argtypes = [vp, vp, vp, vp, i32]
         L.lbm_magnetic_fields.argtypes = [vp, vp, vp, i32]
         L.lbm_init_magnetic.restype = i32
@@ -367,8 +370,7 @@ class Ensemble:
         assert r.numel() == n ** 3 and v.numel() == 3 * n ** 3
         t.cuda.synchronize()  # the ensemble works on its own stream
         _check(lib().lbm_ensemble_init(self.e, int(box), r.data_ptr(), v.data_ptr(), 1))
-        _check(lib().lbm_ensemble_energy(self.e, None, np.zeros(len(self.boxes)).ctypes.data_as(
-            ctypes.POINTER(ctypes.c_double))))  # synchronizes before r, v go out of scope
+        t.cuda.synchronize()  # every stream: r and v stay alive until the init kernel is done
 
     def set_mlp(self, mlp):
         _check(lib().lbm_ensemble_set_mlp(self.e, None if mlp is None else mlp.m))
@@ -537,6 +539,13 @@ class Lattice:
     @property
     def step_count(self):
         return lbm_step_count(self.h)
+
+    def tune(self, trial_steps=10):
+        """Pick the step kernel's work-group shape and cache policy by timing
+        real steps (the state advances); returns (block_x, block_y, policy)."""
+        bx, by, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_tune(self.h, int(trial_steps), ctypes.byref(bx), ctypes.byref(by), ctypes.byref(nt)))
+        return bx.value, by.value, nt.value
 
     # -- two-phase lattices ------------------------------------------------
     def init_phase(self, phi, p, u):

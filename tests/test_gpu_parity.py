@@ -211,3 +211,47 @@ def test_stable_run_passes_checks():
     lat.step(10)
     assert lat.step_count == 10
     lat.close()
+
+
+@pytest.mark.parametrize("streaming", ["ab", "aa"])
+def test_tuned_launch_is_bitwise_identical(streaming):
+    """The autotuner only changes the work-group shape and cache hints: a tuned
+    lattice, stepped on, equals an untuned one after the same number of steps,
+    bit for bit; a second lattice of the same kind reuses the cached choice
+    without running steps."""
+    nx, ny, nz = 40, 24, 16
+    rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=31, umax=0.05, fmax=1e-3)
+    import torch
+
+    ff = torch.from_numpy(np.ascontiguousarray(F)).cuda()
+
+    def make():
+        p = L.make_params(nx, ny, nz, precision="fp32", streaming=streaming, omega=1.8, walls_y=True,
+                          force_mode=L.LBM_FORCE_FIELD, force_field_ptr=ff.data_ptr())
+        lat = L.Lattice(p, force_field=ff)
+        lat.init(rho, u)
+        return lat
+
+    a = make()
+    cfg = a.tune(4)
+    taken = a.step_count
+    say(f"  tuned {streaming}: block {cfg[0]}x{cfg[1]}, cache policy {cfg[2]}, {taken} steps")
+    assert taken > 0
+    a.step(7)
+    b = make()
+    b.step(taken + 7)
+    assert np.array_equal(a.get_populations().cpu().numpy(), b.get_populations().cpu().numpy())
+    c = make()
+    assert c.tune(4) == cfg and c.step_count == 0
+    for lat in (a, b, c):
+        lat.close()
+
+
+def test_xcd_interleaved_grid_is_bitwise_identical(monkeypatch):
+    """The optional XCD-interleaved step grid visits every node once: same bits."""
+    nx, ny, nz = 64, 48, 32
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=32, umax=0.05)
+    ref = gpu_run(nx, ny, nz, rho, u, 9, "fp32", "ab", omega=1.7)
+    monkeypatch.setenv("LBM_XCD_CHUNK", "4")
+    got = gpu_run(nx, ny, nz, rho, u, 9, "fp32", "ab", omega=1.7)
+    assert np.array_equal(ref["f"], got["f"])
