@@ -211,15 +211,18 @@ int lbm_set_coupled_populations(lbm_handle *h, const double *in, int on_device);
 
 /* Autotuner of the plain step kernel: runs 2 + trial_steps (rounded up to
  * even) real steps for each work-group shape 256x1, 128x2, 64x4, 128x1, 64x2,
- * 64x1 (those that fit the lattice) with and without non-temporal hints,
- * keeps the fastest for later lbm_step calls and reports it (block_x,
- * block_y, cache_policy 1 = non-temporal, 2 = cached; each may be NULL).  The
+ * 64x1 (those that fit the lattice) with and without non-temporal hints and,
+ * where a work-group spans whole x rows (A-B, periodic), with and without
+ * staging the x-moving populations through LDS; keeps the fastest for later
+ * lbm_step calls and reports it (block_x, block_y, cache_policy 1 =
+ * non-temporal, 2 = cached, row_stage 1 = staged; each may be NULL).  The
  * state advances by the steps taken and the step counter counts them.  The
  * choice is cached for the process per (GPU architecture, lattice size, q,
  * precision, streaming, walls, general rates): a later call with the same key
  * applies it without running steps.  Not for coupled lattices or attached
  * networks (LBM_EUNSUPPORTED). */
-int lbm_tune(lbm_handle *h, int32_t trial_steps, int32_t *block_x, int32_t *block_y, int32_t *cache_policy);
+int lbm_tune(lbm_handle *h, int32_t trial_steps, int32_t *block_x, int32_t *block_y, int32_t *cache_policy,
+             int32_t *row_stage);
 
 /* Number of steps taken since lbm_init. */
 int64_t lbm_step_count(const lbm_handle *h);

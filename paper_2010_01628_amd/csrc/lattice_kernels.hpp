@@ -296,6 +296,66 @@ __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* _
     step_node<L, S, AB, WALLS, GENERAL, NT>(src, dst, g, ph);
 }
 
+// A-B, periodic, with work-groups of whole x rows (blockDim.x == nx): the
+// populations that move along x are staged through LDS.  Each such
+// population's source row (y - c_y, z - c_z) is read aligned, each element
+// once, into LDS, and node x takes element x - c_x (wrapped) from there;
+// reading it straight from memory would start each wavefront's load four
+// bytes off a line boundary.  Same values as k_step_ab, bit for bit.
+template <class L> __host__ __device__ constexpr int moving_x_count()
+{
+    int k = 0;
+    for (int i = 0; i < L::Q; ++i) k += L::cx(i) != 0;
+    return k;
+}
+
+template <class L, class S, bool GENERAL, bool NT>
+__global__ __launch_bounds__(256) void k_step_ab_rows(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
+{
+    using R = typename Codec<S>::R;
+    constexpr int QX = moving_x_count<L>();
+    __shared__ S rows[QX][256];
+    int bxi, byi, z;
+    block_coords(g, g.xcd_chunk, bxi, byi, z);
+    const int x = threadIdx.x; // bxi == 0: one work-group spans the row
+    const int yr = byi * blockDim.y + threadIdx.y;
+    const bool valid = yr < g.ny;
+    const int y = valid ? yr : g.ny - 1;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int row0 = threadIdx.y * blockDim.x;
+    {
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            if (L::cx(i) != 0) {
+                rows[k][row0 + x] = ld<S, NT>(src + (int64_t)i * g.stride + nb(d, 0, -L::cy(i), -L::cz(i)));
+                ++k;
+            }
+    }
+    __syncthreads();
+    R s[L::Q];
+    {
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            if (L::cx(i) != 0) {
+                int xs = x - L::cx(i);
+                xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+                s[i] = Codec<S>::dec(rows[k][row0 + xs]);
+                ++k;
+            } else {
+                s[i] = Codec<S>::dec(ld<S, NT>(src + (int64_t)i * g.stride + nb(d, 0, -L::cy(i), -L::cz(i))));
+            }
+        }
+    }
+    R Fx, Fy, Fz;
+    node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
+    NodeMacro<R> mac;
+    L::template collide<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    if (valid) scatter<L, S, AB, false, NT>(dst, g.stride, d, s);
+}
+
 // AA: one buffer, each node rewrites exactly the locations it read.
 template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
 __global__ __launch_bounds__(256) void k_step_aa(S* buf, Geom g, Phys ph)
@@ -480,7 +540,10 @@ template <class L, class S> struct Launch {
         if (L::Q == 27) general = false;
 #define LBM_STEP(P, W, G)                                                                                        \
     do {                                                                                                         \
-        if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT>), grid, block, 0, st, a, b, g, ph); \
+        if constexpr (P == AB && !W) {                                                                           \
+            if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT>), grid, block, 0, st, a, b, g, ph); \
+            else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT>), grid, block, 0, st, a, b, g, ph);              \
+        } else if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT>), grid, block, 0, st, a, b, g, ph); \
         else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT>), grid, block, 0, st, b, g, ph);                   \
     } while (0)
 #define LBM_STEP_G(P, W)                                 \

@@ -138,7 +138,7 @@ def lib():
                      "lbm_ensemble_destroy"):
             getattr(L, name).restype = i32
         ip32 = ctypes.POINTER(ctypes.c_int32)
-        L.lbm_tune.argtypes = [vp, ctypes.c_int32, ip32, ip32, ip32]
+        L.lbm_tune.argtypes = [vp, ctypes.c_int32, ip32, ip32, ip32, ip32]
         L.lbm_tune.restype = i32
         L.lbm_init_magnetic.argtypes = [vp, vp, vp, vp, i32]
         L.lbm_magnetic_fields.argtypes = [vp, vp, vp, i32]
@@ -541,11 +541,13 @@ class Lattice:
         return lbm_step_count(self.h)
 
     def tune(self, trial_steps=10):
-        """Pick the step kernel's work-group shape and cache policy by timing
-        real steps (the state advances); returns (block_x, block_y, policy)."""
-        bx, by, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().lbm_tune(self.h, int(trial_steps), ctypes.byref(bx), ctypes.byref(by), ctypes.byref(nt)))
-        return bx.value, by.value, nt.value
+        """Pick the step kernel's work-group shape, cache policy and row
+        staging by timing real steps (the state advances); returns
+        (block_x, block_y, policy, row_stage)."""
+        bx, by, nt, rs = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_tune(self.h, int(trial_steps), ctypes.byref(bx), ctypes.byref(by), ctypes.byref(nt),
+                              ctypes.byref(rs)))
+        return bx.value, by.value, nt.value, rs.value
 
     # -- two-phase lattices ------------------------------------------------
     def init_phase(self, phi, p, u):

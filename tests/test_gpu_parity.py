@@ -255,3 +255,17 @@ def test_xcd_interleaved_grid_is_bitwise_identical(monkeypatch):
     monkeypatch.setenv("LBM_XCD_CHUNK", "4")
     got = gpu_run(nx, ny, nz, rho, u, 9, "fp32", "ab", omega=1.7)
     assert np.array_equal(ref["f"], got["f"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_row_staged_step_is_bitwise_identical(precision, monkeypatch):
+    """Whole-row work-groups stage the x-moving populations through LDS; the
+    values are the same as direct pull reads, bit for bit."""
+    nx, ny, nz = 64, 44, 12  # 64-wide rows: one work-group per 4 rows, ragged in y
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=33, umax=0.05)
+    staged = gpu_run(nx, ny, nz, rho, u, 7, precision, "ab", omega=1.85, force_mode=L.LBM_FORCE_KOLMOGOROV,
+                     kolmogorov_amp=1e-4)
+    monkeypatch.setenv("LBM_ROW_STAGING", "0")
+    direct = gpu_run(nx, ny, nz, rho, u, 7, precision, "ab", omega=1.85, force_mode=L.LBM_FORCE_KOLMOGOROV,
+                     kolmogorov_amp=1e-4)
+    assert np.array_equal(staged["f"], direct["f"])
