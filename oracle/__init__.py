@@ -23,6 +23,8 @@ _SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c"
 
 DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
 CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
+RM_DEFINITION = 2   # raw-moment variant of App. C (N = I): f* = M^-1 k* by a dense solve
+RM_CLOSED_FORM = 3  # raw-moment variant, f* by the closed forms of App. C with r* = k*
 
 Q = 19
 
@@ -58,6 +60,9 @@ def lib():
         L.orc19_keq.argtypes = [f64, dp]
         L.orc19_Rcm.argtypes = [f64, f64, f64, dp]
         L.orc19_rstar.argtypes = [f64, f64, f64, f64, dp, dp]
+        L.orc19_M.argtypes = [dp]
+        L.orc19_keq_rm.argtypes = [f64, f64, f64, f64, dp]
+        L.orc19_Rrm.argtypes = [f64, f64, f64, f64, f64, f64, dp]
         L.orc19_fstar.argtypes = [dp, dp]
         L.orc19_collide.argtypes = [dp, dp, dp, i32, dp, dp, dp, dp]
         L.orc19_collide.restype = i32
@@ -165,6 +170,25 @@ def keq(rho):
 def Rcm(F):
     out = np.zeros(Q)
     lib().orc19_Rcm(float(F[0]), float(F[1]), float(F[2]), _p(out))
+    return out
+
+
+def M():
+    """Raw-moment matrix of App. C (T at u = 0), row-major 19 x 19."""
+    out = np.zeros((Q, Q))
+    lib().orc19_M(_p(out))
+    return out
+
+
+def keq_rm(rho, u):
+    out = np.zeros(Q)
+    lib().orc19_keq_rm(float(rho), float(u[0]), float(u[1]), float(u[2]), _p(out))
+    return out
+
+
+def Rrm(u, F):
+    out = np.zeros(Q)
+    lib().orc19_Rrm(float(u[0]), float(u[1]), float(u[2]), float(F[0]), float(F[1]), float(F[2]), _p(out))
     return out
 
 

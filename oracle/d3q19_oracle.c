@@ -25,6 +25,12 @@
  *       w_hi = 1 (Sec. II.B).  w_b and w_hi are kept as free inputs so that the
  *       learned-rate variant and the bulk-rate tests can use them.
  *   R6  F is a force density (eq. "lbe" and the Rayleigh-Taylor body force).
+ *   R9  Raw-moment variant (App. C, N = I): its printed post-collision list
+ *       carries only the forcing terms of the CM scheme (F/2 on rows 1-3,
+ *       cs^2 F/2 on rows 10-15).  The relaxation eq. (posColl0) with T = M
+ *       needs the raw moments of the same forcing term, which App. B prints
+ *       (eq. RMQ19, with velocity terms on rows 4-18); those are used.  Both
+ *       agree when F = 0, and at K = I the variant equals the CM scheme.
  *
  * Layout: populations are structure-of-arrays, f[i*N + n] with
  * n = x + nx*(y + ny*z); forces F[d*N + n].
@@ -164,6 +170,62 @@ void orc19_Rcm(double Fx, double Fy, double Fz, double *R)
     R[15] = CS2 * Fy; /* cy cz^2 */
 }
 
+/* App. C: raw-moment matrix M = T(0), the un-shifted basis (N = I). */
+void orc19_M(double *M) { orc19_T(0.0, 0.0, 0.0, M); }
+
+/* App. C: equilibrium raw moments of the RM formulation, as printed there
+ * (rows in the order of M). */
+void orc19_keq_rm(double rho, double ux, double uy, double uz, double *k)
+{
+    const double x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+    k[0] = rho;
+    k[1] = rho * ux;
+    k[2] = rho * uy;
+    k[3] = rho * uz;
+    k[4] = rho * (3.0 * CS2 + x2 + y2 + z2);
+    k[5] = rho * (x2 - y2);
+    k[6] = rho * (y2 - z2);
+    k[7] = rho * ux * uy;
+    k[8] = rho * ux * uz;
+    k[9] = rho * uy * uz;
+    k[10] = rho * uy * (x2 + CS2);
+    k[11] = rho * ux * (y2 + CS2);
+    k[12] = rho * uz * (x2 + CS2);
+    k[13] = rho * ux * (z2 + CS2);
+    k[14] = rho * uz * (y2 + CS2);
+    k[15] = rho * uy * (z2 + CS2);
+    k[16] = rho * (x2 + CS2) * (y2 + CS2);
+    k[17] = rho * (x2 + CS2) * (z2 + CS2);
+    k[18] = rho * (y2 + CS2) * (z2 + CS2);
+}
+
+/* App. B, eq. (RMQ19): raw moments R_pqr of the forcing term, placed in the
+ * row order of M (rows 4..6 are the trace and the two differences of the
+ * second-order ones).  Reading R9. */
+void orc19_Rrm(double ux, double uy, double uz, double Fx, double Fy, double Fz, double *R)
+{
+    const double r200 = 2.0 * ux * Fx, r020 = 2.0 * uy * Fy, r002 = 2.0 * uz * Fz;
+    R[0] = 0.0;
+    R[1] = Fx;
+    R[2] = Fy;
+    R[3] = Fz;
+    R[4] = r200 + r020 + r002;
+    R[5] = r200 - r020;
+    R[6] = r020 - r002;
+    R[7] = ux * Fy + uy * Fx;
+    R[8] = ux * Fz + uz * Fx;
+    R[9] = uy * Fz + uz * Fy;
+    R[10] = CS2 * Fy + ux * (ux * Fy + 2.0 * uy * Fx); /* 210 */
+    R[11] = CS2 * Fx + uy * (uy * Fx + 2.0 * ux * Fy); /* 120 */
+    R[12] = CS2 * Fz + ux * (ux * Fz + 2.0 * uz * Fx); /* 201 */
+    R[13] = CS2 * Fx + uz * (uz * Fx + 2.0 * ux * Fz); /* 102 */
+    R[14] = CS2 * Fz + uy * (uy * Fz + 2.0 * uz * Fy); /* 021 */
+    R[15] = CS2 * Fy + uz * (uz * Fy + 2.0 * uy * Fz); /* 012 */
+    R[16] = 2.0 * (ux * uy * (ux * Fy + uy * Fx) + CS2 * (ux * Fx + uy * Fy));
+    R[17] = 2.0 * (ux * uz * (ux * Fz + uz * Fx) + CS2 * (ux * Fx + uz * Fz));
+    R[18] = 2.0 * (uy * uz * (uy * Fz + uz * Fy) + CS2 * (uy * Fy + uz * Fz));
+}
+
 /* Macroscopic moments, Sec. II.A eq. (macro) with the F/2 shift (reading R2). */
 static void macro(const double *f, const double *F, double *rho, double *u)
 {
@@ -280,7 +342,7 @@ static int solve19(double *A, double *b, double *x)
 /* The same elimination for the other oracle files (n <= 19; A, b overwritten). */
 int orc_solve19(double *A, double *b, double *x) { return solve19(A, b, x); }
 
-enum { ORC_DEFINITION = 0, ORC_CLOSED_FORM = 1 };
+enum { ORC_DEFINITION = 0, ORC_CLOSED_FORM = 1, ORC_RM_DEFINITION = 2, ORC_RM_CLOSED_FORM = 3 };
 
 /*
  * One collision at one node, Sec. II.B eqs. (posColl0) and (system):
@@ -288,31 +350,48 @@ enum { ORC_DEFINITION = 0, ORC_CLOSED_FORM = 1 };
  *   k* = (I - K) k + K k_eq + (I - K/2) R;
  *   f* = T(u)^-1 k*   (mode ORC_DEFINITION: dense solve)
  *      = M^-1 N^-1 k* (mode ORC_CLOSED_FORM: App. C two-step closed forms).
+ * Modes ORC_RM_*: the raw-moment variant of App. C (N = I, T = M): k = M f,
+ * the raw equilibrium and forcing moments (reading R9), the same relaxation,
+ * f* = M^-1 k* by a dense solve (ORC_RM_DEFINITION) or by the closed forms
+ * of eq. (pdfQ19) with r* = k* (ORC_RM_CLOSED_FORM).
  * K holds the 19 diagonal entries of the relaxation matrix.  If kout/uout are
- * given they receive k (pre-collision CMs) and the shifted velocity.
+ * given they receive k (pre-collision moments) and the shifted velocity.
  */
 int orc19_collide(const double *f, const double *F, const double *K, int mode, double *fstar,
                   double *kout, double *rho_out, double *uout)
 {
     double rho, u[3];
     macro(f, F, &rho, u);
+    const int raw = (mode == ORC_RM_DEFINITION || mode == ORC_RM_CLOSED_FORM);
     double T[Q * Q], k[Q], keq[Q], R[Q], ks[Q];
-    orc19_T(u[0], u[1], u[2], T);
+    if (raw)
+        orc19_M(T);
+    else
+        orc19_T(u[0], u[1], u[2], T);
     for (int r = 0; r < Q; ++r) {
         double s = 0.0;
         for (int i = 0; i < Q; ++i) s += T[r * Q + i] * f[i];
         k[r] = s;
     }
-    orc19_keq(rho, keq);
-    orc19_Rcm(F[0], F[1], F[2], R);
+    if (raw) {
+        orc19_keq_rm(rho, u[0], u[1], u[2], keq);
+        orc19_Rrm(u[0], u[1], u[2], F[0], F[1], F[2], R);
+    } else {
+        orc19_keq(rho, keq);
+        orc19_Rcm(F[0], F[1], F[2], R);
+    }
     for (int r = 0; r < Q; ++r) ks[r] = (1.0 - K[r]) * k[r] + K[r] * keq[r] + (1.0 - 0.5 * K[r]) * R[r];
     if (kout) memcpy(kout, k, sizeof k);
     if (rho_out) *rho_out = rho;
     if (uout) memcpy(uout, u, sizeof u);
-    if (mode == ORC_DEFINITION) {
+    if (mode == ORC_DEFINITION || mode == ORC_RM_DEFINITION) {
         double b[Q];
         memcpy(b, ks, sizeof ks);
         return solve19(T, b, fstar);
+    }
+    if (mode == ORC_RM_CLOSED_FORM) {
+        orc19_fstar(ks, fstar);
+        return 0;
     }
     double rs[Q];
     /* The closed forms of App. C take k0* = rho. */
