@@ -37,11 +37,12 @@ def elem_bytes(precision: str) -> int:
     return {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[precision]
 
 
-def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fields, mlp=None, tune=True):
+def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fields, mlp=None, tune=True,
+                 moments="central"):
     nu = 1e-3
     p = L.make_params(size, size, size, precision=precision, streaming=streaming,
                       omega=inputs.omega_from_nu(nu), force_mode=L.LBM_FORCE_KOLMOGOROV,
-                      kolmogorov_amp=1e-6)
+                      kolmogorov_amp=1e-6, moments=moments)
     lat = L.Lattice(p)
     rho_d, u_d = fields
     lat.init(rho_d, u_d)
@@ -240,8 +241,10 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--streaming", default="ab", choices=["ab", "aa"])
-    ap.add_argument("--variants", default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,fp64:ab,fp32+mlp:ab,fp16+mlp:ab",
-                    help="extra precision[+mlp]:streaming pairs to time ('' = none); +mlp = learned rates")
+    ap.add_argument("--variants",
+                    default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,fp64:ab,fp32+mlp:ab,fp16+mlp:ab,fp32+raw:ab,fp16+raw:ab",
+                    help="extra precision[+mlp|+raw]:streaming pairs to time ('' = none); +mlp = learned "
+                         "rates, +raw = raw-moment collision (the N = I variant)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble workload")
     ap.add_argument("--no-coupled", action="store_true", help="skip the two-phase and magnetic workloads")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
@@ -292,15 +295,18 @@ def main(argv=None):
     for spec in [v for v in args.variants.split(",") if v]:
         prec, _, strm = spec.partition(":")
         strm = strm or args.streaming
-        prec, plus, _ = prec.partition("+")
+        prec, _, plus = prec.partition("+")
         if (prec, strm) == (args.precision, args.streaming) and not plus:
             continue
-        if plus and mlp is None:
+        if plus not in ("", "mlp", "raw"):
+            raise SystemExit(f"unknown variant modifier +{plus}")
+        if plus == "mlp" and mlp is None:
             mlp = bench_network(L)
         log(f"bench: timing variant {spec}")
-        variants[f"{prec}{'_learned' if plus else ''}_{strm}"] = time_variant(
+        tag = {"": "", "mlp": "_learned", "raw": "_raw"}[plus]
+        variants[f"{prec}{tag}_{strm}"] = time_variant(
             L, inputs, torch, size, prec, strm, max(20, args.steps // 4), max(5, args.warmup // 4), fields,
-            mlp=mlp if plus else None, tune=not args.no_tune)
+            mlp=mlp if plus == "mlp" else None, tune=not args.no_tune, moments="raw" if plus == "raw" else "central")
     del fields
     torch.cuda.empty_cache()
     ensemble = None

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2
+#define LBM_ABI_VERSION 3
 
 typedef enum {
     LBM_OK = 0,
@@ -69,6 +69,14 @@ typedef enum {
     LBM_FORCE_FIELD = 2,      /* F read from force_field (device, double[3*N]) */
     LBM_FORCE_KOLMOGOROV = 3  /* F_x = kolmogorov_amp * sin(2 pi y / ny), F_y = F_z = 0 */
 } lbm_force_mode;
+
+/* Moment space of the collision.  Central moments (Sec. II.B) are the
+ * paper's method; raw moments are its N = I special case, the classical
+ * raw-moment MRT written in the same basis (App. C): k = M f, the raw
+ * equilibrium moments printed there, the raw moments of the forcing term of
+ * App. B (eq. RMQ19), the same K, f* = M^-1 k*.  With K = I both give the
+ * same populations. */
+typedef enum { LBM_CENTRAL_MOMENTS = 0, LBM_RAW_MOMENTS = 1 } lbm_moment_space;
 
 /* Lattice coupled to the flow (Sec. III multiphysics cases). */
 typedef enum {
@@ -137,6 +145,8 @@ typedef struct {
                                  rho0 = 1 */
     lbm_magnetic_params magnetic; /* LBM_COUPLED_MAGNETIC: q = 19, FP64 or FP32, A-B, the paper's
                                  bulk and higher-order rates; any external force mode */
+    int32_t moments;          /* lbm_moment_space; LBM_RAW_MOMENTS needs q = 19 and no coupled
+                                 lattice, and takes no network (lbm_set_mlp) */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

@@ -375,6 +375,87 @@ __host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, co
     post_collide(st, p, s);
 }
 
+// Raw-moment variant (App. C with N = I, the classical MRT in the paper's
+// basis): the same relaxation applied to un-shifted moments, towards the raw
+// equilibrium, with the raw moments of the forcing term of App. B (eq. RMQ19).
+// No binomial shifts.  GENERAL = false assumes the paper's rates.
+template <class R, bool GENERAL>
+__host__ __device__ inline void collide_rm(R s[19], R rho0, R Fx, R Fy, R Fz, const Rates<R>& rt, NodeMacro<R>& mac)
+{
+    RawMoments<R> m;
+    raw_from_pops(s, m);
+    const R drho = m.m000, rho = rho0 + drho, irho = R(1) / rho;
+    const R ux = (m.m100 + R(0.5) * Fx) * irho;
+    const R uy = (m.m010 + R(0.5) * Fy) * irho;
+    const R uz = (m.m001 + R(0.5) * Fz) * irho;
+    mac.rho = rho;
+    mac.ux = ux;
+    mac.uy = uy;
+    mac.uz = uz;
+    RawMoments<R> e;
+    eq_raw_deviation(drho, rho, ux, uy, uz, e);
+    const R third = R(1) / R(3), cs2 = third;
+    // second-order forcing moments: 2 u_a F_a on the diagonal, u_a F_b + u_b F_a off it
+    const R fxx = R(2) * ux * Fx, fyy = R(2) * uy * Fy, fzz = R(2) * uz * Fz;
+    const R w1 = R(1) - rt.omega, h1 = R(1) - R(0.5) * rt.omega;
+    const R n5 = (m.m200 - e.m200) - (m.m020 - e.m020);
+    const R n6 = (m.m020 - e.m020) - (m.m002 - e.m002);
+    const R p5 = w1 * n5 + h1 * (fxx - fyy);
+    const R p6 = w1 * n6 + h1 * (fyy - fzz);
+    R p4;
+    if constexpr (GENERAL) {
+        const R n4 = (m.m200 - e.m200) + (m.m020 - e.m020) + (m.m002 - e.m002);
+        p4 = (R(1) - rt.omega_bulk) * n4 + (R(1) - R(0.5) * rt.omega_bulk) * (fxx + fyy + fzz);
+    } else {
+        p4 = R(0.5) * (fxx + fyy + fzz);
+    }
+    RawMoments<R> p;
+    p.m000 = e.m000;
+    p.m100 = e.m100 + R(0.5) * Fx;
+    p.m010 = e.m010 + R(0.5) * Fy;
+    p.m001 = e.m001 + R(0.5) * Fz;
+    p.m200 = e.m200 + third * (p4 + R(2) * p5 + p6);
+    p.m020 = e.m020 + third * (p4 - p5 + p6);
+    p.m002 = e.m002 + third * (p4 - p5 - R(2) * p6);
+    p.m110 = e.m110 + w1 * (m.m110 - e.m110) + h1 * (ux * Fy + uy * Fx);
+    p.m101 = e.m101 + w1 * (m.m101 - e.m101) + h1 * (ux * Fz + uz * Fx);
+    p.m011 = e.m011 + w1 * (m.m011 - e.m011) + h1 * (uy * Fz + uz * Fy);
+    // third- and fourth-order forcing moments
+    const R f210 = cs2 * Fy + ux * (ux * Fy + R(2) * uy * Fx);
+    const R f120 = cs2 * Fx + uy * (uy * Fx + R(2) * ux * Fy);
+    const R f201 = cs2 * Fz + ux * (ux * Fz + R(2) * uz * Fx);
+    const R f102 = cs2 * Fx + uz * (uz * Fx + R(2) * ux * Fz);
+    const R f021 = cs2 * Fz + uy * (uy * Fz + R(2) * uz * Fy);
+    const R f012 = cs2 * Fy + uz * (uz * Fy + R(2) * uy * Fz);
+    const R f220 = R(2) * (ux * uy * (ux * Fy + uy * Fx) + cs2 * (ux * Fx + uy * Fy));
+    const R f202 = R(2) * (ux * uz * (ux * Fz + uz * Fx) + cs2 * (ux * Fx + uz * Fz));
+    const R f022 = R(2) * (uy * uz * (uy * Fz + uz * Fy) + cs2 * (uy * Fy + uz * Fz));
+    if constexpr (GENERAL) {
+        const R* oh = rt.omega_hi;
+        auto rel = [](R mm, R ee, R ff, R w) { return ee + (R(1) - w) * (mm - ee) + (R(1) - R(0.5) * w) * ff; };
+        p.m210 = rel(m.m210, e.m210, f210, oh[0]);
+        p.m120 = rel(m.m120, e.m120, f120, oh[1]);
+        p.m201 = rel(m.m201, e.m201, f201, oh[2]);
+        p.m102 = rel(m.m102, e.m102, f102, oh[3]);
+        p.m021 = rel(m.m021, e.m021, f021, oh[4]);
+        p.m012 = rel(m.m012, e.m012, f012, oh[5]);
+        p.m220 = rel(m.m220, e.m220, f220, oh[6]);
+        p.m202 = rel(m.m202, e.m202, f202, oh[7]);
+        p.m022 = rel(m.m022, e.m022, f022, oh[8]);
+    } else {
+        p.m210 = e.m210 + R(0.5) * f210;
+        p.m120 = e.m120 + R(0.5) * f120;
+        p.m201 = e.m201 + R(0.5) * f201;
+        p.m102 = e.m102 + R(0.5) * f102;
+        p.m021 = e.m021 + R(0.5) * f021;
+        p.m012 = e.m012 + R(0.5) * f012;
+        p.m220 = e.m220 + R(0.5) * f220;
+        p.m202 = e.m202 + R(0.5) * f202;
+        p.m022 = e.m022 + R(0.5) * f022;
+    }
+    pops_from_raw(p, s);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoints (transposes) of the linear maps of the back-transform, for the
 // gradient of a loss on post-collision populations with respect to the

@@ -58,6 +58,15 @@ struct LatD3Q19 {
     }
 };
 
+// Same lattice, raw-moment collision (App. C with N = I).
+struct LatD3Q19RM : LatD3Q19 {
+    template <class R, bool GENERAL>
+    __device__ static void collide(R* s, R rho0, R Fx, R Fy, R Fz, const Phys& ph, NodeMacro<R>& mac)
+    {
+        collide_rm<R, GENERAL>(s, rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
+    }
+};
+
 struct LatD3Q27 {
     static constexpr int Q = 27;
     __host__ __device__ static constexpr int cx(int i) { return cx27(i); }

@@ -103,6 +103,9 @@ int validate(const lbm_params* p)
     const int bx = p->block_x ? p->block_x : 64, by = p->block_y ? p->block_y : 1;
     if (bx * by > 256 || (bx * by) % 64 != 0)
         return fail(LBM_EINVAL, "block_x*block_y must be a multiple of 64 and at most 256");
+    if (p->moments != LBM_CENTRAL_MOMENTS && p->moments != LBM_RAW_MOMENTS) return fail(LBM_EINVAL, "bad moments");
+    if (p->moments == LBM_RAW_MOMENTS && (p->q != 19 || p->coupled != LBM_COUPLED_NONE))
+        return fail(LBM_EUNSUPPORTED, "raw moments: D3Q19 without a coupled lattice");
     if (p->coupled < LBM_COUPLED_NONE || p->coupled > LBM_COUPLED_MAGNETIC) return fail(LBM_EINVAL, "bad coupled");
     if (p->coupled != LBM_COUPLED_NONE) return coupled_validate(p);
     return LBM_OK;
@@ -366,7 +369,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
             lbm::launch_step_mlp(h->p.precision, pat, h->walls, h->nt, h->buf[src], h->buf[dst], h->g, h->ph,
                                  h->mlp->packed, h->fb_partials, h->grid, h->block, h->stream);
         else
-            lbm::launch_step(h->p.q, h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g,
+            lbm::launch_step(h->p.q, h->p.moments == LBM_RAW_MOMENTS, h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g,
                              h->ph, h->step_grid, h->step_block, h->stream);
         h->cur = dst;
         h->steps++;
@@ -463,7 +466,7 @@ namespace {
 
 struct TuneEntry {
     std::string arch;
-    int nx, ny, nz, q, precision, streaming, walls, general;
+    int nx, ny, nz, q, moments, precision, streaming, walls, general;
     int bx, by, nt, rs;
 };
 std::mutex g_tune_mu;
@@ -488,10 +491,11 @@ int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* bloc
     if (h->cp || h->mlp) return fail(LBM_EUNSUPPORTED, "the tuner sets up the plain step (no coupled lattice or network)");
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, h->device));
-    TuneEntry key{prop.gcnArchName, h->g.nx, h->g.ny, h->g.nz, h->p.q, h->p.precision, h->p.streaming,
-                  h->walls ? 1 : 0, h->general ? 1 : 0, 0, 0, 0, 0};
+    TuneEntry key{prop.gcnArchName, h->g.nx, h->g.ny, h->g.nz, h->p.q, h->p.moments, h->p.precision,
+                  h->p.streaming, h->walls ? 1 : 0, h->general ? 1 : 0, 0, 0, 0, 0};
     auto same = [&](const TuneEntry& e) {
         return e.arch == key.arch && e.nx == key.nx && e.ny == key.ny && e.nz == key.nz && e.q == key.q &&
+               e.moments == key.moments &&
                e.precision == key.precision && e.streaming == key.streaming && e.walls == key.walls &&
                e.general == key.general;
     };
@@ -663,6 +667,8 @@ int lbm_set_mlp(lbm_handle* h, const lbm_mlp* m)
     if (m) {
         if (h->cp) return fail(LBM_EUNSUPPORTED, "learned rates apply to the single-phase lattice");
         if (h->p.q != 19) return fail(LBM_EUNSUPPORTED, "learned rates need the D3Q19 lattice");
+        if (h->p.moments != LBM_CENTRAL_MOMENTS)
+            return fail(LBM_EUNSUPPORTED, "learned rates act on central moments");
         if (h->p.precision == LBM_FP64) return fail(LBM_EUNSUPPORTED, "learned rates run with FP32 collision");
         if (!h->fb_partials) {
             HIP_TRY(hipMalloc((void**)&h->fb_partials, sizeof(uint32_t) * h->nblocks));
@@ -772,7 +778,8 @@ int lbm_mlp_adam_step(lbm_mlp* m, double lr, double beta1, double beta2, double 
 int lbm_feature_rms(lbm_handle* h, double rms[11])
 {
     if (!h || !rms) return fail(LBM_EINVAL, "NULL argument");
-    if (h->p.q != 19 || h->p.precision == LBM_FP64) return fail(LBM_EUNSUPPORTED, "D3Q19 with FP32/16-bit storage");
+    if (h->p.q != 19 || h->p.precision == LBM_FP64 || h->p.moments != LBM_CENTRAL_MOMENTS)
+        return fail(LBM_EUNSUPPORTED, "central-moment D3Q19 with FP32/16-bit storage");
     double* part = nullptr;
     double* out = nullptr;
     HIP_TRY(hipMalloc((void**)&part, sizeof(double) * 11 * (h->nblocks + 1)));

@@ -42,11 +42,16 @@ LBM_DECLARE_LAUNCHERS(q19)
 LBM_DECLARE_LAUNCHERS(q27)
 #undef LBM_DECLARE_LAUNCHERS
 
-// Dispatch on the lattice (q = 19 or 27).
-inline void launch_step(int q, int precision, int pattern, bool walls, bool general, bool nt, const void* src,
-                        void* dst, const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st)
+void launch_step_q19rm(int precision, int pattern, bool walls, bool general, bool nt, const void* src, void* dst,
+                       const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st);
+
+// Dispatch on the lattice (q = 19 or 27) and the moment space (raw: D3Q19 only).
+inline void launch_step(int q, bool raw, int precision, int pattern, bool walls, bool general, bool nt,
+                        const void* src, void* dst, const Geom& g, const Phys& ph, dim3 grid, dim3 block,
+                        hipStream_t st)
 {
     if (q == 27) launch_step_q27(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
+    else if (raw) launch_step_q19rm(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
     else launch_step_q19(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
 }
 inline void launch_init(int q, int precision, int pattern, bool walls, void* buf, const Geom& g, double rho0,

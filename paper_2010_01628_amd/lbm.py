@@ -19,14 +19,16 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3
 LBM_AB, LBM_AA = 0, 1
 LBM_FORCE_NONE, LBM_FORCE_UNIFORM, LBM_FORCE_FIELD, LBM_FORCE_KOLMOGOROV = 0, 1, 2, 3
+LBM_CENTRAL_MOMENTS, LBM_RAW_MOMENTS = 0, 1
 
 PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16_SHIFTED, "bf16": LBM_BF16_SHIFTED}
 STREAMING = {"ab": LBM_AB, "aa": LBM_AA}
+MOMENTS = {"central": LBM_CENTRAL_MOMENTS, "raw": LBM_RAW_MOMENTS}
 
 
 class LbmError(RuntimeError):
@@ -69,6 +71,7 @@ class lbm_params(ctypes.Structure):
         ("coupled", ctypes.c_int32),
         ("phase", lbm_phase_params),
         ("magnetic", lbm_magnetic_params),
+        ("moments", ctypes.c_int32),
     ]
 
 
@@ -415,10 +418,11 @@ class Ensemble:
 def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
                 rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
                 force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0,
-                q=19, phase=None, magnetic=None) -> lbm_params:
+                q=19, phase=None, magnetic=None, moments="central") -> lbm_params:
     """phase: dict(rho_light, rho_heavy, sigma, width, mobility) makes a
     two-phase lattice (coupled = LBM_COUPLED_PHASE); magnetic: dict(eta,
-    b_wall=(bx, by, bz)) a magnetic one (LBM_COUPLED_MAGNETIC)."""
+    b_wall=(bx, by, bz)) a magnetic one (LBM_COUPLED_MAGNETIC); moments:
+    "central" (the paper's scheme) or "raw" (its N = I variant)."""
     p = lbm_params_default()
     p.q = int(q)
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -439,6 +443,7 @@ def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_b
     p.check_every = int(check_every)
     p.block_x, p.block_y = int(block[0]), int(block[1])
     p.cache_policy = int(cache_policy)
+    p.moments = MOMENTS[moments] if isinstance(moments, str) else int(moments)
     if magnetic is not None:
         p.coupled = LBM_COUPLED_MAGNETIC
         p.magnetic.eta = float(magnetic["eta"])

@@ -27,7 +27,7 @@ def rel_l2_fluct(rho_a, rho_b):
 
 def gpu_run(nx, ny, nz, rho, u, steps, precision="fp64", streaming="ab", omega=1.0, omega_bulk=1.0,
             omega_hi=None, force=None, force_mode=L.LBM_FORCE_NONE, kolmogorov_amp=0.0, walls=False,
-            uniform=(0.0, 0.0, 0.0), block=(0, 0), want_pops=True, q=19):
+            uniform=(0.0, 0.0, 0.0), block=(0, 0), want_pops=True, q=19, moments="central"):
     """Run the GPU library; returns dict(rho, u, f, diag) as numpy float64."""
     import torch
 
@@ -37,7 +37,8 @@ def gpu_run(nx, ny, nz, rho, u, steps, precision="fp64", streaming="ab", omega=1
         force_mode = L.LBM_FORCE_FIELD
     p = L.make_params(nx, ny, nz, precision=precision, streaming=streaming, omega=omega, omega_bulk=omega_bulk,
                       omega_hi=omega_hi, force_mode=force_mode, force=uniform, kolmogorov_amp=kolmogorov_amp,
-                      force_field_ptr=None if ff is None else ff.data_ptr(), walls_y=walls, block=block)
+                      force_field_ptr=None if ff is None else ff.data_ptr(), walls_y=walls, block=block,
+                      moments=moments)
     p.q = q
     lat = L.Lattice(p, force_field=ff)
     try:
@@ -53,8 +54,9 @@ def gpu_run(nx, ny, nz, rho, u, steps, precision="fp64", streaming="ab", omega=1
         lat.close()
 
 
-def oracle_run(orc, rho, u, steps, omega=1.0, omega_bulk=1.0, omega_hi=None, F=None, walls=False):
+def oracle_run(orc, rho, u, steps, omega=1.0, omega_bulk=1.0, omega_hi=None, F=None, walls=False,
+               mode=None):
     Kd = orc.K(omega, omega_bulk, omega_hi)
-    f = orc.run(orc.init(rho, u), steps, Kd, F=F, walls_y=walls)
+    f = orc.run(orc.init(rho, u), steps, Kd, F=F, walls_y=walls, mode=orc.CLOSED_FORM if mode is None else mode)
     r, v = orc.moments(f, F)
     return {"rho": r, "u": v, "f": f}

@@ -159,3 +159,22 @@ def test_magnetic_lattice_validation(lbm, kw, code):
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_create(p, None)
     assert e.value.code == code, lbm.lib().lbm_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(moments=2), -1), (dict(moments=-1), -1), (dict(moments=1, q=27), -5),
+    (dict(moments=1, phase=True), -5), (dict(moments=1, magnetic=True), -5),
+])
+def test_raw_moment_validation(lbm, kw, code):
+    kw = dict(kw)
+    extra = {}
+    if kw.pop("phase", False):
+        extra["phase"] = dict(rho_light=1.0, rho_heavy=10.0, sigma=1e-3, width=4.0, mobility=0.1)
+    if kw.pop("magnetic", False):
+        extra["magnetic"] = dict(eta=0.1)
+    p = lbm.make_params(8, 8, 8, precision="fp32", **extra)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, None)
+    assert e.value.code == code, lbm.lib().lbm_last_error().decode()
