@@ -19,7 +19,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c", "mhd_oracle.c"]
+_SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c", "mhd_oracle.c",
+            "shan_chen_oracle.c"]
 
 DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
 CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
@@ -114,6 +115,13 @@ def lib():
         L.orc_mhd_step.restype = i32
         L.orc_mhd_init.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp]
         L.orc_mhd_fields.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_sc_psi.argtypes = [f64]
+        L.orc_sc_psi.restype = f64
+        L.orc_sc_force.argtypes = [i32, i32, i32, dp, f64, dp, dp]
+        L.orc_sc_step.argtypes = [i32, i32, i32, f64, dp, f64, dp, dp, dp]
+        L.orc_sc_step.restype = i32
+        L.orc_sc_fields.argtypes = [i32, i32, i32, f64, dp, dp, dp, dp, dp]
+        L.orc_sc_fields.restype = i32
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
         _lib = L
@@ -629,3 +637,53 @@ class mhd:
         Fa = None if F is None else _f64(F)
         lib().orc_mhd_fields(nx, ny, nz, _p(_f64(prm)), _p(f), _p(g), _p(Fa), _p(rho), _p(u), _p(b), _p(j))
         return rho, u, b, j
+
+
+class shan_chen:
+    """Shan-Chen pseudo-potential two-phase flow (static-bubble case of
+    Sec. III) on the paper's D3Q19 CM collision, periodic."""
+
+    @staticmethod
+    def psi(rho):
+        return lib().orc_sc_psi(float(rho))
+
+    @staticmethod
+    def force(rho, G, Fu=None):
+        rho = _f64(rho)
+        nz, ny, nx = rho.shape
+        F = np.zeros((3, nz, ny, nx))
+        lib().orc_sc_force(nx, ny, nz, _p(rho), float(G), _p(None if Fu is None else _f64(Fu)), _p(F))
+        return F
+
+    @staticmethod
+    def step(f, G, omega, Fu=None, out=None, F_out=None):
+        f = _f64(f)
+        _, nz, ny, nx = f.shape
+        out = np.empty_like(f) if out is None else out
+        if lib().orc_sc_step(nx, ny, nz, float(G), _p(None if Fu is None else _f64(Fu)), float(omega), _p(f),
+                             _p(out), _p(F_out)) != 0:
+            raise ArithmeticError("Shan-Chen step failed")
+        return out
+
+    @staticmethod
+    def run(f, nsteps, G, omega, Fu=None):
+        a = _f64(f).copy()
+        b = np.empty_like(a)
+        for _ in range(int(nsteps)):
+            shan_chen.step(a, G, omega, Fu=Fu, out=b)
+            a, b = b, a
+        return a
+
+    @staticmethod
+    def fields(f, G, Fu=None):
+        """(rho, u, p): u force-shifted with the interaction force;
+        p = cs^2 rho + G cs^2 psi^2 / 2, the bulk pressure of the model."""
+        f = _f64(f)
+        _, nz, ny, nx = f.shape
+        rho = np.zeros((nz, ny, nx))
+        u = np.zeros((3, nz, ny, nx))
+        p = np.zeros((nz, ny, nx))
+        if lib().orc_sc_fields(nx, ny, nz, float(G), _p(None if Fu is None else _f64(Fu)), _p(f), _p(rho), _p(u),
+                               _p(p)) != 0:
+            raise MemoryError("Shan-Chen fields")
+        return rho, u, p
