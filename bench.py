@@ -127,9 +127,11 @@ def time_ensemble(L, inputs, torch, steps, warmup, mlp, tune=True):
 
 def time_coupled(L, inputs, torch, steps, warmup):
     """Coupled-lattice workloads: the two-phase droplet (192^3, R = 32,
-    density ratio 10, sigma = 1e-3, W = 4, FP32) and the Hartmann channel
-    (32 x 128 x 32, Ha = 10, FP32).  Algorithmic bytes per node and step:
-    two-phase 244 (flow 152, phase 56, phi 32 + 4), magnetic 320."""
+    density ratio 10, sigma = 1e-3, W = 4, FP32), the Hartmann channel
+    (32 x 128 x 32, Ha = 10, FP32) and the Shan-Chen static bubble (100^3,
+    R = 20, G = -5, nu = 0.0333, FP32).  Algorithmic bytes per node and step:
+    two-phase 244 (flow 152, phase 56, phi 32 + 4), magnetic 320, Shan-Chen
+    236 (psi launch 76 + 4, step 152 + 4)."""
     import numpy as np
 
     out = {}
@@ -152,6 +154,15 @@ def time_coupled(L, inputs, torch, steps, warmup):
     b[1] = b0
     lat.init_magnetic(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)), b)
     out["hartmann_32x128x32"] = _time_lattice(lat, torch, 4 * steps, warmup, nx * ny * nz, 320)
+    lat.close()
+    n = 100
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r = np.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2 + (z - n / 2) ** 2)
+    rho = 0.15 + 1.8 * 0.5 * (1 - np.tanh((r - 20.0) / 2.0))
+    par = L.make_params(n, n, n, precision="fp32", omega=inputs.omega_from_nu(0.0333), shan_chen=dict(G=-5.0))
+    lat = L.Lattice(par)
+    lat.init(rho, np.zeros((3,) + rho.shape))
+    out["shan_chen_bubble_100"] = _time_lattice(lat, torch, 4 * steps, warmup, n ** 3, 236)
     lat.close()
     return out
 

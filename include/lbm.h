@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 3
+#define LBM_ABI_VERSION 4
 
 typedef enum {
     LBM_OK = 0,
@@ -82,7 +82,8 @@ typedef enum { LBM_CENTRAL_MOMENTS = 0, LBM_RAW_MOMENTS = 1 } lbm_moment_space;
 typedef enum {
     LBM_COUPLED_NONE = 0,
     LBM_COUPLED_PHASE = 1,    /* two-phase flow with a conservative phase field (see below) */
-    LBM_COUPLED_MAGNETIC = 2  /* magnetohydrodynamics with a vector magnetic lattice (see below) */
+    LBM_COUPLED_MAGNETIC = 2, /* magnetohydrodynamics with a vector magnetic lattice (see below) */
+    LBM_COUPLED_SHAN_CHEN = 3 /* Shan-Chen pseudo-potential two-phase flow (see below) */
 } lbm_coupling;
 
 /* Two-phase flow (not in the paper, whose multiphase models are Shan-Chen and
@@ -116,6 +117,17 @@ typedef struct {
     double b_wall[3];         /* field imposed at the y walls (walls_y = 1) */
 } lbm_magnetic_params;
 
+/* Shan-Chen two-phase flow (static-bubble case of Sec. III): pseudo-potential
+ * psi = 1 - exp(-rho) and interaction force
+ * F(x) = -G psi(x) sum_i w_i c_i psi(x + c_i) (X. Shan & H. Chen, Phys. Rev. E
+ * 47, 1993) from the density of the step's populations; any uniform force
+ * (force_mode LBM_FORCE_UNIFORM) adds to it; the sum enters the collision as
+ * F.  Bulk pressure p = rho/3 + G psi^2 / 6.  No extra populations: one more
+ * field (psi) and one more launch per step. */
+typedef struct {
+    double G;                 /* interaction strength (the paper: -5); finite */
+} lbm_shan_chen_params;
+
 typedef struct {
     uint32_t abi_version;     /* must be LBM_ABI_VERSION */
     int32_t nx, ny, nz;       /* lattice nodes; periodic in x and z, and in y unless walls_y */
@@ -147,6 +159,9 @@ typedef struct {
                                  bulk and higher-order rates; any external force mode */
     int32_t moments;          /* lbm_moment_space; LBM_RAW_MOMENTS needs q = 19 and no coupled
                                  lattice, and takes no network (lbm_set_mlp) */
+    lbm_shan_chen_params shan_chen; /* LBM_COUPLED_SHAN_CHEN: q = 19, FP64 or FP32, A-B, periodic,
+                                 force mode NONE or UNIFORM; any rates; initialised with
+                                 lbm_init (f = f_eq(rho, u)) */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

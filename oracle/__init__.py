@@ -118,7 +118,7 @@ def lib():
         L.orc_sc_psi.argtypes = [f64]
         L.orc_sc_psi.restype = f64
         L.orc_sc_force.argtypes = [i32, i32, i32, dp, f64, dp, dp]
-        L.orc_sc_step.argtypes = [i32, i32, i32, f64, dp, f64, dp, dp, dp]
+        L.orc_sc_step.argtypes = [i32, i32, i32, f64, dp, dp, dp, dp, dp]
         L.orc_sc_step.restype = i32
         L.orc_sc_fields.argtypes = [i32, i32, i32, f64, dp, dp, dp, dp, dp]
         L.orc_sc_fields.restype = i32
@@ -657,10 +657,12 @@ class shan_chen:
 
     @staticmethod
     def step(f, G, omega, Fu=None, out=None, F_out=None):
+        """omega: the shear rate (the paper's K) or a full K diagonal (19)."""
         f = _f64(f)
         _, nz, ny, nx = f.shape
         out = np.empty_like(f) if out is None else out
-        if lib().orc_sc_step(nx, ny, nz, float(G), _p(None if Fu is None else _f64(Fu)), float(omega), _p(f),
+        Kd = _f64(omega) if np.ndim(omega) else K(float(omega))
+        if lib().orc_sc_step(nx, ny, nz, float(G), _p(None if Fu is None else _f64(Fu)), _p(Kd), _p(f),
                              _p(out), _p(F_out)) != 0:
             raise ArithmeticError("Shan-Chen step failed")
         return out

@@ -19,7 +19,7 @@
  *       force.
  *
  * Layout: f[i*N + n], F[d*N + n], n = x + nx*(y + ny*z), velocity order of
- * Sec. II.A.  Rates: omega on k5..k9, 1 elsewhere (the paper's).
+ * Sec. II.A.  Rates: any K (the paper's: omega on k5..k9, 1 elsewhere).
  */
 #include <math.h>
 #include <stdint.h>
@@ -28,7 +28,6 @@
 
 /* from d3q19_oracle.c */
 void orc19_tables(int *c, double *w, int *opp);
-void orc19_K(double omega, double omega_bulk, const double *omega_hi, double *K);
 int orc19_step(int nx, int ny, int nz, int walls_y, const double *f, double *fnew, const double *F,
                const double *Krates, int per_node_K, int mode);
 
@@ -76,11 +75,12 @@ static void density(int nx, int ny, int nz, const double *f, double *rho)
 
 /*
  * One step: rho from f, the force field above, then the paper's collision
- * and periodic streaming (closed-form mode of the D3Q19 oracle).  F_out
+ * with the 19 relaxation rates K and periodic streaming (closed-form mode of
+ * the D3Q19 oracle).  F_out
  * (3N, optional) receives the force used.  Returns 0, -1 on a singular
  * collision system, -2 on allocation failure.
  */
-int orc_sc_step(int nx, int ny, int nz, double G, const double *Fu, double omega, const double *f, double *fnew,
+int orc_sc_step(int nx, int ny, int nz, double G, const double *Fu, const double *K, const double *f, double *fnew,
                 double *F_out)
 {
     const int64_t N = (int64_t)nx * ny * nz;
@@ -93,8 +93,6 @@ int orc_sc_step(int nx, int ny, int nz, double G, const double *Fu, double omega
     }
     density(nx, ny, nz, f, rho);
     orc_sc_force(nx, ny, nz, rho, G, Fu, F);
-    double K[Q];
-    orc19_K(omega, 1.0, NULL, K);
     const int rc = orc19_step(nx, ny, nz, 0, f, fnew, F, K, 0, 1);
     free(rho);
     if (!F_out) free(F);

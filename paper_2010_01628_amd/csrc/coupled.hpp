@@ -43,4 +43,12 @@ void launch_mhd_get_g(int precision, bool walls, const void* gbuf, const Geom& g
 void launch_mhd_set_g(int precision, bool walls, void* gbuf, const Geom& g, const MhdConst& mc, const double* in,
                       dim3 grid, dim3 block, hipStream_t st);
 
+// Shan-Chen two-phase flow: psi from the pulled densities into `psi`, then
+// the fused step with the interaction force.
+void launch_sc_step(int precision, bool general, bool nt, const void* src, void* dst, void* psi, const Geom& g,
+                    const Phys& ph, double G, dim3 grid, dim3 block, hipStream_t st);
+// psi refreshed from src, then rho, force-shifted u and the partial sums.
+void launch_sc_fields(int precision, const void* src, void* psi, const Geom& g, const Phys& ph, double G, double* rho,
+                      double* u, double* partials, dim3 grid, dim3 block, hipStream_t st);
+
 } // namespace lbm

@@ -61,9 +61,23 @@ static int magnetic_validate(const lbm_params* p)
     return LBM_OK;
 }
 
+static int shan_chen_validate(const lbm_params* p)
+{
+    if (p->q != 19) return lbm_fail(LBM_EUNSUPPORTED, "the Shan-Chen lattice is D3Q19");
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
+        return lbm_fail(LBM_EUNSUPPORTED, "the Shan-Chen lattice stores FP64 or FP32");
+    if (p->streaming != LBM_AB) return lbm_fail(LBM_EUNSUPPORTED, "the Shan-Chen lattice streams A-B");
+    if (p->walls_y) return lbm_fail(LBM_EUNSUPPORTED, "the Shan-Chen lattice is periodic");
+    if (p->force_mode != LBM_FORCE_NONE && p->force_mode != LBM_FORCE_UNIFORM)
+        return lbm_fail(LBM_EUNSUPPORTED, "the Shan-Chen lattice adds only a uniform external force");
+    if (!std::isfinite(p->shan_chen.G)) return lbm_fail(LBM_EINVAL, "G must be finite");
+    return LBM_OK;
+}
+
 int coupled_validate(const lbm_params* p)
 {
     if (p->coupled == LBM_COUPLED_MAGNETIC) return magnetic_validate(p);
+    if (p->coupled == LBM_COUPLED_SHAN_CHEN) return shan_chen_validate(p);
     const lbm_phase_params& q = p->phase;
     if (p->q != 19) return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice is D3Q19");
     if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
@@ -88,8 +102,15 @@ int coupled_create(lbm_handle* h)
     const lbm_params& p = h->p;
     lbm_coupled* c = new lbm_coupled();
     h->cp = c;
-    c->q = p.coupled == LBM_COUPLED_MAGNETIC ? 21 : 7;
     const int eb = eb_of(p.precision);
+    if (p.coupled == LBM_COUPLED_SHAN_CHEN) {
+        c->q = 0;
+        c->sc_G = p.shan_chen.G;
+        CHIP(hipMalloc(&c->scratch, (int64_t)h->g.N * eb));
+        h->bytes += (int64_t)h->g.N * eb;
+        return LBM_OK;
+    }
+    c->q = p.coupled == LBM_COUPLED_MAGNETIC ? 21 : 7;
     const int64_t bytes = (int64_t)c->q * h->g.stride * eb;
     for (int b = 0; b < 2; ++b) {
         CHIP(hipMalloc(&c->buf[b], bytes));
@@ -128,6 +149,12 @@ int coupled_step(lbm_handle* h)
 {
     lbm_coupled* c = h->cp;
     const int src = h->cur, dst = 1 - h->cur;
+    if (h->p.coupled == LBM_COUPLED_SHAN_CHEN) {
+        lbm::launch_sc_step(h->p.precision, h->general, h->nt, h->buf[src], h->buf[dst], c->scratch, h->g, h->ph, c->sc_G,
+                            h->grid, h->block, h->stream);
+        CHIP(hipGetLastError());
+        return LBM_OK;
+    }
     if (h->p.coupled == LBM_COUPLED_MAGNETIC) {
         lbm::launch_mhd_step(h->p.precision, h->walls, h->nt, h->buf[src], h->buf[dst], c->buf[src], c->buf[dst], h->g,
                              h->ph, c->mc, h->grid, h->block, h->stream);
@@ -152,7 +179,10 @@ int coupled_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_
         drho = rho ? staging : nullptr;
         du = u ? staging + N : nullptr;
     }
-    if (h->p.coupled == LBM_COUPLED_MAGNETIC)
+    if (h->p.coupled == LBM_COUPLED_SHAN_CHEN)
+        lbm::launch_sc_fields(h->p.precision, h->buf[h->cur], c->scratch, h->g, h->ph, c->sc_G, drho, du, h->partials,
+                              h->grid, h->block, h->stream);
+    else if (h->p.coupled == LBM_COUPLED_MAGNETIC)
         lbm::launch_mhd_fields(h->p.precision, h->walls, h->buf[h->cur], c->buf[h->cur], h->g, h->ph, c->mc, drho, du,
                                nullptr, nullptr, h->partials, h->grid, h->block, h->stream);
     else
@@ -224,7 +254,7 @@ int lbm_phase_fields(lbm_handle* h, double* phi, double* p, int on_device)
 int lbm_get_coupled_populations(lbm_handle* h, double* out, int on_device)
 {
     if (!h || !out) return lbm_fail(LBM_EINVAL, "NULL argument");
-    if (!h->cp) return lbm_fail(LBM_EINVAL, "no coupled lattice");
+    if (!h->cp || h->cp->q == 0) return lbm_fail(LBM_EINVAL, "no coupled populations");
     const int64_t bytes = sizeof(double) * h->cp->q * (int64_t)h->g.N;
     double* dst = out;
     if (!on_device) CHIP(hipMalloc((void**)&dst, bytes));
@@ -246,7 +276,7 @@ int lbm_get_coupled_populations(lbm_handle* h, double* out, int on_device)
 int lbm_set_coupled_populations(lbm_handle* h, const double* in, int on_device)
 {
     if (!h || !in) return lbm_fail(LBM_EINVAL, "NULL argument");
-    if (!h->cp) return lbm_fail(LBM_EINVAL, "no coupled lattice");
+    if (!h->cp || h->cp->q == 0) return lbm_fail(LBM_EINVAL, "no coupled populations");
     Staged s;
     int rc = stage_in(in, (int64_t)h->cp->q * h->g.N, on_device, h->stream, s);
     if (rc) return rc;

@@ -12,8 +12,9 @@
 // State of a coupled lattice (lbm_params.coupled != LBM_COUPLED_NONE).
 struct lbm_coupled {
     void* buf[2] = {nullptr, nullptr}; // its populations (A-B), same stride as the flow lattice
-    int q = 0;                         // populations per node (7 phase, 21 magnetic)
-    void* scratch = nullptr;           // phase field phi (storage-precision arithmetic type)
+    int q = 0;                         // populations per node (7 phase, 21 magnetic, 0 Shan-Chen)
+    void* scratch = nullptr;           // phase field phi or pseudo-potential psi (collision arithmetic type)
+    double sc_G = 0.0;                 // Shan-Chen interaction strength
     lbm::PhaseConst pc{};
     lbm::MhdConst mc{};
 };

@@ -106,7 +106,7 @@ int validate(const lbm_params* p)
     if (p->moments != LBM_CENTRAL_MOMENTS && p->moments != LBM_RAW_MOMENTS) return fail(LBM_EINVAL, "bad moments");
     if (p->moments == LBM_RAW_MOMENTS && (p->q != 19 || p->coupled != LBM_COUPLED_NONE))
         return fail(LBM_EUNSUPPORTED, "raw moments: D3Q19 without a coupled lattice");
-    if (p->coupled < LBM_COUPLED_NONE || p->coupled > LBM_COUPLED_MAGNETIC) return fail(LBM_EINVAL, "bad coupled");
+    if (p->coupled < LBM_COUPLED_NONE || p->coupled > LBM_COUPLED_SHAN_CHEN) return fail(LBM_EINVAL, "bad coupled");
     if (p->coupled != LBM_COUPLED_NONE) return coupled_validate(p);
     return LBM_OK;
 }
@@ -317,7 +317,8 @@ int lbm_destroy(lbm_handle* h)
 int lbm_init(lbm_handle* h, const double* rho, const double* u, int on_device)
 {
     if (!h || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
-    if (h->cp) return fail(LBM_EINVAL, "a coupled lattice starts from its own init call (lbm_init_phase)");
+    if (h->cp && h->p.coupled != LBM_COUPLED_SHAN_CHEN)
+        return fail(LBM_EINVAL, "a coupled lattice starts from its own init call (lbm_init_phase)");
     const int64_t N = h->g.N;
     const double* drho = rho;
     const double* du = u;

@@ -19,7 +19,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3
 LBM_AB, LBM_AA = 0, 1
@@ -46,7 +46,11 @@ class lbm_magnetic_params(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("b_wall", ctypes.c_double * 3)]
 
 
-LBM_COUPLED_NONE, LBM_COUPLED_PHASE, LBM_COUPLED_MAGNETIC = 0, 1, 2
+class lbm_shan_chen_params(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double)]
+
+
+LBM_COUPLED_NONE, LBM_COUPLED_PHASE, LBM_COUPLED_MAGNETIC, LBM_COUPLED_SHAN_CHEN = 0, 1, 2, 3
 
 
 class lbm_params(ctypes.Structure):
@@ -72,6 +76,7 @@ class lbm_params(ctypes.Structure):
         ("phase", lbm_phase_params),
         ("magnetic", lbm_magnetic_params),
         ("moments", ctypes.c_int32),
+        ("shan_chen", lbm_shan_chen_params),
     ]
 
 
@@ -418,11 +423,12 @@ class Ensemble:
 def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
                 rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
                 force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0,
-                q=19, phase=None, magnetic=None, moments="central") -> lbm_params:
+                q=19, phase=None, magnetic=None, moments="central", shan_chen=None) -> lbm_params:
     """phase: dict(rho_light, rho_heavy, sigma, width, mobility) makes a
     two-phase lattice (coupled = LBM_COUPLED_PHASE); magnetic: dict(eta,
     b_wall=(bx, by, bz)) a magnetic one (LBM_COUPLED_MAGNETIC); moments:
-    "central" (the paper's scheme) or "raw" (its N = I variant)."""
+    "central" (the paper's scheme) or "raw" (its N = I variant); shan_chen:
+    dict(G) a Shan-Chen two-phase lattice (LBM_COUPLED_SHAN_CHEN)."""
     p = lbm_params_default()
     p.q = int(q)
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -450,6 +456,9 @@ def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_b
         bw = magnetic.get("b_wall", (0.0, 0.0, 0.0))
         for d in range(3):
             p.magnetic.b_wall[d] = float(bw[d])
+    if shan_chen is not None:
+        p.coupled = LBM_COUPLED_SHAN_CHEN
+        p.shan_chen.G = float(shan_chen["G"])
     if phase is not None:
         p.coupled = LBM_COUPLED_PHASE
         for k in ("rho_light", "rho_heavy", "sigma", "width", "mobility"):

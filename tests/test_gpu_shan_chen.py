@@ -1,0 +1,188 @@
+"""Shan-Chen two-phase lattice (static-bubble case of Sec. III) on the GPU
+against the FP64 oracle, through the C ABI: element by element in FP64
+(ragged and degenerate shapes, uniform force, general rates), relative L2 in
+FP32, and the paper's static-bubble workload (100^3, R = 15..30, densities
+1.95 / 0.15, nu = 0.0333, G = -5): the pressure jump is linear in 1/R
+(Young-Laplace) and the spurious currents are reported beside those of the
+single-rate (BGK) collision."""
+import numpy as np
+import pytest
+
+from gpu_helpers import rel_l2, say
+from paper_2010_01628_amd import inputs
+from paper_2010_01628_amd import lbm as L
+
+pytestmark = pytest.mark.gpu
+
+G = -5.0
+NU = 0.0333
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+
+
+def droplet_rho(shape, R, center=None, rho_l=1.95, rho_g=0.15, W=2.0):
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = center if center is not None else ((nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2)
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+    return rho_g + (rho_l - rho_g) * 0.5 * (1 - np.tanh((r - R) / W))
+
+
+def pressure(rho):
+    psi = 1.0 - np.exp(-rho)
+    return rho / 3.0 + G * psi ** 2 / 6.0
+
+
+def gpu_sc(shape, rho, u, steps, precision="fp64", omega=None, omega_bulk=1.0, omega_hi=None, Fu=None):
+    nx, ny, nz = shape
+    om = inputs.omega_from_nu(NU) if omega is None else omega
+    par = L.make_params(nx, ny, nz, precision=precision, omega=om, omega_bulk=omega_bulk, omega_hi=omega_hi,
+                        force_mode=L.LBM_FORCE_UNIFORM if Fu is not None else L.LBM_FORCE_NONE,
+                        force=(0.0, 0.0, 0.0) if Fu is None else Fu, shan_chen=dict(G=G))
+    lat = L.Lattice(par)
+    try:
+        lat.init(rho, u)
+        lat.step(steps)
+        r, v, diag = lat.moments()
+        return dict(f=lat.get_populations().cpu().numpy(), rho=r.cpu().numpy(), u=v.cpu().numpy(), diag=diag)
+    finally:
+        lat.close()
+
+
+CASES = [
+    # shape, steps, general rates, uniform force
+    ((14, 11, 9), 9, False, None),
+    ((14, 11, 9), 7, True, (1e-5, -2e-5, 3e-6)),
+    ((64, 6, 5), 6, False, (0.0, 1e-5, 0.0)),   # whole-row work-groups
+    ((1, 12, 7), 8, True, None),                # degenerate x
+]
+
+
+@pytest.mark.parametrize("shape,steps,general,Fu", CASES)
+def test_fp64_matches_oracle(orc, shape, steps, general, Fu):
+    say(f"shan-chen fp64 {shape} steps={steps} general={general} Fu={Fu}")
+    nx, ny, nz = shape
+    rho = droplet_rho(shape, min(shape) / 3 + 1, W=1.5)
+    _, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=nx + ny + nz, umax=0.02)
+    rng = np.random.default_rng(nx * ny)
+    om = rng.uniform(0.8, 1.9)
+    ob, oh = (rng.uniform(0.7, 1.8), rng.uniform(0.7, 1.8, 9)) if general else (1.0, None)
+    g = gpu_sc(shape, rho, u, steps, "fp64", om, ob, oh, Fu)
+    Kd = orc.K(om, ob, oh)
+    fo = orc.init(rho, u)
+    for _ in range(steps):
+        fo = orc.shan_chen.step(fo, G, Kd, Fu=None if Fu is None else np.array(Fu))
+    ro, uo, _ = orc.shan_chen.fields(fo, G, Fu=None if Fu is None else np.array(Fu))
+    err = np.abs(g["f"] - fo).max()
+    say(f"  max |f_gpu - f_oracle| = {err:.3e}")
+    assert err < 1e-13
+    assert np.abs(g["rho"] - ro).max() < 1e-13
+    assert np.abs(g["u"] - uo).max() < 1e-13
+
+
+def test_fp32_matches_oracle(orc):
+    shape, steps = (24, 20, 18), 100
+    rho = droplet_rho(shape, 6.0)
+    u = np.zeros((3,) + rho.shape)
+    g = gpu_sc(shape, rho, u, steps, "fp32")
+    fo = orc.shan_chen.run(orc.init(rho, u), steps, G, inputs.omega_from_nu(NU))
+    ro, uo, _ = orc.shan_chen.fields(fo, G)
+    e_r, e_u = rel_l2(g["rho"], ro), rel_l2(g["u"], uo)
+    say(f"  fp32 rel L2 rho {e_r:.2e}, u {e_u:.2e}")
+    assert e_r < 1e-6 and e_u < 1e-4
+
+
+def test_uniform_density_equals_plain_lattice_bitwise():
+    """Uniform density: psi is uniform and the interaction force sums to
+    exactly zero (differences of equal values), so the step equals the plain
+    FP32 lattice with the same uniform force, bit for bit.  One step: the
+    random velocity makes the density non-uniform after it."""
+    shape = (20, 12, 9)
+    nx, ny, nz = shape
+    _, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=4, umax=0.03)
+    rho = np.full((nz, ny, nx), 1.2)
+    a = gpu_sc(shape, rho, u, 1, "fp32", Fu=(1e-5, 0.0, -1e-5))
+    par = L.make_params(nx, ny, nz, precision="fp32", omega=inputs.omega_from_nu(NU), force_mode=L.LBM_FORCE_UNIFORM,
+                        force=(1e-5, 0.0, -1e-5))
+    lat = L.Lattice(par)
+    lat.init(rho, u)
+    lat.step(1)
+    b = lat.get_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(a["f"], b)
+
+
+def static_bubble(R, steps=20000, omega_all=False, n=100):
+    """Paper's static bubble at L = 100 (FP32), run 20,000 steps (converged
+    to 1e-4 in the pressure jump by 10,000).  Returns the pressure jump
+    between the centre and the far corner, the spurious max|u|, and the
+    equilibrium radius from the liquid volume sum((rho - rho_g)/(rho_l - rho_g))
+    (the radius settles a few nodes above the initial one as the bulk
+    densities relax to coexistence)."""
+    import torch
+
+    rho = droplet_rho((n, n, n), R, center=(n / 2, n / 2, n / 2))
+    om = inputs.omega_from_nu(NU)
+    kw = dict(omega_bulk=om, omega_hi=[om] * 9) if omega_all else {}
+    par = L.make_params(n, n, n, precision="fp32", omega=om, shan_chen=dict(G=G), **kw)
+    lat = L.Lattice(par)
+    try:
+        lat.init(torch.from_numpy(rho).cuda(), torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda"))
+        lat.step(steps)
+        r, u, _ = lat.moments()
+        rn = r.cpu().numpy()
+        umax = float(torch.linalg.vector_norm(u, dim=0).max().item())
+    finally:
+        lat.close()
+    c = n // 2
+    rl = rn[c - 2:c + 3, c - 2:c + 3, c - 2:c + 3].mean()
+    rg = rn[:4, :4, :4].mean()
+    dp = float(pressure(rl) - pressure(rg))
+    Req = float((3.0 / (4 * np.pi) * np.sum((rn - rg) / (rl - rg))) ** (1.0 / 3.0))
+    return dp, umax, Req, rl, rg
+
+
+def test_static_bubble_young_laplace():
+    """100^3, initial R = 15, 20, 25, 30: the steady pressure jump is a
+    straight line in 1/R (equilibrium radius) through the origin within a few
+    per cent, i.e. dp = 2 sigma / R with one sigma for all radii."""
+    res = []
+    for R in (15.0, 20.0, 25.0, 30.0):
+        dp, umax, Req, rl, rg = static_bubble(R)
+        say(f"  R0 = {R}: R_eq = {Req:.3f}, dp = {dp:.6e}, max|u| = {umax:.3e}, rho_l = {rl:.5f}, rho_g = {rg:.5f}")
+        res.append((Req, dp))
+    Rv = np.array([a for a, _ in res])
+    dp = np.array([b for _, b in res])
+    A = np.vstack([1.0 / Rv, np.ones_like(Rv)]).T
+    (slope, icpt), *_ = np.linalg.lstsq(A, dp, rcond=None)
+    fit = A @ np.array([slope, icpt])
+    r2 = 1 - np.sum((dp - fit) ** 2) / np.sum((dp - dp.mean()) ** 2)
+    sig = dp * Rv / 2
+    say(f"  fit: sigma = slope/2 = {slope / 2:.5e}, intercept {icpt:.3e} ({icpt / dp.min():.2%} of the smallest "
+        f"jump), R^2 {r2:.6f}; dp R / 2 = {np.round(sig, 5)}")
+    assert np.all(np.diff(dp) < 0) and np.all(dp > 0)
+    assert r2 > 0.9995
+    assert abs(icpt) < 0.1 * dp.min()
+    assert sig.max() / sig.min() - 1 < 0.05
+
+
+def test_spurious_currents_cm_vs_bgk():
+    """R = 20: the collision of Sec. II.B (higher-order and bulk moments at
+    equilibrium) against every rate equal to omega (BGK with the extended
+    equilibrium).  The paper reports markedly weaker spurious currents for the
+    former; measured here 1.4e-2 against 3.7e-2.  Both runs must keep the
+    same pressure jump (the interface physics does not depend on the
+    non-hydrodynamic rates) within 1 %."""
+    dp_cm, u_cm, _, _, _ = static_bubble(20.0)
+    dp_bgk, u_bgk, _, _, _ = static_bubble(20.0, omega_all=True)
+    say(f"  spurious max|u|: CM {u_cm:.3e}, BGK {u_bgk:.3e}; dp CM {dp_cm:.4e}, BGK {dp_bgk:.4e}")
+    assert u_cm < 0.5 * u_bgk
+    assert u_bgk < 0.1
+    assert abs(dp_cm / dp_bgk - 1) < 0.01
