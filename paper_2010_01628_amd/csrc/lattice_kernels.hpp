@@ -113,6 +113,26 @@ __device__ inline void node_idx(const Geom& g, int x, int y, int z, NodeIdx& d)
     d.yhi = y == g.ny - 1;
 }
 
+// Node of this thread: a 3-D grid of (bx, by) work-groups over x rows and z
+// planes, or (g.flat) a 1-D grid over all N nodes in index order, which
+// leaves no lane idle when nx is not a multiple of the work-group width.
+__device__ inline bool thread_node(const Geom& g, int& x, int& y, int& z)
+{
+    if (g.flat) {
+        const int n = blockIdx.x * blockDim.x + threadIdx.x;
+        if (n >= g.N) return false;
+        const int t = n / g.nx;
+        x = n - t * g.nx;
+        y = t % g.ny;
+        z = t / g.ny;
+        return true;
+    }
+    x = blockIdx.x * blockDim.x + threadIdx.x;
+    y = blockIdx.y * blockDim.y + threadIdx.y;
+    z = blockIdx.z;
+    return x < g.nx && y < g.ny;
+}
+
 // index of node x + (dx, dy, dz), dx etc. in {-1, 0, 1}
 __device__ inline int nb(const NodeIdx& d, int dx, int dy, int dz) { return d.ox[1 + dx] + d.oy[1 + dy] + d.oz[1 + dz]; }
 

@@ -35,10 +35,8 @@ __global__ __launch_bounds__(256) void k_phase_sum(const S* __restrict__ hsrc, t
                                                   Geom g)
 {
     using R = typename Codec<S>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
+    int x, y, z;
+    if (!thread_node(g, x, y, z)) return;
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R h[7];
@@ -61,10 +59,8 @@ __global__ __launch_bounds__(256) void k_phase_step(const S* __restrict__ gsrc, 
                                                    const typename Codec<S>::R* __restrict__ phi, Geom g, PhaseConst pc)
 {
     using R = typename Codec<S>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
+    int x, y, z;
+    if (!thread_node(g, x, y, z)) return;
     NodeIdx d;
     node_idx(g, x, y, z, d);
     const int n = nb(d, 0, 0, 0);

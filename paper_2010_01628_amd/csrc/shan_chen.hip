@@ -6,6 +6,7 @@
 // One step is two launches over all nodes (A-B pull streaming, periodic):
 //   k_sc_psi:  psi(x) from the density of the populations node x pulls
 //              (4 or 8 bytes per node written);
+// Both take a 1-D grid over all nodes (Geom::flat) or the 3-D one.
 //   k_sc_step: psi at the 19 stencil nodes (cached reads of a small field),
 //              the force, then the fused gather-collide-store of the plain
 //              lattice.
@@ -21,10 +22,8 @@ __global__ __launch_bounds__(256) void k_sc_psi(const S* __restrict__ src, typen
                                                double rho0)
 {
     using R = typename Codec<S>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
+    int x, y, z;
+    if (!thread_node(g, x, y, z)) return;
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R s[19];
@@ -61,10 +60,8 @@ __global__ __launch_bounds__(256) void k_sc_step(const S* __restrict__ src, S* _
                                                 const typename Codec<S>::R* __restrict__ psi, Geom g, Phys ph, double G)
 {
     using R = typename Codec<S>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
+    int x, y, z;
+    if (!thread_node(g, x, y, z)) return;
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R Fx, Fy, Fz;
