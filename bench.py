@@ -261,6 +261,8 @@ def main(argv=None):
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
     ap.add_argument("--mem-check", action="store_true",
                     help="also run 512^3 AA FP32 and FP16 (device bytes and MLUPS)")
+    ap.add_argument("--no-cost-table", action="store_true",
+                    help="skip the D3Q19/D3Q27 x raw/central cost table over D = 32..128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM counters)")
@@ -331,6 +333,12 @@ def main(argv=None):
     if not args.no_coupled:
         log("bench: coupled-lattice workloads")
         coupled = time_coupled(L, inputs, torch, max(20, args.steps // 2), max(4, args.warmup // 2))
+    cost = None
+    if not args.no_cost_table:
+        from paper_2010_01628_amd import taylor_green
+
+        log("bench: cost table (Taylor-Green, D = 32..128)")
+        cost = taylor_green.cost_table()
     mem = None
     if args.mem_check:
         log("bench: 512^3 memory check")
@@ -393,6 +401,7 @@ def main(argv=None):
                      for k, v in variants.items()},
         "ensemble": ensemble,
         "coupled": coupled,
+        "cost_table": cost,
         "mem_check_512": mem,
         "kernel_source_hash": kernel_source_hash(),
     }

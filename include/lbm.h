@@ -75,7 +75,8 @@ typedef enum {
  * raw-moment MRT written in the same basis (App. C): k = M f, the raw
  * equilibrium moments printed there, the raw moments of the forcing term of
  * App. B (eq. RMQ19), the same K, f* = M^-1 k*.  With K = I both give the
- * same populations. */
+ * same populations.  For D3Q27 (timed in App. D, not written out) the raw
+ * moments of the same equilibrium and forcing term are used. */
 typedef enum { LBM_CENTRAL_MOMENTS = 0, LBM_RAW_MOMENTS = 1 } lbm_moment_space;
 
 /* Lattice coupled to the flow (Sec. III multiphysics cases). */
@@ -157,8 +158,9 @@ typedef struct {
                                  rho0 = 1 */
     lbm_magnetic_params magnetic; /* LBM_COUPLED_MAGNETIC: q = 19, FP64 or FP32, A-B, the paper's
                                  bulk and higher-order rates; any external force mode */
-    int32_t moments;          /* lbm_moment_space; LBM_RAW_MOMENTS needs q = 19 and no coupled
-                                 lattice, and takes no network (lbm_set_mlp) */
+    int32_t moments;          /* lbm_moment_space; LBM_RAW_MOMENTS: no coupled lattice and no
+                                 network (lbm_set_mlp); with q = 27 the D3Q27 rates and forcing
+                                 of the CM lattice, in raw moments */
     lbm_shan_chen_params shan_chen; /* LBM_COUPLED_SHAN_CHEN: q = 19, FP64 or FP32, A-B, periodic,
                                  force mode NONE or UNIFORM; any rates; initialised with
                                  lbm_init (f = f_eq(rho, u)) */

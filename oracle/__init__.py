@@ -85,6 +85,12 @@ def lib():
         L.orc27_collide.restype = i32
         L.orc27_step.argtypes = [i32, i32, i32, i32, dp, dp, dp, dp]
         L.orc27_step.restype = i32
+        L.orc27_step_mode.argtypes = [i32, i32, i32, i32, dp, dp, dp, dp, i32]
+        L.orc27_step_mode.restype = i32
+        L.orc27_collide_mode.argtypes = [dp, dp, dp, i32, dp, dp, dp]
+        L.orc27_collide_mode.restype = i32
+        L.orc27_keq_rm.argtypes = [f64, f64, f64, f64, dp]
+        L.orc27_Rrm.argtypes = [f64, f64, f64, f64, f64, f64, dp]
         L.orc27_init.argtypes = [i32, i32, i32, dp, dp, dp]
         L.orc27_moments.argtypes = [i32, i32, i32, dp, dp, dp, dp]
         i64p = ctypes.POINTER(ctypes.c_int64)
@@ -336,20 +342,33 @@ class d3q27:
         return out
 
     @staticmethod
+    def keq_rm(rho, u):
+        out = np.zeros(Q27)
+        lib().orc27_keq_rm(float(rho), float(u[0]), float(u[1]), float(u[2]), _p(out))
+        return out
+
+    @staticmethod
+    def Rrm(u, F):
+        out = np.zeros(Q27)
+        lib().orc27_Rrm(float(u[0]), float(u[1]), float(u[2]), float(F[0]), float(F[1]), float(F[2]), _p(out))
+        return out
+
+    @staticmethod
     def K(omega):
         out = np.zeros(Q27)
         lib().orc27_K(float(omega), _p(out))
         return out
 
     @staticmethod
-    def collide(f, F=(0.0, 0.0, 0.0), Kdiag=None):
+    def collide(f, F=(0.0, 0.0, 0.0), Kdiag=None, raw=False):
+        """raw: the raw-moment variant (N = I)."""
         f = _f64(f)
         F = _f64(F)
         Kd = _f64(Kdiag if Kdiag is not None else d3q27.K(1.0))
         fs = np.zeros(Q27)
         rho = np.zeros(1)
         u = np.zeros(3)
-        if lib().orc27_collide(_p(f), _p(F), _p(Kd), _p(fs), _p(rho), _p(u)) != 0:
+        if lib().orc27_collide_mode(_p(f), _p(F), _p(Kd), int(bool(raw)), _p(fs), _p(rho), _p(u)) != 0:
             raise ArithmeticError("singular collision system")
         return fs, float(rho[0]), u
 
@@ -363,22 +382,23 @@ class d3q27:
         return f
 
     @staticmethod
-    def step(f, Kdiag, F=None, walls_y=False, out=None):
+    def step(f, Kdiag, F=None, walls_y=False, out=None, raw=False):
         f = _f64(f)
         _, nz, ny, nx = f.shape
         if out is None:
             out = np.empty_like(f)
         Fa = None if F is None else _f64(F)
-        if lib().orc27_step(nx, ny, nz, int(bool(walls_y)), _p(f), _p(out), _p(Fa), _p(_f64(Kdiag))) != 0:
+        if lib().orc27_step_mode(nx, ny, nz, int(bool(walls_y)), _p(f), _p(out), _p(Fa), _p(_f64(Kdiag)),
+                                 int(bool(raw))) != 0:
             raise ArithmeticError("singular collision system")
         return out
 
     @staticmethod
-    def run(f, nsteps, Kdiag, F=None, walls_y=False):
+    def run(f, nsteps, Kdiag, F=None, walls_y=False, raw=False):
         a = _f64(f).copy()
         b = np.empty_like(a)
         for _ in range(int(nsteps)):
-            d3q27.step(a, Kdiag, F=F, walls_y=walls_y, out=b)
+            d3q27.step(a, Kdiag, F=F, walls_y=walls_y, out=b, raw=raw)
             a, b = b, a
         return a
 

@@ -16,6 +16,11 @@
  *       R_pqr = sum_a p_a F_a k^eq_{pqr - e_a} / rho, which reproduces the
  *       D3Q19 list of App. B eq. (CMQ19) on the shared monomials.
  *   Q4  force-shifted velocity and halfway bounce-back, as for D3Q19.
+ *   Q6  raw-moment variant (timed in App. D, not written out): N = I, i.e.
+ *       T = T(0) = M; k_eq and R are the raw moments of the same equilibrium
+ *       and forcing term, rho mu_p(ux) mu_q(uy) mu_r(uz) with
+ *       mu = (1, u, u^2 + 1/3) and R_pqr = sum_a p_a F_a (raw eq moment with
+ *       p_a lowered by one)/rho; the same K.
  * f* = T(u)^-1 k* by a dense solve per node (N^-1 is not printed).
  */
 #include <math.h>
@@ -179,6 +184,43 @@ void orc27_Rcm(double Fx, double Fy, double Fz, double *R)
     }
 }
 
+/* Reading Q6: raw moments of the Q1 equilibrium over rho, per monomial. */
+static double mu1(int p, double u) { return p == 0 ? 1.0 : (p == 1 ? u : u * u + 1.0 / 3.0); }
+static double keq_raw_mono(int p, int q, int s, double ux, double uy, double uz)
+{
+    return mu1(p, ux) * mu1(q, uy) * mu1(s, uz);
+}
+
+void orc27_keq_rm(double rho, double ux, double uy, double uz, double *keq)
+{
+    for (int r = 0; r < Q27; ++r) {
+        row_def d = row_monomials(r);
+        double v = 0.0;
+        for (int k = 0; k < d.n; ++k) v += d.coef[k] * keq_raw_mono(d.e[k][0], d.e[k][1], d.e[k][2], ux, uy, uz);
+        keq[r] = rho * v;
+    }
+}
+
+/* Reading Q6: Gaussian rule on the raw equilibrium moments. */
+static double rrm_mono(int p, int q, int s, double ux, double uy, double uz, double Fx, double Fy, double Fz)
+{
+    double v = 0.0;
+    if (p > 0) v += p * Fx * keq_raw_mono(p - 1, q, s, ux, uy, uz);
+    if (q > 0) v += q * Fy * keq_raw_mono(p, q - 1, s, ux, uy, uz);
+    if (s > 0) v += s * Fz * keq_raw_mono(p, q, s - 1, ux, uy, uz);
+    return v;
+}
+
+void orc27_Rrm(double ux, double uy, double uz, double Fx, double Fy, double Fz, double *R)
+{
+    for (int r = 0; r < Q27; ++r) {
+        row_def d = row_monomials(r);
+        double v = 0.0;
+        for (int k = 0; k < d.n; ++k) v += d.coef[k] * rrm_mono(d.e[k][0], d.e[k][1], d.e[k][2], ux, uy, uz, Fx, Fy, Fz);
+        R[r] = v;
+    }
+}
+
 /* Reading Q2. */
 void orc27_K(double omega, double *K)
 {
@@ -213,8 +255,10 @@ static int solve27(double *A, double *b, double *x)
     return 0;
 }
 
-/* One D3Q27 collision: k = T(u) f, k* = (I-K)k + K k_eq + (I-K/2) R, f* = T^-1 k*. */
-int orc27_collide(const double *f, const double *F, const double *K, double *fstar, double *rho_out, double *uout)
+/* One D3Q27 collision: k = T(u) f, k* = (I-K)k + K k_eq + (I-K/2) R, f* = T^-1 k*;
+ * raw != 0: the raw-moment variant (reading Q6), T = T(0). */
+int orc27_collide_mode(const double *f, const double *F, const double *K, int raw, double *fstar, double *rho_out,
+                       double *uout)
 {
     double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     for (int i = 0; i < Q27; ++i) {
@@ -225,25 +269,40 @@ int orc27_collide(const double *f, const double *F, const double *K, double *fst
     }
     const double ux = (jx + 0.5 * F[0]) / rho, uy = (jy + 0.5 * F[1]) / rho, uz = (jz + 0.5 * F[2]) / rho;
     double T[Q27 * Q27], k[Q27], keq[Q27], R[Q27], ks[Q27];
-    orc27_T(ux, uy, uz, T);
+    if (raw)
+        orc27_T(0.0, 0.0, 0.0, T);
+    else
+        orc27_T(ux, uy, uz, T);
     for (int r = 0; r < Q27; ++r) {
         double s = 0.0;
         for (int i = 0; i < Q27; ++i) s += T[r * Q27 + i] * f[i];
         k[r] = s;
     }
-    orc27_keq(rho, keq);
-    orc27_Rcm(F[0], F[1], F[2], R);
+    if (raw) {
+        orc27_keq_rm(rho, ux, uy, uz, keq);
+        orc27_Rrm(ux, uy, uz, F[0], F[1], F[2], R);
+    } else {
+        orc27_keq(rho, keq);
+        orc27_Rcm(F[0], F[1], F[2], R);
+    }
     for (int r = 0; r < Q27; ++r) ks[r] = (1.0 - K[r]) * k[r] + K[r] * keq[r] + (1.0 - 0.5 * K[r]) * R[r];
     if (rho_out) *rho_out = rho;
     if (uout) { uout[0] = ux; uout[1] = uy; uout[2] = uz; }
     return solve27(T, ks, fstar);
 }
 
+int orc27_collide(const double *f, const double *F, const double *K, double *fstar, double *rho_out, double *uout)
+{
+    return orc27_collide_mode(f, F, K, 0, fstar, rho_out, uout);
+}
+
 static inline int64_t node27(int x, int y, int z, int nx, int ny) { return (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z); }
 static inline int wrap27(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-/* Full step with streaming (periodic, or halfway bounce-back walls in y). */
-int orc27_step(int nx, int ny, int nz, int walls_y, const double *f, double *fnew, const double *F, const double *K)
+/* Full step with streaming (periodic, or halfway bounce-back walls in y);
+ * raw selects the raw-moment variant. */
+int orc27_step_mode(int nx, int ny, int nz, int walls_y, const double *f, double *fnew, const double *F,
+                    const double *K, int raw)
 {
     const int64_t N = (int64_t)nx * ny * nz;
     int err = 0;
@@ -254,7 +313,7 @@ int orc27_step(int nx, int ny, int nz, int walls_y, const double *f, double *fne
         for (int i = 0; i < Q27; ++i) fl[i] = f[(int64_t)i * N + n];
         if (F)
             for (int d = 0; d < 3; ++d) Fl[d] = F[(int64_t)d * N + n];
-        if (orc27_collide(fl, Fl, K, fs, NULL, NULL) != 0) err |= 1;
+        if (orc27_collide_mode(fl, Fl, K, raw, fs, NULL, NULL) != 0) err |= 1;
         for (int i = 0; i < Q27; ++i) {
             int yd = y + CY[i];
             if (walls_y && (yd < 0 || yd >= ny)) {
@@ -265,6 +324,11 @@ int orc27_step(int nx, int ny, int nz, int walls_y, const double *f, double *fne
         }
     }
     return err ? -1 : 0;
+}
+
+int orc27_step(int nx, int ny, int nz, int walls_y, const double *f, double *fnew, const double *F, const double *K)
+{
+    return orc27_step_mode(nx, ny, nz, walls_y, f, fnew, F, K, 0);
 }
 
 void orc27_init(int nx, int ny, int nz, const double *rho, const double *u, double *f)

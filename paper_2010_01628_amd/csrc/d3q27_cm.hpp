@@ -242,6 +242,66 @@ __host__ __device__ inline void collide_cm27(R s[27], R rho0, R Fx, R Fy, R Fz, 
     pops_from_cube(p, s);
 }
 
+// Raw-moment variant (N = I): the same rates applied to un-shifted moments of
+// the cube, towards the raw equilibrium, with the raw forcing moments of the
+// Gaussian rule R_pqr = sum_a p_a F_a mu_{pqr - e_a}, mu = (1, u, u^2 + 1/3)
+// per axis.  No binomial shifts.
+template <class R>
+__host__ __device__ inline void collide_rm27(R s[27], R rho0, R Fx, R Fy, R Fz, R omega, NodeMacro<R>& mac)
+{
+    const R third = R(1) / R(3);
+    Cube<R> m;
+    cube_from_pops(s, m);
+    const R drho = m.v[0][0][0];
+    const R rho = rho0 + drho;
+    const R irho = R(1) / rho;
+    const R ux = (m.v[1][0][0] + R(0.5) * Fx) * irho;
+    const R uy = (m.v[0][1][0] + R(0.5) * Fy) * irho;
+    const R uz = (m.v[0][0][1] + R(0.5) * Fz) * irho;
+    mac.rho = rho;
+    mac.ux = ux;
+    mac.uy = uy;
+    mac.uz = uz;
+    Cube<R> e;
+    cube_eq_deviation(drho, rho, ux, uy, uz, e);
+    const R mx[3] = {R(1), ux, ux * ux + third}, my[3] = {R(1), uy, uy * uy + third},
+            mz[3] = {R(1), uz, uz * uz + third};
+    Cube<R> f; // raw forcing moments
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                R v = R(0);
+                if (a) v += R(a) * Fx * (mx[a - 1] * my[b] * mz[c]);
+                if (b) v += R(b) * Fy * (mx[a] * my[b - 1] * mz[c]);
+                if (c) v += R(c) * Fz * (mx[a] * my[b] * mz[c - 1]);
+                f.v[a][b][c] = v;
+            }
+    // rate 1 everywhere but the deviatoric second-order moments
+    Cube<R> p;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) p.v[a][b][c] = e.v[a][b][c] + R(0.5) * f.v[a][b][c];
+    const R w1 = R(1) - omega, h1 = R(1) - R(0.5) * omega;
+    p.v[1][1][0] = e.v[1][1][0] + w1 * (m.v[1][1][0] - e.v[1][1][0]) + h1 * f.v[1][1][0];
+    p.v[1][0][1] = e.v[1][0][1] + w1 * (m.v[1][0][1] - e.v[1][0][1]) + h1 * f.v[1][0][1];
+    p.v[0][1][1] = e.v[0][1][1] + w1 * (m.v[0][1][1] - e.v[0][1][1]) + h1 * f.v[0][1][1];
+    const R n200 = m.v[2][0][0] - e.v[2][0][0], n020 = m.v[0][2][0] - e.v[0][2][0], n002 = m.v[0][0][2] - e.v[0][0][2];
+    const R t = (e.v[2][0][0] + e.v[0][2][0] + e.v[0][0][2]) + R(0.5) * (f.v[2][0][0] + f.v[0][2][0] + f.v[0][0][2]);
+    const R d1 = (e.v[2][0][0] - e.v[0][2][0]) + w1 * (n200 - n020) + h1 * (f.v[2][0][0] - f.v[0][2][0]);
+    const R d2 = (e.v[2][0][0] - e.v[0][0][2]) + w1 * (n200 - n002) + h1 * (f.v[2][0][0] - f.v[0][0][2]);
+    p.v[2][0][0] = third * (t + d1 + d2);
+    p.v[0][2][0] = p.v[2][0][0] - d1;
+    p.v[0][0][2] = p.v[2][0][0] - d2;
+    p.v[0][0][0] = drho;
+    pops_from_cube(p, s);
+}
+
 template <class R> __host__ __device__ inline void equilibrium_deviation27(R rho, R rho0, R ux, R uy, R uz, R s[27])
 {
     Cube<R> e;

@@ -85,6 +85,15 @@ struct LatD3Q27 {
     }
 };
 
+// Same lattice, raw-moment collision (N = I).
+struct LatD3Q27RM : LatD3Q27 {
+    template <class R, bool GENERAL>
+    __device__ static void collide(R* s, R rho0, R Fx, R Fy, R Fz, const Phys& ph, NodeMacro<R>& mac)
+    {
+        collide_rm27<R>(s, rho0, Fx, Fy, Fz, (R)ph.omega, mac);
+    }
+};
+
 // Node indexing -------------------------------------------------------------
 struct NodeIdx {
     int x, y, z;

@@ -104,8 +104,8 @@ int validate(const lbm_params* p)
     if (bx * by > 256 || (bx * by) % 64 != 0)
         return fail(LBM_EINVAL, "block_x*block_y must be a multiple of 64 and at most 256");
     if (p->moments != LBM_CENTRAL_MOMENTS && p->moments != LBM_RAW_MOMENTS) return fail(LBM_EINVAL, "bad moments");
-    if (p->moments == LBM_RAW_MOMENTS && (p->q != 19 || p->coupled != LBM_COUPLED_NONE))
-        return fail(LBM_EUNSUPPORTED, "raw moments: D3Q19 without a coupled lattice");
+    if (p->moments == LBM_RAW_MOMENTS && p->coupled != LBM_COUPLED_NONE)
+        return fail(LBM_EUNSUPPORTED, "raw moments: no coupled lattice");
     if (p->coupled < LBM_COUPLED_NONE || p->coupled > LBM_COUPLED_SHAN_CHEN) return fail(LBM_EINVAL, "bad coupled");
     if (p->coupled != LBM_COUPLED_NONE) return coupled_validate(p);
     return LBM_OK;

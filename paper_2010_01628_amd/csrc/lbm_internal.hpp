@@ -46,12 +46,16 @@ LBM_DECLARE_LAUNCHERS(q27)
 void launch_step_q19rm(int precision, int pattern, bool walls, bool general, bool nt, const void* src, void* dst,
                        const Geom& g, const Phys& ph, dim3 grid, dim3 block, hipStream_t st);
 
-// Dispatch on the lattice (q = 19 or 27) and the moment space (raw: D3Q19 only).
+void launch_step_q27rm(int precision, int pattern, bool walls, bool nt, const void* src, void* dst, const Geom& g,
+                       const Phys& ph, dim3 grid, dim3 block, hipStream_t st);
+
+// Dispatch on the lattice (q = 19 or 27) and the moment space.
 inline void launch_step(int q, bool raw, int precision, int pattern, bool walls, bool general, bool nt,
                         const void* src, void* dst, const Geom& g, const Phys& ph, dim3 grid, dim3 block,
                         hipStream_t st)
 {
-    if (q == 27) launch_step_q27(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
+    if (q == 27 && raw) launch_step_q27rm(precision, pattern, walls, nt, src, dst, g, ph, grid, block, st);
+    else if (q == 27) launch_step_q27(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
     else if (raw) launch_step_q19rm(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
     else launch_step_q19(precision, pattern, walls, general, nt, src, dst, g, ph, grid, block, st);
 }

@@ -89,6 +89,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2010_01628_amd.build`")
+        # torch first: its HIP runtime is then the one the library binds to
+        # (one runtime per process, whose devices, streams and pointers both use)
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
         P = ctypes.POINTER(lbm_params)

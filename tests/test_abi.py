@@ -163,7 +163,7 @@ def test_magnetic_lattice_validation(lbm, kw, code):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(moments=2), -1), (dict(moments=-1), -1), (dict(moments=1, q=27), -5),
+    (dict(moments=2), -1), (dict(moments=-1), -1), (dict(moments=1, q=27, precision=2), -5),
     (dict(moments=1, phase=True), -5), (dict(moments=1, magnetic=True), -5),
 ])
 def test_raw_moment_validation(lbm, kw, code):

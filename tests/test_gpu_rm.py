@@ -155,3 +155,36 @@ def test_full_size_sampled_single_step(orc):
     err = np.abs(got - want).max()
     say(f"  max |f_gpu - f_oracle| over {len(nodes)} nodes = {err:.3e}")
     assert err < 2e-8
+
+
+# --------------------------------------------------------------------------
+# D3Q27 raw-moment variant (the raw moments of the D3Q27 lattice's
+# equilibrium and forcing term, N = I)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("nx,ny,nz,walls,streaming,steps", [
+    (12, 10, 8, False, "ab", 7), (9, 6, 5, True, "aa", 9), (1, 3, 7, False, "aa", 5)])
+def test_d3q27_fp64_elementwise(orc, nx, ny, nz, walls, streaming, steps):
+    say(f"raw d3q27 fp64 {nx}x{ny}x{nz} walls={walls} {streaming}")
+    rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=nx + 5 * ny + 3 * nz, umax=0.06, fmax=2e-3)
+    om = 1.64
+    g = gpu_run(nx, ny, nz, rho, u, steps, "fp64", streaming, omega=om, force=F, walls=walls, q=27, moments="raw")
+    q = orc.d3q27
+    fo = q.run(q.init(rho, u), steps, q.K(om), F=F, walls_y=walls, raw=True)
+    err = np.abs(g["f"] - fo).max()
+    say(f"  max |f_gpu - f_oracle| = {err:.3e}")
+    assert err < 1e-13
+
+
+def test_d3q27_fp32_vs_oracle(orc):
+    n, steps = 24, 60
+    om = inputs.omega_from_nu(1e-3)
+    rho, u = inputs.taylor_green_noise(n, 0.05, 1e-4, seed=8)
+    g = gpu_run(n, n, n, rho, u, steps, "fp32", "ab", omega=om, q=27, force_mode=L.LBM_FORCE_KOLMOGOROV,
+                kolmogorov_amp=1e-6, moments="raw")
+    q = orc.d3q27
+    F = inputs.kolmogorov_force(n, n, n, 1e-6)
+    fo = q.run(q.init(rho, u), steps, q.K(om), F=F, raw=True)
+    _, uo = q.moments(fo, F)
+    err = rel_l2(g["u"], uo)
+    say(f"  raw d3q27 fp32 rel L2 u = {err:.3e}")
+    assert err < 1e-5

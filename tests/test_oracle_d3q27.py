@@ -191,3 +191,91 @@ def test_lattice_conservation_d3q27(q27):
             if not walls:
                 assert np.allclose(np.einsum("iabc,id->d", g, c) - p0, F.reshape(3, -1).sum(axis=1), atol=1e-13)
         assert abs(g.sum() - m0) / m0 < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Raw-moment variant (reading Q6: N = I with the same equilibrium and force)
+# --------------------------------------------------------------------------
+def test_raw_equilibrium_is_M_times_population_equilibrium(q27):
+    """The raw equilibrium moments in the App. D basis equal T27(0) f_eq with
+    the tensor-product populations (pinned above as products of D1Q3
+    moments)."""
+    rng = np.random.default_rng(21)
+    M = q27.T([0.0, 0.0, 0.0])
+    for _ in range(30):
+        rho = 1 + 0.2 * rng.uniform(-1, 1)
+        u = rng.uniform(-0.3, 0.3, 3)
+        assert np.allclose(q27.keq_rm(rho, u), M @ q27.feq(rho, u), atol=1e-15)
+
+
+def test_raw_forcing_is_raw_moments_of_the_cm_forcing(q27):
+    """Raw forcing moments = M T27(u)^-1 R^CM: the same velocity-space forcing
+    term as the central-moment scheme."""
+    rng = np.random.default_rng(22)
+    M = q27.T([0.0, 0.0, 0.0])
+    for _ in range(30):
+        u = rng.uniform(-0.3, 0.3, 3)
+        F = rng.normal(size=3)
+        Fi = np.linalg.solve(q27.T(u), q27.Rcm(F))
+        assert np.allclose(q27.Rrm(u, F), M @ Fi, atol=1e-14)
+
+
+def test_raw_unit_rates_equal_cm_and_conserve(q27):
+    c, _, _ = q27.tables()
+    rng = np.random.default_rng(23)
+    for _ in range(20):
+        rho = 1 + 0.1 * rng.uniform(-1, 1)
+        u = rng.uniform(-0.1, 0.1, 3)
+        f = q27.feq(rho, u) * (1 + 0.05 * rng.uniform(-1, 1, 27))
+        F = 1e-2 * rng.normal(size=3)
+        a, _, _ = q27.collide(f, F, q27.K(1.0))
+        b, _, _ = q27.collide(f, F, q27.K(1.0), raw=True)
+        assert np.abs(a - b).max() < 1e-15
+        K = q27.K(rng.uniform(0.3, 1.95))
+        fs, _, _ = q27.collide(f, F, K, raw=True)
+        assert np.isclose(fs.sum(), f.sum(), atol=1e-15)
+        assert np.allclose(fs @ c, f @ c + F, atol=1e-15)
+        fe = q27.feq(rho, u)
+        assert np.allclose(q27.collide(fe, (0, 0, 0), K, raw=True)[0], fe, atol=1e-15)
+        # and differs from the CM scheme away from unit rates
+        assert np.abs(q27.collide(f, F, K, raw=True)[0] - q27.collide(f, F, K)[0]).max() > 1e-9
+
+
+def test_raw_d3q27_and_raw_d3q19_agree_on_the_shared_moments(orc, q27):
+    """Raw variants of both lattices relax the same second-order raw moments
+    towards the same equilibrium with the same forcing; all other shared
+    moments go to equilibrium plus half the forcing: identical post-collision
+    values on the 19 shared raw moments."""
+    rng = np.random.default_rng(24)
+    for _ in range(20):
+        rho = 1 + 0.1 * rng.uniform(-1, 1)
+        u = rng.uniform(-0.1, 0.1, 3)
+        f27 = q27.feq(rho, u) * (1 + 0.1 * rng.uniform(-1, 1, 27))
+        F = 1e-2 * rng.normal(size=3)
+        om = rng.uniform(0.3, 1.99)
+        f27s, _, _ = q27.collide(f27, F, q27.K(om), raw=True)
+        f19, A19, A27 = project_to_q19(orc, q27, f27)
+        f19s, _, _, _ = orc.collide(f19, F, orc.K(om), orc.RM_CLOSED_FORM)
+        assert np.allclose(A19 @ f19s, A27 @ f27s, atol=2e-15)
+
+
+def test_raw_linear_modes_match_von_neumann_d3q27(q27):
+    """About rest the raw and central bases coincide to first order: the
+    same linear operator as above."""
+    c, w, _ = q27.tables()
+    rng = np.random.default_rng(25)
+    n, steps, A = 6, 8, 1e-5
+    kvec = 2 * np.pi * np.array([2, -1, 1]) / n
+    Kd = q27.K(1.45)
+    M = q27.T([0.0, 0.0, 0.0])
+    J = w[:, None] * (1.0 + 3.0 * (c @ c.T))
+    C = J + np.linalg.solve(M, np.diag(1.0 - Kd) @ M) @ (np.eye(27) - J)
+    L = np.diag(np.exp(-1j * (c @ kvec))) @ C
+    v0 = rng.normal(size=27) + 1j * rng.normal(size=27)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    phase = np.exp(1j * (kvec[0] * x + kvec[1] * y + kvec[2] * z))
+    pert = np.real(v0[:, None, None, None] * phase[None])
+    runs = [q27.run(w[:, None, None, None] + s * A * pert, steps, Kd, raw=True) for s in (1, -1)]
+    lin = (runs[0] - runs[1]) / (2 * A)
+    want = np.real((np.linalg.matrix_power(L, steps) @ v0)[:, None, None, None] * phase[None])
+    assert np.abs(lin - want).max() / np.abs(want).max() < 1e-7
