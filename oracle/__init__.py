@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c", "mhd_oracle.c",
-            "shan_chen_oracle.c"]
+            "shan_chen_oracle.c", "colour_gradient_oracle.c"]
 
 DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
 CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
@@ -128,6 +128,15 @@ def lib():
         L.orc_sc_step.restype = i32
         L.orc_sc_fields.argtypes = [i32, i32, i32, f64, dp, dp, dp, dp, dp]
         L.orc_sc_fields.restype = i32
+        L.orc_cg_phi_i.argtypes = [i32, f64]
+        L.orc_cg_phi_i.restype = f64
+        L.orc_cg_heq.argtypes = [f64, f64, f64, f64, f64, dp]
+        L.orc_cg_collide.argtypes = [dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_cg_collide.restype = i32
+        L.orc_cg_step.argtypes = [i32, i32, i32, i32, dp, dp, dp, dp, dp]
+        L.orc_cg_step.restype = i32
+        L.orc_cg_init.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp, dp]
+        L.orc_cg_fields.argtypes = [i32, i32, i32, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
         _lib = L
@@ -709,3 +718,70 @@ class shan_chen:
                                _p(p)) != 0:
             raise MemoryError("Shan-Chen fields")
         return rho, u, p
+
+
+class colour_gradient:
+    """Colour-gradient two-phase flow of App. E on the D3Q19 CM collision
+    (readings G1-G6 in colour_gradient_oracle.c)."""
+
+    @staticmethod
+    def params(omega, alpha_r, alpha_b=1.0 / 3.0, A=0.0, beta=0.7, g=(0.0, 0.0, 0.0), rho_ref=0.0):
+        return np.array([omega, alpha_r, alpha_b, A, beta, g[0], g[1], g[2], rho_ref], dtype=np.float64)
+
+    @staticmethod
+    def phi_i(c2, alpha):
+        return lib().orc_cg_phi_i(int(c2), float(alpha))
+
+    @staticmethod
+    def heq(rho, u, alpha):
+        out = np.zeros(Q)
+        lib().orc_cg_heq(float(rho), float(u[0]), float(u[1]), float(u[2]), float(alpha), _p(out))
+        return out
+
+    @staticmethod
+    def collide(prm, fr, fb, grad):
+        a, b = np.zeros(Q), np.zeros(Q)
+        rho, u = np.zeros(1), np.zeros(3)
+        if lib().orc_cg_collide(_p(_f64(fr)), _p(_f64(fb)), _p(_f64(grad)), _p(_f64(prm)), _p(a), _p(b), _p(rho),
+                                _p(u)) != 0:
+            raise ArithmeticError("singular collision system")
+        return a, b, float(rho[0]), u
+
+    @staticmethod
+    def init(prm, rho_r, rho_b, u):
+        rr, rb, uu = _f64(rho_r), _f64(rho_b), _f64(u)
+        nz, ny, nx = rr.shape
+        fr = np.zeros((Q, nz, ny, nx))
+        fb = np.zeros((Q, nz, ny, nx))
+        lib().orc_cg_init(nx, ny, nz, _p(_f64(prm)), _p(rr), _p(rb), _p(uu), _p(fr), _p(fb))
+        return fr, fb
+
+    @staticmethod
+    def step(prm, fr, fb, walls_y=False, frn=None, fbn=None):
+        fr, fb = _f64(fr), _f64(fb)
+        _, nz, ny, nx = fr.shape
+        frn = np.empty_like(fr) if frn is None else frn
+        fbn = np.empty_like(fb) if fbn is None else fbn
+        if lib().orc_cg_step(nx, ny, nz, int(bool(walls_y)), _p(_f64(prm)), _p(fr), _p(fb), _p(frn), _p(fbn)) != 0:
+            raise ArithmeticError("colour-gradient step failed")
+        return frn, fbn
+
+    @staticmethod
+    def run(prm, fr, fb, nsteps, walls_y=False):
+        a, b = _f64(fr).copy(), _f64(fb).copy()
+        a2, b2 = np.empty_like(a), np.empty_like(b)
+        for _ in range(int(nsteps)):
+            colour_gradient.step(prm, a, b, walls_y, a2, b2)
+            a, a2 = a2, a
+            b, b2 = b2, b
+        return a, b
+
+    @staticmethod
+    def fields(prm, fr, fb):
+        """(rho_r, rho_b, phi, u, p)."""
+        fr, fb = _f64(fr), _f64(fb)
+        _, nz, ny, nx = fr.shape
+        rr, rb, phi, p = (np.zeros((nz, ny, nx)) for _ in range(4))
+        u = np.zeros((3, nz, ny, nx))
+        lib().orc_cg_fields(nx, ny, nz, _p(_f64(prm)), _p(fr), _p(fb), _p(rr), _p(rb), _p(phi), _p(u), _p(p))
+        return rr, rb, phi, u, p
