@@ -128,10 +128,12 @@ def time_ensemble(L, inputs, torch, steps, warmup, mlp, tune=True):
 def time_coupled(L, inputs, torch, steps, warmup):
     """Coupled-lattice workloads: the two-phase droplet (192^3, R = 32,
     density ratio 10, sigma = 1e-3, W = 4, FP32), the Hartmann channel
-    (32 x 128 x 32, Ha = 10, FP32) and the Shan-Chen static bubble (100^3,
-    R = 20, G = -5, nu = 0.0333, FP32).  Algorithmic bytes per node and step:
+    (32 x 128 x 32, Ha = 10, FP32), the Shan-Chen static bubble (100^3,
+    R = 20, G = -5, nu = 0.0333, FP32) and the colour-gradient Rayleigh-Taylor
+    case (64 x 256 x 64, FP32).  Algorithmic bytes per node and step:
     two-phase 244 (flow 152, phase 56, phi 32 + 4), magnetic 320, Shan-Chen
-    236 (psi launch 76 + 4, step 152 + 4)."""
+    236 (psi launch 76 + 4, step 152 + 4), colour gradient 464 (phi launch
+    152 + 4, step 304 + 4)."""
     import numpy as np
 
     out = {}
@@ -163,6 +165,13 @@ def time_coupled(L, inputs, torch, steps, warmup):
     lat = L.Lattice(par)
     lat.init(rho, np.zeros((3,) + rho.shape))
     out["shan_chen_bubble_100"] = _time_lattice(lat, torch, 4 * steps, warmup, n ** 3, 236)
+    lat.close()
+    from paper_2010_01628_amd import rayleigh_taylor
+
+    par, rr, rb, _ = rayleigh_taylor.setup(64)
+    lat = L.Lattice(par)
+    lat.init_colour(rr, rb, np.zeros((3,) + rr.shape))
+    out["rayleigh_taylor_64x256x64"] = _time_lattice(lat, torch, 4 * steps, warmup, rr.size, 464)
     lat.close()
     return out
 

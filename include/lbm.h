@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 4
+#define LBM_ABI_VERSION 5
 
 typedef enum {
     LBM_OK = 0,
@@ -84,7 +84,8 @@ typedef enum {
     LBM_COUPLED_NONE = 0,
     LBM_COUPLED_PHASE = 1,    /* two-phase flow with a conservative phase field (see below) */
     LBM_COUPLED_MAGNETIC = 2, /* magnetohydrodynamics with a vector magnetic lattice (see below) */
-    LBM_COUPLED_SHAN_CHEN = 3 /* Shan-Chen pseudo-potential two-phase flow (see below) */
+    LBM_COUPLED_SHAN_CHEN = 3, /* Shan-Chen pseudo-potential two-phase flow (see below) */
+    LBM_COUPLED_COLOUR = 4    /* colour-gradient two-phase flow (see below) */
 } lbm_coupling;
 
 /* Two-phase flow (not in the paper, whose multiphase models are Shan-Chen and
@@ -129,6 +130,27 @@ typedef struct {
     double G;                 /* interaction strength (the paper: -5); finite */
 } lbm_shan_chen_params;
 
+/* Colour-gradient two-phase flow (App. E; the Rayleigh-Taylor case of
+ * Sec. III): red and blue populations f^r, f^b; the total f collides with the
+ * scheme of Sec. II.B towards h_eq = f_eq(rho, u) + rho (phi_i(alpha) - w_i),
+ * phi_i = alpha, (1 - alpha)/12, (1 - alpha)/24 by |c_i|^2,
+ * alpha = (rho_r alpha_r + rho_b alpha_b)/rho; the perturbation
+ * (A/2)|grad phi| [w_i (c_i.grad phi)^2/|grad phi|^2 - B_i] adds interfacial
+ * tension sigma = (2/9) A / omega; the recolouring
+ * f^r,b = (rho_r,b / rho) f -/+ beta (rho_r rho_b / rho^2) cos(theta_i) rho phi_i(alpha)
+ * separates the colours (phi = (rho_r - rho_b)/rho, grad phi from the isotropic
+ * stencil, mirrored at the y walls); body force F = (rho - rho_ref) gravity.
+ * Both colours are stored whole (rho0 is not used). */
+typedef struct {
+    double alpha_red;         /* rest fraction of red, in [0, 1); stable densities
+                                 rho_r0 (1 - alpha_red) = rho_b0 (1 - alpha_blue) */
+    double alpha_blue;        /* rest fraction of blue (the paper: 1/3) */
+    double A;                 /* perturbation amplitude A_r + A_b >= 0 */
+    double beta;              /* recolouring parameter in [0, 1] (the paper: 0.7) */
+    double gravity[3];        /* g; F = (rho - rho_ref) g */
+    double rho_ref;
+} lbm_colour_params;
+
 typedef struct {
     uint32_t abi_version;     /* must be LBM_ABI_VERSION */
     int32_t nx, ny, nz;       /* lattice nodes; periodic in x and z, and in y unless walls_y */
@@ -164,6 +186,11 @@ typedef struct {
     lbm_shan_chen_params shan_chen; /* LBM_COUPLED_SHAN_CHEN: q = 19, FP64 or FP32, A-B, periodic,
                                  force mode NONE or UNIFORM; any rates; initialised with
                                  lbm_init (f = f_eq(rho, u)) */
+    lbm_colour_params colour; /* LBM_COUPLED_COLOUR: q = 19, FP64 or FP32, A-B, walls_y allowed,
+                                 force mode NONE (gravity is in here), the paper's bulk and
+                                 higher-order rates; initialised with lbm_init_colour; the
+                                 populations of lbm_get/set_populations are red, those of
+                                 lbm_get/set_coupled_populations blue */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -233,6 +260,12 @@ int lbm_magnetic_fields(lbm_handle *h, double *b, double *j, int on_device);
  * q_c = 7 for the phase field, 21 = 3 x 7 for the magnetic field with
  * k = 7 a + i for component a), host or device; set replaces them (step
  * counter kept). */
+/* Colour-gradient lattice: f^k = (rho_k / rho) h_eq(rho, u) from the colour
+ * densities rho_red, rho_blue (double[N], rho_red + rho_blue > 0) and u
+ * (double[3N]) (host or device); resets the step count. */
+int lbm_init_colour(lbm_handle *h, const double *rho_red, const double *rho_blue, const double *u, int on_device);
+/* Colour densities (double[N] each, host or device; either may be NULL). */
+int lbm_colour_fields(lbm_handle *h, double *rho_red, double *rho_blue, int on_device);
 int lbm_get_coupled_populations(lbm_handle *h, double *out, int on_device);
 int lbm_set_coupled_populations(lbm_handle *h, const double *in, int on_device);
 

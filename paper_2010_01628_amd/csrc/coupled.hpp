@@ -15,6 +15,16 @@ struct MhdConst {
     double b_wall[3]; // field imposed at the y walls
 };
 
+// Constants of the colour-gradient lattice.
+struct CgConst {
+    double omega;            // shear rate
+    double alpha_r, alpha_b; // rest fractions of the colours (App. E)
+    double A;                // perturbation amplitude A_r + A_b
+    double beta;             // recolouring parameter
+    double g[3];             // gravity; body force (rho - rho_ref) g
+    double rho_ref;
+};
+
 // One step of the two-phase lattice: phi = sum h into `phi`, then the fused
 // flow + phase collide-stream from (gsrc, hsrc) into (gdst, hdst).
 void launch_phase_step(int precision, bool nt, const void* gsrc, void* gdst, const void* hsrc, void* hdst, void* phi,
@@ -50,5 +60,15 @@ void launch_sc_step(int precision, bool general, bool nt, const void* src, void*
 // psi refreshed from src, then rho, force-shifted u and the partial sums.
 void launch_sc_fields(int precision, const void* src, void* psi, const Geom& g, const Phys& ph, double G, double* rho,
                       double* u, double* partials, dim3 grid, dim3 block, hipStream_t st);
+
+// Colour-gradient two-phase flow: phi from the pulled colours into `phi`,
+// then the fused step of both colours.
+void launch_cg_step(int precision, bool walls, bool nt, const void* rsrc, void* rdst, const void* bsrc, void* bdst,
+                    void* phi, const Geom& g, const CgConst& cc, dim3 grid, dim3 block, hipStream_t st);
+void launch_cg_init(int precision, bool walls, void* red, void* blue, const Geom& g, const CgConst& cc,
+                    const double* rho_r, const double* rho_b, const double* u, dim3 grid, dim3 block, hipStream_t st);
+void launch_cg_fields(int precision, bool walls, const void* red, const void* blue, const Geom& g, const CgConst& cc,
+                      double* rho, double* u, double* rho_r, double* rho_b, double* partials, dim3 grid, dim3 block,
+                      hipStream_t st);
 
 } // namespace lbm

@@ -75,9 +75,32 @@ static int shan_chen_validate(const lbm_params* p)
     return LBM_OK;
 }
 
+static int colour_validate(const lbm_params* p)
+{
+    if (p->q != 19) return lbm_fail(LBM_EUNSUPPORTED, "the colour-gradient lattice is D3Q19");
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
+        return lbm_fail(LBM_EUNSUPPORTED, "the colour-gradient lattice stores FP64 or FP32");
+    if (p->streaming != LBM_AB) return lbm_fail(LBM_EUNSUPPORTED, "the colour-gradient lattice streams A-B");
+    if (p->force_mode != LBM_FORCE_NONE)
+        return lbm_fail(LBM_EUNSUPPORTED, "the colour-gradient lattice takes its body force from colour.gravity");
+    bool paper = p->omega_bulk == 1.0;
+    for (int j = 0; j < 9; ++j) paper = paper && p->omega_hi[j] == 1.0;
+    if (!paper) return lbm_fail(LBM_EUNSUPPORTED, "the colour-gradient lattice uses the paper's bulk and higher-order rates");
+    const lbm_colour_params& c = p->colour;
+    auto frac = [](double a) { return std::isfinite(a) && a >= 0.0 && a < 1.0; };
+    if (!frac(c.alpha_red) || !frac(c.alpha_blue)) return lbm_fail(LBM_EINVAL, "alpha must be in [0, 1)");
+    if (!(std::isfinite(c.A) && c.A >= 0.0)) return lbm_fail(LBM_EINVAL, "A must be >= 0");
+    if (!(std::isfinite(c.beta) && c.beta >= 0.0 && c.beta <= 1.0)) return lbm_fail(LBM_EINVAL, "beta must be in [0, 1]");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c.gravity[a])) return lbm_fail(LBM_EINVAL, "gravity must be finite");
+    if (!std::isfinite(c.rho_ref)) return lbm_fail(LBM_EINVAL, "rho_ref must be finite");
+    return LBM_OK;
+}
+
 int coupled_validate(const lbm_params* p)
 {
     if (p->coupled == LBM_COUPLED_MAGNETIC) return magnetic_validate(p);
+    if (p->coupled == LBM_COUPLED_COLOUR) return colour_validate(p);
     if (p->coupled == LBM_COUPLED_SHAN_CHEN) return shan_chen_validate(p);
     const lbm_phase_params& q = p->phase;
     if (p->q != 19) return lbm_fail(LBM_EUNSUPPORTED, "the two-phase lattice is D3Q19");
@@ -111,11 +134,26 @@ int coupled_create(lbm_handle* h)
         h->bytes += (int64_t)h->g.N * eb;
         return LBM_OK;
     }
-    c->q = p.coupled == LBM_COUPLED_MAGNETIC ? 21 : 7;
+    c->q = p.coupled == LBM_COUPLED_MAGNETIC ? 21 : (p.coupled == LBM_COUPLED_COLOUR ? 19 : 7);
     const int64_t bytes = (int64_t)c->q * h->g.stride * eb;
     for (int b = 0; b < 2; ++b) {
         CHIP(hipMalloc(&c->buf[b], bytes));
         h->bytes += bytes;
+    }
+    if (p.coupled == LBM_COUPLED_COLOUR) {
+        CHIP(hipMalloc(&c->scratch, (int64_t)h->g.N * eb));
+        h->bytes += (int64_t)h->g.N * eb;
+        const lbm_colour_params& q = p.colour;
+        c->cc.omega = p.omega;
+        c->cc.alpha_r = q.alpha_red;
+        c->cc.alpha_b = q.alpha_blue;
+        c->cc.A = q.A;
+        c->cc.beta = q.beta;
+        for (int a = 0; a < 3; ++a) c->cc.g[a] = q.gravity[a];
+        c->cc.rho_ref = q.rho_ref;
+        h->p.rho0 = 0.0; // both colours are stored whole
+        h->ph.rho0 = 0.0;
+        return LBM_OK;
     }
     if (p.coupled == LBM_COUPLED_MAGNETIC) {
         c->mc.omega_m = 1.0 / (p.magnetic.eta / 0.25 + 0.5);
@@ -170,6 +208,12 @@ int coupled_step(lbm_handle* h)
     lbm::Geom fg;
     dim3 fgrid, fblock;
     flat_launch(h, fg, fgrid, fblock);
+    if (h->p.coupled == LBM_COUPLED_COLOUR) {
+        lbm::launch_cg_step(h->p.precision, h->walls, h->nt, h->buf[src], h->buf[dst], c->buf[src], c->buf[dst],
+                            c->scratch, fg, c->cc, fgrid, fblock, h->stream);
+        CHIP(hipGetLastError());
+        return LBM_OK;
+    }
     if (h->p.coupled == LBM_COUPLED_SHAN_CHEN) {
         lbm::launch_sc_step(h->p.precision, h->general, h->nt, h->buf[src], h->buf[dst], c->scratch, fg, h->ph, c->sc_G,
                             fgrid, fblock, h->stream);
@@ -200,7 +244,10 @@ int coupled_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_
         drho = rho ? staging : nullptr;
         du = u ? staging + N : nullptr;
     }
-    if (h->p.coupled == LBM_COUPLED_SHAN_CHEN)
+    if (h->p.coupled == LBM_COUPLED_COLOUR)
+        lbm::launch_cg_fields(h->p.precision, h->walls, h->buf[h->cur], c->buf[h->cur], h->g, c->cc, drho, du, nullptr,
+                              nullptr, h->partials, h->grid, h->block, h->stream);
+    else if (h->p.coupled == LBM_COUPLED_SHAN_CHEN)
         lbm::launch_sc_fields(h->p.precision, h->buf[h->cur], c->scratch, h->g, h->ph, c->sc_G, drho, du, h->partials,
                               h->grid, h->block, h->stream);
     else if (h->p.coupled == LBM_COUPLED_MAGNETIC)
@@ -279,7 +326,10 @@ int lbm_get_coupled_populations(lbm_handle* h, double* out, int on_device)
     const int64_t bytes = sizeof(double) * h->cp->q * (int64_t)h->g.N;
     double* dst = out;
     if (!on_device) CHIP(hipMalloc((void**)&dst, bytes));
-    if (h->p.coupled == LBM_COUPLED_MAGNETIC)
+    if (h->p.coupled == LBM_COUPLED_COLOUR)
+        lbm::launch_get_pops(19, h->p.precision, 0, h->walls, h->cp->buf[h->cur], h->g, 0.0, dst, h->grid, h->block,
+                             h->stream);
+    else if (h->p.coupled == LBM_COUPLED_MAGNETIC)
         lbm::launch_mhd_get_g(h->p.precision, h->walls, h->cp->buf[h->cur], h->g, h->cp->mc, dst, h->grid, h->block,
                               h->stream);
     else
@@ -301,13 +351,62 @@ int lbm_set_coupled_populations(lbm_handle* h, const double* in, int on_device)
     Staged s;
     int rc = stage_in(in, (int64_t)h->cp->q * h->g.N, on_device, h->stream, s);
     if (rc) return rc;
-    if (h->p.coupled == LBM_COUPLED_MAGNETIC)
+    if (h->p.coupled == LBM_COUPLED_COLOUR)
+        lbm::launch_set_pops(19, h->p.precision, 0, h->walls, h->cp->buf[h->cur], h->g, 0.0, s.ptr, h->grid, h->block,
+                             h->stream);
+    else if (h->p.coupled == LBM_COUPLED_MAGNETIC)
         lbm::launch_mhd_set_g(h->p.precision, h->walls, h->cp->buf[h->cur], h->g, h->cp->mc, s.ptr, h->grid, h->block,
                               h->stream);
     else
         lbm::launch_phase_set_h(h->p.precision, h->cp->buf[h->cur], h->g, s.ptr, h->grid, h->block, h->stream);
     CHIP(hipGetLastError());
     if (!on_device) CHIP(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_init_colour(lbm_handle* h, const double* rho_red, const double* rho_blue, const double* u, int on_device)
+{
+    if (!h || !rho_red || !rho_blue || !u) return lbm_fail(LBM_EINVAL, "NULL argument");
+    if (!h->cp || h->p.coupled != LBM_COUPLED_COLOUR) return lbm_fail(LBM_EINVAL, "not a colour-gradient lattice");
+    const int64_t N = h->g.N;
+    Staged sr, sb, su;
+    int rc = stage_in(rho_red, N, on_device, h->stream, sr);
+    if (!rc) rc = stage_in(rho_blue, N, on_device, h->stream, sb);
+    if (!rc) rc = stage_in(u, 3 * N, on_device, h->stream, su);
+    if (rc) return rc;
+    h->steps = 0;
+    h->cur = 0;
+    lbm::launch_cg_init(h->p.precision, h->walls, h->buf[0], h->cp->buf[0], h->g, h->cp->cc, sr.ptr, sb.ptr, su.ptr,
+                        h->grid, h->block, h->stream);
+    CHIP(hipGetLastError());
+    if (!on_device) CHIP(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_colour_fields(lbm_handle* h, double* rho_red, double* rho_blue, int on_device)
+{
+    if (!h) return lbm_fail(LBM_EINVAL, "NULL handle");
+    if (!h->cp || h->p.coupled != LBM_COUPLED_COLOUR) return lbm_fail(LBM_EINVAL, "not a colour-gradient lattice");
+    const int64_t N = h->g.N;
+    double* dr = rho_red;
+    double* db = rho_blue;
+    double* staging = nullptr;
+    if (!on_device && (rho_red || rho_blue)) {
+        CHIP(hipMalloc((void**)&staging, sizeof(double) * 2 * N));
+        dr = rho_red ? staging : nullptr;
+        db = rho_blue ? staging + N : nullptr;
+    }
+    lbm::launch_cg_fields(h->p.precision, h->walls, h->buf[h->cur], h->cp->buf[h->cur], h->g, h->cp->cc, nullptr,
+                          nullptr, dr, db, h->partials, h->grid, h->block, h->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && staging) {
+        if (rho_red) e = hipMemcpyAsync(rho_red, staging, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && rho_blue)
+            e = hipMemcpyAsync(rho_blue, staging + N, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    if (staging) hipFree(staging);
+    if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "colour fields: %s", hipGetErrorString(e));
     return LBM_OK;
 }
 

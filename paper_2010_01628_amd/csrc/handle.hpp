@@ -15,6 +15,7 @@ struct lbm_coupled {
     int q = 0;                         // populations per node (7 phase, 21 magnetic, 0 Shan-Chen)
     void* scratch = nullptr;           // phase field phi or pseudo-potential psi (collision arithmetic type)
     double sc_G = 0.0;                 // Shan-Chen interaction strength
+    lbm::CgConst cc{};                 // colour-gradient constants (buf: blue colour)
     lbm::PhaseConst pc{};
     lbm::MhdConst mc{};
 };

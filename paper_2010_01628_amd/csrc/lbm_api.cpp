@@ -106,7 +106,7 @@ int validate(const lbm_params* p)
     if (p->moments != LBM_CENTRAL_MOMENTS && p->moments != LBM_RAW_MOMENTS) return fail(LBM_EINVAL, "bad moments");
     if (p->moments == LBM_RAW_MOMENTS && p->coupled != LBM_COUPLED_NONE)
         return fail(LBM_EUNSUPPORTED, "raw moments: no coupled lattice");
-    if (p->coupled < LBM_COUPLED_NONE || p->coupled > LBM_COUPLED_SHAN_CHEN) return fail(LBM_EINVAL, "bad coupled");
+    if (p->coupled < LBM_COUPLED_NONE || p->coupled > LBM_COUPLED_COLOUR) return fail(LBM_EINVAL, "bad coupled");
     if (p->coupled != LBM_COUPLED_NONE) return coupled_validate(p);
     return LBM_OK;
 }

@@ -19,7 +19,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3
 LBM_AB, LBM_AA = 0, 1
@@ -50,7 +50,12 @@ class lbm_shan_chen_params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double)]
 
 
-LBM_COUPLED_NONE, LBM_COUPLED_PHASE, LBM_COUPLED_MAGNETIC, LBM_COUPLED_SHAN_CHEN = 0, 1, 2, 3
+class lbm_colour_params(ctypes.Structure):
+    _fields_ = [("alpha_red", ctypes.c_double), ("alpha_blue", ctypes.c_double), ("A", ctypes.c_double),
+                ("beta", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("rho_ref", ctypes.c_double)]
+
+
+LBM_COUPLED_NONE, LBM_COUPLED_PHASE, LBM_COUPLED_MAGNETIC, LBM_COUPLED_SHAN_CHEN, LBM_COUPLED_COLOUR = 0, 1, 2, 3, 4
 
 
 class lbm_params(ctypes.Structure):
@@ -77,6 +82,7 @@ class lbm_params(ctypes.Structure):
         ("magnetic", lbm_magnetic_params),
         ("moments", ctypes.c_int32),
         ("shan_chen", lbm_shan_chen_params),
+        ("colour", lbm_colour_params),
     ]
 
 
@@ -158,10 +164,12 @@ def lib():
         L.lbm_magnetic_fields.restype = i32
         L.lbm_init_phase.argtypes = [vp, vp, vp, vp, i32]
         L.lbm_phase_fields.argtypes = [vp, vp, vp, i32]
+        L.lbm_init_colour.argtypes = [vp, vp, vp, vp, i32]
+        L.lbm_colour_fields.argtypes = [vp, vp, vp, i32]
         L.lbm_get_coupled_populations.argtypes = [vp, vp, i32]
         L.lbm_set_coupled_populations.argtypes = [vp, vp, i32]
         for name in ("lbm_init_phase", "lbm_phase_fields", "lbm_get_coupled_populations",
-                     "lbm_set_coupled_populations"):
+                     "lbm_set_coupled_populations", "lbm_init_colour", "lbm_colour_fields"):
             getattr(L, name).restype = i32
         for name in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_get_populations",
                      "lbm_set_populations", "lbm_destroy", "lbm_mlp_create", "lbm_mlp_set_params",
@@ -427,12 +435,14 @@ class Ensemble:
 def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
                 rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
                 force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0,
-                q=19, phase=None, magnetic=None, moments="central", shan_chen=None) -> lbm_params:
+                q=19, phase=None, magnetic=None, moments="central", shan_chen=None, colour=None) -> lbm_params:
     """phase: dict(rho_light, rho_heavy, sigma, width, mobility) makes a
     two-phase lattice (coupled = LBM_COUPLED_PHASE); magnetic: dict(eta,
     b_wall=(bx, by, bz)) a magnetic one (LBM_COUPLED_MAGNETIC); moments:
     "central" (the paper's scheme) or "raw" (its N = I variant); shan_chen:
-    dict(G) a Shan-Chen two-phase lattice (LBM_COUPLED_SHAN_CHEN)."""
+    dict(G) a Shan-Chen two-phase lattice (LBM_COUPLED_SHAN_CHEN); colour:
+    dict(alpha_red, alpha_blue=1/3, A=0, beta=0.7, gravity=(0,0,0), rho_ref=0)
+    a colour-gradient lattice (LBM_COUPLED_COLOUR)."""
     p = lbm_params_default()
     p.q = int(q)
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -460,6 +470,16 @@ def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_b
         bw = magnetic.get("b_wall", (0.0, 0.0, 0.0))
         for d in range(3):
             p.magnetic.b_wall[d] = float(bw[d])
+    if colour is not None:
+        p.coupled = LBM_COUPLED_COLOUR
+        p.colour.alpha_red = float(colour["alpha_red"])
+        p.colour.alpha_blue = float(colour.get("alpha_blue", 1.0 / 3.0))
+        p.colour.A = float(colour.get("A", 0.0))
+        p.colour.beta = float(colour.get("beta", 0.7))
+        gv = colour.get("gravity", (0.0, 0.0, 0.0))
+        for d in range(3):
+            p.colour.gravity[d] = float(gv[d])
+        p.colour.rho_ref = float(colour.get("rho_ref", 0.0))
     if shan_chen is not None:
         p.coupled = LBM_COUPLED_SHAN_CHEN
         p.shan_chen.G = float(shan_chen["G"])
@@ -534,6 +554,8 @@ class Lattice:
 
     def set_populations(self, f):
         ff = self._dev(f)
+        if ff.numel() != self.q * self.N:
+            raise ValueError(f"expected {self.q} x {self.N} values, got {ff.numel()}")
         assert ff.numel() == self.q * self.N
         lbm_set_populations(self.h, ff.data_ptr(), True)
         self.stream.synchronize()
@@ -583,6 +605,22 @@ class Lattice:
         self.stream.synchronize()
         return phi, p
 
+    # -- colour-gradient lattices -------------------------------------------
+    def init_colour(self, rho_red, rho_blue, u):
+        a, b, c = self._dev(rho_red), self._dev(rho_blue), self._dev(u)
+        assert a.numel() == self.N and b.numel() == self.N and c.numel() == 3 * self.N
+        _check(lib().lbm_init_colour(self.h, a.data_ptr(), b.data_ptr(), c.data_ptr(), 1))
+        self.stream.synchronize()
+
+    def colour_fields(self):
+        """(rho_red, rho_blue) as device float64 tensors (nz, ny, nx)."""
+        t = self.torch
+        a = t.empty(self.shape, dtype=t.float64, device="cuda")
+        b = t.empty(self.shape, dtype=t.float64, device="cuda")
+        _check(lib().lbm_colour_fields(self.h, a.data_ptr(), b.data_ptr(), 1))
+        self.stream.synchronize()
+        return a, b
+
     # -- magnetic lattices ---------------------------------------------------
     def init_magnetic(self, rho, u, b):
         a, c, e = self._dev(rho), self._dev(u), self._dev(b)
@@ -599,9 +637,16 @@ class Lattice:
         self.stream.synchronize()
         return b, j
 
-    def get_coupled_populations(self, q=None):
+    def _coupled_q(self):
+        """Populations per node of the coupled lattice (the library writes that
+        many arrays of N doubles)."""
+        q = {LBM_COUPLED_PHASE: 7, LBM_COUPLED_MAGNETIC: 21, LBM_COUPLED_COLOUR: 19}.get(self.params.coupled)
         if q is None:
-            q = 21 if self.params.coupled == LBM_COUPLED_MAGNETIC else 7
+            raise LbmError(LBM_EINVAL, "this lattice has no coupled populations")
+        return q
+
+    def get_coupled_populations(self):
+        q = self._coupled_q()
         t = self.torch
         f = t.empty((q,) + self.shape, dtype=t.float64, device="cuda")
         _check(lib().lbm_get_coupled_populations(self.h, f.data_ptr(), 1))
@@ -610,6 +655,8 @@ class Lattice:
 
     def set_coupled_populations(self, f):
         ff = self._dev(f)
+        if ff.numel() != self._coupled_q() * self.N:
+            raise ValueError(f"expected {self._coupled_q()} x {self.N} values, got {ff.numel()}")
         _check(lib().lbm_set_coupled_populations(self.h, ff.data_ptr(), 1))
         self.stream.synchronize()
 

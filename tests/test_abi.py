@@ -63,7 +63,8 @@ def test_params_struct_layout_matches_header(lbm, tmp_path):
     assert int(got["sizeof"]) == ctypes.sizeof(lbm.lbm_params)
     # nested parameter blocks of the coupled lattices
     for sname, cls in (("lbm_phase_params", lbm.lbm_phase_params), ("lbm_magnetic_params", lbm.lbm_magnetic_params),
-                       ("lbm_shan_chen_params", lbm.lbm_shan_chen_params)):
+                       ("lbm_shan_chen_params", lbm.lbm_shan_chen_params),
+                       ("lbm_colour_params", lbm.lbm_colour_params)):
         body = "\n".join(f'printf("{f} %zu\\n", offsetof({sname}, {f}));' for f, _ in cls._fields_)
         src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"lbm.h\"\n"
                        "int main(void){" + body + f'printf("sizeof %zu\\n", sizeof({sname})); return 0;}}\n')
@@ -190,6 +191,23 @@ def test_shan_chen_lattice_validation(lbm, kw, code):
     for k, v in kw.items():
         if k == "G":
             p.shan_chen.G = v
+        else:
+            setattr(p, k, v)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, None)
+    assert e.value.code == code, lbm.lib().lbm_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(q=27), -5), (dict(precision=2), -5), (dict(streaming=1), -5), (dict(force_mode=1), -5),
+    (dict(omega_bulk=1.3), -5), (dict(alpha_red=1.0), -1), (dict(alpha_blue=-0.1), -1), (dict(A=-1.0), -1),
+    (dict(beta=1.5), -1), (dict(rho_ref=float("nan")), -1), (dict(moments=1), -5),
+])
+def test_colour_lattice_validation(lbm, kw, code):
+    p = lbm.make_params(8, 8, 8, precision="fp32", colour=dict(alpha_red=7.0 / 9.0))
+    for k, v in kw.items():
+        if k in ("alpha_red", "alpha_blue", "A", "beta", "rho_ref"):
+            setattr(p.colour, k, v)
         else:
             setattr(p, k, v)
     with pytest.raises(lbm.LbmError) as e:
