@@ -181,6 +181,24 @@ template <class S, bool NT> __device__ inline void st(S* p, S v)
     }
 }
 
+// Element `idx` of population array `slot`.  O32: every population array is
+// below 4 GiB, so the element's byte offset is formed in 32 bits and added to
+// the array base, which is the same for the whole wavefront when the slot is a
+// constant: the access then takes a scalar base and a 32-bit vector offset
+// instead of a 64-bit address per lane.
+template <class S, bool O32> __device__ inline const S* pop_at(const S* buf, int64_t stride, int slot, int idx)
+{
+    const S* base = buf + (int64_t)slot * stride;
+    if constexpr (O32)
+        return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + (uint32_t)idx * (uint32_t)sizeof(S));
+    else
+        return base + idx;
+}
+template <class S, bool O32> __device__ inline S* pop_at(S* buf, int64_t stride, int slot, int idx)
+{
+    return const_cast<S*>(pop_at<S, O32>(static_cast<const S*>(buf), stride, slot, idx));
+}
+
 // Where f_i(x, t) lives in the buffer for pattern P (slot, node index).
 template <class L, Pattern P, bool WALLS>
 __device__ inline void state_loc(const NodeIdx& d, int i, int& slot, int& idx)
@@ -202,19 +220,19 @@ __device__ inline void state_loc(const NodeIdx& d, int i, int& slot, int& idx)
 }
 
 // Load f_i(x, t) (as deviations) for the current pattern.
-template <class L, class S, Pattern P, bool WALLS, bool NT = false>
+template <class L, class S, Pattern P, bool WALLS, bool NT = false, bool O32 = false>
 __device__ inline void gather(const S* __restrict__ buf, int64_t stride, const NodeIdx& d, typename Codec<S>::R* s)
 {
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         int slot, idx;
         state_loc<L, P, WALLS>(d, i, slot, idx);
-        s[i] = Codec<S>::dec(ld<S, NT>(buf + (int64_t)slot * stride + idx));
+        s[i] = Codec<S>::dec(ld<S, NT>(pop_at<S, O32>(buf, stride, slot, idx)));
     }
 }
 
 // Store f_i*(x, t) (deviations) for the current pattern.
-template <class L, class S, Pattern P, bool WALLS, bool NT>
+template <class L, class S, Pattern P, bool WALLS, bool NT, bool O32 = false>
 __device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeIdx& d, const typename Codec<S>::R* s)
 {
     const int n = nb(d, 0, 0, 0);
@@ -237,7 +255,7 @@ __device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeId
                 idx = nb(d, cx, cy, cz);
             }
         }
-        st<S, NT>(buf + (int64_t)slot * stride + idx, Codec<S>::enc(s[i]));
+        st<S, NT>(pop_at<S, O32>(buf, stride, slot, idx), Codec<S>::enc(s[i]));
     }
 }
 
@@ -307,7 +325,7 @@ __device__ inline void block_coords(const Geom& g, int chunk, int& bxi, int& byi
     }
 }
 
-template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
+template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT, bool O32>
 __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys& ph)
 {
     using R = typename Codec<S>::R;
@@ -319,19 +337,19 @@ __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R s[L::Q];
-    gather<L, S, P, WALLS, NT>(src, g.stride, d, s);
+    gather<L, S, P, WALLS, NT, O32>(src, g.stride, d, s);
     R Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
     L::template collide<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
-    scatter<L, S, P, WALLS, NT>(dst, g.stride, d, s);
+    scatter<L, S, P, WALLS, NT, O32>(dst, g.stride, d, s);
 }
 
 // A-B: two distinct buffers.
-template <class L, class S, bool WALLS, bool GENERAL, bool NT>
+template <class L, class S, bool WALLS, bool GENERAL, bool NT, bool O32>
 __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
 {
-    step_node<L, S, AB, WALLS, GENERAL, NT>(src, dst, g, ph);
+    step_node<L, S, AB, WALLS, GENERAL, NT, O32>(src, dst, g, ph);
 }
 
 // A-B, periodic, with work-groups of whole x rows (blockDim.x == nx): the
@@ -347,7 +365,7 @@ template <class L> __host__ __device__ constexpr int moving_x_count()
     return k;
 }
 
-template <class L, class S, bool GENERAL, bool NT>
+template <class L, class S, bool GENERAL, bool NT, bool O32>
 __global__ __launch_bounds__(256) void k_step_ab_rows(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
 {
     using R = typename Codec<S>::R;
@@ -367,7 +385,7 @@ __global__ __launch_bounds__(256) void k_step_ab_rows(const S* __restrict__ src,
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
             if (L::cx(i) != 0) {
-                rows[k][row0 + x] = ld<S, NT>(src + (int64_t)i * g.stride + nb(d, 0, -L::cy(i), -L::cz(i)));
+                rows[k][row0 + x] = ld<S, NT>(pop_at<S, O32>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i))));
                 ++k;
             }
     }
@@ -383,7 +401,7 @@ __global__ __launch_bounds__(256) void k_step_ab_rows(const S* __restrict__ src,
                 s[i] = Codec<S>::dec(rows[k][row0 + xs]);
                 ++k;
             } else {
-                s[i] = Codec<S>::dec(ld<S, NT>(src + (int64_t)i * g.stride + nb(d, 0, -L::cy(i), -L::cz(i))));
+                s[i] = Codec<S>::dec(ld<S, NT>(pop_at<S, O32>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i)))));
             }
         }
     }
@@ -391,14 +409,14 @@ __global__ __launch_bounds__(256) void k_step_ab_rows(const S* __restrict__ src,
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
     L::template collide<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
-    if (valid) scatter<L, S, AB, false, NT>(dst, g.stride, d, s);
+    if (valid) scatter<L, S, AB, false, NT, O32>(dst, g.stride, d, s);
 }
 
 // AA: one buffer, each node rewrites exactly the locations it read.
-template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT>
+template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT, bool O32>
 __global__ __launch_bounds__(256) void k_step_aa(S* buf, Geom g, Phys ph)
 {
-    step_node<L, S, P, WALLS, GENERAL, NT>(buf, buf, g, ph);
+    step_node<L, S, P, WALLS, GENERAL, NT, O32>(buf, buf, g, ph);
 }
 
 // Initialisation at equilibrium from rho, u (double, device).
@@ -576,13 +594,18 @@ template <class L, class S> struct Launch {
     {
         // D3Q27 has fixed rates: no general-rate variant
         if (L::Q == 27) general = false;
-#define LBM_STEP(P, W, G)                                                                                        \
-    do {                                                                                                         \
-        if constexpr (P == AB && !W) {                                                                           \
-            if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT>), grid, block, 0, st, a, b, g, ph); \
-            else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT>), grid, block, 0, st, a, b, g, ph);              \
-        } else if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT>), grid, block, 0, st, a, b, g, ph); \
-        else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT>), grid, block, 0, st, b, g, ph);                   \
+#define LBM_STEP_O(P, W, G, O)                                                                                      \
+    do {                                                                                                            \
+        if constexpr (P == AB && !W) {                                                                              \
+            if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
+            else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph);              \
+        } else if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
+        else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);                   \
+    } while (0)
+#define LBM_STEP(P, W, G)                        \
+    do {                                         \
+        if (g.off32) LBM_STEP_O(P, W, G, true);  \
+        else LBM_STEP_O(P, W, G, false);         \
     } while (0)
 #define LBM_STEP_G(P, W)                                 \
     if constexpr (L::Q == 19) {                          \
@@ -601,6 +624,7 @@ template <class L, class S> struct Launch {
 #undef LBM_STEP_W
 #undef LBM_STEP_G
 #undef LBM_STEP
+#undef LBM_STEP_O
     }
 
 #define LBM_DISPATCH_PW(KERNEL, ...)                                                                     \

@@ -215,6 +215,7 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
     h->g.nxy = p->nx * p->ny;
     h->g.N = p->nx * p->ny * p->nz;
     h->g.stride = pad_stride(h->g.N, eb);
+    h->g.off32 = h->g.stride * eb < ((int64_t)1 << 32);
     h->walls = p->walls_y != 0;
     // default: streaming hints for A-B with 4- and 8-byte storage, ordinary
     // accesses for AA (in place) and 16-bit storage -- the faster choice of

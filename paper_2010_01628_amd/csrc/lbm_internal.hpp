@@ -16,6 +16,7 @@ struct Geom {
     int xcd_chunk = 1; // 1-D step grids: rows per XCD run (1 = launch order)
     int row_stage = 0; // A-B periodic step with whole-row work-groups: x-moving populations via LDS
     int flat = 0;      // kernels that use thread_node(): 1-D grid over all nodes in index order
+    int off32 = 0;     // every population array is below 4 GiB (32-bit element byte offsets)
 };
 
 struct Phys {
