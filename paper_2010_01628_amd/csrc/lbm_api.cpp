@@ -215,7 +215,12 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
     h->g.nxy = p->nx * p->ny;
     h->g.N = p->nx * p->ny * p->nz;
     h->g.stride = pad_stride(h->g.N, eb);
-    h->g.off32 = h->g.stride * eb < ((int64_t)1 << 32);
+    // 32-bit element offsets while every population array is below 4 GiB;
+    // LBM_OFF32=0 keeps 64-bit addressing (the path of larger lattices)
+    {
+        const char* env = std::getenv("LBM_OFF32");
+        h->g.off32 = h->g.stride * eb < ((int64_t)1 << 32) && !(env && env[0] == '0');
+    }
     h->walls = p->walls_y != 0;
     // default: streaming hints for A-B with 4- and 8-byte storage, ordinary
     // accesses for AA (in place) and 16-bit storage -- the faster choice of
