@@ -90,6 +90,30 @@ def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fi
     }
 
 
+def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
+    """Device copy bandwidth (read + write bytes per second) of torch's copy
+    of a 2 GiB buffer, HIP events, best of `reps`: a measured copy rate the
+    step kernel is compared with beside the nominal 8 TB/s (one read and one
+    write stream; a copy of 19 streams in and 19 out, the step's access
+    pattern, runs faster)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def time_ensemble(L, inputs, torch, steps, warmup, mlp, tune=True):
     """The 64-box ensemble workload (sides 48/64/96, random-phase fields,
     u_rms 0.04, nu log-uniform in [1e-4, 1e-3]): MLUPS of plain D3Q19, learned
@@ -363,6 +387,7 @@ def main(argv=None):
         torch.cuda.empty_cache()
 
     traffic = load_traffic(args.precision, args.streaming, size, head["algo_bytes_per_launch"])
+    copy_gbs = copy_bandwidth(torch)
     roof = {
         "bound": "hbm",
         "achieved": round(head["achieved_GBs"], 1),
@@ -374,6 +399,8 @@ def main(argv=None):
         "kernel_ms_avg": round(head["kernel_ms_avg"], 5),
         "algo_bytes_per_launch": head["algo_bytes_per_launch"],
         "launch": head["launch"],
+        "torch_copy_GBs": round(copy_gbs, 1),
+        "frac_of_torch_copy": round(head["achieved_GBs"] / copy_gbs, 4),
     }
     cpu = None
     if not args.no_cpu_baseline:
