@@ -42,7 +42,7 @@ __device__ inline Geom box_geom(const BoxDesc& bd)
     return g;
 }
 
-template <class L, class S>
+template <class L, class S, bool O32>
 __global__ __launch_bounds__(256) void k_ens_step(const S* __restrict__ src_all, S* __restrict__ dst_all,
                                                   const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
                                                   int ntiles, float rho0)
@@ -58,20 +58,20 @@ __global__ __launch_bounds__(256) void k_ens_step(const S* __restrict__ src_all,
         NodeIdx d;
         node_idx(g, x, y, z, d);
         R s[L::Q];
-        gather<L, S, AB, false, true>(src_all + bd.off, g.stride, d, s);
+        gather<L, S, AB, false, true, O32>(src_all + bd.off, g.stride, d, s);
         Phys ph{};
         ph.omega = bd.omega;
         ph.omega_bulk = 1.0;
         for (int j = 0; j < 9; ++j) ph.omega_hi[j] = 1.0;
         NodeMacro<R> mac;
         L::template collide<R, false>(s, (R)rho0, R(0), R(0), R(0), ph, mac);
-        scatter<L, S, AB, false, true>(dst_all + bd.off, g.stride, d, s);
+        scatter<L, S, AB, false, true, O32>(dst_all + bd.off, g.stride, d, s);
     }
 }
 
 // Learned rates (D3Q19, FP32 collision): every thread of a block takes part in
 // the network each iteration (tiles past a box's end work on a clamped node).
-template <class S>
+template <class S, bool O32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ens_step_mlp(const S* __restrict__ src_all, S* __restrict__ dst_all,
                                                       const BoxDesc* __restrict__ boxes, const int* __restrict__ tile_box,
                                                       int ntiles, float rho0, const MlpPacked* __restrict__ net,
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         NodeIdx d;
         node_idx(g, x, y, z, d);
         float s[19];
-        gather<LatD3Q19, S, AB, false, true>(src_all + bd.off, g.stride, d, s);
+        gather<LatD3Q19, S, AB, false, true, O32>(src_all + bd.off, g.stride, d, s);
         float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];
         {
             CMState<float> st0;
@@ -111,11 +111,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         // the network is re-read every tile (L1/L2 hits) rather than held in
         // registers across the loop: hoisting its loads costs ~70 registers
-        const MlpPacked* netp = net;
-        asm volatile("" : "+s"(netp));
-        mlp_forward_regs(*netp, xin, zout);
+        // (pinned as a global-address-space pointer: the loads stay global,
+        // not flat, instructions)
+        typedef __attribute__((address_space(1))) const MlpPacked gnet_t;
+        gnet_t* netg = (gnet_t*)net;
+        asm volatile("" : "+s"(netg));
+        mlp_forward_regs(*(const MlpPacked*)netg, xin, zout);
         const bool fb = mlp_rates(zout, rates);
-        // recomputed rather than kept live across the network (registers)
+        // recomputed rather than kept live across the network: with the tile
+        // loop's own state, keeping it would spill at four waves per SIMD
 #pragma unroll
         for (int i = 0; i < 19; ++i) asm volatile("" : "+v"(s[i]));
         CMState<float> st;
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         else
             relax<float, true>(st, rt, p);
         post_collide(st, p, s);
-        if (valid) scatter<LatD3Q19, S, AB, false, true>(dst_all + bd.off, g.stride, d, s);
+        if (valid) scatter<LatD3Q19, S, AB, false, true, O32>(dst_all + bd.off, g.stride, d, s);
         my_fb += (valid && fb) ? 1u : 0u;
     }
     // per-block fallback count (no atomics: one slot per block)
@@ -235,30 +239,41 @@ __global__ __launch_bounds__(256) void k_ens_box_sums(const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-void launch_ens_step(int q, int precision, bool mlp, const void* src, void* dst, const void* boxes, const int* tile_box,
-                     int ntiles, float rho0, const void* net, uint32_t* fb, int grid, int block, hipStream_t st)
+template <bool O32>
+static void ens_step_o(int q, int precision, bool mlp, const void* src, void* dst, const BoxDesc* bd, const int* tile_box,
+                       int ntiles, float rho0, const void* net, uint32_t* fb, int grid, int block, hipStream_t st)
 {
-    const BoxDesc* bd = (const BoxDesc*)boxes;
     if (mlp) {
-        hipLaunchKernelGGL(k_ens_step_mlp<float>, dim3(grid), dim3(block), 0, st, (const float*)src, (float*)dst, bd,
-                           tile_box, ntiles, rho0, (const MlpPacked*)net, fb);
+        hipLaunchKernelGGL((k_ens_step_mlp<float, O32>), dim3(grid), dim3(block), 0, st, (const float*)src, (float*)dst,
+                           bd, tile_box, ntiles, rho0, (const MlpPacked*)net, fb);
         return;
     }
     if (q == 27) {
         if (precision == PREC_FP64)
-            hipLaunchKernelGGL((k_ens_step<LatD3Q27, double>), dim3(grid), dim3(block), 0, st, (const double*)src,
+            hipLaunchKernelGGL((k_ens_step<LatD3Q27, double, O32>), dim3(grid), dim3(block), 0, st, (const double*)src,
                                (double*)dst, bd, tile_box, ntiles, rho0);
         else
-            hipLaunchKernelGGL((k_ens_step<LatD3Q27, float>), dim3(grid), dim3(block), 0, st, (const float*)src,
+            hipLaunchKernelGGL((k_ens_step<LatD3Q27, float, O32>), dim3(grid), dim3(block), 0, st, (const float*)src,
                                (float*)dst, bd, tile_box, ntiles, rho0);
     } else {
         if (precision == PREC_FP64)
-            hipLaunchKernelGGL((k_ens_step<LatD3Q19, double>), dim3(grid), dim3(block), 0, st, (const double*)src,
+            hipLaunchKernelGGL((k_ens_step<LatD3Q19, double, O32>), dim3(grid), dim3(block), 0, st, (const double*)src,
                                (double*)dst, bd, tile_box, ntiles, rho0);
         else
-            hipLaunchKernelGGL((k_ens_step<LatD3Q19, float>), dim3(grid), dim3(block), 0, st, (const float*)src,
+            hipLaunchKernelGGL((k_ens_step<LatD3Q19, float, O32>), dim3(grid), dim3(block), 0, st, (const float*)src,
                                (float*)dst, bd, tile_box, ntiles, rho0);
     }
+}
+
+void launch_ens_step(int q, int precision, bool mlp, bool off32, const void* src, void* dst, const void* boxes,
+                     const int* tile_box, int ntiles, float rho0, const void* net, uint32_t* fb, int grid, int block,
+                     hipStream_t st)
+{
+    const BoxDesc* bd = (const BoxDesc*)boxes;
+    if (off32)
+        ens_step_o<true>(q, precision, mlp, src, dst, bd, tile_box, ntiles, rho0, net, fb, grid, block, st);
+    else
+        ens_step_o<false>(q, precision, mlp, src, dst, bd, tile_box, ntiles, rho0, net, fb, grid, block, st);
 }
 
 void launch_ens_energy(int q, int precision, const void* buf, const void* boxes, const int* tile_box, int ntiles,

@@ -47,6 +47,7 @@ struct lbm_ensemble {
     int q = 19, precision = LBM_FP32, nboxes = 0, ntiles = 0;
     int64_t nodes = 0, elems = 0;
     int eb = 4;
+    bool off32 = true; // every box's population arrays below 4 GiB (and LBM_OFF32 != 0)
     std::vector<int> L;
     std::vector<double> omega;
     std::vector<int64_t> off, stride;
@@ -75,7 +76,7 @@ namespace {
 void launch_one(lbm_ensemble* e)
 {
     const int src = e->cur, dst = 1 - e->cur;
-    lbm::launch_ens_step(e->q, e->precision == LBM_FP64 ? 0 : 1, e->mlp != nullptr, e->buf[src], e->buf[dst],
+    lbm::launch_ens_step(e->q, e->precision == LBM_FP64 ? 0 : 1, e->mlp != nullptr, e->off32, e->buf[src], e->buf[dst],
                          e->boxes_dev, e->tile_box_dev, e->ntiles, 1.0f, e->mlp ? e->mlp->packed : nullptr, e->fb,
                          e->grid, TILE, e->stream);
     e->cur = dst;
@@ -143,6 +144,7 @@ int lbm_ensemble_create(const lbm_box* boxes, int32_t nboxes, int32_t q, int32_t
         e->omega.push_back(boxes[b].omega);
         e->off.push_back(elems);
         e->stride.push_back(stride);
+        if (stride * e->eb >= ((int64_t)1 << 32)) e->off32 = false;
         e->tile0.push_back(tiles);
         const int nt = (int)((N + TILE - 1) / TILE);
         e->tiles.push_back(nt);
@@ -152,6 +154,10 @@ int lbm_ensemble_create(const lbm_box* boxes, int32_t nboxes, int32_t q, int32_t
     }
     e->ntiles = tiles;
     e->elems = elems;
+    {
+        const char* env = std::getenv("LBM_OFF32");
+        if (env && env[0] == '0') e->off32 = false;
+    }
     auto cleanup = [&](int code) {
         lbm_ensemble_destroy(e);
         return code;

@@ -185,18 +185,38 @@ template <class S, bool NT> __device__ inline void st(S* p, S v)
 // below 4 GiB, so the element's byte offset is formed in 32 bits and added to
 // the array base, which is the same for the whole wavefront when the slot is a
 // constant: the access then takes a scalar base and a 32-bit vector offset
-// instead of a 64-bit address per lane.
-template <class S, bool O32> __device__ inline const S* pop_at(const S* buf, int64_t stride, int slot, int idx)
+// instead of a 64-bit address per lane.  UNIFORM (the slot is the same for
+// every lane: a constant of the unrolled loop, not a per-node bounce-back
+// choice; buf and stride are kernel arguments): the empty asm pins the base
+// in scalar registers.  Without it the compiler hoists the offset that the 19
+// stores share into one 64-bit vector pointer and rebuilds every store
+// address from it with 64-bit vector multiply-adds.
+template <class S, bool O32, bool UNIFORM = false>
+__device__ inline const S* pop_at(const S* buf, int64_t stride, int slot, int idx)
 {
     const S* base = buf + (int64_t)slot * stride;
-    if constexpr (O32)
-        return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + (uint32_t)idx * (uint32_t)sizeof(S));
-    else
+    if constexpr (O32) {
+        const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(S);
+        if constexpr (UNIFORM) {
+            // pinned as a global-address-space pointer, so accesses stay
+            // global (not flat) instructions
+            typedef __attribute__((address_space(1))) const char gchar;
+            gchar* gb = (gchar*)base;
+            asm("" : "+s"(gb));
+            // the offset passes through an asm of its own for each (array,
+            // offset) pair, so its 64-bit extension is formed beside the
+            // access; not volatile: the accesses keep their scheduling freedom
+            uint32_t o;
+            asm("" : "=v"(o) : "0"(off), "s"(gb));
+            return reinterpret_cast<const S*>((const char*)(gb + o));
+        }
+        return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off);
+    } else
         return base + idx;
 }
-template <class S, bool O32> __device__ inline S* pop_at(S* buf, int64_t stride, int slot, int idx)
+template <class S, bool O32, bool UNIFORM = false> __device__ inline S* pop_at(S* buf, int64_t stride, int slot, int idx)
 {
-    return const_cast<S*>(pop_at<S, O32>(static_cast<const S*>(buf), stride, slot, idx));
+    return const_cast<S*>(pop_at<S, O32, UNIFORM>(static_cast<const S*>(buf), stride, slot, idx));
 }
 
 // Where f_i(x, t) lives in the buffer for pattern P (slot, node index).
@@ -227,7 +247,9 @@ __device__ inline void gather(const S* __restrict__ buf, int64_t stride, const N
     for (int i = 0; i < L::Q; ++i) {
         int slot, idx;
         state_loc<L, P, WALLS>(d, i, slot, idx);
-        s[i] = Codec<S>::dec(ld<S, NT>(pop_at<S, O32>(buf, stride, slot, idx)));
+        // the slot depends on the node only where a wall bounces it back
+        constexpr bool U = !WALLS || P == AA_EVEN;
+        s[i] = Codec<S>::dec(ld<S, NT>(pop_at<S, O32, U>(buf, stride, slot, idx)));
     }
 }
 
@@ -255,7 +277,8 @@ __device__ inline void scatter(S* __restrict__ buf, int64_t stride, const NodeId
                 idx = nb(d, cx, cy, cz);
             }
         }
-        st<S, NT>(pop_at<S, O32>(buf, stride, slot, idx), Codec<S>::enc(s[i]));
+        constexpr bool U = !WALLS || P != AA_ODD;
+        st<S, NT>(pop_at<S, O32, U>(buf, stride, slot, idx), Codec<S>::enc(s[i]));
     }
 }
 
@@ -385,7 +408,7 @@ __global__ __launch_bounds__(256) void k_step_ab_rows(const S* __restrict__ src,
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
             if (L::cx(i) != 0) {
-                rows[k][row0 + x] = ld<S, NT>(pop_at<S, O32>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i))));
+                rows[k][row0 + x] = ld<S, NT>(pop_at<S, O32, true>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i))));
                 ++k;
             }
     }
@@ -401,7 +424,7 @@ __global__ __launch_bounds__(256) void k_step_ab_rows(const S* __restrict__ src,
                 s[i] = Codec<S>::dec(rows[k][row0 + xs]);
                 ++k;
             } else {
-                s[i] = Codec<S>::dec(ld<S, NT>(pop_at<S, O32>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i)))));
+                s[i] = Codec<S>::dec(ld<S, NT>(pop_at<S, O32, true>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i)))));
             }
         }
     }

@@ -41,7 +41,7 @@ __device__ inline void load_net(uint32_t* d, const MlpPacked* __restrict__ src, 
 // edge work on a clamped node and store nothing).  Per block, the number of
 // nodes that fell back is added to fb_partials[block].
 // ---------------------------------------------------------------------------
-template <class S, Pattern P, bool WALLS, bool NT>
+template <class S, Pattern P, bool WALLS, bool NT, bool O32 = false>
 __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const Phys& ph,
                                      const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
 {
@@ -55,26 +55,17 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
     NodeIdx d;
     node_idx(g, x, y, z, d);
     float s[19];
-    gather<LatD3Q19, S, P, WALLS, NT>(src, g.stride, d, s);
+    gather<LatD3Q19, S, P, WALLS, NT, O32>(src, g.stride, d, s);
     float Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];
-    {
-        CMState<float> st0;
-        pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st0);
-        mlp_features(st0, xin);
-    }
+    CMState<float> st;
+    pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
+    mlp_features(st, xin);
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int w = tid >> 6;
     mlp_forward_regs(*net, xin, zout);
     const bool fb = mlp_rates(zout, rates);
-    // the collision state is recomputed rather than kept live across the
-    // network (register pressure); the empty asm keeps the compiler from
-    // reusing the first computation
-#pragma unroll
-    for (int i = 0; i < 19; ++i) asm volatile("" : "+v"(s[i]));
-    CMState<float> st;
-    pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
     Rates<float> rt = rates_of<float>(ph);
 #pragma unroll
     for (int j = 0; j < MLP_NOUT; ++j) rt.omega_hi[j] = rates[j];
@@ -84,7 +75,7 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
     else
         relax<float, true>(st, rt, p);
     post_collide(st, p, s);
-    if (valid) scatter<LatD3Q19, S, P, WALLS, NT>(dst, g.stride, d, s);
+    if (valid) scatter<LatD3Q19, S, P, WALLS, NT, O32>(dst, g.stride, d, s);
     // fallback count of the block
     const uint64_t ballot = __ballot(valid && fb);
     if ((tid & 63) == 0) wave_fb[w] = (uint32_t)__popcll(ballot);
@@ -97,13 +88,14 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
     }
 }
 
-// A-B fits four waves per SIMD without spilling (115 VGPRs); the AA variants
-// would spill under that limit and keep the compiler's choice.
-template <class S, bool WALLS, bool NT>
+// A-B fits four waves per SIMD without spilling (~125 VGPRs, the collision
+// state kept live across the network); the AA variants would spill under
+// that limit and keep the compiler's choice.
+template <class S, bool WALLS, bool NT, bool O32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_step_mlp_ab(
     const S* src, S* dst, Geom g, Phys ph, const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
 {
-    step_mlp_body<S, AB, WALLS, NT>(src, dst, g, ph, net, fb_partials);
+    step_mlp_body<S, AB, WALLS, NT, O32>(src, dst, g, ph, net, fb_partials);
 }
 
 template <class S, Pattern P, bool WALLS, bool NT>
@@ -487,7 +479,10 @@ static void step_mlp_s(int pattern, bool walls, bool nt, const void* src, void* 
     const MlpPacked* w = (const MlpPacked*)net;
 #define LBM_MLP_STEP(P, W, NT_)                                                                       \
     do {                                                                                              \
-        if constexpr (P == AB) hipLaunchKernelGGL((k_step_mlp_ab<S, W, NT_>), grid, block, 0, st, a, b, g, ph, w, fb); \
+        if constexpr (P == AB) {                                                                      \
+            if (g.off32) hipLaunchKernelGGL((k_step_mlp_ab<S, W, NT_, true>), grid, block, 0, st, a, b, g, ph, w, fb); \
+            else hipLaunchKernelGGL((k_step_mlp_ab<S, W, NT_, false>), grid, block, 0, st, a, b, g, ph, w, fb); \
+        }                                                                                             \
         else hipLaunchKernelGGL((k_step_mlp<S, P, W, NT_>), grid, block, 0, st, a, b, g, ph, w, fb);    \
     } while (0)
 #define LBM_MLP_NT(P, W) \

@@ -32,7 +32,7 @@ static_assert(MLP_OFF_B3 + MLP_NOUT == MLP_NPARAM, "parameter layout");
 // master parameters).  Matrices are bf16 [row][col], zero padded to 32 x 32
 // (W1 to 32 x 16); the transposed copies serve the backward products.
 struct MlpPacked {
-    // inference part (what the step kernel stages in LDS)
+    // inference part (what the step kernels read)
     uint16_t w1[32 * 16]; // [out][in]
     uint16_t w2[32 * 32]; // [out][in]
     uint16_t w3[32 * 32]; // [out (9 used)][in]
@@ -200,15 +200,20 @@ __device__ inline void swap_halves(float& a, float& b)
     b = __builtin_bit_cast(float, ub);
 }
 
-// bias in accumulator layout: acc[r] = b[8 (r / 4) + 4 (l / 32) + r % 4] (rows < nrows)
-__device__ inline f32x16_t bias_acc(const float* b, int nrows)
+// bias in accumulator layout: acc[4m + v] = b[8m + 4 (l / 32) + v].  b holds
+// 32 floats, zero past the layer's rows (the packed layout), 16-byte aligned:
+// four unguarded 16-byte loads per lane.
+__device__ inline f32x16_t bias_acc(const float* b)
 {
-    const int kh = 4 * (lane_id() >> 5);
+    const float4* p = reinterpret_cast<const float4*>(b + 4 * (lane_id() >> 5));
     f32x16_t acc;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int j = 8 * (r >> 2) + kh + (r & 3);
-        acc[r] = j < nrows ? b[j] : 0.0f;
+    for (int m = 0; m < 4; ++m) {
+        const float4 q = p[2 * m];
+        acc[4 * m] = q.x;
+        acc[4 * m + 1] = q.y;
+        acc[4 * m + 2] = q.z;
+        acc[4 * m + 3] = q.w;
     }
     return acc;
 }
@@ -228,18 +233,18 @@ __device__ inline void mlp_block_regs(const MlpPacked& W, const bf16x4_t in[2], 
 {
     const int l = lane_id();
     const int row = l & 31, kh = 4 * (l >> 5);
-    f32x16_t acc = bias_acc(W.b1, MLP_NH);
+    f32x16_t acc = bias_acc(W.b1);
 #pragma unroll
     for (int s = 0; s < 2; ++s)
         acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w1 + row * 16 + 8 * s + kh), in[s], acc, 0, 0, 0);
     bf16x4_t h[4];
     act_to_operands(acc, h);
-    acc = bias_acc(W.b2, MLP_NH);
+    acc = bias_acc(W.b2);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
         acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w2 + row * 32 + 8 * m + kh), h[m], acc, 0, 0, 0);
     act_to_operands(acc, h);
-    acc = bias_acc(W.b3, MLP_NOUT);
+    acc = bias_acc(W.b3);
 #pragma unroll
     for (int m = 0; m < 4; ++m)
         acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w3 + row * 32 + 8 * m + kh), h[m], acc, 0, 0, 0);

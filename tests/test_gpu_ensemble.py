@@ -94,6 +94,28 @@ def test_fp32_matches_single_lattice_bitwise(q):
     ens.close()
 
 
+@pytest.mark.parametrize("q,learned", [(19, False), (27, False), (19, True)])
+def test_64bit_addressing_is_bitwise_identical(q, learned, monkeypatch):
+    """Boxes whose population arrays are below 4 GiB take 32-bit offsets
+    against the box's array base; forcing 64-bit addresses (the path of
+    larger boxes) gives the same values, bit for bit."""
+    boxes = [(12, 1.85), (7, 1.7), (10, 1.9)]
+    mlp = L.Mlp(0.08 * np.random.default_rng(3).normal(size=L.MLP_NPARAM), SCALES) if learned else None
+    out = []
+    for off32 in ("1", "0"):
+        monkeypatch.setenv("LBM_OFF32", off32)
+        ens = make_ensemble(boxes, q=q, precision="fp32")
+        if mlp is not None:
+            ens.set_mlp(mlp)
+        ens.step(9)
+        out.append([ens.get_populations(b) for b in range(len(boxes))])
+        ens.close()
+    if mlp is not None:
+        mlp.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("chunk", ["2", "16", "0"])
 def test_graph_replay_equals_single_steps(chunk, monkeypatch):
     """Stepping through captured graphs of `chunk` steps (0: no graph) gives

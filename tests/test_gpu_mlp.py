@@ -85,6 +85,28 @@ def test_mlp_step_matches_oracle(orc, streaming, walls):
     mlp.close()
 
 
+def test_mlp_64bit_addressing_is_bitwise_identical(orc, monkeypatch):
+    """The learned A-B step with 32-bit offsets against each array base and
+    with 64-bit addresses (the path of arrays of 4 GiB and more) gives the
+    same populations, bit for bit."""
+    nx, ny, nz = 64, 10, 6
+    rng = np.random.default_rng(2)
+    P = 0.08 * rng.normal(size=L.MLP_NPARAM)
+    f0 = noneq_state(orc, nx, ny, nz, 9)
+    mlp = L.Mlp(P, SCALES)
+    out = []
+    for off32 in ("1", "0"):
+        monkeypatch.setenv("LBM_OFF32", off32)
+        lat = make_lattice(nx, ny, nz, f0, 1.8)
+        lat.attach_mlp(mlp)
+        lat.step(4)
+        out.append(lat.get_populations().cpu().numpy())
+        assert lat.fallback_count() == 0
+        lat.close()
+    mlp.close()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_fallback_is_plain_scheme_bitwise(orc):
     nx, ny, nz = 20, 9, 7
     f0 = noneq_state(orc, nx, ny, nz, 5)

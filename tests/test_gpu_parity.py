@@ -271,14 +271,18 @@ def test_row_staged_step_is_bitwise_identical(precision, monkeypatch):
     assert np.array_equal(staged["f"], direct["f"])
 
 
-@pytest.mark.parametrize("precision,streaming,walls", [("fp32", "ab", False), ("fp16", "aa", True), ("fp64", "ab", True)])
-def test_64bit_addressing_is_bitwise_identical(precision, streaming, walls, monkeypatch):
+@pytest.mark.parametrize("precision,streaming,walls,q", [
+    ("fp32", "ab", False, 19), ("fp16", "aa", True, 19), ("fp64", "ab", True, 19), ("bf16", "ab", True, 19),
+    ("fp32", "aa", False, 19), ("fp32", "ab", True, 27), ("fp64", "aa", True, 27)])
+def test_64bit_addressing_is_bitwise_identical(precision, streaming, walls, q, monkeypatch):
     """Population arrays of 4 GiB and more take 64-bit addresses; smaller ones
-    32-bit offsets against the array base.  Forcing the 64-bit path on a small
-    lattice gives the same values, bit for bit."""
+    32-bit offsets against the array base (a scalar base where the array is
+    the same for the whole wavefront, a per-lane address where a wall picks it
+    per node).  Forcing the 64-bit path on a small lattice gives the same
+    values, bit for bit."""
     nx, ny, nz = 64, 20, 9
     rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=44, umax=0.05, fmax=1e-3)
-    kw = dict(omega=1.8, omega_hi=[1.4] * 9, force=F, walls=walls)
+    kw = dict(omega=1.8, omega_hi=[1.4] * 9 if q == 19 else None, force=F, walls=walls, q=q)
     a = gpu_run(nx, ny, nz, rho, u, 6, precision, streaming, **kw)
     monkeypatch.setenv("LBM_OFF32", "0")
     b = gpu_run(nx, ny, nz, rho, u, 6, precision, streaming, **kw)
