@@ -27,7 +27,7 @@ template <class R> __host__ __device__ inline R cg_phi_i(int c2, R alpha)
 __host__ __device__ constexpr double cg_B(int c2) { return c2 == 0 ? -1.0 / 3.0 : (c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0); }
 __host__ __device__ constexpr int c2_19(int i) { return cx19(i) * cx19(i) + cy19(i) * cy19(i) + cz19(i) * cz19(i); }
 
-template <class S, bool WALLS>
+template <class S, bool WALLS, bool O32>
 __global__ __launch_bounds__(256) void k_cg_phi(const S* __restrict__ red, const S* __restrict__ blue,
                                                typename Codec<S>::R* __restrict__ phi, Geom g)
 {
@@ -37,8 +37,8 @@ __global__ __launch_bounds__(256) void k_cg_phi(const S* __restrict__ red, const
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R a[19], b[19];
-    gather<LatD3Q19, S, AB, WALLS>(red, g.stride, d, a);
-    gather<LatD3Q19, S, AB, WALLS>(blue, g.stride, d, b);
+    gather<LatD3Q19, S, AB, WALLS, false, O32>(red, g.stride, d, a);
+    gather<LatD3Q19, S, AB, WALLS, false, O32>(blue, g.stride, d, b);
     R rr = R(0), rb = R(0);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
@@ -121,7 +121,7 @@ __host__ __device__ inline void cg_node(R a[19], R b[19], R gx, R gy, R gz, cons
     }
 }
 
-template <class S, bool WALLS, bool NT>
+template <class S, bool WALLS, bool NT, bool O32>
 __global__ __launch_bounds__(256) void k_cg_step(const S* __restrict__ rsrc, S* __restrict__ rdst,
                                                 const S* __restrict__ bsrc, S* __restrict__ bdst,
                                                 const typename Codec<S>::R* __restrict__ phi, Geom g, CgConst cc)
@@ -142,11 +142,11 @@ __global__ __launch_bounds__(256) void k_cg_step(const S* __restrict__ rsrc, S* 
         if (cz19(i)) gz += R(cz19(i)) * dp;
     }
     R a[19], b[19];
-    gather<LatD3Q19, S, AB, WALLS, NT>(rsrc, g.stride, d, a);
-    gather<LatD3Q19, S, AB, WALLS, NT>(bsrc, g.stride, d, b);
+    gather<LatD3Q19, S, AB, WALLS, NT, O32>(rsrc, g.stride, d, a);
+    gather<LatD3Q19, S, AB, WALLS, NT, O32>(bsrc, g.stride, d, b);
     cg_node(a, b, gx, gy, gz, cc);
-    scatter<LatD3Q19, S, AB, WALLS, NT>(rdst, g.stride, d, a);
-    scatter<LatD3Q19, S, AB, WALLS, NT>(bdst, g.stride, d, b);
+    scatter<LatD3Q19, S, AB, WALLS, NT, O32>(rdst, g.stride, d, a);
+    scatter<LatD3Q19, S, AB, WALLS, NT, O32>(bdst, g.stride, d, b);
 }
 
 // f^k = (rho_k / rho) h_eq(rho, u), placed where the first step pulls it.
@@ -239,8 +239,8 @@ __global__ __launch_bounds__(256) void k_cg_fields(const S* __restrict__ red, co
     block_reduce_store(v, partials + (int64_t)bid * NDIAG);
 }
 
-template <class S>
-static void cg_step_t(bool walls, bool nt, const void* rs, void* rd, const void* bs, void* bd, void* phi, const Geom& g,
+template <class S, bool O32>
+static void cg_step_o(bool walls, bool nt, const void* rs, void* rd, const void* bs, void* bd, void* phi, const Geom& g,
                       const CgConst& cc, dim3 grid, dim3 block, hipStream_t st)
 {
     using R = typename Codec<S>::R;
@@ -249,8 +249,8 @@ static void cg_step_t(bool walls, bool nt, const void* rs, void* rd, const void*
     R* p = (R*)phi;
 #define CG_STEP(W, NTV)                                                                                     \
     do {                                                                                                    \
-        hipLaunchKernelGGL((k_cg_phi<S, W>), grid, block, 0, st, a, b, p, g);                               \
-        hipLaunchKernelGGL((k_cg_step<S, W, NTV>), grid, block, 0, st, a, ad, b, bdd, (const R*)p, g, cc); \
+        hipLaunchKernelGGL((k_cg_phi<S, W, O32>), grid, block, 0, st, a, b, p, g);                          \
+        hipLaunchKernelGGL((k_cg_step<S, W, NTV, O32>), grid, block, 0, st, a, ad, b, bdd, (const R*)p, g, cc); \
     } while (0)
     if (walls) {
         if (nt) CG_STEP(true, true);
@@ -260,6 +260,14 @@ static void cg_step_t(bool walls, bool nt, const void* rs, void* rd, const void*
         else CG_STEP(false, false);
     }
 #undef CG_STEP
+}
+
+template <class S>
+static void cg_step_t(bool walls, bool nt, const void* rs, void* rd, const void* bs, void* bd, void* phi, const Geom& g,
+                      const CgConst& cc, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (g.off32) cg_step_o<S, true>(walls, nt, rs, rd, bs, bd, phi, g, cc, grid, block, st);
+    else cg_step_o<S, false>(walls, nt, rs, rd, bs, bd, phi, g, cc, grid, block, st);
 }
 
 void launch_cg_step(int precision, bool walls, bool nt, const void* rsrc, void* rdst, const void* bsrc, void* bdst,

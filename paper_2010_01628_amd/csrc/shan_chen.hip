@@ -17,7 +17,7 @@
 
 namespace lbm {
 
-template <class S>
+template <class S, bool O32>
 __global__ __launch_bounds__(256) void k_sc_psi(const S* __restrict__ src, typename Codec<S>::R* __restrict__ psi, Geom g,
                                                double rho0)
 {
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_sc_psi(const S* __restrict__ src, typen
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R s[19];
-    gather<LatD3Q19, S, AB, false>(src, g.stride, d, s);
+    gather<LatD3Q19, S, AB, false, false, O32>(src, g.stride, d, s);
     R m = s[0];
 #pragma unroll
     for (int i = 1; i < 19; ++i) m += s[i];
@@ -55,7 +55,7 @@ __device__ inline void sc_force(const R* __restrict__ psi, const NodeIdx& d, R G
     Fz = a * sz + (uni ? (R)ph.force[2] : R(0));
 }
 
-template <class S, bool GENERAL, bool NT>
+template <class S, bool GENERAL, bool NT, bool O32>
 __global__ __launch_bounds__(256) void k_sc_step(const S* __restrict__ src, S* __restrict__ dst,
                                                 const typename Codec<S>::R* __restrict__ psi, Geom g, Phys ph, double G)
 {
@@ -67,10 +67,10 @@ __global__ __launch_bounds__(256) void k_sc_step(const S* __restrict__ src, S* _
     R Fx, Fy, Fz;
     sc_force(psi, d, (R)G, ph, Fx, Fy, Fz);
     R s[19];
-    gather<LatD3Q19, S, AB, false, NT>(src, g.stride, d, s);
+    gather<LatD3Q19, S, AB, false, NT, O32>(src, g.stride, d, s);
     NodeMacro<R> mac;
     collide_cm<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
-    scatter<LatD3Q19, S, AB, false, NT>(dst, g.stride, d, s);
+    scatter<LatD3Q19, S, AB, false, NT, O32>(dst, g.stride, d, s);
 }
 
 // rho, force-shifted u (any output may be NULL) and FP64 partial sums of the
@@ -126,16 +126,16 @@ __global__ __launch_bounds__(256) void k_sc_fields(const S* __restrict__ src, co
     block_reduce_store(v, partials + (int64_t)bid * NDIAG);
 }
 
-template <class S>
-static void sc_step_t(bool general, bool nt, const void* src, void* dst, void* psi, const Geom& g, const Phys& ph,
+template <class S, bool O32>
+static void sc_step_o(bool general, bool nt, const void* src, void* dst, void* psi, const Geom& g, const Phys& ph,
                       double G, dim3 grid, dim3 block, hipStream_t st)
 {
     using R = typename Codec<S>::R;
     const S* a = (const S*)src;
     S* b = (S*)dst;
     R* p = (R*)psi;
-    hipLaunchKernelGGL((k_sc_psi<S>), grid, block, 0, st, a, p, g, ph.rho0);
-#define SC_STEP(GEN, NTV) hipLaunchKernelGGL((k_sc_step<S, GEN, NTV>), grid, block, 0, st, a, b, p, g, ph, G)
+    hipLaunchKernelGGL((k_sc_psi<S, O32>), grid, block, 0, st, a, p, g, ph.rho0);
+#define SC_STEP(GEN, NTV) hipLaunchKernelGGL((k_sc_step<S, GEN, NTV, O32>), grid, block, 0, st, a, b, p, g, ph, G)
     if (general) {
         if (nt) SC_STEP(true, true);
         else SC_STEP(true, false);
@@ -144,6 +144,14 @@ static void sc_step_t(bool general, bool nt, const void* src, void* dst, void* p
         else SC_STEP(false, false);
     }
 #undef SC_STEP
+}
+
+template <class S>
+static void sc_step_t(bool general, bool nt, const void* src, void* dst, void* psi, const Geom& g, const Phys& ph,
+                      double G, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (g.off32) sc_step_o<S, true>(general, nt, src, dst, psi, g, ph, G, grid, block, st);
+    else sc_step_o<S, false>(general, nt, src, dst, psi, g, ph, G, grid, block, st);
 }
 
 void launch_sc_step(int precision, bool general, bool nt, const void* src, void* dst, void* psi, const Geom& g,
@@ -157,11 +165,11 @@ void launch_sc_fields(int precision, const void* src, void* psi, const Geom& g, 
                       double* u, double* partials, dim3 grid, dim3 block, hipStream_t st)
 {
     if (precision == PREC_FP64) {
-        hipLaunchKernelGGL((k_sc_psi<double>), grid, block, 0, st, (const double*)src, (double*)psi, g, ph.rho0);
+        hipLaunchKernelGGL((k_sc_psi<double, false>), grid, block, 0, st, (const double*)src, (double*)psi, g, ph.rho0);
         hipLaunchKernelGGL((k_sc_fields<double>), grid, block, 0, st, (const double*)src, (const double*)psi, g, ph, G,
                            rho, u, partials);
     } else {
-        hipLaunchKernelGGL((k_sc_psi<float>), grid, block, 0, st, (const float*)src, (float*)psi, g, ph.rho0);
+        hipLaunchKernelGGL((k_sc_psi<float, false>), grid, block, 0, st, (const float*)src, (float*)psi, g, ph.rho0);
         hipLaunchKernelGGL((k_sc_fields<float>), grid, block, 0, st, (const float*)src, (const float*)psi, g, ph, G,
                            rho, u, partials);
     }

@@ -80,6 +80,20 @@ def test_fp64_matches_oracle(orc, shape, walls, steps):
     assert np.abs(g["u"] - o["u"]).max() < 1e-13
 
 
+@pytest.mark.parametrize("walls", [True, False])
+def test_64bit_addressing_is_bitwise_identical(walls, monkeypatch):
+    """32-bit offsets against each population array's base (arrays below
+    4 GiB; per lane where a wall picks the array) and 64-bit addresses
+    (LBM_OFF32=0, the path of larger lattices) give the same red and blue
+    populations, bit for bit."""
+    shape = (14, 10, 7)
+    rr, rb, u = mixture(shape, 12)
+    a = gpu_cg(shape, rr, rb, u, 6, "fp32", 1.6, walls, colour_kw())
+    monkeypatch.setenv("LBM_OFF32", "0")
+    b = gpu_cg(shape, rr, rb, u, 6, "fp32", 1.6, walls, colour_kw())
+    assert np.array_equal(a["fr"], b["fr"]) and np.array_equal(a["fb"], b["fb"])
+
+
 def test_fp32_matches_oracle(orc):
     shape, steps = (20, 24, 16), 60
     rr, rb, u = mixture(shape, 3)

@@ -99,6 +99,20 @@ def test_fp32_matches_oracle(orc):
     assert e_r < 1e-6 and e_u < 1e-4
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_64bit_addressing_is_bitwise_identical(precision, monkeypatch):
+    """32-bit offsets against each population array's base (arrays below
+    4 GiB) and 64-bit addresses (LBM_OFF32=0, the path of larger lattices)
+    give the same populations, bit for bit."""
+    shape = (23, 17, 11)
+    rho = droplet_rho(shape, 5.0)
+    _, u, _ = inputs.random_lattice_fields(*shape, seed=6, umax=0.02)
+    a = gpu_sc(shape, rho, u, 9, precision, omega_hi=[1.3] * 9)
+    monkeypatch.setenv("LBM_OFF32", "0")
+    b = gpu_sc(shape, rho, u, 9, precision, omega_hi=[1.3] * 9)
+    assert np.array_equal(a["f"], b["f"])
+
+
 def test_uniform_density_equals_plain_lattice_bitwise():
     """Uniform density: psi is uniform and the interaction force sums to
     exactly zero (differences of equal values), so the step equals the plain
