@@ -1,9 +1,10 @@
 """Accuracy of every storage precision and streaming pattern over a long run:
 the config-2 recipe (Taylor-Green U0 = 0.05 + seeded noise 1e-4, nu = 1e-3,
-Kolmogorov force 1e-6) at 64^3 for 1000 steps against the FP64 oracle run
-once on the host; relative L2 of u and of rho - mean(rho).  (The timed
-256^3 lattice is checked at full size step by step in test_gpu_fullsize.py;
-1000 oracle steps at 256^3 would take the host many minutes.)"""
+Kolmogorov force 1e-6) at 64^3 and 128^3 for 1000 steps against the FP64
+oracle run once per size on the host; relative L2 of u and of rho -
+mean(rho).  (The timed 256^3 lattice is checked at full size step by step in
+test_gpu_fullsize.py; 1000 oracle steps at 256^3 would take the host ~10
+minutes.)"""
 import numpy as np
 import pytest
 
@@ -13,13 +14,19 @@ from paper_2010_01628_amd import lbm as L
 
 pytestmark = pytest.mark.gpu
 
-N, STEPS, NU = 64, 1000, 1e-3
-# bounds per storage precision, about twice the measured values (u / rho:
-# FP32 1.9e-5 / 3.0e-5, FP16 6.0e-4 / 5.7e-3, BF16 2.8e-2 / 7.6e-2, the same
-# for A-B and AA); 16-bit storage rounds every population at every step, so
-# its error grows with the step count (at 200 steps: FP16 3.3e-4, BF16 3.0e-3)
-TOL_U = {"fp32": 5e-5, "fp16": 2e-3, "bf16": 6e-2}
-TOL_RHO = {"fp32": 1e-4, "fp16": 2e-2, "bf16": 0.15}
+STEPS, NU = 1000, 1e-3
+# bounds per size and storage precision, about twice the measured values
+# (u / rho - mean(rho), the same for A-B and AA):
+#   64^3:  FP32 1.9e-5 / 3.0e-5, FP16 6.0e-4 / 5.7e-3, BF16 2.8e-2 / 7.6e-2
+#   128^3: FP32 2.5e-5 / 3.2e-5, FP16 4.9e-4 / 9.1e-3, BF16 3.5e-2 / 1.07
+# 16-bit storage rounds every population at every step, so its error grows
+# with the step count (64^3 at 200 steps: FP16 3.3e-4, BF16 3.0e-3).  With
+# BF16's 8-bit mantissa the density fluctuations (~1e-3 of rho) are lost at
+# 128^3: deterministic rounding of a smooth field is nearly the same at
+# neighbouring nodes and drives long acoustic modes that viscosity hardly
+# damps at this size; the bound there only guards against blow-up.
+TOL_U = {64: {"fp32": 5e-5, "fp16": 2e-3, "bf16": 6e-2}, 128: {"fp32": 5e-5, "fp16": 1e-3, "bf16": 7e-2}}
+TOL_RHO = {64: {"fp32": 1e-4, "fp16": 2e-2, "bf16": 0.15}, 128: {"fp32": 1e-4, "fp16": 2e-2, "bf16": 2.5}}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -31,23 +38,24 @@ def _gpu():
     L.lib()
 
 
-@pytest.fixture(scope="module")
-def reference(orc):
-    say(f"oracle: {N}^3, {STEPS} steps (FP64, host)")
+@pytest.fixture(scope="module", params=[64, 128])
+def reference(orc, request):
+    N = request.param
+    say(f"oracle: {N}^3, {STEPS} steps (FP64, host; ~80 s at 128^3 on 16 threads)")
     rho, u = inputs.taylor_green_noise(N, 0.05, 1e-4, seed=20101628)
     F = inputs.kolmogorov_force(N, N, N, 1e-6)
     f = orc.run(orc.init(rho, u), STEPS, orc.K(inputs.omega_from_nu(NU)), F=F)
     r, v = orc.moments(f, F)
-    return rho, u, r, v
+    return N, rho, u, r, v
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("streaming", ["ab", "aa"])
 def test_long_run_error(reference, precision, streaming):
-    rho, u, ro, uo = reference
+    N, rho, u, ro, uo = reference
     say(f"{precision} {streaming}: {N}^3, {STEPS} steps")
     g = gpu_run(N, N, N, rho, u, STEPS, precision, streaming, omega=inputs.omega_from_nu(NU),
                 force_mode=L.LBM_FORCE_KOLMOGOROV, kolmogorov_amp=1e-6, want_pops=False)
     eu, er = rel_l2(g["u"], uo), rel_l2_fluct(g["rho"], ro)
     say(f"  rel L2 u = {eu:.3e}, rho - mean(rho) = {er:.3e}")
-    assert eu < TOL_U[precision] and er < TOL_RHO[precision]
+    assert eu < TOL_U[N][precision] and er < TOL_RHO[N][precision]
