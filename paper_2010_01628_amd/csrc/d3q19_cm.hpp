@@ -71,7 +71,15 @@ template <> struct Codec<float> {
 template <> struct Codec<_Float16> {
     using R = float;
     __device__ static inline float dec(_Float16 v) { return (float)v; }
-    __device__ static inline _Float16 enc(float v) { return (_Float16)v; }
+    // the empty asm keeps the last FP32 operation of the collision from being
+    // fused into a mixed-precision FMA with the conversion: the value is
+    // rounded to FP32 first, then RNE to FP16 (and the plain conversion timed
+    // ~1.5 % faster in the 16-bit step)
+    __device__ static inline _Float16 enc(float v)
+    {
+        asm("" : "+v"(v));
+        return (_Float16)v;
+    }
 };
 template <> struct Codec<bf16_t> {
     using R = float;
