@@ -273,8 +273,8 @@ int lbm_set_coupled_populations(lbm_handle *h, const double *in, int on_device);
  * even) real steps, three times in interleaved rounds, for each work-group
  * shape 256x1, 128x2, 64x4, 128x1, 64x2, 64x1 (those that fit the lattice)
  * with and without non-temporal hints and, where a work-group spans whole x
- * rows (A-B, periodic), with and without staging the x-moving populations
- * through LDS; keeps the fastest (by each candidate's best round) for later
+ * rows (periodic; A-B, or the odd step of AA), with and without staging the
+ * x-moving populations through LDS; keeps the fastest (by each candidate's best round) for later
  * lbm_step calls and reports it (block_x, block_y, cache_policy 1 =
  * non-temporal, 2 = cached, row_stage 1 = staged; each may be NULL).  The
  * state advances by the steps taken and the step counter counts them.  The

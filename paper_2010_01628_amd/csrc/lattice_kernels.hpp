@@ -442,6 +442,89 @@ __global__ __launch_bounds__(256) void k_step_aa(S* buf, Geom g, Phys ph)
     step_node<L, S, P, WALLS, GENERAL, NT, O32>(buf, buf, g, ph);
 }
 
+// AA odd step, periodic, with work-groups of whole x rows (blockDim.x == nx).
+// Node x reads slot opp(i) at x - c_i and writes slot i at x + c_i; for the
+// populations that move along x both accesses are staged through LDS so that
+// every global access is aligned: thread x reads element x of the source row
+// (y - c_y, z - c_z) of array opp(i) into LDS and takes element x - c_x;
+// after the collision it puts its value at x + c_x of an LDS row, and thread
+// x stores element x of the destination row (y + c_y, z + c_z) of array i.
+// In place and race free as the plain kernel: location (i, m) is read only
+// by node m - c_i, which lies in the same x row, and a thread stores only
+// elements it loaded itself earlier.  Same values as k_step_aa, bit for bit.
+template <class L, class S, bool GENERAL, bool NT, bool O32>
+__global__ __launch_bounds__(256) void k_step_aa_odd_rows(S* __restrict__ buf, Geom g, Phys ph)
+{
+    using R = typename Codec<S>::R;
+    constexpr int QX = moving_x_count<L>();
+    __shared__ S rows[QX][256];
+    int bxi, byi, z;
+    block_coords(g, g.xcd_chunk, bxi, byi, z);
+    const int x = threadIdx.x; // bxi == 0: one work-group spans the row
+    const int yr = byi * blockDim.y + threadIdx.y;
+    const bool valid = yr < g.ny;
+    const int y = valid ? yr : g.ny - 1;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int row0 = threadIdx.y * blockDim.x;
+    {
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            if (L::cx(i) != 0) {
+                rows[k][row0 + x] =
+                    ld<S, NT>(pop_at<S, O32, true>(buf, g.stride, L::opp(i), nb(d, 0, -L::cy(i), -L::cz(i))));
+                ++k;
+            }
+    }
+    __syncthreads();
+    R s[L::Q];
+    {
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            if (L::cx(i) != 0) {
+                int xs = x - L::cx(i);
+                xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+                s[i] = Codec<S>::dec(rows[k][row0 + xs]);
+                ++k;
+            } else {
+                s[i] = Codec<S>::dec(
+                    ld<S, NT>(pop_at<S, O32, true>(buf, g.stride, L::opp(i), nb(d, 0, -L::cy(i), -L::cz(i)))));
+            }
+        }
+    }
+    R Fx, Fy, Fz;
+    node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
+    NodeMacro<R> mac;
+    L::template collide<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    __syncthreads(); // every staged value has been taken out of LDS
+    {
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            if (L::cx(i) != 0) {
+                int xd = x + L::cx(i);
+                xd = xd < 0 ? xd + g.nx : (xd >= g.nx ? xd - g.nx : xd);
+                rows[k][row0 + xd] = Codec<S>::enc(s[i]);
+                ++k;
+            } else if (valid) {
+                st<S, NT>(pop_at<S, O32, true>(buf, g.stride, i, nb(d, 0, L::cy(i), L::cz(i))), Codec<S>::enc(s[i]));
+            }
+        }
+    }
+    __syncthreads();
+    if (valid) {
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            if (L::cx(i) != 0) {
+                st<S, NT>(pop_at<S, O32, true>(buf, g.stride, i, nb(d, 0, L::cy(i), L::cz(i))), rows[k][row0 + x]);
+                ++k;
+            }
+    }
+}
+
 // Initialisation at equilibrium from rho, u (double, device).
 template <class L, class S, Pattern P, bool WALLS>
 __global__ __launch_bounds__(256) void k_init(S* __restrict__ buf, Geom g, double rho0, const double* __restrict__ rho,
@@ -623,7 +706,10 @@ template <class L, class S> struct Launch {
             if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
             else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph);              \
         } else if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
-        else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);                   \
+        else if constexpr (P == AA_ODD && !W) {                                                                     \
+            if (g.row_stage) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O>), grid, block, 0, st, b, g, ph); \
+            else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);               \
+        } else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);                 \
     } while (0)
 #define LBM_STEP(P, W, G)                        \
     do {                                         \

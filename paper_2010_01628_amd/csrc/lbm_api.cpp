@@ -136,17 +136,20 @@ void default_block(const lbm_params* p, int& bx, int& by)
     while (by > 1 && by / 2 >= ny2 && bx * (by / 2) >= 64) by /= 2;
 }
 
-// Row staging of the x-moving populations through LDS: possible for A-B,
-// periodic, work-groups spanning whole rows.  By default on for 4- and
-// 8-byte storage and off for 16-bit storage (measured at 256^3: FP32 +4.6 %,
-// FP64 +4.2 %, FP16 -9 %); the tuner may choose either; LBM_ROW_STAGING=0
-// turns it off.
+// Row staging of the x-moving populations through LDS: possible for a
+// periodic lattice with work-groups spanning whole rows, in the A-B step and
+// the AA odd step (the AA even step is local).  By default on for 4- and
+// 8-byte storage and off for 16-bit storage (A-B measured at 256^3 before
+// the scalar-base addressing: FP32 +4.6 %, FP64 +4.2 %, FP16 -9 %); the
+// tuner may choose either; LBM_ROW_STAGING=0 turns it off, =1 on wherever it
+// is possible (both override the default and the tuner).
 void set_row_stage(lbm_handle* h)
 {
     const char* env = std::getenv("LBM_ROW_STAGING");
-    const bool allowed = !(env && env[0] == '0') && h->p.streaming == LBM_AB && !h->walls &&
-                         (int)h->step_block.x == h->g.nx;
-    const bool want = h->row_stage_pref >= 0 ? h->row_stage_pref == 1 : elem_bytes(h->p.precision) >= 4;
+    const bool allowed = !(env && env[0] == '0') && (h->p.streaming == LBM_AB || h->p.streaming == LBM_AA) &&
+                         !h->walls && (int)h->step_block.x == h->g.nx;
+    const bool want = (env && env[0] == '1') ||
+                      (h->row_stage_pref >= 0 ? h->row_stage_pref == 1 : elem_bytes(h->p.precision) >= 4);
     h->g.row_stage = allowed && want;
 }
 

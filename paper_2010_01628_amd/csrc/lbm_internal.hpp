@@ -14,7 +14,7 @@ struct Geom {
     int N;          // nodes
     int64_t stride; // elements between consecutive population arrays (>= N)
     int xcd_chunk = 1; // 1-D step grids: rows per XCD run (1 = launch order)
-    int row_stage = 0; // A-B periodic step with whole-row work-groups: x-moving populations via LDS
+    int row_stage = 0; // periodic A-B / AA odd step with whole-row work-groups: x-moving populations via LDS
     int flat = 0;      // kernels that use thread_node(): 1-D grid over all nodes in index order
     int off32 = 0;     // every population array is below 4 GiB (32-bit element byte offsets)
 };

@@ -257,17 +257,21 @@ def test_xcd_interleaved_grid_is_bitwise_identical(monkeypatch):
     assert np.array_equal(ref["f"], got["f"])
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
-def test_row_staged_step_is_bitwise_identical(precision, monkeypatch):
-    """Whole-row work-groups stage the x-moving populations through LDS; the
-    values are the same as direct pull reads, bit for bit."""
+@pytest.mark.parametrize("precision,streaming,q", [
+    ("fp32", "ab", 19), ("fp16", "ab", 19), ("fp32", "aa", 19), ("fp16", "aa", 19), ("bf16", "aa", 19),
+    ("fp64", "aa", 19), ("fp32", "aa", 27), ("fp64", "ab", 27)])
+def test_row_staged_step_is_bitwise_identical(precision, streaming, q, monkeypatch):
+    """Whole-row work-groups stage the x-moving populations through LDS (the
+    A-B reads; the AA odd step's reads and writes); the values are the same
+    as direct accesses, bit for bit.  An odd step count ends on an odd AA
+    step."""
     nx, ny, nz = 64, 44, 12  # 64-wide rows: one work-group per 4 rows, ragged in y
     rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=33, umax=0.05)
-    staged = gpu_run(nx, ny, nz, rho, u, 7, precision, "ab", omega=1.85, force_mode=L.LBM_FORCE_KOLMOGOROV,
-                     kolmogorov_amp=1e-4)
+    kw = dict(omega=1.85, force_mode=L.LBM_FORCE_KOLMOGOROV, kolmogorov_amp=1e-4, q=q)
+    monkeypatch.setenv("LBM_ROW_STAGING", "1")
+    staged = gpu_run(nx, ny, nz, rho, u, 7, precision, streaming, **kw)
     monkeypatch.setenv("LBM_ROW_STAGING", "0")
-    direct = gpu_run(nx, ny, nz, rho, u, 7, precision, "ab", omega=1.85, force_mode=L.LBM_FORCE_KOLMOGOROV,
-                     kolmogorov_amp=1e-4)
+    direct = gpu_run(nx, ny, nz, rho, u, 7, precision, streaming, **kw)
     assert np.array_equal(staged["f"], direct["f"])
 
 
