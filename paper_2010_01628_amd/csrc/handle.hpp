@@ -35,7 +35,7 @@ struct lbm_handle {
     double* diag_host = nullptr;
     dim3 grid, block;
     dim3 step_grid, step_block;        // launch shape of the plain step kernel (tunable)
-    int row_stage_pref = -1;           // -1: default rule (4/8-byte storage), 0/1: tuner's choice
+    int row_stage_pref = -1;           // -1: default (staged wherever possible), 0/1: tuner's choice
     bool walls = false, general = false, nt = true;
     int64_t bytes = 0;
     int nblocks = 0;

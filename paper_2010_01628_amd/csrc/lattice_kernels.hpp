@@ -388,12 +388,14 @@ template <class L> __host__ __device__ constexpr int moving_x_count()
     return k;
 }
 
-template <class L, class S, bool GENERAL, bool NT, bool O32>
-__global__ __launch_bounds__(256) void k_step_ab_rows(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
+// W: the widest row a work-group may span (256, or 512 for rows of 257..512
+// nodes with one 512-thread work-group per row).
+template <class L, class S, bool GENERAL, bool NT, bool O32, int W = 256>
+__global__ __launch_bounds__(W) void k_step_ab_rows(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
 {
     using R = typename Codec<S>::R;
     constexpr int QX = moving_x_count<L>();
-    __shared__ S rows[QX][256];
+    __shared__ S rows[QX][W];
     int bxi, byi, z;
     block_coords(g, g.xcd_chunk, bxi, byi, z);
     const int x = threadIdx.x; // bxi == 0: one work-group spans the row
@@ -452,12 +454,12 @@ __global__ __launch_bounds__(256) void k_step_aa(S* buf, Geom g, Phys ph)
 // In place and race free as the plain kernel: location (i, m) is read only
 // by node m - c_i, which lies in the same x row, and a thread stores only
 // elements it loaded itself earlier.  Same values as k_step_aa, bit for bit.
-template <class L, class S, bool GENERAL, bool NT, bool O32>
-__global__ __launch_bounds__(256) void k_step_aa_odd_rows(S* __restrict__ buf, Geom g, Phys ph)
+template <class L, class S, bool GENERAL, bool NT, bool O32, int W = 256>
+__global__ __launch_bounds__(W) void k_step_aa_odd_rows(S* __restrict__ buf, Geom g, Phys ph)
 {
     using R = typename Codec<S>::R;
     constexpr int QX = moving_x_count<L>();
-    __shared__ S rows[QX][256];
+    __shared__ S rows[QX][W];
     int bxi, byi, z;
     block_coords(g, g.xcd_chunk, bxi, byi, z);
     const int x = threadIdx.x; // bxi == 0: one work-group spans the row
@@ -700,16 +702,31 @@ template <class L, class S> struct Launch {
     {
         // D3Q27 has fixed rates: no general-rate variant
         if (L::Q == 27) general = false;
+        // 512-wide work-groups (one per row of 257..512 nodes) exist only for
+        // the staged kernels; every other step kernel of such a launch (the AA
+        // even step, and any kernel whose staging rows would not fit in 64 KB
+        // of LDS) runs on 256-wide work-groups over the same rows
+        const bool wide = block.x > 256;
+        constexpr bool wide_fits = moving_x_count<L>() * 512 * sizeof(S) <= 65536;
+        const dim3 block256(wide ? 256 : block.x, wide ? 1 : block.y, 1);
+        const dim3 grid256(wide ? (g.nx + 255) / 256 : grid.x, wide ? g.ny : grid.y, grid.z);
 #define LBM_STEP_O(P, W, G, O)                                                                                      \
     do {                                                                                                            \
         if constexpr (P == AB && !W) {                                                                              \
-            if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
+            if (g.row_stage && wide) {                                                                              \
+                if constexpr (wide_fits) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O, 512>), grid, block, 0, st, a, b, g, ph); \
+                else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid256, block256, 0, st, a, b, g, ph);     \
+            } else if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
             else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph);              \
         } else if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
         else if constexpr (P == AA_ODD && !W) {                                                                     \
-            if (g.row_stage) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O>), grid, block, 0, st, b, g, ph); \
+            if (g.row_stage && wide) {                                                                              \
+                if constexpr (wide_fits) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O, 512>), grid, block, 0, st, b, g, ph); \
+                else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph);     \
+            } else if (g.row_stage) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O>), grid, block, 0, st, b, g, ph); \
             else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);               \
-        } else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);                 \
+        } else if (wide) hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph); \
+        else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);                   \
     } while (0)
 #define LBM_STEP(P, W, G)                        \
     do {                                         \

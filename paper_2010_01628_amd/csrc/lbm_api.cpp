@@ -138,9 +138,10 @@ void default_block(const lbm_params* p, int& bx, int& by)
 
 // Row staging of the x-moving populations through LDS: possible for a
 // periodic lattice with work-groups spanning whole rows, in the A-B step and
-// the AA odd step (the AA even step is local).  By default on for 4- and
-// 8-byte storage and off for 16-bit storage (A-B measured at 256^3 before
-// the scalar-base addressing: FP32 +4.6 %, FP64 +4.2 %, FP16 -9 %); the
+// the AA odd step (the AA even step is local).  On by default wherever it is
+// possible: with the scalar-base addressing it is the tuner's choice at 256^3
+// for every storage type, A-B and AA, and it keeps HBM traffic at the
+// algorithmic bytes (direct x-shifted accesses fetched 16-38 % more); the
 // tuner may choose either; LBM_ROW_STAGING=0 turns it off, =1 on wherever it
 // is possible (both override the default and the tuner).
 void set_row_stage(lbm_handle* h)
@@ -148,9 +149,25 @@ void set_row_stage(lbm_handle* h)
     const char* env = std::getenv("LBM_ROW_STAGING");
     const bool allowed = !(env && env[0] == '0') && (h->p.streaming == LBM_AB || h->p.streaming == LBM_AA) &&
                          !h->walls && (int)h->step_block.x == h->g.nx;
-    const bool want = (env && env[0] == '1') ||
-                      (h->row_stage_pref >= 0 ? h->row_stage_pref == 1 : elem_bytes(h->p.precision) >= 4);
+    const bool want = (env && env[0] == '1') || h->row_stage_pref < 0 || h->row_stage_pref == 1;
     h->g.row_stage = allowed && want;
+    // a 512-wide step work-group exists only for the staged kernels: without
+    // staging the step falls back to 256-wide work-groups over the rows
+    if (h->step_block.x > 256 && !h->g.row_stage) {
+        h->step_block = dim3(256, 1, 1);
+        h->step_grid = dim3((h->g.nx + 255) / 256, h->g.ny, h->g.nz);
+    }
+}
+
+// Can one 512-thread work-group span each row (257..512 nodes) with staging?
+// Periodic A-B / AA, the 3-D grid (no XCD remap), and the staged rows of the
+// x-moving populations within 64 KB of LDS.
+bool wide_rows_possible(const lbm_handle* h)
+{
+    const int qx = h->p.q == 27 ? 18 : 10;
+    return h->g.nx > 256 && h->g.nx <= 512 && !h->walls && h->g.xcd_chunk == 1 &&
+           (h->p.streaming == LBM_AB || h->p.streaming == LBM_AA) &&
+           (int64_t)qx * 512 * elem_bytes(h->p.precision) <= 65536;
 }
 
 int64_t pad_stride(int64_t N, int eb)
@@ -226,9 +243,9 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
         h->g.off32 = h->g.stride * eb < ((int64_t)1 << 32) && !(env && env[0] == '0');
     }
     h->walls = p->walls_y != 0;
-    // default: streaming hints for A-B with 4- and 8-byte storage, ordinary
-    // accesses for AA (in place) and 16-bit storage -- the faster choice of
-    // each pair measured at 256^3
+    // default: streaming hints for A-B with 4- and 8-byte storage and for
+    // every staged step (set below), ordinary accesses otherwise -- the
+    // tuner's choices at 256^3
     if (p->cache_policy == 0)
         h->nt = p->streaming == LBM_AB && eb >= 4;
     else
@@ -263,6 +280,17 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
         h->step_grid = remap ? dim3(h->nblocks, 1, 1) : h->grid;
         h->step_block = h->block;
         set_row_stage(h);
+        // rows of 257..512 nodes: one 512-thread work-group per row, staged
+        // (unless LBM_ROW_STAGING=0)
+        if (!remap && wide_rows_possible(h)) {
+            const char* rs = std::getenv("LBM_ROW_STAGING");
+            if (!(rs && rs[0] == '0')) {
+                h->step_block = dim3(h->g.nx, 1, 1);
+                h->step_grid = dim3(1, h->g.ny, h->g.nz);
+                set_row_stage(h);
+            }
+        }
+        if (p->cache_policy == 0 && h->g.row_stage) h->nt = true;
     }
 
     const int64_t pop_bytes = (int64_t)p->q * h->g.stride * eb;
@@ -521,8 +549,9 @@ int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* bloc
     }
     if (!cached) {
         const int steps = trial_steps + (trial_steps & 1);
-        const int shapes[][2] = {{256, 1}, {128, 2}, {64, 4}, {128, 1}, {64, 2}, {64, 1}};
+        const int shapes[][2] = {{512, 1}, {256, 1}, {128, 2}, {64, 4}, {128, 1}, {64, 2}, {64, 1}};
         const int nx2 = next_pow2(h->g.nx), ny2 = next_pow2(h->g.ny);
+        const bool wide_ok = wide_rows_possible(h);
         struct Cand {
             int bx, by, nt, rs;
             float ms;
@@ -531,8 +560,11 @@ int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* bloc
         for (const auto& sh : shapes) {
             // skip shapes that would leave most of a work-group idle
             if ((sh[0] > 64 && sh[0] > nx2) || (sh[1] > 1 && sh[1] > ny2)) continue;
+            // one 512-wide work-group per row: only staged, only where it spans the row
+            if (sh[0] > 256 && (!wide_ok || sh[0] != h->g.nx)) continue;
             for (int c = 0; c < 4; ++c) {
                 const int nt = c & 1 ? 0 : 1, rs = c >> 1 ? 0 : 1;
+                if (sh[0] > 256 && rs == 0) continue;
                 apply_launch(h, sh[0], sh[1], nt != 0, rs);
                 if (rs == 1 && !h->g.row_stage) continue; // staging not possible with this shape
                 cands.push_back({sh[0], sh[1], nt, h->g.row_stage ? 1 : 0, 1e30f});

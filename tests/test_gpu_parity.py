@@ -275,6 +275,25 @@ def test_row_staged_step_is_bitwise_identical(precision, streaming, q, monkeypat
     assert np.array_equal(staged["f"], direct["f"])
 
 
+@pytest.mark.parametrize("nx", [320, 512])
+@pytest.mark.parametrize("precision,streaming,q", [
+    ("fp32", "ab", 19), ("fp32", "aa", 19), ("fp16", "ab", 19), ("fp16", "aa", 19), ("fp64", "aa", 19),
+    ("fp32", "aa", 27)])
+def test_wide_row_staged_step_is_bitwise_identical(nx, precision, streaming, q, monkeypatch):
+    """Rows of 257..512 nodes: one 512-thread work-group per row stages the
+    x-moving populations (the AA even step runs on 256-wide work-groups of
+    the same launch); the values equal those of 256-wide work-groups with
+    direct accesses, bit for bit.  An odd step count ends on an odd AA step."""
+    ny, nz = 6, 5
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=35, umax=0.05)
+    kw = dict(omega=1.8, force_mode=L.LBM_FORCE_KOLMOGOROV, kolmogorov_amp=1e-4, q=q)
+    monkeypatch.setenv("LBM_ROW_STAGING", "1")
+    staged = gpu_run(nx, ny, nz, rho, u, 5, precision, streaming, **kw)
+    monkeypatch.setenv("LBM_ROW_STAGING", "0")
+    direct = gpu_run(nx, ny, nz, rho, u, 5, precision, streaming, **kw)
+    assert np.array_equal(staged["f"], direct["f"])
+
+
 @pytest.mark.parametrize("precision,streaming,walls,q", [
     ("fp32", "ab", False, 19), ("fp16", "aa", True, 19), ("fp64", "ab", True, 19), ("bf16", "ab", True, 19),
     ("fp32", "aa", False, 19), ("fp32", "ab", True, 27), ("fp64", "aa", True, 27)])
