@@ -16,21 +16,22 @@
 
 namespace lbm {
 
-template <class S> __device__ inline void gather7(const S* __restrict__ buf, int64_t stride, const NodeIdx& d,
-                                                   typename Codec<S>::R h[7])
+template <class S, bool O32 = false>
+__device__ inline void gather7(const S* __restrict__ buf, int64_t stride, const NodeIdx& d, typename Codec<S>::R h[7])
 {
 #pragma unroll
-    for (int i = 0; i < 7; ++i) h[i] = Codec<S>::dec(buf[(int64_t)i * stride + nb(d, -cx7(i), -cy7(i), -cz7(i))]);
+    for (int i = 0; i < 7; ++i)
+        h[i] = Codec<S>::dec(*pop_at<S, O32, true>(buf, stride, i, nb(d, -cx7(i), -cy7(i), -cz7(i))));
 }
 
-template <class S, bool NT> __device__ inline void store7(S* __restrict__ buf, int64_t stride, int n,
-                                                          const typename Codec<S>::R h[7])
+template <class S, bool NT, bool O32 = false>
+__device__ inline void store7(S* __restrict__ buf, int64_t stride, int n, const typename Codec<S>::R h[7])
 {
 #pragma unroll
-    for (int i = 0; i < 7; ++i) st<S, NT>(buf + (int64_t)i * stride + n, Codec<S>::enc(h[i]));
+    for (int i = 0; i < 7; ++i) st<S, NT>(pop_at<S, O32, true>(buf, stride, i, n), Codec<S>::enc(h[i]));
 }
 
-template <class S>
+template <class S, bool O32>
 __global__ __launch_bounds__(256) void k_phase_sum(const S* __restrict__ hsrc, typename Codec<S>::R* __restrict__ phi,
                                                   Geom g)
 {
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(256) void k_phase_sum(const S* __restrict__ hsrc, t
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R h[7];
-    gather7<S>(hsrc, g.stride, d, h);
+    gather7<S, O32>(hsrc, g.stride, d, h);
     R s = h[0];
 #pragma unroll
     for (int i = 1; i < 7; ++i) s += h[i];
@@ -53,7 +54,7 @@ template <class R> __device__ inline void phi_stencil(const R* __restrict__ phi,
     for (int i = 0; i < 19; ++i) phin[i] = phi[nb(d, cx19(i), cy19(i), cz19(i))];
 }
 
-template <class S, bool NT>
+template <class S, bool NT, bool O32>
 __global__ __launch_bounds__(256) void k_phase_step(const S* __restrict__ gsrc, S* __restrict__ gdst,
                                                    const S* __restrict__ hsrc, S* __restrict__ hdst,
                                                    const typename Codec<S>::R* __restrict__ phi, Geom g, PhaseConst pc)
@@ -67,18 +68,18 @@ __global__ __launch_bounds__(256) void k_phase_step(const S* __restrict__ gsrc, 
     R phin[19];
     phi_stencil(phi, d, phin);
     R s[19];
-    gather<LatD3Q19, S, AB, false, NT>(gsrc, g.stride, d, s);
+    gather<LatD3Q19, S, AB, false, NT, O32>(gsrc, g.stride, d, s);
     RawMoments<R> m;
     raw_from_pops(s, m);
     PhaseMacro<R> o;
     R gx, gy, gz;
     phase_macro(m, phin, pc, o, gx, gy, gz);
     phase_collide_g(s, m, o, (R)pc.omega);
-    scatter<LatD3Q19, S, AB, false, NT>(gdst, g.stride, d, s);
+    scatter<LatD3Q19, S, AB, false, NT, O32>(gdst, g.stride, d, s);
     R h[7];
-    gather7<S>(hsrc, g.stride, d, h);
+    gather7<S, O32>(hsrc, g.stride, d, h);
     phase_collide_h(h, phin[0], gx, gy, gz, o.ux, o.uy, o.uz, pc);
-    store7<S, NT>(hdst, g.stride, n, h);
+    store7<S, NT, O32>(hdst, g.stride, n, h);
 }
 
 // Equilibrium of the initial fields, written where the first step pulls it:
@@ -197,25 +198,29 @@ __global__ __launch_bounds__(256) void k_phase_set_h(S* __restrict__ hbuf, Geom 
 }
 
 // ---------------------------------------------------------------------------
+template <class S, bool O32>
+static void phase_step_o(bool nt, const void* gsrc, void* gdst, const void* hsrc, void* hdst, void* phi, const Geom& g,
+                         const PhaseConst& pc, dim3 grid, dim3 block, hipStream_t st)
+{
+    using R = typename Codec<S>::R;
+    hipLaunchKernelGGL((k_phase_sum<S, O32>), grid, block, 0, st, (const S*)hsrc, (R*)phi, g);
+    if (nt)
+        hipLaunchKernelGGL((k_phase_step<S, true, O32>), grid, block, 0, st, (const S*)gsrc, (S*)gdst, (const S*)hsrc,
+                           (S*)hdst, (const R*)phi, g, pc);
+    else
+        hipLaunchKernelGGL((k_phase_step<S, false, O32>), grid, block, 0, st, (const S*)gsrc, (S*)gdst, (const S*)hsrc,
+                           (S*)hdst, (const R*)phi, g, pc);
+}
+
 void launch_phase_step(int precision, bool nt, const void* gsrc, void* gdst, const void* hsrc, void* hdst, void* phi,
                        const Geom& g, const PhaseConst& pc, dim3 grid, dim3 block, hipStream_t st)
 {
     if (precision == PREC_FP64) {
-        hipLaunchKernelGGL(k_phase_sum<double>, grid, block, 0, st, (const double*)hsrc, (double*)phi, g);
-        if (nt)
-            hipLaunchKernelGGL((k_phase_step<double, true>), grid, block, 0, st, (const double*)gsrc, (double*)gdst,
-                               (const double*)hsrc, (double*)hdst, (const double*)phi, g, pc);
-        else
-            hipLaunchKernelGGL((k_phase_step<double, false>), grid, block, 0, st, (const double*)gsrc, (double*)gdst,
-                               (const double*)hsrc, (double*)hdst, (const double*)phi, g, pc);
+        if (g.off32) phase_step_o<double, true>(nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, st);
+        else phase_step_o<double, false>(nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, st);
     } else {
-        hipLaunchKernelGGL(k_phase_sum<float>, grid, block, 0, st, (const float*)hsrc, (float*)phi, g);
-        if (nt)
-            hipLaunchKernelGGL((k_phase_step<float, true>), grid, block, 0, st, (const float*)gsrc, (float*)gdst,
-                               (const float*)hsrc, (float*)hdst, (const float*)phi, g, pc);
-        else
-            hipLaunchKernelGGL((k_phase_step<float, false>), grid, block, 0, st, (const float*)gsrc, (float*)gdst,
-                               (const float*)hsrc, (float*)hdst, (const float*)phi, g, pc);
+        if (g.off32) phase_step_o<float, true>(nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, st);
+        else phase_step_o<float, false>(nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, st);
     }
 }
 
@@ -233,11 +238,11 @@ void launch_phase_fields(int precision, const void* gsrc, const void* hsrc, void
                          double* partials, dim3 grid, dim3 block, hipStream_t st)
 {
     if (precision == PREC_FP64) {
-        hipLaunchKernelGGL(k_phase_sum<double>, grid, block, 0, st, (const double*)hsrc, (double*)phi, g);
+        hipLaunchKernelGGL((k_phase_sum<double, false>), grid, block, 0, st, (const double*)hsrc, (double*)phi, g);
         hipLaunchKernelGGL(k_phase_fields<double>, grid, block, 0, st, (const double*)gsrc, (const double*)phi, g, pc,
                            phi_out, p_out, rho_out, u_out, partials);
     } else {
-        hipLaunchKernelGGL(k_phase_sum<float>, grid, block, 0, st, (const float*)hsrc, (float*)phi, g);
+        hipLaunchKernelGGL((k_phase_sum<float, false>), grid, block, 0, st, (const float*)hsrc, (float*)phi, g);
         hipLaunchKernelGGL(k_phase_fields<float>, grid, block, 0, st, (const float*)gsrc, (const float*)phi, g, pc,
                            phi_out, p_out, rho_out, u_out, partials);
     }
