@@ -271,7 +271,8 @@ int lbm_set_coupled_populations(lbm_handle *h, const double *in, int on_device);
 
 /* Autotuner of the plain step kernel: runs 2 + trial_steps (rounded up to
  * even) real steps, three times in interleaved rounds, for each work-group
- * shape 256x1, 128x2, 64x4, 128x1, 64x2, 64x1 (those that fit the lattice)
+ * shape 256x1, 128x2, 64x4, 128x1, 64x2, 64x1 (those that fit the lattice;
+ * for rows of 257..512 nodes also nx x 1, staged only)
  * with and without non-temporal hints and, where a work-group spans whole x
  * rows (periodic; A-B, or the odd step of AA), with and without staging the
  * x-moving populations through LDS; keeps the fastest (by each candidate's best round) for later

@@ -560,14 +560,15 @@ int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* bloc
         for (const auto& sh : shapes) {
             // skip shapes that would leave most of a work-group idle
             if ((sh[0] > 64 && sh[0] > nx2) || (sh[1] > 1 && sh[1] > ny2)) continue;
-            // one 512-wide work-group per row: only staged, only where it spans the row
-            if (sh[0] > 256 && (!wide_ok || sh[0] != h->g.nx)) continue;
+            // the wide entry: one work-group of nx threads per row (257..512), staged only
+            if (sh[0] > 256 && !wide_ok) continue;
+            const int bx = sh[0] > 256 ? h->g.nx : sh[0];
             for (int c = 0; c < 4; ++c) {
                 const int nt = c & 1 ? 0 : 1, rs = c >> 1 ? 0 : 1;
-                if (sh[0] > 256 && rs == 0) continue;
-                apply_launch(h, sh[0], sh[1], nt != 0, rs);
+                if (bx > 256 && rs == 0) continue;
+                apply_launch(h, bx, sh[1], nt != 0, rs);
                 if (rs == 1 && !h->g.row_stage) continue; // staging not possible with this shape
-                cands.push_back({sh[0], sh[1], nt, h->g.row_stage ? 1 : 0, 1e30f});
+                cands.push_back({bx, sh[1], nt, h->g.row_stage ? 1 : 0, 1e30f});
             }
         }
         hipEvent_t a, b;

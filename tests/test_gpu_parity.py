@@ -213,6 +213,40 @@ def test_stable_run_passes_checks():
     lat.close()
 
 
+@pytest.mark.parametrize("nx,streaming,precision", [(320, "ab", "fp32"), (320, "aa", "fp16"), (300, "aa", "fp64")])
+def test_tuned_wide_rows_are_bitwise_identical(nx, streaming, precision):
+    """Rows of 257..512 nodes: the tuner also tries one staged work-group of
+    nx threads per row; whatever it keeps, the tuned lattice equals one with
+    256-wide direct work-groups after the same steps, bit for bit."""
+    import os
+
+    ny, nz = 8, 6
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=36, umax=0.05)
+
+    def make():
+        p = L.make_params(nx, ny, nz, precision=precision, streaming=streaming, omega=1.8,
+                          force_mode=L.LBM_FORCE_KOLMOGOROV, kolmogorov_amp=1e-4)
+        lat = L.Lattice(p)
+        lat.init(rho, u)
+        return lat
+
+    a = make()
+    cfg = a.tune(2)
+    taken = a.step_count
+    say(f"  tuned nx={nx} {streaming} {precision}: block {cfg[0]}x{cfg[1]}, cache policy {cfg[2]}, staged {cfg[3]}")
+    assert cfg[0] in (64, 128, 256, nx) and (cfg[0] <= 256 or cfg[3] == 1)
+    a.step(5)
+    os.environ["LBM_ROW_STAGING"] = "0"
+    try:
+        b = make()
+    finally:
+        del os.environ["LBM_ROW_STAGING"]
+    b.step(taken + 5)
+    assert np.array_equal(a.get_populations().cpu().numpy(), b.get_populations().cpu().numpy())
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("streaming", ["ab", "aa"])
 def test_tuned_launch_is_bitwise_identical(streaming):
     """The autotuner only changes the work-group shape and cache hints: a tuned
