@@ -171,9 +171,15 @@ typedef struct {
                                  y = ny - 1 (halfway bounce-back) */
     int32_t check_every;      /* > 0: every that many steps lbm_step checks that the density
                                  is finite and positive everywhere (FP64 reduction) */
-    int32_t block_x, block_y; /* work-group shape of the step kernels; 0 = library default */
-    int32_t cache_policy;     /* population loads/stores: 0 = library default, 1 = non-temporal
-                                 (streaming) hints, 2 = ordinary cached accesses */
+    int32_t block_x, block_y; /* work-group shape of the step kernels (product a multiple of 64,
+                                 at most 256); 0 = library default: whole x rows of up to 256
+                                 nodes per work-group, one work-group of nx threads per row
+                                 of 257..512 nodes, the x-moving populations staged through
+                                 LDS on periodic lattices */
+    int32_t cache_policy;     /* population loads/stores: 0 = library default (non-temporal
+                                 for staged steps and for A-B with 4- and 8-byte storage,
+                                 cached otherwise), 1 = non-temporal (streaming) hints,
+                                 2 = ordinary cached accesses */
     int32_t coupled;          /* lbm_coupling */
     lbm_phase_params phase;   /* LBM_COUPLED_PHASE: q = 19, FP64 or FP32, A-B, periodic, no
                                  external force, the paper's bulk and higher-order rates,
@@ -194,6 +200,21 @@ typedef struct {
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
+
+/* Environment variables read by lbm_create (testing and measurement; none is
+ * needed in normal use):
+ *   LBM_OFF32=0         64-bit population addresses even where every array is
+ *                       below 4 GiB (the path of larger lattices);
+ *   LBM_ROW_STAGING=0/1 no staging of the x-moving populations / staging
+ *                       wherever it is possible, overriding the default and
+ *                       lbm_tune;
+ *   LBM_XCD_CHUNK=c     a 1-D step grid in which each XCD sweeps runs of c
+ *                       consecutive rows;
+ *   LBM_COUPLED_FLAT=0  the 3-D grid of row work-groups instead of the flat
+ *                       1-D grid for the two-phase, Shan-Chen and
+ *                       colour-gradient step kernels.
+ * None of them changes results: every path is tested bit for bit against the
+ * default one. */
 
 /* Fill *p with defaults: 32^3, q = 19, FP32, A-B, omega = 1, all other rates
  * 1, rho0 = 1, no force, periodic, no checks. */

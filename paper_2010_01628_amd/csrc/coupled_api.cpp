@@ -184,7 +184,8 @@ void coupled_destroy(lbm_handle* h)
     h->cp = nullptr;
 }
 
-// Launch shape of the two-phase and Shan-Chen step kernels: a 1-D grid of
+// Launch shape of the two-phase, Shan-Chen and colour-gradient step kernels
+// (not the magnetic lattice, which keeps the 3-D grid): a 1-D grid of
 // 256-wide work-groups over all nodes, so that no lane idles when nx is not a
 // multiple of the work-group width (192^3: a quarter of a 256-wide row
 // block, 100^3: 28 % of a 128-wide one); LBM_COUPLED_FLAT=0 keeps the 3-D

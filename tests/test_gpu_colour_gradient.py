@@ -94,6 +94,17 @@ def test_64bit_addressing_is_bitwise_identical(walls, monkeypatch):
     assert np.array_equal(a["fr"], b["fr"]) and np.array_equal(a["fb"], b["fb"])
 
 
+def test_flat_and_3d_grids_are_bitwise_identical(monkeypatch):
+    """Flat 1-D grid (default) and 3-D grid (LBM_COUPLED_FLAT=0) of the
+    colour-gradient step: same red and blue populations, bit for bit."""
+    shape = (14, 10, 7)
+    rr, rb, u = mixture(shape, 13)
+    a = gpu_cg(shape, rr, rb, u, 6, "fp32", 1.6, True, colour_kw())
+    monkeypatch.setenv("LBM_COUPLED_FLAT", "0")
+    b = gpu_cg(shape, rr, rb, u, 6, "fp32", 1.6, True, colour_kw())
+    assert np.array_equal(a["fr"], b["fr"]) and np.array_equal(a["fb"], b["fb"])
+
+
 def test_fp32_matches_oracle(orc):
     shape, steps = (20, 24, 16), 60
     rr, rb, u = mixture(shape, 3)

@@ -49,6 +49,19 @@ def gpu_phase(shape, prm, phi, p, u, steps, precision="fp64"):
 PRMS = [(1.0, 10.0, 5e-3, 4.0, 0.1, 1.25), (1.0, 3.0, 1e-2, 4.0, 0.02, 1.8)]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_flat_and_3d_grids_are_bitwise_identical(precision, monkeypatch):
+    """The coupled step runs on a flat 1-D grid over all nodes by default and
+    on the 3-D grid of row work-groups with LBM_COUPLED_FLAT=0: same values,
+    bit for bit (ragged shape)."""
+    shape = (17, 9, 5)
+    phi, p, u = case(shape, 21)
+    a = gpu_phase(shape, PRMS[0], phi, p, u, 6, precision)
+    monkeypatch.setenv("LBM_COUPLED_FLAT", "0")
+    b = gpu_phase(shape, PRMS[0], phi, p, u, 6, precision)
+    assert np.array_equal(a["g"], b["g"]) and np.array_equal(a["h"], b["h"])
+
+
 @pytest.mark.parametrize("prm", PRMS)
 @pytest.mark.parametrize("shape,steps", [((16, 12, 10), 1), ((17, 9, 5), 10)])
 def test_fp64_matches_oracle(orc, prm, shape, steps):
