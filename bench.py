@@ -303,7 +303,7 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--streaming", default="ab", choices=["ab", "aa"])
     ap.add_argument("--variants",
-                    default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,fp64:ab,fp32+mlp:ab,fp16+mlp:ab,fp32+raw:ab,fp16+raw:ab",
+                    default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,bf16:aa,fp64:ab,fp32+mlp:ab,fp16+mlp:ab,fp32+raw:ab,fp16+raw:ab",
                     help="extra precision[+mlp|+raw]:streaming pairs to time ('' = none); +mlp = learned "
                          "rates, +raw = raw-moment collision (the N = I variant)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble workload")
