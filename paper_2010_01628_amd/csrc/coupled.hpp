@@ -27,8 +27,12 @@ struct CgConst {
 
 // One step of the two-phase lattice: phi = sum h into `phi`, then the fused
 // flow + phase collide-stream from (gsrc, hsrc) into (gdst, hdst).
+// grid/block: k_phase_sum and, when rblock.x == 0, k_phase_step on geometry g;
+// rblock.x > 0: k_phase_step_rows on gr with rgrid/rblock (whole x rows of
+// nx <= 256 nodes, periodic)
 void launch_phase_step(int precision, bool nt, const void* gsrc, void* gdst, const void* hsrc, void* hdst, void* phi,
-                       const Geom& g, const PhaseConst& pc, dim3 grid, dim3 block, hipStream_t st);
+                       const Geom& g, const PhaseConst& pc, dim3 grid, dim3 block, const Geom& gr, dim3 rgrid,
+                       dim3 rblock, hipStream_t st);
 void launch_phase_init(int precision, void* gbuf, void* hbuf, const Geom& g, const PhaseConst& pc, const double* phi,
                        const double* p, const double* u, dim3 grid, dim3 block, hipStream_t st);
 // phi (scratch, refreshed from hsrc), then macroscopic fields and partials.

@@ -82,6 +82,75 @@ __global__ __launch_bounds__(256) void k_phase_step(const S* __restrict__ gsrc, 
     store7<S, NT, O32>(hdst, g.stride, n, h);
 }
 
+// k_phase_step with work-groups of whole x rows (blockDim.x == nx <= 256,
+// periodic): the x-moving populations of both lattices (10 flow, 2 phase)
+// are read as aligned source rows into LDS, each element once, and node x
+// takes element x - c_x there, as in the plain staged step.  Same values as
+// k_phase_step, bit for bit.
+template <class S, bool NT, bool O32>
+__global__ __launch_bounds__(256) void k_phase_step_rows(const S* __restrict__ gsrc, S* __restrict__ gdst,
+                                                        const S* __restrict__ hsrc, S* __restrict__ hdst,
+                                                        const typename Codec<S>::R* __restrict__ phi, Geom g,
+                                                        PhaseConst pc)
+{
+    using R = typename Codec<S>::R;
+    constexpr int QX = moving_x_count<LatD3Q19>();
+    __shared__ S rows[QX + 2][256];
+    const int x = threadIdx.x;
+    const int yr = blockIdx.y * blockDim.y + threadIdx.y;
+    const bool valid = yr < g.ny;
+    const int y = valid ? yr : g.ny - 1;
+    const int z = blockIdx.z;
+    NodeIdx d;
+    node_idx(g, x, y, z, d);
+    const int row0 = threadIdx.y * blockDim.x;
+    {
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i)
+            if (cx19(i) != 0) {
+                rows[k][row0 + x] = ld<S, NT>(pop_at<S, O32, true>(gsrc, g.stride, i, nb(d, 0, -cy19(i), -cz19(i))));
+                ++k;
+            }
+        rows[QX][row0 + x] = *pop_at<S, O32, true>(hsrc, g.stride, 1, nb(d, 0, 0, 0));     // -x population
+        rows[QX + 1][row0 + x] = *pop_at<S, O32, true>(hsrc, g.stride, 4, nb(d, 0, 0, 0)); // +x population
+    }
+    __syncthreads();
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int n = nb(d, 0, 0, 0);
+    R phin[19];
+    phi_stencil(phi, d, phin);
+    R s[19];
+    {
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            if (cx19(i) != 0) {
+                s[i] = Codec<S>::dec(rows[k][row0 + (cx19(i) > 0 ? xm : xp)]);
+                ++k;
+            } else {
+                s[i] = Codec<S>::dec(ld<S, NT>(pop_at<S, O32, true>(gsrc, g.stride, i, nb(d, 0, -cy19(i), -cz19(i)))));
+            }
+        }
+    }
+    RawMoments<R> m;
+    raw_from_pops(s, m);
+    PhaseMacro<R> o;
+    R gx, gy, gz;
+    phase_macro(m, phin, pc, o, gx, gy, gz);
+    phase_collide_g(s, m, o, (R)pc.omega);
+    if (valid) scatter<LatD3Q19, S, AB, false, NT, O32>(gdst, g.stride, d, s);
+    R h[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        if (i == 1) h[i] = Codec<S>::dec(rows[QX][row0 + xp]);          // pulled from x + 1
+        else if (i == 4) h[i] = Codec<S>::dec(rows[QX + 1][row0 + xm]); // pulled from x - 1
+        else h[i] = Codec<S>::dec(*pop_at<S, O32, true>(hsrc, g.stride, i, nb(d, -cx7(i), -cy7(i), -cz7(i))));
+    }
+    phase_collide_h(h, phin[0], gx, gy, gz, o.ux, o.uy, o.uz, pc);
+    if (valid) store7<S, NT, O32>(hdst, g.stride, n, h);
+}
+
 // Equilibrium of the initial fields, written where the first step pulls it:
 // flow population i of node x at x - c_i, phase population likewise.
 template <class S>
@@ -200,28 +269,39 @@ __global__ __launch_bounds__(256) void k_phase_set_h(S* __restrict__ hbuf, Geom 
 // ---------------------------------------------------------------------------
 template <class S, bool O32>
 static void phase_step_o(bool nt, const void* gsrc, void* gdst, const void* hsrc, void* hdst, void* phi, const Geom& g,
-                         const PhaseConst& pc, dim3 grid, dim3 block, hipStream_t st)
+                         const PhaseConst& pc, dim3 grid, dim3 block, const Geom& gr, dim3 rgrid, dim3 rblock,
+                         hipStream_t st)
 {
     using R = typename Codec<S>::R;
     hipLaunchKernelGGL((k_phase_sum<S, O32>), grid, block, 0, st, (const S*)hsrc, (R*)phi, g);
-    if (nt)
-        hipLaunchKernelGGL((k_phase_step<S, true, O32>), grid, block, 0, st, (const S*)gsrc, (S*)gdst, (const S*)hsrc,
-                           (S*)hdst, (const R*)phi, g, pc);
-    else
-        hipLaunchKernelGGL((k_phase_step<S, false, O32>), grid, block, 0, st, (const S*)gsrc, (S*)gdst, (const S*)hsrc,
-                           (S*)hdst, (const R*)phi, g, pc);
+    const bool rows = rblock.x > 0;
+#define PH_STEP(NTV)                                                                                              \
+    do {                                                                                                          \
+        if (rows)                                                                                                 \
+            hipLaunchKernelGGL((k_phase_step_rows<S, NTV, O32>), rgrid, rblock, 0, st, (const S*)gsrc, (S*)gdst,   \
+                               (const S*)hsrc, (S*)hdst, (const R*)phi, gr, pc);                                  \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_phase_step<S, NTV, O32>), grid, block, 0, st, (const S*)gsrc, (S*)gdst,          \
+                               (const S*)hsrc, (S*)hdst, (const R*)phi, g, pc);                                   \
+    } while (0)
+    if (nt) PH_STEP(true);
+    else PH_STEP(false);
+#undef PH_STEP
 }
 
 void launch_phase_step(int precision, bool nt, const void* gsrc, void* gdst, const void* hsrc, void* hdst, void* phi,
-                       const Geom& g, const PhaseConst& pc, dim3 grid, dim3 block, hipStream_t st)
+                       const Geom& g, const PhaseConst& pc, dim3 grid, dim3 block, const Geom& gr, dim3 rgrid,
+                       dim3 rblock, hipStream_t st)
 {
+#define PH_ARGS nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, gr, rgrid, rblock, st
     if (precision == PREC_FP64) {
-        if (g.off32) phase_step_o<double, true>(nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, st);
-        else phase_step_o<double, false>(nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, st);
+        if (g.off32) phase_step_o<double, true>(PH_ARGS);
+        else phase_step_o<double, false>(PH_ARGS);
     } else {
-        if (g.off32) phase_step_o<float, true>(nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, st);
-        else phase_step_o<float, false>(nt, gsrc, gdst, hsrc, hdst, phi, g, pc, grid, block, st);
+        if (g.off32) phase_step_o<float, true>(PH_ARGS);
+        else phase_step_o<float, false>(PH_ARGS);
     }
+#undef PH_ARGS
 }
 
 void launch_phase_init(int precision, void* gbuf, void* hbuf, const Geom& g, const PhaseConst& pc, const double* phi,

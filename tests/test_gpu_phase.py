@@ -49,11 +49,25 @@ def gpu_phase(shape, prm, phi, p, u, steps, precision="fp64"):
 PRMS = [(1.0, 10.0, 5e-3, 4.0, 0.1, 1.25), (1.0, 3.0, 1e-2, 4.0, 0.02, 1.8)]
 
 
+@pytest.mark.parametrize("shape,precision", [((17, 9, 5), "fp64"), ((17, 9, 5), "fp32"), ((192, 6, 4), "fp32")])
+def test_row_staged_step_is_bitwise_identical(shape, precision, monkeypatch):
+    """The two-phase step stages the x-moving flow and phase populations of
+    whole-row work-groups through LDS (rows of up to 256 nodes, several rows
+    per work-group when narrow); LBM_ROW_STAGING=0 reads them directly: same
+    values, bit for bit."""
+    phi, p, u = case(shape, 22)
+    a = gpu_phase(shape, PRMS[1], phi, p, u, 7, precision)
+    monkeypatch.setenv("LBM_ROW_STAGING", "0")
+    b = gpu_phase(shape, PRMS[1], phi, p, u, 7, precision)
+    assert np.array_equal(a["g"], b["g"]) and np.array_equal(a["h"], b["h"])
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_flat_and_3d_grids_are_bitwise_identical(precision, monkeypatch):
-    """The coupled step runs on a flat 1-D grid over all nodes by default and
-    on the 3-D grid of row work-groups with LBM_COUPLED_FLAT=0: same values,
-    bit for bit (ragged shape)."""
+    """The density launch (and, with staging off, the step) runs on a flat
+    1-D grid over all nodes by default and on the 3-D grid of row
+    work-groups with LBM_COUPLED_FLAT=0: same values, bit for bit (ragged
+    shape)."""
     shape = (17, 9, 5)
     phi, p, u = case(shape, 21)
     a = gpu_phase(shape, PRMS[0], phi, p, u, 6, precision)
