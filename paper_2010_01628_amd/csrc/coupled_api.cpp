@@ -210,6 +210,22 @@ int coupled_step(lbm_handle* h)
     lbm::Geom fg;
     dim3 fgrid, fblock;
     flat_launch(h, fg, fgrid, fblock);
+    // the two-phase step on whole-row work-groups with the x-moving
+    // populations staged through LDS (rows of up to 256 nodes, periodic);
+    // LBM_ROW_STAGING=0 keeps the density launch's grid.  (Staging the
+    // Shan-Chen step measured 2 % slower at 100^3: rows of 100 nodes leave a
+    // fifth of the lanes idle.)
+    lbm::Geom rg = h->g;
+    dim3 rgrid(0, 0, 0), rblock(0, 0, 0);
+    {
+        const char* env = std::getenv("LBM_ROW_STAGING");
+        if (h->g.nx <= 256 && !h->walls && !(env && env[0] == '0')) {
+            const int by = std::max(1, 256 / h->g.nx);
+            rg.flat = 0;
+            rblock = dim3(h->g.nx, by, 1);
+            rgrid = dim3(1, (h->g.ny + by - 1) / by, h->g.nz);
+        }
+    }
     if (h->p.coupled == LBM_COUPLED_COLOUR) {
         lbm::launch_cg_step(h->p.precision, h->walls, h->nt, h->buf[src], h->buf[dst], c->buf[src], c->buf[dst],
                             c->scratch, fg, c->cc, fgrid, fblock, h->stream);
@@ -227,20 +243,6 @@ int coupled_step(lbm_handle* h)
                              h->ph, c->mc, h->grid, h->block, h->stream);
         CHIP(hipGetLastError());
         return LBM_OK;
-    }
-    // the two-phase step on whole-row work-groups with the x-moving
-    // populations staged through LDS (rows of up to 256 nodes; the lattice is
-    // periodic); LBM_ROW_STAGING=0 keeps the launch of k_phase_sum
-    lbm::Geom rg = h->g;
-    dim3 rgrid(0, 0, 0), rblock(0, 0, 0);
-    {
-        const char* env = std::getenv("LBM_ROW_STAGING");
-        if (h->g.nx <= 256 && !(env && env[0] == '0')) {
-            const int by = std::max(1, 256 / h->g.nx);
-            rg.flat = 0;
-            rblock = dim3(h->g.nx, by, 1);
-            rgrid = dim3(1, (h->g.ny + by - 1) / by, h->g.nz);
-        }
     }
     lbm::launch_phase_step(h->p.precision, h->nt, h->buf[src], h->buf[dst], c->buf[src], c->buf[dst], c->scratch, fg,
                            c->pc, fgrid, fblock, rg, rgrid, rblock, h->stream);
