@@ -119,7 +119,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         mlp_forward_regs(*(const MlpPacked*)netg, xin, zout);
         const bool fb = mlp_rates(zout, rates);
         // recomputed rather than kept live across the network: with the tile
-        // loop's own state, keeping it would spill at four waves per SIMD
+        // loop's own state, keeping it would spill at four waves per SIMD;
+        // kept at three waves per SIMD (15 % fewer VALU instructions) the
+        // step measured the same
 #pragma unroll
         for (int i = 0; i < 19; ++i) asm volatile("" : "+v"(s[i]));
         CMState<float> st;
