@@ -319,11 +319,11 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark measures one GPU only; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         return 2
     if "RANK" in os.environ and os.environ.get("WORLD_SIZE", "1") != "1":
-        print(json.dumps({"error": "single-GPU build: launch without torch.distributed"}))
+        print(json.dumps({"error": "one-GPU benchmark: launch without torch.distributed"}))
         return 2
 
     import torch

@@ -46,7 +46,7 @@ typedef enum {
     LBM_ENOMEM = -2,       /* device allocation failed */
     LBM_EDEVICE = -3,      /* HIP runtime error */
     LBM_EUNSTABLE = -4,    /* a stability check found a non-finite or non-positive density */
-    LBM_EUNSUPPORTED = -5  /* valid request this build does not implement */
+    LBM_EUNSUPPORTED = -5  /* valid request the library does not implement */
 } lbm_status;
 
 /* Storage precision of the populations.  Collision arithmetic is FP64 for

@@ -14,7 +14,7 @@
  * adds interfacial tension; the recolouring operator splits the result
  * between the colours; each colour streams.
  *
- * Readings (each also listed in the design doc):
+ * Readings:
  *   G1  Perturbation: (A/2) |grad phi| [w_i (c_i . grad phi)^2 / |grad phi|^2
  *       - B_i], the projection squared (as printed, linear, it would not
  *       conserve mass: sum_i B_i = 1/3), applied once to the total f after

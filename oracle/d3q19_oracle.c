@@ -10,7 +10,7 @@
  * D3Q19 lattice Boltzmann methods based on central moments" (arXiv
  * 2010.01628).  Every function names the section/equation it follows.
  *
- * Readings of the paper taken here (each one is also listed in the design doc):
+ * Readings of the paper taken here:
  *   R1  Last row of the CM basis T (eq. "matrix") and of M (App. C) is printed
  *       as cy^2 cy^2; it is cy^2 cz^2 (the printed numeric M row is non-zero
  *       exactly at the four populations with cy,cz both non-zero).

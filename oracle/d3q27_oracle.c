@@ -4,7 +4,7 @@
  *
  * Paper: App. D (velocity set, CM basis T = N M, population formulas of M^-1).
  * The paper does not print the D3Q27 equilibrium, K, k* or R (it defers them
- * to the authors' earlier D3Q27 work).  Readings taken here (also in the design doc):
+ * to the authors' earlier D3Q27 work).  Readings taken here:
  *   Q1  equilibrium: tensor product of the D1Q3 equilibrium per axis,
  *       phi(0,u) = 2/3 - u^2, phi(+-1,u) = (u^2 + 1/3 +- u)/2, f_eq = rho
  *       phi(cx,ux) phi(cy,uy) phi(cz,uz); its central moments are

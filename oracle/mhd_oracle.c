@@ -11,7 +11,7 @@
  * equation is taken here in the vector-valued lattice Boltzmann form of
  * P. J. Dellar, J. Comput. Phys. 179 (2002) 95, on a D3Q7 lattice.
  *
- * Readings (each also listed in the design doc):
+ * Readings:
  *   M1  Magnetic populations g_{i,a} (i in D3Q7: weights 1/4, 1/8, cs^2 = 1/4;
  *       a = x, y, z) with b_a = sum_i g_{i,a} and equilibrium
  *       g_eq_{i,a} = w_i (b_a + c_{i,c} (u_c b_a - b_c u_a) / cs^2),

@@ -6,7 +6,7 @@
  * The paper fixes the rates of the higher-order CMs k10..k18 to 1 (Sec. II.B).
  * The learned variant replaces them, per node, by the output of a small MLP;
  * the conserved (k0..k3), bulk (k4) and viscous (k5..k9) rates are untouched.
- * This part is not in the paper; the readings are (also in the design doc):
+ * This part is not in the paper; the readings are:
  *   L1  inputs (11): rho - 1, (k4 - rho)/rho, k10..k15 / rho,
  *       (k16..k18 - rho cs^4)/rho, each divided by a fixed per-feature scale;
  *       k are the pre-collision CMs T(u) f of Sec. II.B.

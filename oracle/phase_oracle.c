@@ -18,7 +18,7 @@
  *     paper's Sec. II.B (central moments, relaxation matrix K, CM forcing of
  *     App. B) applied to them.
  *
- * Readings (each also listed in the design doc):
+ * Readings:
  *   P1  Flow populations g: Pi = sum g + S0/2 is p / cs^2 (p the hydrodynamic
  *       pressure), u = (sum g c + F/2) / rho(phi), S0 = u . grad(rho) is the
  *       zeroth-moment source that turns the pressure equation into

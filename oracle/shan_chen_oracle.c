@@ -11,7 +11,7 @@
  * H. Chen, Phys. Rev. E 47, 1993), handed to the paper's D3Q19 CM collision
  * (Sec. II.B, forcing of App. B) as the force density F, on a periodic box.
  *
- * Readings (each also listed in the design doc):
+ * Readings:
  *   S1  psi and F of one step use the density of that step's populations
  *       before the collision (rho = sum_i f_i, no force shift: F depends on
  *       rho only).
