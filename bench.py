@@ -283,6 +283,18 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def kernel_label(streaming: str, launch) -> str:
+    """Name of the timed step kernel for a launch (block_x, block_y, cache
+    policy, staged) as lbm_tune reports it (None: the library default,
+    which stages wherever whole-row work-groups allow it)."""
+    staged = launch is None or bool(launch[3])
+    if streaming == "ab":
+        name = "lbm::k_step_ab_rows" if staged else "lbm::k_step_ab"
+    else:
+        name = "lbm::k_step_aa (even) + lbm::k_step_aa_odd_rows" if staged else "lbm::k_step_aa"
+    return name + " (fused gather-collide-store" + (", x-moving populations staged through LDS)" if staged else ")")
+
+
 def load_traffic(precision: str, streaming: str, size: int, launches_algo_bytes: float):
     path = os.path.join(ROOT, "profiles", f"traffic_d3q19_step_{precision}_{streaming}_{size}.json")
     if not os.path.exists(path):
@@ -412,7 +424,7 @@ def main(argv=None):
         "unit": "GB/s",
         "frac": round(head["achieved_GBs"] / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": f"lbm::k_step_{args.streaming} (fused gather-collide-store)",
+        "kernel": kernel_label(args.streaming, head["launch"]),
         "kernel_ms_avg": round(head["kernel_ms_avg"], 5),
         "algo_bytes_per_launch": head["algo_bytes_per_launch"],
         "launch": head["launch"],
