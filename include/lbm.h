@@ -174,8 +174,9 @@ typedef struct {
     int32_t block_x, block_y; /* work-group shape of the step kernels (product a multiple of 64,
                                  at most 256); 0 = library default: whole x rows of up to 256
                                  nodes per work-group, one work-group of nx threads per row
-                                 of 257..512 nodes, the x-moving populations staged through
-                                 LDS on periodic lattices */
+                                 of 257..1024 nodes (where the staging rows fit in 64 KB of
+                                 LDS), the x-moving populations staged through LDS on
+                                 periodic lattices */
     int32_t cache_policy;     /* population loads/stores: 0 = library default (non-temporal
                                  for staged steps and for A-B with 4- and 8-byte storage,
                                  cached otherwise), 1 = non-temporal (streaming) hints,
@@ -293,7 +294,7 @@ int lbm_set_coupled_populations(lbm_handle *h, const double *in, int on_device);
 /* Autotuner of the plain step kernel: runs 2 + trial_steps (rounded up to
  * even) real steps, three times in interleaved rounds, for each work-group
  * shape 256x1, 128x2, 64x4, 128x1, 64x2, 64x1 (those that fit the lattice;
- * for rows of 257..512 nodes also nx x 1, staged only)
+ * for rows of 257..1024 nodes also nx x 1, staged only)
  * with and without non-temporal hints and, where a work-group spans whole x
  * rows (periodic; A-B, or the odd step of AA), with and without staging the
  * x-moving populations through LDS; keeps the fastest (by each candidate's best round) for later

@@ -388,8 +388,8 @@ template <class L> __host__ __device__ constexpr int moving_x_count()
     return k;
 }
 
-// W: the widest row a work-group may span (256, or 512 for rows of 257..512
-// nodes with one 512-thread work-group per row).
+// W: the widest row a work-group may span (256; 512 or 1024 for rows of
+// 257..512 or 513..1024 nodes with one work-group of nx threads per row).
 template <class L, class S, bool GENERAL, bool NT, bool O32, int W = 256>
 __global__ __launch_bounds__(W) void k_step_ab_rows(const S* __restrict__ src, S* __restrict__ dst, Geom g, Phys ph)
 {
@@ -702,26 +702,34 @@ template <class L, class S> struct Launch {
     {
         // D3Q27 has fixed rates: no general-rate variant
         if (L::Q == 27) general = false;
-        // 512-wide work-groups (one per row of 257..512 nodes) exist only for
-        // the staged kernels; every other step kernel of such a launch (the AA
-        // even step, and any kernel whose staging rows would not fit in 64 KB
-        // of LDS) runs on 256-wide work-groups over the same rows
+        // wide work-groups (one per row of 257..1024 nodes; kernels for rows
+        // up to 512 or up to 1024) exist only for the staged kernels; every
+        // other step kernel of such a launch (the AA even step, and any kernel
+        // whose staging rows would not fit in 64 KB of LDS) runs on 256-wide
+        // work-groups over the same rows
         const bool wide = block.x > 256;
         constexpr bool wide_fits = moving_x_count<L>() * 512 * sizeof(S) <= 65536;
+        constexpr bool fits1024 = moving_x_count<L>() * 1024 * sizeof(S) <= 65536;
         const dim3 block256(wide ? 256 : block.x, wide ? 1 : block.y, 1);
         const dim3 grid256(wide ? (g.nx + 255) / 256 : grid.x, wide ? g.ny : grid.y, grid.z);
 #define LBM_STEP_O(P, W, G, O)                                                                                      \
     do {                                                                                                            \
         if constexpr (P == AB && !W) {                                                                              \
             if (g.row_stage && wide) {                                                                              \
-                if constexpr (wide_fits) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O, 512>), grid, block, 0, st, a, b, g, ph); \
+                if (block.x > 512) {                                                                                \
+                    if constexpr (fits1024) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O, 1024>), grid, block, 0, st, a, b, g, ph); \
+                    else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid256, block256, 0, st, a, b, g, ph); \
+                } else if constexpr (wide_fits) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O, 512>), grid, block, 0, st, a, b, g, ph); \
                 else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid256, block256, 0, st, a, b, g, ph);     \
             } else if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
             else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph);              \
         } else if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
         else if constexpr (P == AA_ODD && !W) {                                                                     \
             if (g.row_stage && wide) {                                                                              \
-                if constexpr (wide_fits) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O, 512>), grid, block, 0, st, b, g, ph); \
+                if (block.x > 512) {                                                                                \
+                    if constexpr (fits1024) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O, 1024>), grid, block, 0, st, b, g, ph); \
+                    else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph); \
+                } else if constexpr (wide_fits) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O, 512>), grid, block, 0, st, b, g, ph); \
                 else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph);     \
             } else if (g.row_stage) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O>), grid, block, 0, st, b, g, ph); \
             else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);               \

@@ -159,15 +159,17 @@ void set_row_stage(lbm_handle* h)
     }
 }
 
-// Can one 512-thread work-group span each row (257..512 nodes) with staging?
-// Periodic A-B / AA, the 3-D grid (no XCD remap), and the staged rows of the
-// x-moving populations within 64 KB of LDS.
+// Can one work-group of nx threads span each row (257..1024 nodes) with
+// staging?  Periodic A-B / AA, the 3-D grid (no XCD remap), and the staged
+// rows of the x-moving populations (kernels for rows up to 512 or up to 1024)
+// within 64 KB of LDS.
 bool wide_rows_possible(const lbm_handle* h)
 {
     const int qx = h->p.q == 27 ? 18 : 10;
-    return h->g.nx > 256 && h->g.nx <= 512 && !h->walls && h->g.xcd_chunk == 1 &&
+    const int w = h->g.nx <= 512 ? 512 : 1024;
+    return h->g.nx > 256 && h->g.nx <= 1024 && !h->walls && h->g.xcd_chunk == 1 &&
            (h->p.streaming == LBM_AB || h->p.streaming == LBM_AA) &&
-           (int64_t)qx * 512 * elem_bytes(h->p.precision) <= 65536;
+           (int64_t)qx * w * elem_bytes(h->p.precision) <= 65536;
 }
 
 int64_t pad_stride(int64_t N, int eb)
@@ -280,11 +282,16 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
         h->step_grid = remap ? dim3(h->nblocks, 1, 1) : h->grid;
         h->step_block = h->block;
         set_row_stage(h);
-        // rows of 257..512 nodes: one 512-thread work-group per row, staged
-        // (unless LBM_ROW_STAGING=0)
+        // rows of 257..1024 nodes: one work-group of nx threads per row,
+        // staged (unless LBM_ROW_STAGING=0), except A-B with 16-bit storage,
+        // where 256-wide work-groups with direct cached accesses measured
+        // faster (512 and 1024 wide rows: FP16 65.4 / 67.2 GLUPS against
+        // 57.4 / 60.2 staged); AA stages at every width
         if (!remap && wide_rows_possible(h)) {
             const char* rs = std::getenv("LBM_ROW_STAGING");
-            if (!(rs && rs[0] == '0')) {
+            const bool want = (rs && rs[0] == '1') ||
+                              (!(rs && rs[0] == '0') && (eb >= 4 || p->streaming == LBM_AA));
+            if (want) {
                 h->step_block = dim3(h->g.nx, 1, 1);
                 h->step_grid = dim3(1, h->g.ny, h->g.nz);
                 set_row_stage(h);
@@ -549,7 +556,7 @@ int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* bloc
     }
     if (!cached) {
         const int steps = trial_steps + (trial_steps & 1);
-        const int shapes[][2] = {{512, 1}, {256, 1}, {128, 2}, {64, 4}, {128, 1}, {64, 2}, {64, 1}};
+        const int shapes[][2] = {{1024, 1}, {256, 1}, {128, 2}, {64, 4}, {128, 1}, {64, 2}, {64, 1}};
         const int nx2 = next_pow2(h->g.nx), ny2 = next_pow2(h->g.ny);
         const bool wide_ok = wide_rows_possible(h);
         struct Cand {
@@ -558,10 +565,10 @@ int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* bloc
         };
         std::vector<Cand> cands;
         for (const auto& sh : shapes) {
-            // skip shapes that would leave most of a work-group idle
-            if ((sh[0] > 64 && sh[0] > nx2) || (sh[1] > 1 && sh[1] > ny2)) continue;
-            // the wide entry: one work-group of nx threads per row (257..512), staged only
+            // the wide entry: one work-group of nx threads per row (257..1024), staged only
             if (sh[0] > 256 && !wide_ok) continue;
+            // skip shapes that would leave most of a work-group idle
+            if (sh[0] <= 256 && ((sh[0] > 64 && sh[0] > nx2) || (sh[1] > 1 && sh[1] > ny2))) continue;
             const int bx = sh[0] > 256 ? h->g.nx : sh[0];
             for (int c = 0; c < 4; ++c) {
                 const int nt = c & 1 ? 0 : 1, rs = c >> 1 ? 0 : 1;

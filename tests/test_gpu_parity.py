@@ -309,15 +309,17 @@ def test_row_staged_step_is_bitwise_identical(precision, streaming, q, monkeypat
     assert np.array_equal(staged["f"], direct["f"])
 
 
-@pytest.mark.parametrize("nx", [320, 512])
+@pytest.mark.parametrize("nx", [320, 512, 768, 1024])
 @pytest.mark.parametrize("precision,streaming,q", [
     ("fp32", "ab", 19), ("fp32", "aa", 19), ("fp16", "ab", 19), ("fp16", "aa", 19), ("fp64", "aa", 19),
     ("fp32", "aa", 27)])
 def test_wide_row_staged_step_is_bitwise_identical(nx, precision, streaming, q, monkeypatch):
-    """Rows of 257..512 nodes: one 512-thread work-group per row stages the
-    x-moving populations (the AA even step runs on 256-wide work-groups of
-    the same launch); the values equal those of 256-wide work-groups with
-    direct accesses, bit for bit.  An odd step count ends on an odd AA step."""
+    """Rows of 257..1024 nodes: one work-group of nx threads per row stages
+    the x-moving populations where the staging rows fit in 64 KB of LDS (the
+    AA even step runs on 256-wide work-groups of the same launch; FP64 and
+    D3Q27 beyond 512 keep direct accesses); the values equal those of
+    256-wide work-groups with direct accesses, bit for bit.  An odd step
+    count ends on an odd AA step."""
     ny, nz = 6, 5
     rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=35, umax=0.05)
     kw = dict(omega=1.8, force_mode=L.LBM_FORCE_KOLMOGOROV, kolmogorov_amp=1e-4, q=q)
