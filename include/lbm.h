@@ -175,8 +175,9 @@ typedef struct {
                                  at most 256); 0 = library default: whole x rows of up to 256
                                  nodes per work-group, one work-group of nx threads per row
                                  of 257..1024 nodes (where the staging rows fit in 64 KB of
-                                 LDS), the x-moving populations staged through LDS on
-                                 periodic lattices */
+                                 LDS; not for A-B with 16-bit storage, which keeps 256-wide
+                                 direct work-groups there), the x-moving populations staged
+                                 through LDS on periodic lattices */
     int32_t cache_policy;     /* population loads/stores: 0 = library default (non-temporal
                                  for staged steps and for A-B with 4- and 8-byte storage,
                                  cached otherwise), 1 = non-temporal (streaming) hints,
