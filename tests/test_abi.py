@@ -213,3 +213,16 @@ def test_colour_lattice_validation(lbm, kw, code):
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_create(p, None)
     assert e.value.code == code, lbm.lib().lbm_last_error().decode()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises; there is no CPU
+    fallback to take its place."""
+    from paper_2010_01628_amd import lbm as L
+
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "liblbm.so"))
+    with pytest.raises(ImportError):
+        L.lib()
+    with pytest.raises(ImportError):
+        L.Lattice(L.make_params(8, 8, 8))
