@@ -38,14 +38,13 @@ __device__ inline void load_net(uint32_t* d, const MlpPacked* __restrict__ src, 
 // ---------------------------------------------------------------------------
 // Step with learned rates (FP32 collision; FP32/FP16/BF16 storage).  Every
 // lane of every wavefront takes part in the network (lanes past the lattice
-// edge work on a clamped node and store nothing).  Per block, the number of
-// nodes that fell back is added to fb_partials[block].
+// edge work on a clamped node and store nothing).  The number of nodes that
+// fell back is added to fb_partials[block].
 // ---------------------------------------------------------------------------
 template <class S, Pattern P, bool WALLS, bool NT, bool O32 = false>
 __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const Phys& ph,
                                      const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
 {
-    __shared__ uint32_t wave_fb[4];
     const int xr = blockIdx.x * blockDim.x + threadIdx.x;
     const int yr = blockIdx.y * blockDim.y + threadIdx.y;
     const bool valid = xr < g.nx && yr < g.ny;
@@ -63,7 +62,6 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
     pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
     mlp_features(st, xin);
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-    const int w = tid >> 6;
     mlp_forward_regs(*net, xin, zout);
     const bool fb = mlp_rates(zout, rates);
     Rates<float> rt = rates_of<float>(ph);
@@ -76,15 +74,13 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
         relax<float, true>(st, rt, p);
     post_collide(st, p, s);
     if (valid) scatter<LatD3Q19, S, P, WALLS, NT, O32>(dst, g.stride, d, s);
-    // fallback count of the block
+    // fallback count: one atomic add per wavefront that has fallen-back
+    // nodes (none in normal operation), so a wavefront neither waits for the
+    // others of its block nor for a read before it retires
     const uint64_t ballot = __ballot(valid && fb);
-    if ((tid & 63) == 0) wave_fb[w] = (uint32_t)__popcll(ballot);
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t c = 0;
-        for (int i = 0; i < (int)((blockDim.x * blockDim.y + 63) / 64); ++i) c += wave_fb[i];
+    if (ballot != 0 && (tid & 63) == 0) {
         const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        fb_partials[bid] += c;
+        atomicAdd(&fb_partials[bid], (uint32_t)__popcll(ballot));
     }
 }
 

@@ -67,10 +67,13 @@ __host__ __device__ inline float bf16_to_f32(uint16_t b)
 // with the hardware exp and reciprocal (~1 ulp each).  Its absolute error,
 // ~1e-7, is relatively large only for |x| << 1e-2, where the activation's
 // bf16 ulp is below 1e-9 and its contribution to the next layer is
-// negligible; five VALU operations per activation.
+// negligible.  exp(2x) = 2^(x * 2 log2 e): one product, which rounds as
+// (2x) * log2 e does since both scalings by two are exact; four VALU
+// operations per activation, two of them the quarter-rate exp and rcp.
 __device__ inline float tanh_fast(float x)
 {
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * x) + 1.0f);
+    constexpr float two_log2e = 0x1.715476p+1f; // 2 * float(log2 e)
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(x * two_log2e) + 1.0f);
 }
 
 // LDS tile of 64 rows (nodes) of bf16; stride 36 keeps 8-byte alignment and
@@ -161,14 +164,17 @@ __device__ inline void mlp_forward_wave(const MlpPacked& W, uint16_t* tx, uint16
 // features split over the two half-waves) and the output (rates back to the
 // node's lane) cross half-waves, by v_permlane32_swap.
 // ---------------------------------------------------------------------------
+// Round to nearest even, two floats per conversion instruction.
+__device__ inline uint32_t pack2_bf16(float a, float b)
+{
+    typedef float f32x2_t __attribute__((ext_vector_type(2)));
+    typedef __bf16 b16x2_t __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, b16x2_t));
+}
 __device__ inline bf16x4_t pack_bf16(float a, float b, float c, float d)
 {
-    bf16x4_t r;
-    r[0] = __builtin_bit_cast(short, (__bf16)a);
-    r[1] = __builtin_bit_cast(short, (__bf16)b);
-    r[2] = __builtin_bit_cast(short, (__bf16)c);
-    r[3] = __builtin_bit_cast(short, (__bf16)d);
-    return r;
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(bf16x4_t, (u32x2){pack2_bf16(a, b), pack2_bf16(c, d)});
 }
 
 // swap: a <- [a.lo | b.lo], b <- [a.hi | b.hi] (half-waves of 32 lanes)
