@@ -90,6 +90,31 @@ def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fi
     }
 
 
+def stream_copy_bandwidth(torch, L, n, eb=4, q=19, reps=10):
+    """Rate of the library's bandwidth reference (lbm_stream_copy): q arrays
+    of n elements copied with the step's access pattern and streaming hints,
+    read + write bytes per second, HIP events on the stream it runs on, best
+    of `reps` after two untimed launches."""
+    dt = {2: torch.int16, 4: torch.int32, 8: torch.int64}[eb]
+    a = torch.zeros(q * n, dtype=dt, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        L.lbm_stream_copy(a.data_ptr(), b.data_ptr(), n, q, eb, True, st.cuda_stream)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        L.lbm_stream_copy(a.data_ptr(), b.data_ptr(), n, q, eb, True, st.cuda_stream)
+        e1.record(st)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * q * n * eb / (best * 1e-3) / 1e9
+
+
 def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
     """Device copy bandwidth (read + write bytes per second) of torch's copy
     of a 2 GiB buffer, HIP events, best of `reps`: a measured copy rate the
@@ -418,6 +443,7 @@ def main(argv=None):
 
     traffic = load_traffic(args.precision, args.streaming, size, head["algo_bytes_per_launch"])
     copy_gbs = copy_bandwidth(torch)
+    ref_gbs = stream_copy_bandwidth(torch, L, size ** 3, eb=elem_bytes(args.precision))
     roof = {
         "bound": "hbm",
         "achieved": round(head["achieved_GBs"], 1),
@@ -431,6 +457,8 @@ def main(argv=None):
         "launch": head["launch"],
         "torch_copy_GBs": round(copy_gbs, 1),
         "frac_of_torch_copy": round(head["achieved_GBs"] / copy_gbs, 4),
+        "stream_copy_GBs": round(ref_gbs, 1),
+        "frac_of_stream_copy": round(head["achieved_GBs"] / ref_gbs, 4),
     }
     cpu = None
     if not args.no_cpu_baseline:

@@ -382,6 +382,19 @@ int lbm_feature_rms(lbm_handle *h, double rms[11]);
  * float[10*n], may be NULL).  Ordered on `stream`. */
 int lbm_project_q27(const double *f27, int64_t n, double *f19, float *moments, void *stream);
 
+/* Memory-bandwidth reference with the step's access pattern (not part of the
+ * method; for measuring how close a step comes to what its loads and stores
+ * alone reach).  Copies q arrays of n elements of elem_bytes each, array k at
+ * element offset k*n of src (device), to the same places in dst (device, not
+ * overlapping src): each thread reads its element of all q arrays, then
+ * writes them, as the A-B step does without its collision and neighbour
+ * shifts.  q: 19 or 27; elem_bytes: 2, 4 or 8 (the storage types); nt != 0:
+ * the step's non-temporal (streaming) hints.  n = 0 enqueues nothing.
+ * Ordered on `stream` (NULL: the default stream), asynchronous.  Returns
+ * LBM_EINVAL for a NULL buffer, n < 0 or beyond 2^31 work-groups of 256, or
+ * another q or element size; LBM_EDEVICE if the launch fails. */
+int lbm_stream_copy(const void *src, void *dst, int64_t n, int32_t q, int32_t elem_bytes, int32_t nt, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Ensembles: many independent periodic cubic boxes (different sides and
  * viscosities, no force) advanced together, one launch per step over a

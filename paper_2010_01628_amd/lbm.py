@@ -132,6 +132,7 @@ def lib():
         L.lbm_mlp_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.lbm_feature_rms.argtypes = [vp, dp]
         L.lbm_project_q27.argtypes = [vp, i64, vp, vp, vp]
+        L.lbm_stream_copy.argtypes = [vp, vp, i64, i32, i32, i32, vp]
         class _box(ctypes.Structure):
             _fields_ = [("n", ctypes.c_int32), ("omega", ctypes.c_double)]
 
@@ -175,7 +176,7 @@ def lib():
                      "lbm_set_populations", "lbm_destroy", "lbm_mlp_create", "lbm_mlp_set_params",
                      "lbm_mlp_get_params", "lbm_mlp_set_scales", "lbm_mlp_destroy", "lbm_set_mlp",
                      "lbm_mlp_zero_grad", "lbm_mlp_accumulate_grad", "lbm_mlp_get_grad", "lbm_mlp_adam_step",
-                     "lbm_feature_rms", "lbm_project_q27"):
+                     "lbm_feature_rms", "lbm_project_q27", "lbm_stream_copy"):
             getattr(L, name).restype = i32
         if L.lbm_abi_version() != ABI_VERSION:
             raise ImportError("liblbm.so ABI version mismatch")
@@ -307,6 +308,13 @@ def lbm_feature_rms(h):
     out = np.zeros(11)
     _check(lib().lbm_feature_rms(h, _dptr(out)))
     return out
+
+
+def lbm_stream_copy(src_ptr, dst_ptr, n, q, elem_bytes, nt=True, stream=None):
+    """Copy q arrays of n elements (device pointers) with the step's access
+    pattern: a bandwidth reference for the step kernels."""
+    _check(lib().lbm_stream_copy(src_ptr, dst_ptr, int(n), int(q), int(elem_bytes), 1 if nt else 0,
+                                 ctypes.c_void_p(stream or 0)))
 
 
 def lbm_project_q27(f27_ptr, n, f19_ptr, moments_ptr, stream=None):

@@ -215,6 +215,17 @@ def test_colour_lattice_validation(lbm, kw, code):
     assert e.value.code == code, lbm.lib().lbm_last_error().decode()
 
 
+@pytest.mark.parametrize("src,n,q,eb", [(0, 16, 19, 4), (64, -1, 19, 4), (64, 16, 15, 4), (64, 16, 19, 3),
+                                         (64, (1 << 31) * 256 + 1, 19, 4)])
+def test_stream_copy_validation(lbm, src, n, q, eb):
+    """The bandwidth reference rejects bad arguments before any device use
+    (the pointers here are never dereferenced)."""
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_stream_copy(src, 64, n, q, eb)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert "lbm_stream_copy" in lbm.lib().lbm_last_error().decode()
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     """Without the built HIP library the binding raises; there is no CPU
     fallback to take its place."""

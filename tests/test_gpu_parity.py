@@ -346,3 +346,21 @@ def test_64bit_addressing_is_bitwise_identical(precision, streaming, walls, q, m
     monkeypatch.setenv("LBM_OFF32", "0")
     b = gpu_run(nx, ny, nz, rho, u, 6, precision, streaming, **kw)
     assert np.array_equal(a["f"], b["f"])
+
+
+@pytest.mark.parametrize("q,eb,nt", [(19, 4, True), (19, 2, False), (19, 2, True), (27, 8, True), (19, 8, False)])
+def test_stream_copy_is_exact(q, eb, nt):
+    """The bandwidth reference (the step's loads and stores without its
+    arithmetic) copies every element of all q arrays; n = 1000 leaves a
+    ragged last work-group."""
+    import torch
+
+    n = 1000
+    say(f"stream copy q={q} elem_bytes={eb} nt={nt}")
+    dt = {2: torch.int16, 4: torch.int32, 8: torch.int64}[eb]
+    gen = torch.Generator().manual_seed(5)
+    src = torch.randint(-(1 << 15), 1 << 15, (q * n,), generator=gen, dtype=torch.int64).to(dt).cuda()
+    dst = torch.zeros_like(src)
+    L.lbm_stream_copy(src.data_ptr(), dst.data_ptr(), n, q, eb, nt, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
