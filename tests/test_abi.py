@@ -226,6 +226,11 @@ def test_stream_copy_validation(lbm, src, n, q, eb):
     assert "lbm_stream_copy" in lbm.lib().lbm_last_error().decode()
 
 
+def test_stream_copy_of_nothing_enqueues_nothing(lbm):
+    """n = 0 returns before any device call (so it succeeds without a GPU)."""
+    lbm.lbm_stream_copy(64, 64, 0, 19, 4)
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     """Without the built HIP library the binding raises; there is no CPU
     fallback to take its place."""
