@@ -68,7 +68,7 @@ struct lbm_ensemble {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_steps = 0;
-    bool graph_mlp = false;
+    const void* graph_net = nullptr; // network weights the captured launches read (NULL: plain rates)
 };
 
 namespace {
@@ -101,7 +101,7 @@ int build_graph(lbm_ensemble* e, int nsteps)
     if (err != hipSuccess) return efail(LBM_EDEVICE, "graph capture: %s", hipGetErrorString(err));
     EHIP(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
     e->graph_steps = nsteps;
-    e->graph_mlp = e->mlp != nullptr;
+    e->graph_net = e->mlp ? e->mlp->packed : nullptr;
     return LBM_OK;
 }
 
@@ -288,6 +288,9 @@ int lbm_ensemble_set_mlp(lbm_ensemble* e, const lbm_mlp* m)
     if (m && (e->q != 19 || e->precision != LBM_FP32))
         return efail(LBM_EUNSUPPORTED, "learned rates need a D3Q19 FP32 ensemble");
     if (m) EHIP(hipStreamSynchronize(m->stream));
+    // a captured step loop has the previous network's weight pointer baked
+    // into its launches: replaying it would read that network (possibly freed)
+    if (m != e->mlp) drop_graph(e);
     e->mlp = m;
     return LBM_OK;
 }
@@ -296,7 +299,10 @@ int lbm_ensemble_step(lbm_ensemble* e, int64_t nsteps)
 {
     if (!e || nsteps < 0) return efail(LBM_EINVAL, "bad arguments");
     const char* env = std::getenv("LBM_ENSEMBLE_GRAPH_STEPS");
-    const int chunk = env ? std::atoi(env) : 16; // even: a replay leaves the buffer parity unchanged
+    // even (rounded down): a replay then leaves the buffer parity unchanged,
+    // which the replay loop below relies on (e->cur is not advanced by it)
+    int chunk = env ? std::atoi(env) : 16;
+    chunk &= ~1;
     int64_t left = nsteps;
     // single steps until the parity is even, so the graph always starts from buffer 0
     while (left > 0 && (e->cur != 0 || chunk < 2 || left < chunk)) {
@@ -305,7 +311,7 @@ int lbm_ensemble_step(lbm_ensemble* e, int64_t nsteps)
         left--;
     }
     if (left >= chunk && chunk >= 2) {
-        if (!e->exec || e->graph_steps != chunk || e->graph_mlp != (e->mlp != nullptr)) {
+        if (!e->exec || e->graph_steps != chunk || e->graph_net != (e->mlp ? e->mlp->packed : nullptr)) {
             int rc = build_graph(e, chunk);
             if (rc) return rc;
         }

@@ -116,10 +116,11 @@ def test_64bit_addressing_is_bitwise_identical(q, learned, monkeypatch):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("chunk", ["2", "16", "0"])
+@pytest.mark.parametrize("chunk", ["2", "16", "0", "3", "17"])
 def test_graph_replay_equals_single_steps(chunk, monkeypatch):
-    """Stepping through captured graphs of `chunk` steps (0: no graph) gives
-    the same bits as one call per step, including odd totals."""
+    """Stepping through captured graphs of `chunk` steps (0: no graph; odd
+    lengths are rounded down to even) gives the same bits as one call per
+    step, including odd totals."""
     boxes = [(16, 1.9), (20, 1.6), (9, 1.3)]
     monkeypatch.setenv("LBM_ENSEMBLE_GRAPH_STEPS", chunk)
     a = make_ensemble(boxes, precision="fp32")
@@ -185,6 +186,35 @@ def test_learned_rates_match_single_lattice(orc):
     assert ens.fallback_count() == 0
     ens.close()
     mlp.close()
+
+
+def test_graph_follows_network_swaps(monkeypatch):
+    """Captured step loops carry the attached network's weights: after
+    switching between two live networks (and back to the paper's rates)
+    between graph-length chunks, replays equal single steps bit for bit."""
+    boxes = [(12, 1.85), (7, 1.7), (10, 1.9)]
+    rng = np.random.default_rng(8)
+    nets = [L.Mlp(0.08 * rng.normal(size=L.MLP_NPARAM), SCALES), L.Mlp(0.08 * rng.normal(size=L.MLP_NPARAM), SCALES)]
+    a = make_ensemble(boxes, precision="fp32")
+    b = make_ensemble(boxes, precision="fp32")
+    for net in (nets[0], nets[1], nets[0], None, nets[1]):
+        a.set_mlp(net)
+        b.set_mlp(net)
+        monkeypatch.setenv("LBM_ENSEMBLE_GRAPH_STEPS", "8")
+        a.step(16)
+        monkeypatch.setenv("LBM_ENSEMBLE_GRAPH_STEPS", "0")
+        b.step(16)
+    for i in range(len(boxes)):
+        assert np.array_equal(a.get_populations(i), b.get_populations(i))
+    # the swaps changed the result: a run with the first network throughout differs
+    c = make_ensemble(boxes, precision="fp32")
+    c.set_mlp(nets[0])
+    c.step(80)
+    assert not np.array_equal(a.get_populations(0), c.get_populations(0))
+    for x in (a, b, c):
+        x.close()
+    for net in nets:
+        net.close()
 
 
 def test_learned_fallback_counts():
