@@ -245,6 +245,24 @@ int lbm_step(lbm_handle *h, int64_t nsteps);
  *  max |u|] over all nodes. */
 int lbm_moments(lbm_handle *h, double *rho, double *u, double *diag, int on_device);
 
+/* lbm_moments for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same fields and totals, computed by the same kernels, with the
+ * per-work-group partial totals in a fixed 1 MiB device array of the library
+ * (one per GPU, held until the process ends) instead of handle memory.
+ * rho (double[N]), u (double[3*N]) and diag (double[6], the totals of
+ * lbm_moments in the same order) are DEVICE pointers, each may be NULL.
+ * Asynchronous: ordered on the handle's stream, no synchronization, no
+ * allocation, no host copy.  The totals equal lbm_moments' up to the order of
+ * the FP64 summation (the partials group several z planes per work-group).
+ * Every call on one GPU uses that GPU's single array: calls that overlap in
+ * time on one GPU (handles on different streams) race; order them.
+ * Errors: LBM_EINVAL for a NULL handle or a lattice with more than 16384
+ * step work-groups per z plane (the array's capacity; lbm_moments has no
+ * such limit), LBM_EUNSUPPORTED for coupled lattices, LBM_EDEVICE if the
+ * array's address cannot be found or a launch fails. */
+int lbm_moments_noalloc(lbm_handle *h, double *rho, double *u, double *diag);
+
 /* Copy the populations f_i(x, t) at the current time (before collision, the
  * state the paper's algorithm starts a step from) into f (double[19*N], host
  * or device), converting from the storage precision. */

@@ -632,6 +632,8 @@ __device__ inline void block_reduce_store(double v[NDIAG], double* __restrict__ 
     }
 }
 
+// One work-group per (x-block, y-block) covers the planes z = blockIdx.z,
+// blockIdx.z + gridDim.z, ... (one plane when the grid spans all nz planes).
 template <class L, class S, Pattern P, bool WALLS>
 __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ buf, Geom g, Phys ph, double* __restrict__ rho_out,
                                                 double* __restrict__ u_out, double* __restrict__ partials)
@@ -639,9 +641,10 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ buf, Geom
     using R = typename Codec<S>::R;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
     double v[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 1e300};
-    if (x < g.nx && y < g.ny) {
+    bool first = true;
+    for (int z = blockIdx.z; z < g.nz; z += gridDim.z) {
+        if (!(x < g.nx && y < g.ny)) break;
         NodeIdx d;
         node_idx(g, x, y, z, d);
         const int n = nb(d, 0, 0, 0);
@@ -669,14 +672,18 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ buf, Geom
             u_out[2 * (int64_t)g.N + n] = uz;
         }
         const double u2 = ux * ux + uy * uy + uz * uz;
-        v[0] = rho;
-        v[1] = rho * ux;
-        v[2] = rho * uy;
-        v[3] = rho * uz;
-        v[4] = 0.5 * rho * u2;
-        v[5] = sqrt(u2);
-        v[6] = (isfinite(rho) && isfinite(u2) && rho > 0.0) ? 0.0 : 1.0;
-        v[7] = rho;
+        double w[NDIAG];
+        w[0] = rho;
+        w[1] = rho * ux;
+        w[2] = rho * uy;
+        w[3] = rho * uz;
+        w[4] = 0.5 * rho * u2;
+        w[5] = sqrt(u2);
+        w[6] = (isfinite(rho) && isfinite(u2) && rho > 0.0) ? 0.0 : 1.0;
+        w[7] = rho;
+#pragma unroll
+        for (int k = 0; k < NDIAG; ++k) v[k] = first ? w[k] : combine(k, v[k], w[k]);
+        first = false;
     }
     const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_reduce_store(v, partials + (int64_t)bid * NDIAG);

@@ -873,3 +873,62 @@ int lbm_project_q27(const double* f27, int64_t n, double* f19, float* moments, v
 int64_t lbm_device_bytes(const lbm_handle* h) { return h ? h->bytes : -1; }
 
 } // extern "C"
+
+// ---------------------------------------------------------------------------
+// lbm_moments_noalloc: the per-work-group partial totals of the moments kernel
+// live in a fixed device array instead of the handle's allocation, so the
+// call allocates nothing.  In host code `scratch` names a host-side stand-in:
+// its device address is looked up once per device (hipGetSymbolAddress, with
+// that device current) and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int NOALLOC_MAX_PARTIALS = 16384; // work-groups whose partials fit: 16384 x 8 doubles = 1 MiB
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+static __device__ __align__(256) double scratch[NOALLOC_MAX_PARTIALS * lbm::NDIAG_OUT];
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+int scratch_address(int dev, double** out)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(LBM_EUNSUPPORTED, "device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) HIP_TRY(hipSetDevice(cur));
+        if (e != hipSuccess || !ptr) return fail(LBM_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = (double*)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return LBM_OK;
+}
+
+} // namespace
+
+extern "C" int lbm_moments_noalloc(lbm_handle* h, double* rho, double* u, double* diag)
+{
+    if (!h) return fail(LBM_EINVAL, "NULL handle");
+    if (h->cp) return fail(LBM_EUNSUPPORTED, "lbm_moments_noalloc: not for coupled lattices (use lbm_moments)");
+    // one work-group per (x-block, y-block) and per group of z planes: as many
+    // plane groups as the fixed partials array holds
+    const int64_t plane_groups = (int64_t)h->grid.x * h->grid.y;
+    if (plane_groups > NOALLOC_MAX_PARTIALS)
+        return fail(LBM_EINVAL, "lbm_moments_noalloc: %lld work-groups per z plane (nx %d, ny %d) exceed the %d the fixed "
+                    "scratch holds; use lbm_moments", (long long)plane_groups, h->g.nx, h->g.ny, NOALLOC_MAX_PARTIALS);
+    double* part = nullptr;
+    const int rc = scratch_address(h->device, &part);
+    if (rc) return rc;
+    const int64_t gz = std::min<int64_t>(h->grid.z, NOALLOC_MAX_PARTIALS / plane_groups);
+    const dim3 grid(h->grid.x, h->grid.y, (unsigned)gz);
+    lbm::launch_moments(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, rho, u, part, grid,
+                        h->block, h->stream);
+    if (diag) lbm::launch_reduce(part, (int)(plane_groups * gz), diag, h->stream, 6);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}

@@ -85,7 +85,8 @@ inline void launch_moments(int q, int precision, int pattern, bool walls, const 
     if (q == 27) launch_moments_q27(precision, pattern, walls, buf, g, ph, rho, u, partials, grid, block, st);
     else launch_moments_q19(precision, pattern, walls, buf, g, ph, rho, u, partials, grid, block, st);
 }
-void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
+// nout: totals written to out (at most NDIAG_OUT)
+void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st, int nout = 8);
 
 // learned rates (mlp.hip)
 constexpr int MLP_PARAMS = 1737;

@@ -8,9 +8,10 @@ constexpr int NDIAG = NDIAG_OUT;
 __device__ inline double combine(int k, double a, double b) { return k == 5 ? fmax(a, b) : (k == 7 ? fmin(a, b) : a + b); }
 } // namespace
 
-// One block: thread t folds partials t, t+256, ... in order, then a fixed tree.
+// One block: thread t folds partials t, t+256, ... in order, then a fixed tree;
+// the first nout totals are written.
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int nblocks,
-                                                         double* __restrict__ out)
+                                                         double* __restrict__ out, int nout)
 {
     __shared__ double lds[NDIAG][256];
     const int t = threadIdx.x;
@@ -27,12 +28,12 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
         __syncthreads();
     }
     if (t == 0)
-        for (int k = 0; k < NDIAG; ++k) out[k] = lds[k][0];
+        for (int k = 0; k < nout; ++k) out[k] = lds[k][0];
 }
 
-void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st)
+void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st, int nout)
 {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nblocks, out, nout);
 }
 
 } // namespace lbm

@@ -108,6 +108,7 @@ def lib():
         L.lbm_init.argtypes = [vp, vp, vp, i32]
         L.lbm_step.argtypes = [vp, i64]
         L.lbm_moments.argtypes = [vp, vp, vp, vp, i32]
+        L.lbm_moments_noalloc.argtypes = [vp, vp, vp, vp]
         L.lbm_get_populations.argtypes = [vp, vp, i32]
         L.lbm_set_populations.argtypes = [vp, vp, i32]
         L.lbm_step_count.argtypes = [vp]
@@ -172,7 +173,7 @@ def lib():
         for name in ("lbm_init_phase", "lbm_phase_fields", "lbm_get_coupled_populations",
                      "lbm_set_coupled_populations", "lbm_init_colour", "lbm_colour_fields"):
             getattr(L, name).restype = i32
-        for name in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_get_populations",
+        for name in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_moments_noalloc", "lbm_get_populations",
                      "lbm_set_populations", "lbm_destroy", "lbm_mlp_create", "lbm_mlp_set_params",
                      "lbm_mlp_get_params", "lbm_mlp_set_scales", "lbm_mlp_destroy", "lbm_set_mlp",
                      "lbm_mlp_zero_grad", "lbm_mlp_accumulate_grad", "lbm_mlp_get_grad", "lbm_mlp_adam_step",
@@ -213,6 +214,11 @@ def lbm_step(h: int, nsteps: int) -> None:
 
 def lbm_moments(h: int, rho_ptr, u_ptr, diag_ptr, on_device: bool) -> None:
     _check(lib().lbm_moments(h, rho_ptr, u_ptr, diag_ptr, int(on_device)))
+
+
+def lbm_moments_noalloc(h: int, rho_ptr, u_ptr, diag_ptr) -> None:
+    """Device pointers only (each may be None); allocates nothing."""
+    _check(lib().lbm_moments_noalloc(h, rho_ptr, u_ptr, diag_ptr))
 
 
 def lbm_get_populations(h: int, f_ptr: int, on_device: bool) -> None:
