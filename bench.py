@@ -259,8 +259,9 @@ def bench_network(L):
 
 
 def cpu_baseline(inputs, size, seconds_target=12.0):
-    """FP64 oracle (closed-form mode, OpenMP on all host cores) on a bounded
-    sample: whole-lattice steps of the same 256^3 workload."""
+    """FP64 oracle (f* = T(u)^-1 k* by a dense solve per node, OpenMP on all
+    host cores) on a bounded sample: whole-lattice steps of the same 256^3
+    workload."""
     import numpy as np
 
     import oracle
@@ -291,8 +292,8 @@ def cpu_baseline(inputs, size, seconds_target=12.0):
         "unit": "MLUPS",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"{steps} full steps of the {size}^3 workload after 2 untimed steps (FP64, closed-form App. C "
-                  f"path), {el:.1f} s",
+        "sample": f"{steps} full steps of the {size}^3 workload after 2 untimed steps (FP64, dense T(u) "
+                  f"solve per node), {el:.1f} s",
         "cpu_model": cpu_model(),
         "cpus_visible": os.cpu_count(),
     }

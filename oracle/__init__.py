@@ -23,9 +23,7 @@ _SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c"
             "shan_chen_oracle.c", "colour_gradient_oracle.c"]
 
 DEFINITION = 0   # f* = T(u)^-1 k* by a dense solve per node
-CLOSED_FORM = 1  # f* = M^-1 N^-1 k* by the closed forms of App. C
 RM_DEFINITION = 2   # raw-moment variant of App. C (N = I): f* = M^-1 k* by a dense solve
-RM_CLOSED_FORM = 3  # raw-moment variant, f* by the closed forms of App. C with r* = k*
 
 Q = 19
 
@@ -36,7 +34,7 @@ def build(force: bool = True) -> str:
         return _SO
     srcs = [os.path.join(_HERE, s) for s in _SOURCES]
     tmp = _SO + ".tmp"
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+    cmd = ["gcc", "-std=c11", "-O3", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
            "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _SO)
@@ -60,11 +58,9 @@ def lib():
         L.orc19_T.argtypes = [f64, f64, f64, dp]
         L.orc19_keq.argtypes = [f64, dp]
         L.orc19_Rcm.argtypes = [f64, f64, f64, dp]
-        L.orc19_rstar.argtypes = [f64, f64, f64, f64, dp, dp]
         L.orc19_M.argtypes = [dp]
         L.orc19_keq_rm.argtypes = [f64, f64, f64, f64, dp]
         L.orc19_Rrm.argtypes = [f64, f64, f64, f64, f64, f64, dp]
-        L.orc19_fstar.argtypes = [dp, dp]
         L.orc19_collide.argtypes = [dp, dp, dp, i32, dp, dp, dp, dp]
         L.orc19_collide.restype = i32
         L.orc19_K.argtypes = [f64, f64, dp, dp]
@@ -215,18 +211,6 @@ def Rrm(u, F):
     return out
 
 
-def rstar(rho, u, kstar):
-    out = np.zeros(Q)
-    lib().orc19_rstar(float(rho), float(u[0]), float(u[1]), float(u[2]), _p(_f64(kstar)), _p(out))
-    return out
-
-
-def fstar(rstar_):
-    out = np.zeros(Q)
-    lib().orc19_fstar(_p(_f64(rstar_)), _p(out))
-    return out
-
-
 def K(omega, omega_bulk=1.0, omega_hi=None):
     out = np.zeros(Q)
     hi = None if omega_hi is None else _f64(omega_hi)
@@ -234,8 +218,14 @@ def K(omega, omega_bulk=1.0, omega_hi=None):
     return out
 
 
-def collide(f, F=(0.0, 0.0, 0.0), Kdiag=None, mode=CLOSED_FORM):
+def _check_mode(mode):
+    if mode not in (DEFINITION, RM_DEFINITION):
+        raise ValueError(f"unknown collision mode {mode}")
+
+
+def collide(f, F=(0.0, 0.0, 0.0), Kdiag=None, mode=DEFINITION):
     """One node.  Returns (f*, k, rho, u)."""
+    _check_mode(mode)
     f = _f64(f)
     F = _f64(F)
     Kd = _f64(Kdiag if Kdiag is not None else K(1.0))
@@ -259,8 +249,9 @@ def init(rho, u):
     return f
 
 
-def step(f, Kdiag, F=None, walls_y=False, mode=CLOSED_FORM, out=None):
+def step(f, Kdiag, F=None, walls_y=False, mode=DEFINITION, out=None):
     """One collide-and-stream step.  f: (19,nz,ny,nx).  Kdiag: (19,) or (19,nz,ny,nx)."""
+    _check_mode(mode)
     f = _f64(f)
     _, nz, ny, nx = f.shape
     Kd = _f64(Kdiag)
@@ -274,17 +265,21 @@ def step(f, Kdiag, F=None, walls_y=False, mode=CLOSED_FORM, out=None):
     return out
 
 
-def run(f, nsteps, Kdiag, F=None, walls_y=False, mode=CLOSED_FORM):
+def run(f, nsteps, Kdiag, F=None, walls_y=False, mode=DEFINITION, progress=None, every=100):
+    """nsteps steps; progress(t) (optional) is called after every `every` steps."""
     a = _f64(f).copy()
     b = np.empty_like(a)
-    for _ in range(int(nsteps)):
+    for t in range(int(nsteps)):
         step(a, Kdiag, F=F, walls_y=walls_y, mode=mode, out=b)
         a, b = b, a
+        if progress is not None and (t + 1) % every == 0:
+            progress(t + 1)
     return a
 
 
-def step_at(f, nodes, Kdiag, F=None, walls_y=False, mode=CLOSED_FORM):
+def step_at(f, nodes, Kdiag, F=None, walls_y=False, mode=DEFINITION):
     """f_i(x, t+1) (shape (len(nodes), 19)) at the given node indices only."""
+    _check_mode(mode)
     f = _f64(f)
     _, nz, ny, nx = f.shape
     Kd = _f64(Kdiag)

@@ -17,10 +17,12 @@
  *   R2  The velocity used in the shift, the equilibrium and the output is the
  *       force-shifted u = (sum_i f_i c_i + F/2)/rho (App. E macroscopic
  *       variables; required for k1* = Fx/2 of eq. "posColl0").
- *   R3  App. C raw moments r16*, r17* miss cs^2 on the k5* term and r18*
- *       misses cs^2 on the k6* term (eq. "rawQ19"); cs^2 is inserted.
- *   R4  App. C populations f3* ("r4-r5-2-r6") and f12* ("r4-r5-r6") both read
- *       (r4 - r5 - 2 r6) cs^2/2 (eq. "pdfQ19").
+ *   R3  App. C prints the back-transform as closed forms (raw moments
+ *       r* = N^-1 k*, eq. "rawQ19"; populations f* = M^-1 r*, eq. "pdfQ19"),
+ *       three of whose rows lack a cs^2 factor and two of whose population
+ *       formulas are misprinted.  This oracle uses none of the printed closed
+ *       forms: it solves T(u) f* = k* with T(u) built from its definition,
+ *       so those misprints cannot reach it.
  *   R5  K = diag(1,1,1,1, w_b, w,w,w,w,w, w_hi(9)); the paper sets w_b = 1 and
  *       w_hi = 1 (Sec. II.B).  w_b and w_hi are kept as free inputs so that the
  *       learned-rate variant and the bulk-rate tests can use them.
@@ -28,9 +30,10 @@
  *   R9  Raw-moment variant (App. C, N = I): its printed post-collision list
  *       carries only the forcing terms of the CM scheme (F/2 on rows 1-3,
  *       cs^2 F/2 on rows 10-15).  The relaxation eq. (posColl0) with T = M
- *       needs the raw moments of the same forcing term, which App. B prints
- *       (eq. RMQ19, with velocity terms on rows 4-18); those are used.  Both
- *       agree when F = 0, and at K = I the variant equals the CM scheme.
+ *       needs the raw moments of the same equilibrium and forcing term, which
+ *       are computed here from their definition, M f_eq and M T(u)^-1 R^CM
+ *       (App. B prints the latter as eq. RMQ19).  With F = 0 both readings
+ *       agree, and at K = I the variant equals the CM scheme.
  *
  * Layout: populations are structure-of-arrays, f[i*N + n] with
  * n = x + nx*(y + ny*z); forces F[d*N + n].
@@ -79,65 +82,40 @@ void orc19_tables(int *c, double *w, int *opp)
     }
 }
 
-/* Sec. II.A, eq. (EqQ19RM): extended D3Q19 equilibrium, written out term by
- * term exactly as printed (no factorisation). */
-void orc19_feq(double rho, double ux, double uy, double uz, double *feq)
+/* Sec. II.B, eq. (matrix): the 19 rows of the transformation matrix T
+ * evaluated on one shifted velocity (bx, by, bz) = c_i - u, i.e. column i of
+ * T(u).  Row 18 per reading R1. */
+static void t_column(double bx, double by, double bz, double *t)
 {
-    const double x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
-    feq[0] = rho / 3.0 * (1.0 - (x2 + y2 + z2) + 3.0 * (x2 * y2 + x2 * z2 + y2 * z2));
-    feq[1] = rho / 18.0 * (1.0 - 3.0 * ux + 3.0 * (x2 - y2 - z2) + 9.0 * (ux * y2 + ux * z2) - 9.0 * (x2 * y2 + x2 * z2));
-    feq[2] = rho / 18.0 * (1.0 - 3.0 * uy + 3.0 * (-x2 + y2 - z2) + 9.0 * (x2 * uy + uy * z2) - 9.0 * (x2 * y2 + y2 * z2));
-    feq[3] = rho / 18.0 * (1.0 - 3.0 * uz + 3.0 * (-x2 - y2 + z2) + 9.0 * (x2 * uz + y2 * uz) - 9.0 * (x2 * z2 + y2 * z2));
-    feq[4] = rho / 36.0 * (1.0 - 3.0 * (ux + uy) + 3.0 * (x2 + y2) + 9.0 * ux * uy - 9.0 * (x2 * uy + ux * y2) + 9.0 * x2 * y2);
-    feq[5] = rho / 36.0 * (1.0 + 3.0 * (-ux + uy) + 3.0 * (x2 + y2) - 9.0 * ux * uy + 9.0 * (x2 * uy - ux * y2) + 9.0 * x2 * y2);
-    feq[6] = rho / 36.0 * (1.0 - 3.0 * (ux + uz) + 3.0 * (x2 + z2) + 9.0 * ux * uz - 9.0 * (x2 * uz + ux * z2) + 9.0 * x2 * z2);
-    feq[7] = rho / 36.0 * (1.0 + 3.0 * (-ux + uz) + 3.0 * (x2 + z2) - 9.0 * ux * uz + 9.0 * (x2 * uz - ux * z2) + 9.0 * x2 * z2);
-    feq[8] = rho / 36.0 * (1.0 - 3.0 * (uy + uz) + 3.0 * (y2 + z2) + 9.0 * uy * uz - 9.0 * (y2 * uz + uy * z2) + 9.0 * y2 * z2);
-    feq[9] = rho / 36.0 * (1.0 + 3.0 * (-uy + uz) + 3.0 * (y2 + z2) - 9.0 * uy * uz + 9.0 * (y2 * uz - uy * z2) + 9.0 * y2 * z2);
-    feq[10] = rho / 18.0 * (1.0 + 3.0 * ux + 3.0 * (x2 - y2 - z2) - 9.0 * (ux * y2 + ux * z2) - 9.0 * (x2 * y2 + x2 * z2));
-    feq[11] = rho / 18.0 * (1.0 + 3.0 * uy + 3.0 * (-x2 + y2 - z2) - 9.0 * (x2 * uy + uy * z2) - 9.0 * (x2 * y2 + y2 * z2));
-    feq[12] = rho / 18.0 * (1.0 + 3.0 * uz + 3.0 * (-x2 - y2 + z2) - 9.0 * (x2 * uz + y2 * uz) - 9.0 * (x2 * z2 + y2 * z2));
-    feq[13] = rho / 36.0 * (1.0 + 3.0 * (ux + uy) + 3.0 * (x2 + y2) + 9.0 * ux * uy + 9.0 * (x2 * uy + ux * y2) + 9.0 * x2 * y2);
-    feq[14] = rho / 36.0 * (1.0 + 3.0 * (ux - uy) + 3.0 * (x2 + y2) - 9.0 * ux * uy + 9.0 * (-x2 * uy + ux * y2) + 9.0 * x2 * y2);
-    feq[15] = rho / 36.0 * (1.0 + 3.0 * (ux + uz) + 3.0 * (x2 + z2) + 9.0 * ux * uz + 9.0 * (x2 * uz + ux * z2) + 9.0 * x2 * z2);
-    feq[16] = rho / 36.0 * (1.0 + 3.0 * (ux - uz) + 3.0 * (x2 + z2) - 9.0 * ux * uz + 9.0 * (-x2 * uz + ux * z2) + 9.0 * x2 * z2);
-    feq[17] = rho / 36.0 * (1.0 + 3.0 * (uy + uz) + 3.0 * (y2 + z2) + 9.0 * uy * uz + 9.0 * (y2 * uz + uy * z2) + 9.0 * y2 * z2);
-    feq[18] = rho / 36.0 * (1.0 + 3.0 * (uy - uz) + 3.0 * (y2 + z2) - 9.0 * uy * uz + 9.0 * (-y2 * uz + uy * z2) + 9.0 * y2 * z2);
-}
-
-/* Sec. II.B, eq. (matrix): row r of the transformation matrix T evaluated on
- * the shifted velocity (bx, by, bz) = c_i - u.  Row 18 per reading R1. */
-static double t_row(int r, double bx, double by, double bz)
-{
-    switch (r) {
-    case 0: return 1.0;
-    case 1: return bx;
-    case 2: return by;
-    case 3: return bz;
-    case 4: return bx * bx + by * by + bz * bz;
-    case 5: return bx * bx - by * by;
-    case 6: return by * by - bz * bz;
-    case 7: return bx * by;
-    case 8: return bx * bz;
-    case 9: return by * bz;
-    case 10: return bx * bx * by;
-    case 11: return bx * by * by;
-    case 12: return bx * bx * bz;
-    case 13: return bx * bz * bz;
-    case 14: return by * by * bz;
-    case 15: return by * bz * bz;
-    case 16: return bx * bx * by * by;
-    case 17: return bx * bx * bz * bz;
-    default: return by * by * bz * bz;
-    }
+    t[0] = 1.0;
+    t[1] = bx;
+    t[2] = by;
+    t[3] = bz;
+    t[4] = bx * bx + by * by + bz * bz;
+    t[5] = bx * bx - by * by;
+    t[6] = by * by - bz * bz;
+    t[7] = bx * by;
+    t[8] = bx * bz;
+    t[9] = by * bz;
+    t[10] = bx * bx * by;
+    t[11] = bx * by * by;
+    t[12] = bx * bx * bz;
+    t[13] = bx * bz * bz;
+    t[14] = by * by * bz;
+    t[15] = by * bz * bz;
+    t[16] = bx * bx * by * by;
+    t[17] = bx * bx * bz * bz;
+    t[18] = by * by * bz * bz;
 }
 
 /* T(u), row-major 19x19: T[r*19+i] = monomial r of (c_i - u). */
 void orc19_T(double ux, double uy, double uz, double *T)
 {
-    for (int r = 0; r < Q; ++r)
-        for (int i = 0; i < Q; ++i)
-            T[r * Q + i] = t_row(r, CX[i] - ux, CY[i] - uy, CZ[i] - uz);
+    for (int i = 0; i < Q; ++i) {
+        double t[Q];
+        t_column(CX[i] - ux, CY[i] - uy, CZ[i] - uz, t);
+        for (int r = 0; r < Q; ++r) T[r * Q + i] = t[r];
+    }
 }
 
 /* Sec. II.B: Galilean-invariant equilibrium CMs (k0 = rho, k4 = 3 rho cs^2,
@@ -173,59 +151,6 @@ void orc19_Rcm(double Fx, double Fy, double Fz, double *R)
 /* App. C: raw-moment matrix M = T(0), the un-shifted basis (N = I). */
 void orc19_M(double *M) { orc19_T(0.0, 0.0, 0.0, M); }
 
-/* App. C: equilibrium raw moments of the RM formulation, as printed there
- * (rows in the order of M). */
-void orc19_keq_rm(double rho, double ux, double uy, double uz, double *k)
-{
-    const double x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
-    k[0] = rho;
-    k[1] = rho * ux;
-    k[2] = rho * uy;
-    k[3] = rho * uz;
-    k[4] = rho * (3.0 * CS2 + x2 + y2 + z2);
-    k[5] = rho * (x2 - y2);
-    k[6] = rho * (y2 - z2);
-    k[7] = rho * ux * uy;
-    k[8] = rho * ux * uz;
-    k[9] = rho * uy * uz;
-    k[10] = rho * uy * (x2 + CS2);
-    k[11] = rho * ux * (y2 + CS2);
-    k[12] = rho * uz * (x2 + CS2);
-    k[13] = rho * ux * (z2 + CS2);
-    k[14] = rho * uz * (y2 + CS2);
-    k[15] = rho * uy * (z2 + CS2);
-    k[16] = rho * (x2 + CS2) * (y2 + CS2);
-    k[17] = rho * (x2 + CS2) * (z2 + CS2);
-    k[18] = rho * (y2 + CS2) * (z2 + CS2);
-}
-
-/* App. B, eq. (RMQ19): raw moments R_pqr of the forcing term, placed in the
- * row order of M (rows 4..6 are the trace and the two differences of the
- * second-order ones).  Reading R9. */
-void orc19_Rrm(double ux, double uy, double uz, double Fx, double Fy, double Fz, double *R)
-{
-    const double r200 = 2.0 * ux * Fx, r020 = 2.0 * uy * Fy, r002 = 2.0 * uz * Fz;
-    R[0] = 0.0;
-    R[1] = Fx;
-    R[2] = Fy;
-    R[3] = Fz;
-    R[4] = r200 + r020 + r002;
-    R[5] = r200 - r020;
-    R[6] = r020 - r002;
-    R[7] = ux * Fy + uy * Fx;
-    R[8] = ux * Fz + uz * Fx;
-    R[9] = uy * Fz + uz * Fy;
-    R[10] = CS2 * Fy + ux * (ux * Fy + 2.0 * uy * Fx); /* 210 */
-    R[11] = CS2 * Fx + uy * (uy * Fx + 2.0 * ux * Fy); /* 120 */
-    R[12] = CS2 * Fz + ux * (ux * Fz + 2.0 * uz * Fx); /* 201 */
-    R[13] = CS2 * Fx + uz * (uz * Fx + 2.0 * ux * Fz); /* 102 */
-    R[14] = CS2 * Fz + uy * (uy * Fz + 2.0 * uz * Fy); /* 021 */
-    R[15] = CS2 * Fy + uz * (uz * Fy + 2.0 * uy * Fz); /* 012 */
-    R[16] = 2.0 * (ux * uy * (ux * Fy + uy * Fx) + CS2 * (ux * Fx + uy * Fy));
-    R[17] = 2.0 * (ux * uz * (ux * Fz + uz * Fx) + CS2 * (ux * Fx + uz * Fz));
-    R[18] = 2.0 * (uy * uz * (uy * Fz + uz * Fy) + CS2 * (uy * Fy + uz * Fz));
-}
-
 /* Macroscopic moments, Sec. II.A eq. (macro) with the F/2 shift (reading R2). */
 static void macro(const double *f, const double *F, double *rho, double *u)
 {
@@ -240,68 +165,6 @@ static void macro(const double *f, const double *F, double *rho, double *u)
     u[0] = (jx + 0.5 * F[0]) / r;
     u[1] = (jy + 0.5 * F[1]) / r;
     u[2] = (jz + 0.5 * F[2]) / r;
-}
-
-/* App. C, eq. (rawQ19): post-collision raw moments r* = N^-1 k*, with the
- * missing cs^2 factors restored (reading R3). */
-void orc19_rstar(double rho, double ux, double uy, double uz, const double *k, double *r)
-{
-    const double x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
-    r[0] = rho;
-    r[1] = rho * ux + k[1];
-    r[2] = rho * uy + k[2];
-    r[3] = rho * uz + k[3];
-    r[4] = rho * (x2 + y2 + z2) + 2.0 * ux * k[1] + 2.0 * uy * k[2] + 2.0 * uz * k[3] + k[4];
-    r[5] = rho * (x2 - y2) + 2.0 * ux * k[1] - 2.0 * uy * k[2] + k[5];
-    r[6] = rho * (y2 - z2) + 2.0 * uy * k[2] - 2.0 * uz * k[3] + k[6];
-    r[7] = rho * ux * uy + uy * k[1] + ux * k[2] + k[7];
-    r[8] = rho * ux * uz + uz * k[1] + ux * k[3] + k[8];
-    r[9] = rho * uy * uz + uz * k[2] + uy * k[3] + k[9];
-    r[10] = rho * x2 * uy + 2.0 * ux * uy * k[1] + x2 * k[2] + uy * k[4] * CS2 + 2.0 * uy * k[5] * CS2 +
-            uy * k[6] * CS2 + 2.0 * ux * k[7] + k[10];
-    r[11] = rho * ux * y2 + y2 * k[1] + 2.0 * ux * uy * k[2] + ux * k[4] * CS2 - ux * k[5] * CS2 +
-            ux * k[6] * CS2 + 2.0 * uy * k[7] + k[11];
-    r[12] = rho * x2 * uz + 2.0 * ux * uz * k[1] + x2 * k[3] + uz * k[4] * CS2 + 2.0 * uz * k[5] * CS2 +
-            uz * k[6] * CS2 + 2.0 * ux * k[8] + k[12];
-    r[13] = rho * ux * z2 + z2 * k[1] + 2.0 * ux * uz * k[3] + ux * k[4] * CS2 - ux * k[5] * CS2 -
-            2.0 * ux * k[6] * CS2 + 2.0 * uz * k[8] + k[13];
-    r[14] = rho * y2 * uz + 2.0 * uy * uz * k[2] + y2 * k[3] + uz * k[4] * CS2 - uz * k[5] * CS2 +
-            uz * k[6] * CS2 + 2.0 * uy * k[9] + k[14];
-    r[15] = rho * uy * z2 + z2 * k[2] + 2.0 * uy * uz * k[3] + uy * k[4] * CS2 - uy * k[5] * CS2 -
-            2.0 * uy * k[6] * CS2 + 2.0 * uz * k[9] + k[15];
-    r[16] = rho * x2 * y2 + 2.0 * ux * y2 * k[1] + 2.0 * x2 * uy * k[2] + (x2 + y2) * k[4] * CS2 +
-            (2.0 * y2 - x2) * k[5] * CS2 + (x2 + y2) * k[6] * CS2 + 4.0 * ux * uy * k[7] +
-            2.0 * uy * k[10] + 2.0 * ux * k[11] + k[16];
-    r[17] = rho * x2 * z2 + 2.0 * ux * z2 * k[1] + 2.0 * x2 * uz * k[3] + (x2 + z2) * k[4] * CS2 +
-            (2.0 * z2 - x2) * k[5] * CS2 + (z2 - 2.0 * x2) * k[6] * CS2 + 4.0 * ux * uz * k[8] +
-            2.0 * uz * k[12] + 2.0 * ux * k[13] + k[17];
-    r[18] = rho * y2 * z2 + 2.0 * uy * z2 * k[2] + 2.0 * y2 * uz * k[3] + (y2 + z2) * k[4] * CS2 +
-            (-y2 - z2) * k[5] * CS2 + (z2 - 2.0 * y2) * k[6] * CS2 + 4.0 * uy * uz * k[9] +
-            2.0 * uz * k[14] + 2.0 * uy * k[15] + k[18];
-}
-
-/* App. C, eq. (pdfQ19): populations f* = M^-1 r*, with reading R4 on f3, f12. */
-void orc19_fstar(const double *r, double *f)
-{
-    f[0] = r[0] - r[4] + r[16] + r[17] + r[18];
-    f[1] = (r[11] + r[13] - r[1] - r[16] - r[17]) / 2.0 + (r[4] + 2.0 * r[5] + r[6]) * CS2 / 2.0;
-    f[2] = (r[10] + r[15] - r[2] - r[16] - r[18]) / 2.0 + (r[4] + r[6] - r[5]) * CS2 / 2.0;
-    f[3] = (r[12] + r[14] - r[3] - r[17] - r[18]) / 2.0 + (r[4] - r[5] - 2.0 * r[6]) * CS2 / 2.0;
-    f[4] = (r[7] + r[16] - r[10] - r[11]) / 4.0;
-    f[5] = (r[10] + r[16] - r[7] - r[11]) / 4.0;
-    f[6] = (r[8] + r[17] - r[12] - r[13]) / 4.0;
-    f[7] = (r[12] + r[17] - r[8] - r[13]) / 4.0;
-    f[8] = (r[9] + r[18] - r[14] - r[15]) / 4.0;
-    f[9] = (r[14] + r[18] - r[9] - r[15]) / 4.0;
-    f[10] = (r[1] - r[11] - r[13] - r[16] - r[17]) / 2.0 + (r[4] + 2.0 * r[5] + r[6]) * CS2 / 2.0;
-    f[11] = (r[2] - r[10] - r[15] - r[16] - r[18]) / 2.0 + (r[4] + r[6] - r[5]) * CS2 / 2.0;
-    f[12] = (r[3] - r[12] - r[14] - r[17] - r[18]) / 2.0 + (r[4] - r[5] - 2.0 * r[6]) * CS2 / 2.0;
-    f[13] = (r[7] + r[10] + r[11] + r[16]) / 4.0;
-    f[14] = (r[11] + r[16] - r[7] - r[10]) / 4.0;
-    f[15] = (r[8] + r[12] + r[13] + r[17]) / 4.0;
-    f[16] = (r[13] + r[17] - r[8] - r[12]) / 4.0;
-    f[17] = (r[9] + r[14] + r[15] + r[18]) / 4.0;
-    f[18] = (r[15] + r[18] - r[9] - r[14]) / 4.0;
 }
 
 /* Dense solve A x = b (19x19) by Gaussian elimination with partial pivoting.
@@ -324,8 +187,9 @@ static int solve19(double *A, double *b, double *x)
             }
             double t = b[col]; b[col] = b[piv]; b[piv] = t;
         }
+        const double inv_pivot = 1.0 / A[col * Q + col];
         for (int r = col + 1; r < Q; ++r) {
-            double m = A[r * Q + col] / A[col * Q + col];
+            double m = A[r * Q + col] * inv_pivot;
             if (m == 0.0) continue;
             for (int c = col; c < Q; ++c) A[r * Q + c] -= m * A[col * Q + c];
             b[r] -= m * b[col];
@@ -342,18 +206,58 @@ static int solve19(double *A, double *b, double *x)
 /* The same elimination for the other oracle files (n <= 19; A, b overwritten). */
 int orc_solve19(double *A, double *b, double *x) { return solve19(A, b, x); }
 
-enum { ORC_DEFINITION = 0, ORC_CLOSED_FORM = 1, ORC_RM_DEFINITION = 2, ORC_RM_CLOSED_FORM = 3 };
+/* Sec. II.A-B: the extended D3Q19 equilibrium (eq. EqQ19RM) is the
+ * population set whose central moments are the Galilean-invariant k_eq:
+ * f_eq = T(u)^-1 k_eq (the paper states both forms; the CM one is used). */
+void orc19_feq(double rho, double ux, double uy, double uz, double *feq)
+{
+    double T[Q * Q], k[Q];
+    orc19_T(ux, uy, uz, T);
+    orc19_keq(rho, k);
+    solve19(T, k, feq);
+}
+
+/* App. C: raw moments (rows of M) of the same equilibrium, M f_eq, the
+ * equilibrium of the raw-moment variant. */
+void orc19_keq_rm(double rho, double ux, double uy, double uz, double *k)
+{
+    double M[Q * Q], fe[Q];
+    orc19_M(M);
+    orc19_feq(rho, ux, uy, uz, fe);
+    for (int r = 0; r < Q; ++r) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += M[r * Q + i] * fe[i];
+        k[r] = s;
+    }
+}
+
+/* App. B (eq. RMQ19 prints the result): raw moments of the forcing term whose
+ * central moments are R^CM, i.e. M T(u)^-1 R^CM (reading R9). */
+void orc19_Rrm(double ux, double uy, double uz, double Fx, double Fy, double Fz, double *R)
+{
+    double T[Q * Q], M[Q * Q], Rc[Q], Fi[Q];
+    orc19_T(ux, uy, uz, T);
+    orc19_Rcm(Fx, Fy, Fz, Rc);
+    solve19(T, Rc, Fi);
+    orc19_M(M);
+    for (int r = 0; r < Q; ++r) {
+        double s = 0.0;
+        for (int i = 0; i < Q; ++i) s += M[r * Q + i] * Fi[i];
+        R[r] = s;
+    }
+}
+
+enum { ORC_DEFINITION = 0, ORC_RM_DEFINITION = 2 };
 
 /*
  * One collision at one node, Sec. II.B eqs. (posColl0) and (system):
  *   rho, u from f (reading R2); k = T(u) f; k_eq; R = CMs of the force;
  *   k* = (I - K) k + K k_eq + (I - K/2) R;
- *   f* = T(u)^-1 k*   (mode ORC_DEFINITION: dense solve)
- *      = M^-1 N^-1 k* (mode ORC_CLOSED_FORM: App. C two-step closed forms).
- * Modes ORC_RM_*: the raw-moment variant of App. C (N = I, T = M): k = M f,
- * the raw equilibrium and forcing moments (reading R9), the same relaxation,
- * f* = M^-1 k* by a dense solve (ORC_RM_DEFINITION) or by the closed forms
- * of eq. (pdfQ19) with r* = k* (ORC_RM_CLOSED_FORM).
+ *   f* = T(u)^-1 k*   (mode ORC_DEFINITION: dense solve of T(u) f* = k*).
+ * Mode ORC_RM_DEFINITION: the raw-moment variant of App. C (N = I, T = M):
+ * k = M f, the raw moments of the same equilibrium and forcing term (reading
+ * R9), the same relaxation, f* = M^-1 k* by a dense solve.  Any other mode
+ * returns -2.
  * K holds the 19 diagonal entries of the relaxation matrix.  If kout/uout are
  * given they receive k (pre-collision moments) and the shifted velocity.
  */
@@ -362,7 +266,8 @@ int orc19_collide(const double *f, const double *F, const double *K, int mode, d
 {
     double rho, u[3];
     macro(f, F, &rho, u);
-    const int raw = (mode == ORC_RM_DEFINITION || mode == ORC_RM_CLOSED_FORM);
+    if (mode != ORC_DEFINITION && mode != ORC_RM_DEFINITION) return -2;
+    const int raw = mode == ORC_RM_DEFINITION;
     double T[Q * Q], k[Q], keq[Q], R[Q], ks[Q];
     if (raw)
         orc19_M(T);
@@ -384,20 +289,9 @@ int orc19_collide(const double *f, const double *F, const double *K, int mode, d
     if (kout) memcpy(kout, k, sizeof k);
     if (rho_out) *rho_out = rho;
     if (uout) memcpy(uout, u, sizeof u);
-    if (mode == ORC_DEFINITION || mode == ORC_RM_DEFINITION) {
-        double b[Q];
-        memcpy(b, ks, sizeof ks);
-        return solve19(T, b, fstar);
-    }
-    if (mode == ORC_RM_CLOSED_FORM) {
-        orc19_fstar(ks, fstar);
-        return 0;
-    }
-    double rs[Q];
-    /* The closed forms of App. C take k0* = rho. */
-    orc19_rstar(ks[0], u[0], u[1], u[2], ks, rs);
-    orc19_fstar(rs, fstar);
-    return 0;
+    double b[Q];
+    memcpy(b, ks, sizeof ks);
+    return solve19(T, b, fstar);
 }
 
 /* Standard K of Sec. II.B: diag(1,1,1,1, w_b, w x5, w_hi[0..8]). */

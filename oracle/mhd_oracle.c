@@ -110,7 +110,7 @@ static void node_state(const double *fl, const double *gl, const double *Fext, d
 }
 
 /*
- * One time step.  Flow: the paper's collision (closed form, K from omega)
+ * One time step.  Flow: the paper's collision (f* = T(u)^-1 k*, K from omega)
  * with F = F_ext + j x b, streaming with periodic wrap and, if walls_y,
  * halfway bounce-back at y = -1/2 and ny - 1/2.  Magnetic: BGK at w_m with
  * the force-shifted u, streaming likewise with anti-bounce-back (M4).
@@ -138,7 +138,7 @@ int orc_mhd_step(int nx, int ny, int nz, int walls_y, const double *prm, double 
         if (Fext)
             for (int d = 0; d < 3; ++d) Fe[d] = Fext[(int64_t)d * N + n];
         node_state(fl, gl, Fe, omega_m, &rho, u0, b, j, F);
-        if (orc19_collide(fl, F, K, 1, fs, NULL, NULL, u) != 0) err |= 1;
+        if (orc19_collide(fl, F, K, 0, fs, NULL, NULL, u) != 0) err |= 1;
         double geq[3 * Q7];
         orc_mhd_geq(b, u, geq);
         for (int i = 0; i < Q; ++i) {

@@ -170,7 +170,7 @@ int64_t orc19_step_mlp(int nx, int ny, int nz, int walls_y, const double *f, dou
         orc_mlp_forward(P, xf, bf16, NULL, NULL, NULL, zz);
         fallbacks += orc_mlp_rates(zz, rates);
         orc19_K(omega, 1.0, rates, Kd);
-        if (orc19_collide(fl, Fl, Kd, 1, fs, NULL, NULL, NULL) != 0) err |= 1;
+        if (orc19_collide(fl, Fl, Kd, 0, fs, NULL, NULL, NULL) != 0) err |= 1;
         for (int i = 0; i < Q; ++i) {
             int yd = y + c[3 * i + 1];
             if (walls_y && (yd < 0 || yd >= ny)) {
@@ -224,7 +224,7 @@ double orc19_mlp_loss_grad(int nx, int ny, int nz, const double *f, const double
         orc_mlp_forward(P, xf, bf16, NULL, NULL, NULL, zz);
         fb += orc_mlp_rates(zz, rates);
         orc19_K(omega, 1.0, rates, Kd);
-        orc19_collide(fl, Fz, Kd, 1, fs, NULL, NULL, NULL);
+        orc19_collide(fl, Fz, Kd, 0, fs, NULL, NULL, NULL);
         for (int i = 0; i < Q; ++i) fstar[(int64_t)i * N + n] = fs[i];
     }
     /* stream (periodic) */

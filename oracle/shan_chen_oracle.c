@@ -75,8 +75,8 @@ static void density(int nx, int ny, int nz, const double *f, double *rho)
 
 /*
  * One step: rho from f, the force field above, then the paper's collision
- * with the 19 relaxation rates K and periodic streaming (closed-form mode of
- * the D3Q19 oracle).  F_out
+ * with the 19 relaxation rates K and periodic streaming (the D3Q19 oracle's
+ * step, f* = T(u)^-1 k*).  F_out
  * (3N, optional) receives the force used.  Returns 0, -1 on a singular
  * collision system, -2 on allocation failure.
  */
@@ -93,7 +93,7 @@ int orc_sc_step(int nx, int ny, int nz, double G, const double *Fu, const double
     }
     density(nx, ny, nz, f, rho);
     orc_sc_force(nx, ny, nz, rho, G, Fu, F);
-    const int rc = orc19_step(nx, ny, nz, 0, f, fnew, F, K, 0, 1);
+    const int rc = orc19_step(nx, ny, nz, 0, f, fnew, F, K, 0, 0);
     free(rho);
     if (!F_out) free(F);
     return rc;

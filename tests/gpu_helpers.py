@@ -57,6 +57,6 @@ def gpu_run(nx, ny, nz, rho, u, steps, precision="fp64", streaming="ab", omega=1
 def oracle_run(orc, rho, u, steps, omega=1.0, omega_bulk=1.0, omega_hi=None, F=None, walls=False,
                mode=None):
     Kd = orc.K(omega, omega_bulk, omega_hi)
-    f = orc.run(orc.init(rho, u), steps, Kd, F=F, walls_y=walls, mode=orc.CLOSED_FORM if mode is None else mode)
+    f = orc.run(orc.init(rho, u), steps, Kd, F=F, walls_y=walls, mode=orc.DEFINITION if mode is None else mode)
     r, v = orc.moments(f, F)
     return {"rho": r, "u": v, "f": f}

@@ -41,10 +41,11 @@ def _gpu():
 @pytest.fixture(scope="module", params=[64, 128])
 def reference(orc, request):
     N = request.param
-    say(f"oracle: {N}^3, {STEPS} steps (FP64, host; ~80 s at 128^3 on 16 threads)")
+    say(f"oracle: {N}^3, {STEPS} steps (FP64, host)")
     rho, u = inputs.taylor_green_noise(N, 0.05, 1e-4, seed=20101628)
     F = inputs.kolmogorov_force(N, N, N, 1e-6)
-    f = orc.run(orc.init(rho, u), STEPS, orc.K(inputs.omega_from_nu(NU)), F=F)
+    f = orc.run(orc.init(rho, u), STEPS, orc.K(inputs.omega_from_nu(NU)), F=F,
+                progress=lambda t: say(f"  oracle {N}^3: step {t}"))
     r, v = orc.moments(f, F)
     return N, rho, u, r, v
 

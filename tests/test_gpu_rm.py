@@ -46,7 +46,7 @@ def test_random_forced_fp64_elementwise(orc, nx, ny, nz, walls, streaming, steps
     ob, oh = (rng.uniform(0.5, 1.9), rng.uniform(0.6, 1.9, 9)) if general else (1.0, None)
     g = gpu_run(nx, ny, nz, rho, u, steps, "fp64", streaming, omega=om, omega_bulk=ob, omega_hi=oh, force=F,
                 walls=walls, moments="raw")
-    o = oracle_run(orc, rho, u, steps, om, ob, oh, F=F, walls=walls, mode=orc.RM_CLOSED_FORM)
+    o = oracle_run(orc, rho, u, steps, om, ob, oh, F=F, walls=walls, mode=orc.RM_DEFINITION)
     err = np.abs(g["f"] - o["f"]).max()
     say(f"  max |f_gpu - f_oracle| = {err:.3e}")
     assert err < 1e-13
@@ -82,7 +82,7 @@ def test_config2_recipe_vs_oracle(orc, precision, streaming):
     F = inputs.kolmogorov_force(n, n, n, 1e-6)
     g = gpu_run(n, n, n, rho, u, steps, precision, streaming, omega=om, force_mode=L.LBM_FORCE_KOLMOGOROV,
                 kolmogorov_amp=1e-6, want_pops=False, moments="raw")
-    o = oracle_run(orc, rho, u, steps, om, F=F, mode=orc.RM_CLOSED_FORM)
+    o = oracle_run(orc, rho, u, steps, om, F=F, mode=orc.RM_DEFINITION)
     err_u, err_r = rel_l2(g["u"], o["u"]), rel_l2(g["rho"], o["rho"])
     say(f"  rel L2 u = {err_u:.3e}, rho = {err_r:.3e}")
     assert err_u < HALF_U_TOL[precision]
@@ -151,7 +151,7 @@ def test_full_size_sampled_single_step(orc):
     finally:
         lat.close()
     F = inputs.kolmogorov_force(S, S, S, 1e-6)
-    want = orc.step_at(f_t, nodes, orc.K(om), F=F, mode=orc.RM_CLOSED_FORM)
+    want = orc.step_at(f_t, nodes, orc.K(om), F=F, mode=orc.RM_DEFINITION)
     err = np.abs(got - want).max()
     say(f"  max |f_gpu - f_oracle| over {len(nodes)} nodes = {err:.3e}")
     assert err < 2e-8

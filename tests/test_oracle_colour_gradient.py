@@ -60,7 +60,9 @@ def test_heq_central_moments_match_printed_list(orc):
 def test_single_colour_is_the_papers_scheme(orc, walls):
     """Blue only with alpha_b = 1/3: h_eq = f_eq, phi = -1 everywhere (no
     perturbation, no recolouring bias): the paper's step with the body force
-    (rho - rho_ref) g."""
+    (rho - rho_ref) g, to FP64 round-off (the two sides reach f_eq and f* by
+    different linear solves, each rounding at ~1e-16 times the condition
+    number of T(u), about 10)."""
     from paper_2010_01628_amd import inputs
 
     nx, ny, nz = 6, 5, 4
@@ -72,7 +74,7 @@ def test_single_colour_is_the_papers_scheme(orc, walls):
     want = orc.step(orc.init(rho, u), orc.K(1.6), F=F, walls_y=walls)
     ar, ab = C.step(prm, fr, fb, walls_y=walls)
     assert np.abs(ar).max() == 0.0
-    assert np.abs(ab - want).max() < 1e-15
+    assert np.abs(ab - want).max() < 5e-15
 
 
 def random_mixture(shape, seed):

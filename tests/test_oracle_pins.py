@@ -10,6 +10,8 @@ import os
 import numpy as np
 import pytest
 
+import moment_forms as mf
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 CS2 = 1.0 / 3.0
 
@@ -70,7 +72,7 @@ def test_shift_matrix_lower_unitriangular(orc):
 # --------------------------------------------------------------------------
 def test_equilibrium_cms_galilean(orc):
     """Sec. II.B: T(u) f_eq(rho, u) = [rho,0,0,0,3 rho cs^2,0..0, rho cs^4 x3]
-    for every u.  Pins the printed f_eq polynomial against the CM basis."""
+    for every u (the printed list of equilibrium CMs, also the product form)."""
     rng = np.random.default_rng(2)
     for _ in range(50):
         rho, u = rand_state(rng, 0.3)
@@ -81,28 +83,21 @@ def test_equilibrium_cms_galilean(orc):
         want[16:19] = rho * CS2 ** 2
         assert np.allclose(k, want, atol=1e-14)
         assert np.allclose(orc.keq(rho), want, atol=0)
+        assert np.allclose(mf.eq_central(rho), want, atol=1e-16)
 
 
-def test_equilibrium_raw_moments_printed_list(orc):
-    """App. C (raw-moment variant): M f_eq equals the printed raw equilibrium
-    moments k0^eq..k18^eq.  A second, independent printed passage."""
+def test_equilibrium_raw_moments_are_shifted_products(orc):
+    """Raw moments of the equilibrium with the printed M: Galilean-invariant
+    product CMs shifted by u give rho prod_a mu_{p_a}(u_a), mu = (1, u,
+    u^2 + cs^2) (binomial theorem); App. C lists these as the raw-moment
+    variant's equilibrium, which the oracle takes as M f_eq."""
     rng = np.random.default_rng(3)
     M = printed_M()
     for _ in range(50):
-        rho, (ux, uy, uz) = rand_state(rng, 0.3)
-        want = np.array([
-            rho, rho * ux, rho * uy, rho * uz,
-            rho * (3 * CS2 + ux ** 2 + uy ** 2 + uz ** 2),
-            rho * (ux ** 2 - uy ** 2), rho * (uy ** 2 - uz ** 2),
-            rho * ux * uy, rho * ux * uz, rho * uy * uz,
-            rho * uy * (ux ** 2 + CS2), rho * ux * (uy ** 2 + CS2),
-            rho * uz * (ux ** 2 + CS2), rho * ux * (uz ** 2 + CS2),
-            rho * uz * (uy ** 2 + CS2), rho * uy * (uz ** 2 + CS2),
-            rho * (ux ** 2 + CS2) * (uy ** 2 + CS2),
-            rho * (ux ** 2 + CS2) * (uz ** 2 + CS2),
-            rho * (uy ** 2 + CS2) * (uz ** 2 + CS2),
-        ])
-        assert np.allclose(M @ orc.feq(rho, [ux, uy, uz]), want, atol=1e-15)
+        rho, u = rand_state(rng, 0.3)
+        want = mf.eq_raw(rho, u)
+        assert np.allclose(M @ orc.feq(rho, u), want, atol=1e-15)
+        assert np.allclose(orc.keq_rm(rho, u), want, atol=1e-15)
 
 
 def test_equilibrium_hydrodynamic_moments_match_qian(orc):
@@ -130,70 +125,49 @@ def test_equilibrium_hydrodynamic_moments_match_qian(orc):
 
 
 # --------------------------------------------------------------------------
-# Back-transform closed forms (App. C eqs. rawQ19, pdfQ19)
+# Forcing term (App. B) and the dense solve of the back-transform
 # --------------------------------------------------------------------------
-def test_closed_forms_compose_to_T_inverse(orc):
-    """f* = M^-1 N^-1 k* from the App. C closed forms equals a library solve of
-    T(u) f* = k* (numpy.linalg.solve) for random u and k*."""
-    rng = np.random.default_rng(4)
-    for _ in range(50):
-        rho, u = rand_state(rng, 0.3)
-        ks = rng.normal(size=19)
-        ks[0] = rho
-        f_closed = orc.fstar(orc.rstar(rho, u, ks))
-        f_lib = np.linalg.solve(orc.T(u), ks)
-        assert np.allclose(f_closed, f_lib, rtol=0, atol=1e-12)
-
-
-def test_pdf_closed_form_is_printed_M_inverse(orc):
-    """The App. C population formulas are the inverse of the printed M."""
-    M = printed_M()
-    rng = np.random.default_rng(5)
-    for _ in range(20):
-        r = rng.normal(size=19)
-        assert np.allclose(orc.fstar(r), np.linalg.solve(M, r), atol=1e-13)
-
-
-def test_forcing_raw_moments_printed_list(orc):
-    """App. B: R^RM (eq. RMQ19) = N^-1 R^CM (eq. CMQ19), with N^-1 taken from
-    the oracle's App. C closed forms (k* = R^CM, rho = 0 drops the rho terms)."""
+def test_forcing_moments_gaussian_rule(orc):
+    """App. B: the forcing CMs (eq. CMQ19, the oracle's R^CM) and the raw
+    moments of the same forcing term (eq. RMQ19; the oracle's M T(u)^-1 R^CM)
+    both follow the Gaussian rule R_pqr = sum_a p_a F_a m_{pqr-e_a}/rho on the
+    central and raw equilibrium moments; the velocity-space term
+    F_i = M^-1 R^RM carries zero mass, momentum F and momentum flux
+    u F + F u (Guo's forcing moments)."""
     rng = np.random.default_rng(6)
     M = printed_M()
-    order = ["000", "100", "010", "001", None, None, None, "110", "101", "011",
-             "210", "120", "201", "102", "021", "012", "220", "202", "022"]
+    c, _, _ = orc.tables()
     for _ in range(20):
-        ux, uy, uz = rng.uniform(-0.3, 0.3, 3)
-        Fx, Fy, Fz = rng.normal(size=3)
-        Rrm = {
-            "000": 0.0, "100": Fx, "010": Fy, "001": Fz,
-            "200": 2 * ux * Fx, "020": 2 * uy * Fy, "002": 2 * uz * Fz,
-            "110": ux * Fy + uy * Fx, "101": ux * Fz + uz * Fx, "011": uy * Fz + uz * Fy,
-            "210": CS2 * Fy + ux * (ux * Fy + 2 * uy * Fx),
-            "120": CS2 * Fx + uy * (uy * Fx + 2 * ux * Fy),
-            "201": CS2 * Fz + ux * (ux * Fz + 2 * uz * Fx),
-            "102": CS2 * Fx + uz * (uz * Fx + 2 * ux * Fz),
-            "021": CS2 * Fz + uy * (uy * Fz + 2 * uz * Fy),
-            "012": CS2 * Fy + uz * (uz * Fy + 2 * uy * Fz),
-            "220": 2 * (ux * uy * (ux * Fy + uy * Fx) + CS2 * (ux * Fx + uy * Fy)),
-            "202": 2 * (ux * uz * (ux * Fz + uz * Fx) + CS2 * (ux * Fx + uz * Fz)),
-            "022": 2 * (uy * uz * (uy * Fz + uz * Fy) + CS2 * (uy * Fy + uz * Fz)),
-        }
-        want = np.array([Rrm[o] if o else 0.0 for o in order])
-        # rows 4..6 of M are combinations of the second-order raw moments
-        want[4] = Rrm["200"] + Rrm["020"] + Rrm["002"]
-        want[5] = Rrm["200"] - Rrm["020"]
-        want[6] = Rrm["020"] - Rrm["002"]
-        got = orc.rstar(0.0, [ux, uy, uz], orc.Rcm([Fx, Fy, Fz]))
-        assert np.allclose(got, want, atol=1e-14)
-        # and the velocity-space forcing F_i = M^-1 R^RM has the moments of R^RM
-        Fi = np.linalg.solve(M, want)
-        assert np.allclose(M @ Fi, want, atol=1e-13)
+        u = rng.uniform(-0.3, 0.3, 3)
+        F = rng.normal(size=3)
+        assert np.allclose(orc.Rcm(F), mf.forcing_central(F), atol=1e-15)
+        Rrm = orc.Rrm(u, F)
+        assert np.allclose(Rrm, mf.forcing_raw(u, F), atol=1e-14)
+        Fi = np.linalg.solve(M, Rrm)
+        assert abs(Fi.sum()) < 1e-14
+        assert np.allclose(Fi @ c, F, atol=1e-14)
+        assert np.allclose(np.einsum("i,ia,ib->ab", Fi, c, c), np.outer(u, F) + np.outer(F, u), atol=1e-14)
+
+
+def test_dense_solve_matches_library_solve(orc):
+    """f* from the oracle's elimination solves T(u) f* = k*: it equals
+    numpy.linalg.solve on the same system (k* rebuilt from the returned
+    pre-collision moments and the printed relaxation rule)."""
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        rho, u = rand_state(rng, 0.2)
+        f = orc.feq(rho, u) * (1 + 0.1 * rng.uniform(-1, 1, 19))
+        F = 1e-2 * rng.normal(size=3)
+        K = orc.K(rng.uniform(0.1, 1.99), rng.uniform(0.1, 1.99), rng.uniform(0.1, 1.99, 9))
+        fs, k, rr, uu = orc.collide(f, F, K, 0)
+        ks = (1 - K) * k + K * mf.eq_central(rr) + (1 - K / 2) * mf.forcing_central(F)
+        assert np.allclose(fs, np.linalg.solve(orc.T(uu), ks), rtol=0, atol=1e-13)
 
 
 # --------------------------------------------------------------------------
 # Collision (Sec. II.B eqs. posColl0, system)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 2])
 def test_equilibrium_is_fixed_point(orc, mode):
     """collide(f_eq) = f_eq for any rates when F = 0."""
     rng = np.random.default_rng(7)
@@ -205,7 +179,7 @@ def test_equilibrium_is_fixed_point(orc, mode):
         assert np.allclose(fs, fe, atol=1e-15)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 2])
 def test_collision_conserves_mass_and_adds_force(orc, mode):
     """sum f* = sum f and sum f* c = sum f c + F at every node (reading R2)."""
     c, w, _ = orc.tables()
@@ -220,24 +194,11 @@ def test_collision_conserves_mass_and_adds_force(orc, mode):
         assert np.allclose(fs @ c, f @ c + F, rtol=0, atol=1e-15)
 
 
-def test_definition_and_closed_form_agree(orc):
-    """Definition mode (dense T(u) solve) and the App. C closed forms agree to 1e-13."""
-    rng = np.random.default_rng(9)
-    for _ in range(200):
-        rho, u = rand_state(rng, 0.2)
-        f = orc.feq(rho, u) * (1 + 0.1 * rng.uniform(-1, 1, 19))
-        F = 1e-2 * rng.normal(size=3)
-        K = orc.K(rng.uniform(0.1, 1.99), rng.uniform(0.1, 1.99), rng.uniform(0.1, 1.99, 9))
-        a, _, _, _ = orc.collide(f, F, K, 0)
-        b, _, _, _ = orc.collide(f, F, K, 1)
-        assert np.allclose(a, b, rtol=0, atol=1e-13)
-
-
 def test_single_rate_is_bgk_with_guo_forcing(orc):
     """Sec. II.B: with every non-conserved rate equal to w, Lambda = T^-1 K T = w I
     and the scheme is BGK with the extended equilibrium and the (1 - w/2) F_i
-    forcing, F_i = M^-1 R^RM (App. B).  Built here from the printed M, the
-    printed R^RM list and the printed f_eq -- none of the CM machinery."""
+    forcing, F_i = M^-1 R^RM (App. B).  Built here from the printed M and the
+    product / Gaussian-rule moment forms -- none of the CM machinery."""
     c, w, _ = orc.tables()
     M = printed_M()
     rng = np.random.default_rng(10)
@@ -247,27 +208,14 @@ def test_single_rate_is_bgk_with_guo_forcing(orc):
         F = 1e-2 * rng.normal(size=3)
         om = rng.uniform(0.2, 1.95)
         K = orc.K(om, om, np.full(9, om))
-        fs, _, rho_o, u_o = orc.collide(f, F, K, 1)
+        fs, _, rho_o, u_o = orc.collide(f, F, K, 0)
         # macroscopic fields, force-shifted (reading R2)
         rr = f.sum()
         uu = (f @ c + 0.5 * F) / rr
         assert np.isclose(rho_o, rr) and np.allclose(u_o, uu)
-        ux, uy, uz = uu
-        Fx, Fy, Fz = F
-        Rrm = np.array([
-            0.0, Fx, Fy, Fz,
-            2 * (ux * Fx + uy * Fy + uz * Fz),
-            2 * (ux * Fx - uy * Fy), 2 * (uy * Fy - uz * Fz),
-            ux * Fy + uy * Fx, ux * Fz + uz * Fx, uy * Fz + uz * Fy,
-            CS2 * Fy + ux * (ux * Fy + 2 * uy * Fx), CS2 * Fx + uy * (uy * Fx + 2 * ux * Fy),
-            CS2 * Fz + ux * (ux * Fz + 2 * uz * Fx), CS2 * Fx + uz * (uz * Fx + 2 * ux * Fz),
-            CS2 * Fz + uy * (uy * Fz + 2 * uz * Fy), CS2 * Fy + uz * (uz * Fy + 2 * uy * Fz),
-            2 * (ux * uy * (ux * Fy + uy * Fx) + CS2 * (ux * Fx + uy * Fy)),
-            2 * (ux * uz * (ux * Fz + uz * Fx) + CS2 * (ux * Fx + uz * Fz)),
-            2 * (uy * uz * (uy * Fz + uz * Fy) + CS2 * (uy * Fy + uz * Fz)),
-        ])
-        Fi = np.linalg.solve(M, Rrm)
-        bgk = f + om * (orc.feq(rr, uu) - f) + (1 - om / 2) * Fi
+        feq = np.linalg.solve(M, mf.eq_raw(rr, uu))
+        Fi = np.linalg.solve(M, mf.forcing_raw(uu, F))
+        bgk = f + om * (feq - f) + (1 - om / 2) * Fi
         assert np.allclose(fs, bgk, rtol=0, atol=1e-14)
 
 
@@ -298,7 +246,7 @@ def test_precollision_cms_by_binomial_shift(orc):
     for _ in range(64):  # the 4^3 nodes
         f = rng.uniform(0.01, 0.2, 19)
         F = 1e-2 * rng.normal(size=3)
-        _, k, rho, u = orc.collide(f, F, orc.K(1.3), 1)
+        _, k, rho, u = orc.collide(f, F, orc.K(1.3), 0)
         for r, b in enumerate(basis):
             if b is None:
                 continue
@@ -321,7 +269,7 @@ def test_post_collision_cms_match_printed_list(orc):
         f = orc.feq(rho, u) * (1 + 0.05 * rng.uniform(-1, 1, 19))
         Fx, Fy, Fz = 1e-2 * rng.normal(size=3)
         om = rng.uniform(0.2, 1.95)
-        fs, k, rho_o, u_o = orc.collide(f, (Fx, Fy, Fz), orc.K(om), 1)
+        fs, k, rho_o, u_o = orc.collide(f, (Fx, Fy, Fz), orc.K(om), 0)
         ks = orc.T(u_o) @ fs
         want = np.array([
             rho_o, Fx / 2, Fy / 2, Fz / 2, 3 * rho_o * CS2,

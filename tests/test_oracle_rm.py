@@ -1,15 +1,17 @@
 """Pins of the oracle's raw-moment variant (App. C with N = I: the classical
 raw-moment MRT in the paper's basis) against facts outside its own code: the
-printed matrix M, the population equilibrium of Sec. II.A, the central-moment
-forcing of App. B, the printed post-collision list of App. C, invariants and
-the linear (von Neumann) modes about rest."""
+printed matrix M, the shifted-product raw moments of the equilibrium and the
+Gaussian-rule raw moments of the forcing term (App. B, C), the App. C
+post-collision rule, invariants and the linear (von Neumann) modes about
+rest."""
 import numpy as np
 import pytest
 
+import moment_forms as mf
 from test_oracle_physics import linear_operator, printed_M
 
 CS2 = 1.0 / 3.0
-RM_MODES = [2, 3]  # oracle.RM_DEFINITION, oracle.RM_CLOSED_FORM
+RM_MODES = [2]  # oracle.RM_DEFINITION
 
 
 def rand_pops(orc, rng, amp=0.08, neq=0.01):
@@ -26,27 +28,24 @@ def test_M_is_the_printed_matrix(orc):
     assert np.array_equal(orc.M(), printed_M())
 
 
-def test_raw_equilibrium_is_M_times_population_equilibrium(orc):
-    """The printed raw equilibrium list equals M f_eq with the printed M and
-    the population equilibrium of Sec. II.A."""
+def test_raw_equilibrium_is_the_shifted_product(orc):
+    """The raw-moment variant's equilibrium (App. C's list) is the raw moments
+    of the Galilean-invariant equilibrium: rho prod_a mu_{p_a}(u_a)."""
     rng = np.random.default_rng(11)
-    M = printed_M()
     for _ in range(50):
         rho = 1.0 + 0.2 * rng.uniform(-1, 1)
         u = 0.3 * rng.uniform(-1, 1, 3)
-        assert np.allclose(orc.keq_rm(rho, u), M @ orc.feq(rho, u), atol=1e-15)
+        assert np.allclose(orc.keq_rm(rho, u), mf.eq_raw(rho, u), atol=1e-15)
 
 
-def test_raw_forcing_is_raw_moments_of_the_cm_forcing(orc):
-    """App. B: R^RM are the raw moments of the velocity-space forcing term
-    whose central moments are R^CM (eq. CMQ19): R^RM = M T(u)^-1 R^CM."""
+def test_raw_forcing_is_the_gaussian_rule(orc):
+    """App. B: R^RM (eq. RMQ19) are the raw moments of the forcing term whose
+    CMs are R^CM; both follow the Gaussian rule on the equilibrium moments."""
     rng = np.random.default_rng(12)
-    M = printed_M()
     for _ in range(30):
         u = 0.3 * rng.uniform(-1, 1, 3)
         F = rng.normal(size=3)
-        Fi = np.linalg.solve(orc.T(u), orc.Rcm(F))
-        assert np.allclose(orc.Rrm(u, F), M @ Fi, atol=1e-14)
+        assert np.allclose(orc.Rrm(u, F), mf.forcing_raw(u, F), atol=1e-14)
 
 
 @pytest.mark.parametrize("mode", RM_MODES)
@@ -57,20 +56,9 @@ def test_unit_rates_equal_the_cm_scheme(orc, mode):
     for _ in range(30):
         f = rand_pops(orc, rng)
         F = 1e-3 * rng.normal(size=3)
-        want, *_ = orc.collide(f, F, orc.K(1.0), mode=1)
+        want, *_ = orc.collide(f, F, orc.K(1.0), mode=0)
         got, *_ = orc.collide(f, F, orc.K(1.0), mode=mode)
         assert np.abs(got - want).max() < 1e-15
-
-
-def test_definition_and_closed_form_agree(orc):
-    rng = np.random.default_rng(14)
-    for _ in range(30):
-        f = rand_pops(orc, rng)
-        F = 1e-3 * rng.normal(size=3)
-        Kd = rand_K(orc, rng)
-        a, *_ = orc.collide(f, F, Kd, mode=2)
-        b, *_ = orc.collide(f, F, Kd, mode=3)
-        assert np.abs(a - b).max() < 1e-15
 
 
 @pytest.mark.parametrize("mode", RM_MODES)
@@ -99,7 +87,8 @@ def test_collision_conserves_mass_and_adds_force(orc, mode):
 def test_post_collision_matches_printed_list_without_force(orc):
     """App. C post-collision raw moments with the paper's rates and F = 0:
     k5..k9 relax with w towards their equilibrium, all other rows are set to
-    it; k5..k9 are the printed sums over f (eq. PreCollCMS)."""
+    it (the shifted-product raw equilibrium); k5..k9 are the sums over f of
+    eq. (PreCollCMS)."""
     rng = np.random.default_rng(17)
     M = printed_M()
     c, _, _ = orc.tables()
@@ -112,19 +101,9 @@ def test_post_collision_matches_printed_list_without_force(orc):
         k5 = np.sum(f * (cx ** 2 - cy ** 2))
         k6 = np.sum(f * (cy ** 2 - cz ** 2))
         k7, k8, k9 = np.sum(f * cx * cy), np.sum(f * cx * cz), np.sum(f * cy * cz)
-        X, Y, Z = ux ** 2 + CS2, uy ** 2 + CS2, uz ** 2 + CS2
-        want = np.array([
-            rho, rho * ux, rho * uy, rho * uz,
-            rho * (3 * CS2 + ux ** 2 + uy ** 2 + uz ** 2),
-            (1 - om) * k5 + om * rho * (ux ** 2 - uy ** 2),
-            (1 - om) * k6 + om * rho * (uy ** 2 - uz ** 2),
-            (1 - om) * k7 + om * rho * ux * uy,
-            (1 - om) * k8 + om * rho * ux * uz,
-            (1 - om) * k9 + om * rho * uy * uz,
-            rho * uy * X, rho * ux * Y, rho * uz * X, rho * ux * Z, rho * uz * Y, rho * uy * Z,
-            rho * X * Y, rho * X * Z, rho * Y * Z,
-        ])
-        fs, *_ = orc.collide(f, (0.0, 0.0, 0.0), orc.K(om), mode=3)
+        want = mf.eq_raw(rho, (ux, uy, uz))
+        want[5:10] = (1 - om) * np.array([k5, k6, k7, k8, k9]) + om * want[5:10]
+        fs, *_ = orc.collide(f, (0.0, 0.0, 0.0), orc.K(om), mode=2)
         assert np.allclose(M @ fs, want, atol=1e-15)
 
 
@@ -133,8 +112,8 @@ def test_differs_from_cm_away_from_unit_rates(orc):
     different non-equilibrium combinations, so the variants must differ."""
     rng = np.random.default_rng(18)
     f = rand_pops(orc, rng, amp=0.1, neq=0.05)
-    a, *_ = orc.collide(f, (0.0, 0.0, 0.0), orc.K(1.7), mode=1)
-    b, *_ = orc.collide(f, (0.0, 0.0, 0.0), orc.K(1.7), mode=3)
+    a, *_ = orc.collide(f, (0.0, 0.0, 0.0), orc.K(1.7), mode=0)
+    b, *_ = orc.collide(f, (0.0, 0.0, 0.0), orc.K(1.7), mode=2)
     assert np.abs(a - b).max() > 1e-7
 
 
@@ -151,7 +130,7 @@ def test_linear_modes_match_von_neumann(orc):
     z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
     phase = np.exp(1j * (kvec[0] * x + kvec[1] * y + kvec[2] * z))
     pert = np.real(v0[:, None, None, None] * phase[None])
-    runs = [orc.run(w[:, None, None, None] + s * A * pert, steps, Kd, mode=3) for s in (+1, -1)]
+    runs = [orc.run(w[:, None, None, None] + s * A * pert, steps, Kd, mode=2) for s in (+1, -1)]
     lin = (runs[0] - runs[1]) / (2 * A)
     vt = np.linalg.matrix_power(linear_operator(orc, Kd, kvec), steps) @ v0
     want = np.real(vt[:, None, None, None] * phase[None])
@@ -171,7 +150,7 @@ def test_lattice_conservation_with_random_force(orc, walls):
     mass0 = f.sum()
     mom0 = c.T @ f.reshape(19, -1).sum(axis=1)
     steps = 5
-    f = orc.run(f, steps, orc.K(1.6, 1.3, np.full(9, 1.2)), F=F, walls_y=walls, mode=3)
+    f = orc.run(f, steps, orc.K(1.6, 1.3, np.full(9, 1.2)), F=F, walls_y=walls, mode=2)
     assert abs(f.sum() - mass0) / mass0 < 1e-14
     if not walls:
         mom = c.T @ f.reshape(19, -1).sum(axis=1)
