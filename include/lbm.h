@@ -349,7 +349,7 @@ int lbm_abi_version(void);
  *
  * Network: inputs x = (rho - 1, (k4 - rho)/rho, k10..k15 / rho,
  * (k16..k18 - rho/9)/rho) of the node's pre-collision CMs, each multiplied by
- * 1/scale_j; two tanh layers of 32; outputs z; omega_hi_j = 1 + z_j.  If any
+ * 1/scale_j; two ReLU layers of 32; outputs z; omega_hi_j = 1 + z_j.  If any
  * omega_hi_j is outside (0, 2) the node uses the paper's rates (all 1) and is
  * counted as a fallback.  Products run on BF16 MFMA with FP32 accumulation.
  * Parameters: LBM_MLP_NPARAM floats W1[32][11], b1[32], W2[32][32], b2[32],

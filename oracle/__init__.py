@@ -99,6 +99,8 @@ def lib():
         L.orc_mlp_rates.restype = i32
         L.orc19_step_mlp.argtypes = [i32, i32, i32, i32, dp, dp, dp, f64, dp, dp, i32]
         L.orc19_step_mlp.restype = ctypes.c_int64
+        L.orc19_step_mlp_info.argtypes = [i32, i32, i32, i32, dp, dp, dp, f64, dp, dp, i32, f64, dp, dp]
+        L.orc19_step_mlp_info.restype = ctypes.c_int64
         L.orc19_mlp_loss_grad.argtypes = [i32, i32, i32, dp, dp, f64, dp, dp, dp, i32, dp, i64p]
         L.orc19_mlp_loss_grad.restype = f64
         L.orc_pf_tables7.argtypes = [ip, dp]
@@ -474,6 +476,25 @@ class mlp:
         if fb < 0:
             raise ArithmeticError("singular collision system")
         return out, int(fb)
+
+    @staticmethod
+    def step_info(f, omega, P, scales, F=None, walls_y=False, tie_ulps=64.0):
+        """One BF16-emulating step; also returns per node (nz, ny, nx) how far
+        its post-collision populations move if its values within tie_ulps of
+        a bf16 tie round the other way (summed over those roundings, each
+        flipped alone) and the smallest distance of its rates from the ends of
+        (0, 2)."""
+        f = _f64(f)
+        _, nz, ny, nx = f.shape
+        out = np.empty_like(f)
+        flip = np.empty((nz, ny, nx))
+        margin = np.empty((nz, ny, nx))
+        Fa = None if F is None else _f64(F)
+        fb = lib().orc19_step_mlp_info(nx, ny, nz, int(bool(walls_y)), _p(f), _p(out), _p(Fa), float(omega),
+                                       _p(_f64(P)), _p(_f64(scales)), 1, float(tie_ulps), _p(flip), _p(margin))
+        if fb < 0:
+            raise ArithmeticError("singular collision system")
+        return out, int(fb), flip, margin
 
     @staticmethod
     def run(f, nsteps, omega, P, scales, F=None, walls_y=False, bf16=False):

@@ -10,14 +10,15 @@
  *   L1  inputs (11): rho - 1, (k4 - rho)/rho, k10..k15 / rho,
  *       (k16..k18 - rho cs^4)/rho, each divided by a fixed per-feature scale;
  *       k are the pre-collision CMs T(u) f of Sec. II.B.
- *   L2  network 11 -> 32 -> 32 -> 9, tanh hidden, linear output z, rates
- *       omega_hi_j = 1 + z_j.  If any omega_hi_j leaves (0, 2) the node uses
- *       the paper's rates (all 1) -- the fallback.
+ *   L2  network 11 -> 32 -> 32 -> 9, ReLU hidden layers (max(s, 0)), linear
+ *       output z, rates omega_hi_j = 1 + z_j.  If any omega_hi_j leaves (0, 2)
+ *       the node uses the paper's rates (all 1) -- the fallback.
  *   L3  parameter vector (1737 doubles): W1[32][11], b1[32], W2[32][32], b2[32],
  *       W3[9][32], b3[9]; W[out][in], row-major.
  *   L4  optional BF16 emulation of the GPU: the inputs of each matrix product
  *       (features, hidden activations) are rounded to float then to bfloat16
- *       (round to nearest even); weights are passed already rounded.
+ *       (round to nearest even); weights are passed already rounded.  The
+ *       gradient treats each rounding as the identity.
  *   L5  training target: one D3Q19 step (collide with learned rates, stream)
  *       from a state f(t); loss = mean over nodes of
  *       sum_k ((m_k(f(t+1)) - target_k) / sigma_k)^2 with the 10 raw moments
@@ -77,6 +78,81 @@ void orc_mlp_features(double rho, const double *k, const double *scales, double 
     for (int j = 0; j < NIN; ++j) x[j] = raw[j] / scales[j];
 }
 
+/* Distance of v from the nearest bf16 rounding tie (a value halfway between
+ * two adjacent bf16 numbers), in units of 2^-24 * scale: how far an FP32
+ * evaluation of v, in error by a few 2^-24 * scale, can stray before it
+ * rounds to a different bf16 value than v does.  Zero has no tie near it. */
+static double bf16_tie_ulps(double v, double scale)
+{
+    float f = (float)v;
+    if (f == 0.0f || !isfinite(f) || !(scale > 0.0) || !isfinite(scale)) return INFINITY;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    const uint32_t mid = (u & 0xffff0000u) | 0x8000u; /* the tie inside v's bf16 interval */
+    float m;
+    memcpy(&m, &mid, 4);
+    return fabs(v - (double)m) / (ldexp(1.0, -24) * scale);
+}
+
+/* The bf16 neighbour of v other than the one v rounds to (round to nearest
+ * even): the value an FP32 evaluation of v on the other side of the tie
+ * rounds to. */
+static double bf16_other(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u; /* the rounded pattern */
+    const uint32_t t = u & 0xffff0000u;                                 /* truncated towards zero */
+    const uint32_t o = (r == t) ? t + 0x10000u : t;
+    float g;
+    memcpy(&g, &o, 4);
+    return (double)g;
+}
+
+/* BF16-emulating forward (reading L4) in which rounding number `flip` (inputs
+ * 0..10, first hidden layer 11..42, second 43..74; -1: none) takes the other
+ * bf16 neighbour.  If list != NULL, the roundings whose value lies within
+ * tol_ulps of a bf16 tie (bf16_tie_ulps; inputs against xscale[i], hidden
+ * pre-activations against the sum of the magnitudes of their terms) are
+ * written to list (*nlist entries, at most 75). */
+static void forward_flip(const double *P, const double *x, int flip, const double *xscale, double tol_ulps, int *list,
+                         int *nlist, double *z)
+{
+    double xin[NIN], a1[NH], a2[NH];
+    int n = 0;
+    for (int i = 0; i < NIN; ++i) {
+        if (list && bf16_tie_ulps(x[i], xscale[i]) < tol_ulps) list[n++] = i;
+        xin[i] = (i == flip) ? bf16_other(x[i]) : orc_bf16(x[i]);
+    }
+    for (int o = 0; o < NH; ++o) {
+        double s = B1(P)[o], mag = fabs(B1(P)[o]);
+        for (int i = 0; i < NIN; ++i) {
+            s += W1(P)[o * NIN + i] * xin[i];
+            mag += fabs(W1(P)[o * NIN + i] * xin[i]);
+        }
+        if (list && s > 0.0 && bf16_tie_ulps(s, mag) < tol_ulps) list[n++] = NIN + o;
+        const double a = s > 0.0 ? s : 0.0;
+        a1[o] = (NIN + o == flip && s > 0.0) ? bf16_other(a) : orc_bf16(a);
+    }
+    for (int o = 0; o < NH; ++o) {
+        double s = B2(P)[o], mag = fabs(B2(P)[o]);
+        for (int i = 0; i < NH; ++i) {
+            s += W2(P)[o * NH + i] * a1[i];
+            mag += fabs(W2(P)[o * NH + i] * a1[i]);
+        }
+        if (list && s > 0.0 && bf16_tie_ulps(s, mag) < tol_ulps) list[n++] = NIN + NH + o;
+        const double a = s > 0.0 ? s : 0.0;
+        a2[o] = (NIN + NH + o == flip && s > 0.0) ? bf16_other(a) : orc_bf16(a);
+    }
+    for (int o = 0; o < NOUT; ++o) {
+        double s = B3(P)[o];
+        for (int i = 0; i < NH; ++i) s += W3(P)[o * NH + i] * a2[i];
+        z[o] = s;
+    }
+    if (nlist) *nlist = n;
+}
+
 /* Reading L2 forward; optional buffers receive the values used in the
  * products (after BF16 rounding when bf16 != 0). */
 void orc_mlp_forward(const double *P, const double *x, int bf16, double *xq, double *h1, double *h2, double *z)
@@ -86,13 +162,13 @@ void orc_mlp_forward(const double *P, const double *x, int bf16, double *xq, dou
     for (int o = 0; o < NH; ++o) {
         double s = B1(P)[o];
         for (int i = 0; i < NIN; ++i) s += W1(P)[o * NIN + i] * xin[i];
-        a1[o] = tanh(s);
+        a1[o] = s > 0.0 ? s : 0.0;
         if (bf16) a1[o] = orc_bf16(a1[o]);
     }
     for (int o = 0; o < NH; ++o) {
         double s = B2(P)[o];
         for (int i = 0; i < NH; ++i) s += W2(P)[o * NH + i] * a1[i];
-        a2[o] = tanh(s);
+        a2[o] = s > 0.0 ? s : 0.0;
         if (bf16) a2[o] = orc_bf16(a2[o]);
     }
     for (int o = 0; o < NOUT; ++o) {
@@ -103,6 +179,20 @@ void orc_mlp_forward(const double *P, const double *x, int bf16, double *xq, dou
     if (xq) memcpy(xq, xin, sizeof xin);
     if (h1) memcpy(h1, a1, sizeof a1);
     if (h2) memcpy(h2, a2, sizeof a2);
+}
+
+
+/* Smallest distance of the rates 1 + z from the ends of (0, 2) (negative when
+ * one is outside). */
+static double rate_margin(const double *z)
+{
+    double m = INFINITY;
+    for (int j = 0; j < NOUT; ++j) {
+        const double w = 1.0 + z[j];
+        const double d = w < 2.0 - w ? w : 2.0 - w;
+        if (d < m) m = d;
+    }
+    return m;
 }
 
 /* rates 1 + z, or all 1 when any leaves (0, 2); returns 1 on fallback */
@@ -148,9 +238,17 @@ static inline int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n :
  * per node the MLP sets omega_hi from the node's pre-collision CMs, then the
  * collision of Sec. II.B and streaming proceed as in orc19_step.  Returns the
  * number of nodes that fell back to the paper's rates (or -1 on error).
+ * Optional per-node outputs (N each), with bf16: tie, how far the node's
+ * post-collision populations can move if its FP32 values near a bf16 tie
+ * round the other way -- every rounding within tie_ulps of a tie
+ * (forward_flip; an input's scale is the sum of |f_i - w_i| over the node
+ * divided by rho, times the input's 1/scale) is flipped alone and the largest
+ * population change of each flip is summed; margin, the smallest distance of
+ * the node's rates from the ends of (0, 2).
  */
-int64_t orc19_step_mlp(int nx, int ny, int nz, int walls_y, const double *f, double *fnew, const double *F,
-                       double omega, const double *P, const double *scales, int bf16)
+int64_t orc19_step_mlp_info(int nx, int ny, int nz, int walls_y, const double *f, double *fnew, const double *F,
+                            double omega, const double *P, const double *scales, int bf16, double tie_ulps,
+                            double *tie, double *margin)
 {
     int c[3 * Q], opp[Q];
     double wt[Q];
@@ -167,10 +265,37 @@ int64_t orc19_step_mlp(int nx, int ny, int nz, int walls_y, const double *f, dou
             for (int d = 0; d < 3; ++d) Fl[d] = F[(int64_t)d * N + n];
         node_cms(fl, Fl, &rho, u, k);
         orc_mlp_features(rho, k, scales, xf);
-        orc_mlp_forward(P, xf, bf16, NULL, NULL, NULL, zz);
+        int list[NIN + 2 * NH], nlist = 0;
+        if (bf16 && (tie || margin)) {
+            double dev = 0.0, xsc[NIN];
+            for (int i = 0; i < Q; ++i) dev += fabs(fl[i] - wt[i]);
+            for (int j = 0; j < NIN; ++j) xsc[j] = dev / rho / scales[j];
+            forward_flip(P, xf, -1, xsc, tie_ulps, list, &nlist, zz);
+        } else {
+            orc_mlp_forward(P, xf, bf16, NULL, NULL, NULL, zz);
+        }
+        if (margin) margin[n] = rate_margin(zz);
         fallbacks += orc_mlp_rates(zz, rates);
         orc19_K(omega, 1.0, rates, Kd);
         if (orc19_collide(fl, Fl, Kd, 0, fs, NULL, NULL, NULL) != 0) err |= 1;
+        if (tie) {
+            /* each listed rounding taken the other way, one at a time: the
+             * sum of the largest changes of the node's post-collision
+             * populations */
+            double eff = 0.0;
+            for (int q = 0; q < nlist; ++q) {
+                double z2[NOUT], r2[NOUT], K2[Q], f2[Q];
+                forward_flip(P, xf, list[q], NULL, 0.0, NULL, NULL, z2);
+                orc_mlp_rates(z2, r2);
+                orc19_K(omega, 1.0, r2, K2);
+                if (orc19_collide(fl, Fl, K2, 0, f2, NULL, NULL, NULL) != 0) err |= 1;
+                double d = 0.0;
+                for (int i = 0; i < Q; ++i)
+                    if (fabs(f2[i] - fs[i]) > d) d = fabs(f2[i] - fs[i]);
+                eff += d;
+            }
+            tie[n] = eff;
+        }
         for (int i = 0; i < Q; ++i) {
             int yd = y + c[3 * i + 1];
             if (walls_y && (yd < 0 || yd >= ny)) {
@@ -182,6 +307,12 @@ int64_t orc19_step_mlp(int nx, int ny, int nz, int walls_y, const double *f, dou
         }
     }
     return err ? -1 : fallbacks;
+}
+
+int64_t orc19_step_mlp(int nx, int ny, int nz, int walls_y, const double *f, double *fnew, const double *F,
+                       double omega, const double *P, const double *scales, int bf16)
+{
+    return orc19_step_mlp_info(nx, ny, nz, walls_y, f, fnew, F, omega, P, scales, bf16, 0.0, NULL, NULL);
 }
 
 /* The 10 raw moments of reading L5 for one node's populations. */
@@ -320,7 +451,7 @@ double orc19_mlp_loss_grad(int nx, int ny, int nz, const double *f, const double
             for (int i = 0; i < NH; ++i) {
                 double s = 0.0;
                 for (int o = 0; o < NOUT; ++o) s += W3(P)[o * NH + i] * dz[o];
-                dh2[i] = s * (1.0 - h2[i] * h2[i]);
+                dh2[i] = h2[i] > 0.0 ? s : 0.0; /* ReLU: slope 1 where active */
             }
             for (int o = 0; o < NH; ++o) {
                 gB2[o] += dh2[o];
@@ -329,7 +460,7 @@ double orc19_mlp_loss_grad(int nx, int ny, int nz, const double *f, const double
             for (int i = 0; i < NH; ++i) {
                 double s = 0.0;
                 for (int o = 0; o < NH; ++o) s += W2(P)[o * NH + i] * dh2[o];
-                dh1[i] = s * (1.0 - h1[i] * h1[i]);
+                dh1[i] = h1[i] > 0.0 ? s : 0.0;
             }
             for (int o = 0; o < NH; ++o) {
                 gB1[o] += dh1[o];

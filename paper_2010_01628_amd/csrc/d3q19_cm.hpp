@@ -58,17 +58,25 @@ struct bf16_t {
 };
 
 template <class S> struct Codec;
+// increment: the collision returns s + (f* - f), the change computed from the
+// non-equilibrium moments alone (post_collide_increment), rather than f*
+// rebuilt from its moments (post_collide).  Used for FP32 storage, whose
+// long-run error it keeps at the storage rounding's; the rebuilt form's
+// roundings, relative to the equilibrium-sized moments, add ~100 times that.
 template <> struct Codec<double> {
+    static constexpr bool increment = false;
     using R = double;
     __device__ static inline double dec(double v) { return v; }
     __device__ static inline double enc(double v) { return v; }
 };
 template <> struct Codec<float> {
+    static constexpr bool increment = true;
     using R = float;
     __device__ static inline float dec(float v) { return v; }
     __device__ static inline float enc(float v) { return v; }
 };
 template <> struct Codec<_Float16> {
+    static constexpr bool increment = false;
     using R = float;
     __device__ static inline float dec(_Float16 v) { return (float)v; }
     // the empty asm keeps the last FP32 operation of the collision from being
@@ -82,6 +90,7 @@ template <> struct Codec<_Float16> {
     }
 };
 template <> struct Codec<bf16_t> {
+    static constexpr bool increment = false;
     using R = float;
     __device__ static inline float dec(bf16_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
     __device__ static inline bf16_t enc(float v)
@@ -367,20 +376,59 @@ template <class R> __host__ __device__ inline void post_collide(const CMState<R>
     pops_from_raw(p, s);
 }
 
+// Second half in increment form: f* - f = T(u)^-1 (k* - k), where k* - k =
+// -K (k - k_eq) + (I - K/2) R is formed from the non-equilibrium CMs, then
+// shifted back with +u and mapped to populations; s += that change.  Every
+// term is of the size of the non-equilibrium part, so the only rounding of
+// equilibrium size is the final addition.  st.n must hold all non-equilibrium
+// CMs (pre_collide with GENERAL = true).
+template <class R> __host__ __device__ inline void post_collide_increment(const CMState<R>& st, RawMoments<R>& p, R s[19])
+{
+    const RawMoments<R>& n = st.n;
+    p.m000 = R(0);
+    p.m100 -= n.m100;
+    p.m010 -= n.m010;
+    p.m001 -= n.m001;
+    p.m200 -= n.m200;
+    p.m020 -= n.m020;
+    p.m002 -= n.m002;
+    p.m110 -= n.m110;
+    p.m101 -= n.m101;
+    p.m011 -= n.m011;
+    p.m210 -= n.m210;
+    p.m120 -= n.m120;
+    p.m201 -= n.m201;
+    p.m102 -= n.m102;
+    p.m021 -= n.m021;
+    p.m012 -= n.m012;
+    p.m220 -= n.m220;
+    p.m202 -= n.m202;
+    p.m022 -= n.m022;
+    shift_all(p, st.ux, st.uy, st.uz);
+    R d[19];
+    pops_from_raw(p, d);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) s[i] += d[i];
+}
+
 // The collision of Sec. II.B eq. (posColl0) applied to deviations s (in place).
-// GENERAL = false assumes the paper's rates (omega_bulk = 1, omega_hi = 1).
-template <class R, bool GENERAL>
+// GENERAL = false assumes the paper's rates (omega_bulk = 1, omega_hi = 1);
+// INC selects the increment form of the second half.
+template <class R, bool GENERAL, bool INC = false>
 __host__ __device__ inline void collide_cm(R s[19], R rho0, R Fx, R Fy, R Fz, const Rates<R>& rt, NodeMacro<R>& mac)
 {
     CMState<R> st;
-    pre_collide<R, GENERAL>(s, rho0, Fx, Fy, Fz, st);
+    pre_collide<R, GENERAL || INC>(s, rho0, Fx, Fy, Fz, st);
     mac.rho = st.rho;
     mac.ux = st.ux;
     mac.uy = st.uy;
     mac.uz = st.uz;
     RawMoments<R> p;
     relax<R, GENERAL>(st, rt, p);
-    post_collide(st, p, s);
+    if constexpr (INC)
+        post_collide_increment(st, p, s);
+    else
+        post_collide(st, p, s);
 }
 
 // Raw-moment variant (App. C with N = I, the classical MRT in the paper's

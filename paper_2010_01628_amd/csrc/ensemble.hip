@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_ens_step(const S* __restrict__ src_all,
         ph.omega_bulk = 1.0;
         for (int j = 0; j < 9; ++j) ph.omega_hi[j] = 1.0;
         NodeMacro<R> mac;
-        L::template collide<R, false>(s, (R)rho0, R(0), R(0), R(0), ph, mac);
+        L::template collide<R, false, Codec<S>::increment>(s, (R)rho0, R(0), R(0), R(0), ph, mac);
         scatter<L, S, AB, false, true, O32>(dst_all + bd.off, g.stride, d, s);
     }
 }
@@ -136,7 +136,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             relax<float, false>(st, rt, p);
         else
             relax<float, true>(st, rt, p);
-        post_collide(st, p, s);
+        if constexpr (Codec<S>::increment)
+            post_collide_increment(st, p, s);
+        else
+            post_collide(st, p, s);
         if (valid) scatter<LatD3Q19, S, AB, false, true, O32>(dst_all + bd.off, g.stride, d, s);
         my_fb += (valid && fb) ? 1u : 0u;
     }

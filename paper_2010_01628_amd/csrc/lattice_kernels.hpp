@@ -47,10 +47,10 @@ struct LatD3Q19 {
     __host__ __device__ static constexpr int cz(int i) { return cz19(i); }
     __host__ __device__ static constexpr int opp(int i) { return opp19(i); }
     __host__ __device__ static constexpr double w(int i) { return w19(i); }
-    template <class R, bool GENERAL>
+    template <class R, bool GENERAL, bool INC = false>
     __device__ static void collide(R* s, R rho0, R Fx, R Fy, R Fz, const Phys& ph, NodeMacro<R>& mac)
     {
-        collide_cm<R, GENERAL>(s, rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
+        collide_cm<R, GENERAL, INC>(s, rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
     }
     template <class R> __device__ static void eq(R rho, R rho0, R ux, R uy, R uz, R* s)
     {
@@ -60,7 +60,7 @@ struct LatD3Q19 {
 
 // Same lattice, raw-moment collision (App. C with N = I).
 struct LatD3Q19RM : LatD3Q19 {
-    template <class R, bool GENERAL>
+    template <class R, bool GENERAL, bool INC = false>
     __device__ static void collide(R* s, R rho0, R Fx, R Fy, R Fz, const Phys& ph, NodeMacro<R>& mac)
     {
         collide_rm<R, GENERAL>(s, rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
@@ -74,7 +74,7 @@ struct LatD3Q27 {
     __host__ __device__ static constexpr int cz(int i) { return cz27(i); }
     __host__ __device__ static constexpr int opp(int i) { return opp27(i); }
     __host__ __device__ static constexpr double w(int i) { return w27(i); }
-    template <class R, bool GENERAL>
+    template <class R, bool GENERAL, bool INC = false>
     __device__ static void collide(R* s, R rho0, R Fx, R Fy, R Fz, const Phys& ph, NodeMacro<R>& mac)
     {
         collide_cm27<R>(s, rho0, Fx, Fy, Fz, (R)ph.omega, mac);
@@ -87,7 +87,7 @@ struct LatD3Q27 {
 
 // Same lattice, raw-moment collision (N = I).
 struct LatD3Q27RM : LatD3Q27 {
-    template <class R, bool GENERAL>
+    template <class R, bool GENERAL, bool INC = false>
     __device__ static void collide(R* s, R rho0, R Fx, R Fy, R Fz, const Phys& ph, NodeMacro<R>& mac)
     {
         collide_rm27<R>(s, rho0, Fx, Fy, Fz, (R)ph.omega, mac);
@@ -364,7 +364,7 @@ __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys
     R Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
-    L::template collide<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    L::template collide<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
     scatter<L, S, P, WALLS, NT, O32>(dst, g.stride, d, s);
 }
 
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(W) void k_step_ab_rows(const S* __restrict__ src, S
     R Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
-    L::template collide<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    L::template collide<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
     if (valid) scatter<L, S, AB, false, NT, O32>(dst, g.stride, d, s);
 }
 
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(W) void k_step_aa_odd_rows(S* __restrict__ buf, Geo
     R Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
-    L::template collide<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    L::template collide<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
     __syncthreads(); // every staged value has been taken out of LDS
     {
         int k = 0;

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_mhd_step(const S* __restrict__ fsrc, S*
     R rho, u0[3], b[3], j[3], F[3];
     mhd_node(s, g, gm, ph, mc, n, y, rho, u0, b, j, F);
     NodeMacro<R> mac;
-    collide_cm<R, false>(s, (R)ph.rho0, F[0], F[1], F[2], rates_of<R>(ph), mac);
+    collide_cm<R, false, Codec<S>::increment>(s, (R)ph.rho0, F[0], F[1], F[2], rates_of<R>(ph), mac);
     scatter<LatD3Q19, S, AB, WALLS, NT>(fdst, gm.stride, d, s);
     mag_collide(g, b, mac.ux, mac.uy, mac.uz, (R)mc.omega_m);
 #pragma unroll

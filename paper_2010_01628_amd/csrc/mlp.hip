@@ -72,7 +72,10 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
         relax<float, false>(st, rt, p); // the paper's rates: the plain step's arithmetic, bit for bit
     else
         relax<float, true>(st, rt, p);
-    post_collide(st, p, s);
+    if constexpr (Codec<S>::increment)
+        post_collide_increment(st, p, s);
+    else
+        post_collide(st, p, s);
     if (valid) scatter<LatD3Q19, S, P, WALLS, NT, O32>(dst, g.stride, d, s);
     // fallback count: one atomic add per wavefront that has fallen-back
     // nodes (none in normal operation), so a wavefront neither waits for the
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__
             if (o < MLP_NOUT) gp[MLP_OFF_W3 + o * 32 + (l & 31)] = acc[r];
         }
     }
-    // db3, and dh2 = (dz W3) * (1 - h2^2)
+    // db3, and dh2 = (dz W3) * relu'(h2)
     if (l < MLP_NOUT) {
         float sb = 0.0f;
         for (int q = 0; q < 64; ++q) sb += bf16_to_f32(tdz[q * MLP_LDS_STRIDE + l]);
@@ -234,11 +237,11 @@ __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__
         for (int r = 0; r < 16; ++r) {
             const int row = acc_row(rb, r), h = l & 31;
             const float a2 = bf16_to_f32(th2[row * MLP_LDS_STRIDE + h]);
-            tdh[row * MLP_LDS_STRIDE + h] = f32_to_bf16(acc[r] * (1.0f - a2 * a2));
+            tdh[row * MLP_LDS_STRIDE + h] = f32_to_bf16(a2 > 0.0f ? acc[r] : 0.0f);
         }
     }
     __syncthreads();
-    // dW2, db2, dh1 = (dh2 W2) * (1 - h1^2) written over tdz
+    // dW2, db2, dh1 = (dh2 W2) * relu'(h1) written over tdz
     {
         const f32x16_t acc = mfma_AtB(tdh, th1);
 #pragma unroll
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__
         for (int r = 0; r < 16; ++r) {
             const int row = acc_row(rb, r), h = l & 31;
             const float a1 = bf16_to_f32(th1[row * MLP_LDS_STRIDE + h]);
-            tdz[row * MLP_LDS_STRIDE + h] = f32_to_bf16(acc[r] * (1.0f - a1 * a1));
+            tdz[row * MLP_LDS_STRIDE + h] = f32_to_bf16(a1 > 0.0f ? acc[r] : 0.0f);
         }
     }
     __syncthreads();

@@ -1,19 +1,20 @@
 // Learned higher-order relaxation rates: a per-node MLP on BF16 MFMA.
 //
 // Network (not in the paper; it replaces the fixed rate 1 of the CMs k10..k18
-// of Sec. II.B): 11 inputs -> 32 tanh -> 32 tanh -> 9 linear outputs z,
+// of Sec. II.B): 11 inputs -> 32 ReLU -> 32 ReLU -> 9 linear outputs z,
 // omega_hi = 1 + z; any rate outside (0, 2) sends the node back to the
 // paper's rates.  Inputs: rho - 1, (k4 - rho)/rho, k10..k15/rho and
 // (k16..k18 - rho/9)/rho, each times a fixed inverse scale.
 //
 // One wavefront evaluates the network for its 64 nodes (one per lane) with
-// v_mfma_f32_32x32x8bf16_1k: every layer is Y[64 x 32] = X[64 x K] W^T[K x 32]
-// as two 32-row blocks.  MFMA operand layout (lane l, v = 0..3):
+// v_mfma_f32_32x32x8bf16_1k.  MFMA operand layout (lane l, v = 0..3):
 //   A[l % 32][4 (l / 32) + v],  B[4 (l / 32) + v][l % 32],
 //   D: acc[r] = D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-// Activations move between the accumulator layout and the operand layout
-// through per-wavefront LDS tiles (rows = nodes, bf16).  Products take BF16
-// operands and accumulate in FP32; biases, tanh and the rates are FP32.
+// Inference (the step kernels) keeps the activations in registers
+// (mlp_forward_regs); training (mlp_forward_wave) moves them through
+// per-wavefront LDS tiles (rows = nodes, bf16), which its weight-gradient
+// products need.  Products take BF16 operands and accumulate in FP32; biases
+// and the rates are FP32; ReLU is applied to the bf16 activations.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -63,18 +64,9 @@ __host__ __device__ inline float bf16_to_f32(uint16_t b)
     return f;
 }
 
-// tanh for activations that are rounded to bf16 next: 1 - 2/(exp(2x) + 1)
-// with the hardware exp and reciprocal (~1 ulp each).  Its absolute error,
-// ~1e-7, is relatively large only for |x| << 1e-2, where the activation's
-// bf16 ulp is below 1e-9 and its contribution to the next layer is
-// negligible.  exp(2x) = 2^(x * 2 log2 e): one product, which rounds as
-// (2x) * log2 e does since both scalings by two are exact; four VALU
-// operations per activation, two of them the quarter-rate exp and rcp.
-__device__ inline float tanh_fast(float x)
-{
-    constexpr float two_log2e = 0x1.715476p+1f; // 2 * float(log2 e)
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(x * two_log2e) + 1.0f);
-}
+// ReLU of a value that is rounded to bf16 next: max(x, 0).  Rounding keeps
+// the sign and zero, so ReLU then round equals round then ReLU.
+__device__ inline float relu(float x) { return x > 0.0f ? x : 0.0f; }
 
 // LDS tile of 64 rows (nodes) of bf16; stride 36 keeps 8-byte alignment and
 // halves bank conflicts of column-parallel reads.
@@ -122,7 +114,7 @@ __device__ inline void mlp_forward_wave(const MlpPacked& W, uint16_t* tx, uint16
         const f32x16_t acc = mfma_xwT<16>(tx, rb, W.w1, 16);
         const float bias = W.b1[l & 31];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) th1[acc_row(rb, r) * MLP_LDS_STRIDE + (l & 31)] = f32_to_bf16(tanh_fast(acc[r] + bias));
+        for (int r = 0; r < 16; ++r) th1[acc_row(rb, r) * MLP_LDS_STRIDE + (l & 31)] = f32_to_bf16(relu(acc[r] + bias));
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -132,7 +124,7 @@ __device__ inline void mlp_forward_wave(const MlpPacked& W, uint16_t* tx, uint16
         const f32x16_t acc = mfma_xwT<32>(th1, rb, W.w2, 32);
         const float bias = W.b2[l & 31];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) th2[acc_row(rb, r) * MLP_LDS_STRIDE + (l & 31)] = f32_to_bf16(tanh_fast(acc[r] + bias));
+        for (int r = 0; r < 16; ++r) th2[acc_row(rb, r) * MLP_LDS_STRIDE + (l & 31)] = f32_to_bf16(relu(acc[r] + bias));
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -224,13 +216,25 @@ __device__ inline f32x16_t bias_acc(const float* b)
     return acc;
 }
 
-// tanh and bf16 of an accumulator: the next layer's four B operands
+// ReLU of a pair of bf16 values packed in 32 bits: as 16-bit integers a bf16
+// pattern is negative exactly when its sign bit is set, so an integer max
+// with 0 zeroes the negative values (and -0) and keeps the others
+// (one v_pk_max_i16 per two activations).
+__device__ inline uint32_t relu_bf16x2(uint32_t p)
+{
+    typedef short s16x2_t __attribute__((ext_vector_type(2)));
+    const s16x2_t v = __builtin_bit_cast(s16x2_t, p);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, (s16x2_t){0, 0}));
+}
+
+// bf16 and ReLU of an accumulator: the next layer's four B operands
 __device__ inline void act_to_operands(const f32x16_t& acc, bf16x4_t op[4])
 {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        op[m] = pack_bf16(tanh_fast(acc[4 * m]), tanh_fast(acc[4 * m + 1]), tanh_fast(acc[4 * m + 2]),
-                          tanh_fast(acc[4 * m + 3]));
+        op[m] = __builtin_bit_cast(bf16x4_t, (u32x2){relu_bf16x2(pack2_bf16(acc[4 * m], acc[4 * m + 1])),
+                                                    relu_bf16x2(pack2_bf16(acc[4 * m + 2], acc[4 * m + 3]))});
 }
 
 // One 32-node column block through the three layers; o[q] = accumulator

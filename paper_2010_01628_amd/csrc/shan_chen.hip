@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_sc_step(const S* __restrict__ src, S* _
     R s[19];
     gather<LatD3Q19, S, AB, false, NT, O32>(src, g.stride, d, s);
     NodeMacro<R> mac;
-    collide_cm<R, GENERAL>(s, (R)ph.rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
+    collide_cm<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, rates_of<R>(ph), mac);
     scatter<LatD3Q19, S, AB, false, NT, O32>(dst, g.stride, d, s);
 }
 

@@ -1,11 +1,33 @@
 """Accuracy of every storage precision and streaming pattern over a long run:
-the config-2 recipe (Taylor-Green U0 = 0.05 + seeded noise 1e-4, nu = 1e-3,
-Kolmogorov force 1e-6) at 64^3 and 128^3 for 1000 steps against the FP64
-oracle run once per size on the host; relative L2 of u and of rho -
-mean(rho).  (The timed 256^3 lattice is checked at full size step by step in
-test_gpu_fullsize.py; 1000 oracle steps at 256^3 would take the host ~10
-minutes.)"""
-import numpy as np
+the timed workload's recipe (Taylor-Green U0 = 0.05 + seeded noise 1e-4,
+nu = 1e-3, Kolmogorov force 1e-6) at 64^3 and 128^3 for 1000 steps against
+the FP64 oracle run once per size on the host; relative L2 of u and of
+rho - mean(rho).  (The 256^3 lattice is checked at full size step by step in
+test_gpu_fullsize.py.)
+
+The bounds come from the workload's own conditioning under storage rounding,
+measured with the oracle alone (tests/golden/conditioning.py ->
+conditioning_config2.json): the FP64 scheme with its stored deviations
+rounded to FP32, FP16 or BF16 after every step.  That is the error the
+storage format costs by itself; the GPU adds its FP32 collision arithmetic.
+
+  FP32: the stated tolerance 1e-5 on u and on rho - mean(rho).  The increment
+        form of the collision (f* = f + change, the change built from
+        non-equilibrium moments) leaves one equilibrium-sized rounding per
+        population and step, next to the storage rounding: within
+        FP32_FACTOR of the storage-only error.  (The form that rebuilt f* from
+        equilibrium-sized moments measured 1.9e-5 / 3.0e-5 at 64^3, 280 and 50
+        times the storage-only error.)
+  FP16, BF16: the error is the storage's (FP32 arithmetic rounds 2^8 and 2^16
+        times finer): within X16_FACTOR of the storage-only error, the margin
+        covering rounding decisions that differ between the GPU's FP32 values
+        and the oracle's FP64 ones.  FP16 also meets 1e-3 on u; BF16 cannot
+        (its storage alone costs 2.8e-2 on u at 64^3 -- reading recorded with
+        the measurements).
+"""
+import json
+import os
+
 import pytest
 
 from gpu_helpers import gpu_run, rel_l2, rel_l2_fluct, say
@@ -15,18 +37,10 @@ from paper_2010_01628_amd import lbm as L
 pytestmark = pytest.mark.gpu
 
 STEPS, NU = 1000, 1e-3
-# bounds per size and storage precision, about twice the measured values
-# (u / rho - mean(rho), the same for A-B and AA):
-#   64^3:  FP32 1.9e-5 / 3.0e-5, FP16 6.0e-4 / 5.7e-3, BF16 2.8e-2 / 7.6e-2
-#   128^3: FP32 2.5e-5 / 3.2e-5, FP16 4.9e-4 / 9.1e-3, BF16 3.5e-2 / 1.07
-# 16-bit storage rounds every population at every step, so its error grows
-# with the step count (64^3 at 200 steps: FP16 3.3e-4, BF16 3.0e-3).  With
-# BF16's 8-bit mantissa the density fluctuations (~1e-3 of rho) are lost at
-# 128^3: deterministic rounding of a smooth field is nearly the same at
-# neighbouring nodes and drives long acoustic modes that viscosity hardly
-# damps at this size; the bound there only guards against blow-up.
-TOL_U = {64: {"fp32": 5e-5, "fp16": 2e-3, "bf16": 6e-2}, 128: {"fp32": 5e-5, "fp16": 1e-3, "bf16": 7e-2}}
-TOL_RHO = {64: {"fp32": 1e-4, "fp16": 2e-2, "bf16": 0.15}, 128: {"fp32": 1e-4, "fp16": 2e-2, "bf16": 2.5}}
+STATED = {"fp32": 1e-5, "fp16": 1e-3}  # relative L2 on u (and on rho - mean(rho) for FP32)
+FP32_FACTOR = {"u": 4.0, "rho_fluct": 8.0}
+X16_FACTOR = 1.5
+COND = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "conditioning_config2.json")))
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -38,7 +52,11 @@ def _gpu():
     L.lib()
 
 
-@pytest.fixture(scope="module", params=[64, 128])
+# the sizes whose storage-only errors have been measured for every precision (64 and 128)
+SIZES = sorted(int(k) for k, v in COND.items() if all(p in v for p in ("fp32", "fp16", "bf16")))
+
+
+@pytest.fixture(scope="module", params=SIZES)
 def reference(orc, request):
     N = request.param
     say(f"oracle: {N}^3, {STEPS} steps (FP64, host)")
@@ -54,9 +72,18 @@ def reference(orc, request):
 @pytest.mark.parametrize("streaming", ["ab", "aa"])
 def test_long_run_error(reference, precision, streaming):
     N, rho, u, ro, uo = reference
-    say(f"{precision} {streaming}: {N}^3, {STEPS} steps")
+    cond = COND[str(N)][precision][str(STEPS)]
+    say(f"{precision} {streaming}: {N}^3, {STEPS} steps; storage alone: u {cond['u']:.3e}, "
+        f"rho - mean(rho) {cond['rho_fluct']:.3e}")
     g = gpu_run(N, N, N, rho, u, STEPS, precision, streaming, omega=inputs.omega_from_nu(NU),
                 force_mode=L.LBM_FORCE_KOLMOGOROV, kolmogorov_amp=1e-6, want_pops=False)
-    eu, er = rel_l2(g["u"], uo), rel_l2_fluct(g["rho"], ro)
-    say(f"  rel L2 u = {eu:.3e}, rho - mean(rho) = {er:.3e}")
-    assert eu < TOL_U[N][precision] and er < TOL_RHO[N][precision]
+    err = {"u": rel_l2(g["u"], uo), "rho_fluct": rel_l2_fluct(g["rho"], ro)}
+    say(f"  rel L2 u = {err['u']:.3e} ({err['u'] / cond['u']:.2f} x storage alone), rho - mean(rho) = "
+        f"{err['rho_fluct']:.3e} ({err['rho_fluct'] / cond['rho_fluct']:.2f} x)")
+    for k in ("u", "rho_fluct"):
+        factor = FP32_FACTOR[k] if precision == "fp32" else X16_FACTOR
+        assert err[k] <= factor * cond[k]
+    if precision == "fp32":
+        assert err["u"] <= STATED["fp32"] and err["rho_fluct"] <= STATED["fp32"]
+    if precision == "fp16":
+        assert err["u"] <= STATED["fp16"]

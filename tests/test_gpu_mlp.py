@@ -43,10 +43,34 @@ def make_lattice(nx, ny, nz, f, omega, **kw):
     return lat
 
 
-# input scales and weight sizes keep every output rate well inside (0, 2):
-# near that boundary the fallback decision itself could differ between the
-# FP32 GPU and the FP64 oracle
 SCALES = np.array([0.05, 0.02, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3, 5e-3])
+
+# A value the GPU forms in FP32 and rounds to bf16 (a scaled input, a hidden
+# activation) can round to the other neighbour than the oracle's FP64 value
+# when it lies within the FP32 evaluation error of a bf16 tie.  The oracle
+# lists, per node, every rounding within TIE_ULPS x 2^-24 x (the size of the
+# terms the value is computed from) of a tie, takes each the other way and
+# reports how far the node's post-collision populations move (step_info).  A
+# population must then agree with the oracle to FP32 collision accuracy,
+# STRICT, plus that possible move of the node it came from.
+TIE_ULPS = 64.0
+STRICT = 2e-7
+
+
+def from_source(orc, v, walls):
+    """per-node values (nz, ny, nx) -> per population after one step
+    (19, nz, ny, nx): the value at the node the population was streamed from
+    (the node itself for a population bounced back at a y wall)."""
+    c, _, _ = orc.tables()
+    out = np.empty((19,) + v.shape, dtype=v.dtype)
+    for i in range(19):
+        src = np.roll(v, shift=(c[i, 2], c[i, 1], c[i, 0]), axis=(0, 1, 2))
+        if walls and c[i, 1] == 1:
+            src[:, 0, :] = v[:, 0, :]
+        if walls and c[i, 1] == -1:
+            src[:, -1, :] = v[:, -1, :]
+        out[i] = src
+    return out
 
 
 @pytest.mark.parametrize("streaming,walls", [("ab", False), ("aa", True)])
@@ -62,25 +86,67 @@ def test_mlp_step_matches_oracle(orc, streaming, walls):
     f0r = lat.get_populations().cpu().numpy()  # FP32-rounded start, shared with the oracle
     lat.attach_mlp(mlp)
     Pg = gpu_weights(orc, P)
-    g1 = None
-    for steps in (1, 4):
-        lat.step(1 if steps == 1 else 3)
-        g = lat.get_populations().cpu().numpy()
-        o, fb = orc.mlp.run(f0r, steps, om, Pg, SCALES, walls_y=walls, bf16=True)
-        d = np.abs(g - o)
-        err, p999 = d.max(), np.quantile(d, 0.999)
-        say(f"  {steps} steps: max |f_gpu - f_oracle| = {err:.3e}, 99.9% quantile {p999:.3e}, oracle fallbacks {fb}")
-        # An activation within FP32 round-off of a bf16 rounding boundary can round
-        # differently on the two sides (FP32 vs FP64 before rounding): one such
-        # flip moves a rate by ~W 2^-8 h and the node's populations by < 3e-6.
-        # Everything else agrees to FP32 collision accuracy.
-        assert fb == 0
-        assert err < (3e-6 if steps == 1 else 1e-5)
-        assert p999 < (2e-7 if steps == 1 else 1e-6)
-        if steps == 1:
-            g1 = g
+    lat.step(1)
+    g = lat.get_populations().cpu().numpy()
+    o, fb, flip, margin = orc.mlp.step_info(f0r, om, Pg, SCALES, walls_y=walls, tie_ulps=TIE_ULPS)
+    bound = STRICT + from_source(orc, flip, walls)
+    d = np.abs(g - o)
+    say(f"  1 step: max |f_gpu - f_oracle| {d.max():.3e}; max over bound {(d / bound).max():.3f}; "
+        f"{(flip > STRICT).sum()} of {flip.size} nodes with a possible tie flip above {STRICT:g} "
+        f"(largest {flip.max():.2e}); oracle fallbacks {fb}")
+    assert fb == 0 and margin.min() > 1e-2
+    assert np.all(d <= bound)
+    # three more steps: a flip's effect spreads to the neighbours it streams to
+    lat.step(3)
+    g4 = lat.get_populations().cpu().numpy()
+    o4, fb4 = orc.mlp.run(f0r, 4, om, Pg, SCALES, walls_y=walls, bf16=True)
+    d4 = np.abs(g4 - o4)
+    say(f"  4 steps: max {d4.max():.3e}, 99.9% quantile {np.quantile(d4, 0.999):.3e}")
+    assert fb4 == 0
+    assert d4.max() < 4 * (STRICT + flip.max()) and np.quantile(d4, 0.999) < 1e-6
     assert lat.fallback_count() == 0
-    assert g1 is not None
+    lat.close()
+    mlp.close()
+
+
+@pytest.mark.parametrize("bound", ["upper", "lower"])
+def test_fallback_decision_near_the_rate_bounds(orc, bound):
+    """Output 0 is driven to a rate just inside or just outside 2 (or 0) at
+    different nodes.  Where the oracle's rate is farther from the bound than
+    the FP32 evaluation error, the GPU takes the same decision (a tie flip
+    that changes it is in the oracle's flip effect); there the populations
+    agree as in the parity test.  Elsewhere the GPU matches one of the two
+    decisions."""
+    nx, ny, nz = 16, 12, 8
+    rng = np.random.default_rng(21)
+    P = 0.05 * rng.normal(size=L.MLP_NPARAM)
+    P[1440:1440 + 32] *= 8.0  # row 0 of W3: a wide spread of output 0 over the nodes
+    P[1728] = 0.999 if bound == "upper" else -0.999
+    f0 = noneq_state(orc, nx, ny, nz, 4)
+    om = 1.8
+    mlp = L.Mlp(P, SCALES)
+    lat = make_lattice(nx, ny, nz, f0, om)
+    f0r = lat.get_populations().cpu().numpy()
+    lat.attach_mlp(mlp)
+    Pg = gpu_weights(orc, P)
+    lat.step(1)
+    g = lat.get_populations().cpu().numpy()
+    o, fb_o, flip, margin = orc.mlp.step_info(f0r, om, Pg, SCALES, tie_ulps=TIE_ULPS)
+    plain = orc.step(f0r, orc.K(om))  # every node at the paper's rates
+    # a rate is an FP32 sum of 33 terms of size <~ 1 plus one: 2^-18 bounds its error
+    ambiguous = np.abs(margin) < 2.0 ** -18
+    src_amb = from_source(orc, ambiguous, False)
+    bound_p = STRICT + from_source(orc, flip, False)
+    fb_g = lat.fallback_count()
+    say(f"  {bound}: oracle fallbacks {fb_o}, GPU {fb_g}; nodes within FP32 error of the bound {ambiguous.sum()}; "
+        f"margins in [{margin.min():.2e}, {margin.max():.2e}]; largest flip effect {flip.max():.2e}")
+    assert 0 < fb_o < nx * ny * nz  # both decisions occur
+    assert abs(fb_g - fb_o) <= ambiguous.sum() + (flip > 1e-4).sum()
+    d = np.abs(g - o)
+    assert np.all(d[~src_amb] <= bound_p[~src_amb])
+    either = np.minimum(np.abs(g - o), np.abs(g - plain))
+    if src_amb.any():
+        assert np.all(either[src_amb] <= bound_p[src_amb])
     lat.close()
     mlp.close()
 
@@ -176,7 +242,7 @@ def test_gradient_matches_oracle(orc):
     err = np.linalg.norm(g - go) / np.linalg.norm(go)
     cos = g @ go / (np.linalg.norm(g) * np.linalg.norm(go))
     say(f"  gradient rel L2 err {err:.3e}, cosine {cos:.6f}")
-    assert err < 5e-2 and cos > 0.998
+    assert err < 1e-2 and cos > 0.999
     assert lat.step_count == 0  # the state is not advanced
     lat.close()
     mlp.close()

@@ -35,13 +35,13 @@ def test_bf16_rounding_matches_torch(M):
 
 
 def test_forward_matches_torch_layers(M):
-    """The network of reading L2 equals Linear-Tanh-Linear-Tanh-Linear from
+    """The network of reading L2 equals Linear-ReLU-Linear-ReLU-Linear from
     torch.nn in float64 with the same weights."""
     import torch
 
     P = small_params(M, 1, 0.3)
     u = M.unpack(P)
-    net = torch.nn.Sequential(torch.nn.Linear(11, 32), torch.nn.Tanh(), torch.nn.Linear(32, 32), torch.nn.Tanh(),
+    net = torch.nn.Sequential(torch.nn.Linear(11, 32), torch.nn.ReLU(), torch.nn.Linear(32, 32), torch.nn.ReLU(),
                               torch.nn.Linear(32, 9)).double()
     with torch.no_grad():
         for layer, (w, b) in zip([net[0], net[2], net[4]], [("W1", "b1"), ("W2", "b2"), ("W3", "b3")]):
@@ -151,3 +151,30 @@ def test_loss_at_paper_rates_is_plain_step_residual(orc, M):
                      c[:, 0] * c[:, 1], c[:, 0] * c[:, 2], c[:, 1] * c[:, 2]])
     m = np.einsum("ki,iabc->kabc", mono, g)
     assert np.isclose(loss, np.mean(np.sum(m ** 2, axis=0)), rtol=1e-13)
+
+
+def test_step_info_flip_effects(orc, M):
+    """step_info returns the populations of the BF16-emulating step unchanged;
+    with no rounding listed (tie_ulps = 0) every flip effect is zero; listing
+    more roundings (a wider tie band) never lowers a node's effect; a network
+    whose hidden layers are zero has only its inputs' roundings to flip and
+    they cannot move the rates (the first layer's weights are zero)."""
+    nx, ny, nz = 6, 5, 4
+    rng = np.random.default_rng(12)
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=13, umax=0.05)
+    f = orc.init(rho, u) * (1 + 0.02 * rng.uniform(-1, 1, (19, nz, ny, nx)))
+    P = small_params(M, 14, 0.1)
+    scales = np.full(11, 5e-3)
+    g, fb = M.step(f, 1.8, P, scales, bf16=True)
+    o0, fb0, e0, m0 = M.step_info(f, 1.8, P, scales, tie_ulps=0.0)
+    o1, fb1, e1, m1 = M.step_info(f, 1.8, P, scales, tie_ulps=64.0)
+    o2, fb2, e2, m2 = M.step_info(f, 1.8, P, scales, tie_ulps=4096.0)
+    assert np.array_equal(g, o0) and np.array_equal(g, o1) and fb == fb0 == fb1 == 0
+    assert np.all(e0 == 0.0)
+    assert np.all(e2 >= e1) and e2.max() > 0.0
+    assert np.array_equal(m0, m1)
+    Z = P.copy()
+    Z[0:1728] = 0.0  # W1, b1, W2, b2, W3 zero: z = b3 whatever the inputs
+    _, _, ez, mz = M.step_info(f, 1.8, Z, scales, tie_ulps=4096.0)
+    assert np.all(ez == 0.0)
+    assert np.allclose(mz, np.min(np.minimum(1 + Z[-9:], 1 - Z[-9:])), atol=1e-15)
