@@ -38,11 +38,11 @@ def elem_bytes(precision: str) -> int:
 
 
 def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fields, mlp=None, tune=True,
-                 moments="central"):
+                 moments="central", rounding="nearest"):
     nu = 1e-3
     p = L.make_params(size, size, size, precision=precision, streaming=streaming,
                       omega=inputs.omega_from_nu(nu), force_mode=L.LBM_FORCE_KOLMOGOROV,
-                      kolmogorov_amp=1e-6, moments=moments)
+                      kolmogorov_amp=1e-6, moments=moments, rounding=rounding, seed=20101628)
     lat = L.Lattice(p)
     rho_d, u_d = fields
     lat.init(rho_d, u_d)
@@ -90,23 +90,24 @@ def time_variant(L, inputs, torch, size, precision, streaming, steps, warmup, fi
     }
 
 
-def stream_copy_bandwidth(torch, L, n, eb=4, q=19, reps=10):
+def stream_copy_bandwidth(torch, L, n, eb=4, q=19, reps=10, lane=0):
     """Rate of the library's bandwidth reference (lbm_stream_copy): q arrays
-    of n elements copied with the step's access pattern and streaming hints,
-    read + write bytes per second, HIP events on the stream it runs on, best
-    of `reps` after two untimed launches."""
+    of n elements copied with the step's access pattern and streaming hints
+    (lane: bytes per thread and array, 0 = one element as the step), read +
+    write bytes per second, HIP events on the stream it runs on, best of
+    `reps` after two untimed launches."""
     dt = {2: torch.int16, 4: torch.int32, 8: torch.int64}[eb]
     a = torch.zeros(q * n, dtype=dt, device="cuda")
     b = torch.empty_like(a)
     st = torch.cuda.current_stream()
     for _ in range(2):
-        L.lbm_stream_copy(a.data_ptr(), b.data_ptr(), n, q, eb, True, st.cuda_stream)
+        L.lbm_stream_copy(a.data_ptr(), b.data_ptr(), n, q, eb, True, st.cuda_stream, lane_bytes=lane)
     torch.cuda.synchronize()
     best = float("inf")
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
-        L.lbm_stream_copy(a.data_ptr(), b.data_ptr(), n, q, eb, True, st.cuda_stream)
+        L.lbm_stream_copy(a.data_ptr(), b.data_ptr(), n, q, eb, True, st.cuda_stream, lane_bytes=lane)
         e1.record(st)
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1))
@@ -342,14 +343,15 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--streaming", default="ab", choices=["ab", "aa"])
     ap.add_argument("--variants",
-                    default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,bf16:aa,fp64:ab,fp32+mlp:ab,fp16+mlp:ab,fp32+raw:ab,fp16+raw:ab",
-                    help="extra precision[+mlp|+raw]:streaming pairs to time ('' = none); +mlp = learned "
-                         "rates, +raw = raw-moment collision (the N = I variant)")
+                    default="fp16:ab,bf16:ab,fp32:aa,fp16:aa,bf16:aa,fp64:ab,fp32+mlp:ab,fp16+mlp:ab,fp32+raw:ab,"
+                            "fp16+raw:ab,bf16+sr:ab",
+                    help="extra precision[+mlp|+raw|+sr]:streaming pairs to time ('' = none); +mlp = learned "
+                         "rates, +raw = raw-moment collision (the N = I variant), +sr = stochastic rounding")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-box ensemble workload")
     ap.add_argument("--no-coupled", action="store_true", help="skip the two-phase and magnetic workloads")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shape")
-    ap.add_argument("--mem-check", action="store_true",
-                    help="also run 512^3 AA FP32 and FP16 (device bytes and MLUPS)")
+    ap.add_argument("--no-mem-check", action="store_true",
+                    help="skip the 512^3 AA FP32 and FP16 memory check (device bytes and MLUPS)")
     ap.add_argument("--no-cost-table", action="store_true",
                     help="skip the D3Q19/D3Q27 x raw/central cost table over D = 32..128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -400,15 +402,16 @@ def main(argv=None):
         prec, _, plus = prec.partition("+")
         if (prec, strm) == (args.precision, args.streaming) and not plus:
             continue
-        if plus not in ("", "mlp", "raw"):
+        if plus not in ("", "mlp", "raw", "sr"):
             raise SystemExit(f"unknown variant modifier +{plus}")
         if plus == "mlp" and mlp is None:
             mlp = bench_network(L)
         log(f"bench: timing variant {spec}")
-        tag = {"": "", "mlp": "_learned", "raw": "_raw"}[plus]
+        tag = {"": "", "mlp": "_learned", "raw": "_raw", "sr": "_stochastic"}[plus]
         variants[f"{prec}{tag}_{strm}"] = time_variant(
             L, inputs, torch, size, prec, strm, max(20, args.steps // 4), max(5, args.warmup // 4), fields,
-            mlp=mlp if plus == "mlp" else None, tune=not args.no_tune, moments="raw" if plus == "raw" else "central")
+            mlp=mlp if plus == "mlp" else None, tune=not args.no_tune, moments="raw" if plus == "raw" else "central",
+            rounding="stochastic" if plus == "sr" else "nearest")
     del fields
     torch.cuda.empty_cache()
     ensemble = None
@@ -429,7 +432,7 @@ def main(argv=None):
         log("bench: cost table (Taylor-Green, D = 32..128)")
         cost = taylor_green.cost_table()
     mem = None
-    if args.mem_check:
+    if not args.no_mem_check:
         log("bench: 512^3 memory check")
         rho, u = inputs.taylor_green_noise(512, 0.05, 1e-4, seed=20101628)
         f512 = (torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
@@ -445,6 +448,10 @@ def main(argv=None):
     traffic = load_traffic(args.precision, args.streaming, size, head["algo_bytes_per_launch"])
     copy_gbs = copy_bandwidth(torch)
     ref_gbs = stream_copy_bandwidth(torch, L, size ** 3, eb=elem_bytes(args.precision))
+    # the same copy with wider accesses per thread: does the ceiling itself rise?
+    lane_gbs = {str(w): round(stream_copy_bandwidth(torch, L, size ** 3, eb=elem_bytes(args.precision), lane=w), 1)
+                for w in (8, 16) if w > elem_bytes(args.precision)}
+    lane_gbs[str(elem_bytes(args.precision))] = round(ref_gbs, 1)
     roof = {
         "bound": "hbm",
         "achieved": round(head["achieved_GBs"], 1),
@@ -460,6 +467,7 @@ def main(argv=None):
         "frac_of_torch_copy": round(head["achieved_GBs"] / copy_gbs, 4),
         "stream_copy_GBs": round(ref_gbs, 1),
         "frac_of_stream_copy": round(head["achieved_GBs"] / ref_gbs, 4),
+        "stream_copy_GBs_by_lane_bytes": lane_gbs,
     }
     cpu = None
     if not args.no_cpu_baseline:

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 5
+#define LBM_ABI_VERSION 6
 
 typedef enum {
     LBM_OK = 0,
@@ -62,6 +62,16 @@ typedef enum {
 /* Streaming pattern: two buffers (pull from the neighbours into the other
  * buffer) or one buffer updated in place (AA pattern, even/odd steps). */
 typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_streaming;
+
+/* Rounding of the stored populations.  Nearest (even) everywhere by default.
+ * Stochastic (BF16 storage of the plain D3Q19 central-moment lattice only):
+ * each post-collision population rounds up to the next BF16 value with
+ * probability equal to the fraction of the BF16 step it lies above the lower
+ * one, so rounding errors average out instead of repeating at neighbouring
+ * nodes of a smooth field.  The random bits are counter-based: a 32-bit hash
+ * of (seed, step count, node, population), so runs repeat bit for bit, and
+ * A-B and AA agree bit for bit.  Not a method of the paper: a storage option. */
+typedef enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 } lbm_rounding;
 
 typedef enum {
     LBM_FORCE_NONE = 0,
@@ -199,6 +209,10 @@ typedef struct {
                                  higher-order rates; initialised with lbm_init_colour; the
                                  populations of lbm_get/set_populations are red, those of
                                  lbm_get/set_coupled_populations blue */
+    int32_t rounding;         /* lbm_rounding; LBM_ROUND_STOCHASTIC needs q = 19, central moments,
+                                 LBM_BF16_SHIFTED, no coupled lattice and no network
+                                 (LBM_EUNSUPPORTED otherwise) */
+    uint32_t seed;            /* key of the stochastic rounding's random bits */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -404,14 +418,18 @@ int lbm_project_q27(const double *f27, int64_t n, double *f19, float *moments, v
  * method; for measuring how close a step comes to what its loads and stores
  * alone reach).  Copies q arrays of n elements of elem_bytes each, array k at
  * element offset k*n of src (device), to the same places in dst (device, not
- * overlapping src): each thread reads its element of all q arrays, then
- * writes them, as the A-B step does without its collision and neighbour
- * shifts.  q: 19 or 27; elem_bytes: 2, 4 or 8 (the storage types); nt != 0:
- * the step's non-temporal (streaming) hints.  n = 0 enqueues nothing.
- * Ordered on `stream` (NULL: the default stream), asynchronous.  Returns
- * LBM_EINVAL for a NULL buffer, n < 0 or beyond 2^31 work-groups of 256, or
- * another q or element size; LBM_EDEVICE if the launch fails. */
-int lbm_stream_copy(const void *src, void *dst, int64_t n, int32_t q, int32_t elem_bytes, int32_t nt, void *stream);
+ * overlapping src): each thread reads its part of all q arrays, then writes
+ * them, as the A-B step does without its collision and neighbour shifts.
+ * q: 19 or 27; elem_bytes: 2, 4 or 8 (the storage types); lane_bytes: bytes
+ * each thread moves per array -- 0 or elem_bytes (one element, as the step),
+ * or 8 or 16 (wider accesses; larger than elem_bytes and dividing
+ * n * elem_bytes); nt != 0: the step's non-temporal (streaming) hints.  n = 0
+ * enqueues nothing.  Ordered on `stream` (NULL: the default stream),
+ * asynchronous.  Returns LBM_EINVAL for a NULL buffer, n < 0 or beyond 2^31
+ * work-groups of 256, or another q, element or lane size; LBM_EDEVICE if the
+ * launch fails. */
+int lbm_stream_copy(const void *src, void *dst, int64_t n, int32_t q, int32_t elem_bytes, int32_t lane_bytes,
+                    int32_t nt, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Ensembles: many independent periodic cubic boxes (different sides and

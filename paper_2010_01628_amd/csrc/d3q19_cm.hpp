@@ -64,18 +64,21 @@ template <class S> struct Codec;
 // long-run error it keeps at the storage rounding's; the rebuilt form's
 // roundings, relative to the equilibrium-sized moments, add ~100 times that.
 template <> struct Codec<double> {
+    static constexpr bool stochastic = false;
     static constexpr bool increment = false;
     using R = double;
     __device__ static inline double dec(double v) { return v; }
     __device__ static inline double enc(double v) { return v; }
 };
 template <> struct Codec<float> {
+    static constexpr bool stochastic = false;
     static constexpr bool increment = true;
     using R = float;
     __device__ static inline float dec(float v) { return v; }
     __device__ static inline float enc(float v) { return v; }
 };
 template <> struct Codec<_Float16> {
+    static constexpr bool stochastic = false;
     static constexpr bool increment = false;
     using R = float;
     __device__ static inline float dec(_Float16 v) { return (float)v; }
@@ -90,6 +93,7 @@ template <> struct Codec<_Float16> {
     }
 };
 template <> struct Codec<bf16_t> {
+    static constexpr bool stochastic = false;
     static constexpr bool increment = false;
     using R = float;
     __device__ static inline float dec(bf16_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
@@ -101,6 +105,60 @@ template <> struct Codec<bf16_t> {
         return bf16_t{(uint16_t)(u >> 16)};
     }
 };
+
+// BF16 storage with stochastic rounding: after the collision the step kernels
+// round each population to a BF16 value themselves (dither_bf16): uniform
+// random bits are added below the 16 kept ones of its FP32 pattern and the
+// low 16 bits are cut, so it rounds up with probability equal to the fraction
+// it lies above the lower BF16 neighbour.  The stored value is then exact in
+// BF16 and enc (nearest even, as for bf16_t, which init and
+// lbm_set_populations also use) keeps it.  Same layout and decoding as bf16_t.
+struct bf16sr_t {
+    uint16_t bits;
+};
+template <> struct Codec<bf16sr_t> {
+    static constexpr bool stochastic = true;
+    static constexpr bool increment = false;
+    using R = float;
+    __device__ static inline float dec(bf16sr_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
+    __device__ static inline bf16sr_t enc(float v) { return bf16sr_t{Codec<bf16_t>::enc(v).bits}; }
+};
+
+// 32-bit integer hash "lowbias32" (C. Wellons, hash prospector; public
+// domain): xor-shift / multiply rounds, a bijection of 32-bit integers.
+__host__ __device__ inline uint32_t hash32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Stochastic rounding to BF16, counter-based: the post-collision populations
+// of node n in the step whose key is `key` (a hash of the seed and the step
+// count) take 16 random bits each from hash32(10 n + j + key), j = i / 2 (low
+// half for even i, high half for odd i), added to their FP32 patterns before
+// the low 16 bits are cut.  NaN and infinity are left alone.  The bits depend
+// on (seed, step, node, population) only: A-B and AA steps store the same
+// values.
+template <class R> __device__ inline void dither_bf16(R s[19], uint32_t key, uint32_t n)
+{
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        const uint32_t h = hash32(10u * n + (uint32_t)j + key);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = 2 * j + k;
+            if (i < 19) {
+                const uint32_t u = __float_as_uint(s[i]);
+                const uint32_t r = k ? (h >> 16) : (h & 0xffffu);
+                if ((u & 0x7f800000u) != 0x7f800000u) s[i] = __uint_as_float((u + r) & 0xffff0000u);
+            }
+        }
+    }
+}
 
 // Relaxation rates of the non-conserved rows of K (Sec. II.B).
 template <class R> struct Rates {

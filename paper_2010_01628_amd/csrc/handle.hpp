@@ -22,6 +22,7 @@ struct lbm_coupled {
 
 struct lbm_handle {
     lbm_params p;
+    int kprec = 0;                     // kernel storage type (lbm::PREC_*; BF16SR for stochastic rounding)
     int device = 0;
     hipStream_t stream = nullptr;
     lbm::Geom g{};

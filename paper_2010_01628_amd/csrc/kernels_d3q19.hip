@@ -1,4 +1,5 @@
-// D3Q19 instantiations of the lattice kernels (FP64, FP32, FP16, BF16 storage).
+// D3Q19 instantiations of the lattice kernels (FP64, FP32, FP16, BF16 storage;
+// BF16 with stochastic rounding).
 #include "lattice_kernels.hpp"
 
 namespace lbm {
@@ -9,6 +10,7 @@ template <class F> static void by_precision19(int precision, F&& f)
     case PREC_FP64: f(Launch<LatD3Q19, double>{}); break;
     case PREC_FP32: f(Launch<LatD3Q19, float>{}); break;
     case PREC_FP16: f(Launch<LatD3Q19, _Float16>{}); break;
+    case PREC_BF16SR: f(Launch<LatD3Q19, bf16sr_t>{}); break;
     default: f(Launch<LatD3Q19, bf16_t>{}); break;
     }
 }

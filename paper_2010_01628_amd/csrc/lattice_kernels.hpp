@@ -365,6 +365,7 @@ __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
     L::template collide<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    if constexpr (Codec<S>::stochastic) dither_bf16(s, ph.sr_key, (uint32_t)nb(d, 0, 0, 0));
     scatter<L, S, P, WALLS, NT, O32>(dst, g.stride, d, s);
 }
 
@@ -434,6 +435,7 @@ __global__ __launch_bounds__(W) void k_step_ab_rows(const S* __restrict__ src, S
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
     L::template collide<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    if constexpr (Codec<S>::stochastic) dither_bf16(s, ph.sr_key, (uint32_t)nb(d, 0, 0, 0));
     if (valid) scatter<L, S, AB, false, NT, O32>(dst, g.stride, d, s);
 }
 
@@ -500,6 +502,7 @@ __global__ __launch_bounds__(W) void k_step_aa_odd_rows(S* __restrict__ buf, Geo
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
     L::template collide<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
+    if constexpr (Codec<S>::stochastic) dither_bf16(s, ph.sr_key, (uint32_t)nb(d, 0, 0, 0));
     __syncthreads(); // every staged value has been taken out of LDS
     {
         int k = 0;

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "d3q19_cm.hpp"
 #include "handle.hpp"
 
 namespace {
@@ -108,6 +109,11 @@ int validate(const lbm_params* p)
     if (p->moments == LBM_RAW_MOMENTS && p->coupled != LBM_COUPLED_NONE)
         return fail(LBM_EUNSUPPORTED, "raw moments: no coupled lattice");
     if (p->coupled < LBM_COUPLED_NONE || p->coupled > LBM_COUPLED_COLOUR) return fail(LBM_EINVAL, "bad coupled");
+    if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC) return fail(LBM_EINVAL, "bad rounding");
+    if (p->rounding == LBM_ROUND_STOCHASTIC &&
+        (p->precision != LBM_BF16_SHIFTED || p->q != 19 || p->moments != LBM_CENTRAL_MOMENTS ||
+         p->coupled != LBM_COUPLED_NONE))
+        return fail(LBM_EUNSUPPORTED, "stochastic rounding: D3Q19 central moments with BF16 storage, no coupled lattice");
     if (p->coupled != LBM_COUPLED_NONE) return coupled_validate(p);
     return LBM_OK;
 }
@@ -184,7 +190,7 @@ int64_t pad_stride(int64_t N, int eb)
 
 int run_check(lbm_handle* h)
 {
-    lbm::launch_moments(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, nullptr, nullptr,
+    lbm::launch_moments(h->p.q, h->kprec, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, nullptr, nullptr,
                         h->partials, h->grid, h->block, h->stream);
     lbm::launch_reduce(h->partials, h->nblocks, h->diag_dev, h->stream);
     HIP_TRY(hipGetLastError());
@@ -225,6 +231,7 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
     if (rc) return rc;
     lbm_handle* h = new lbm_handle();
     h->p = *p;
+    h->kprec = p->rounding == LBM_ROUND_STOCHASTIC ? lbm::PREC_BF16SR : p->precision;
     h->stream = (hipStream_t)stream;
     auto cleanup = [&](int code) {
         lbm_destroy(h);
@@ -377,7 +384,7 @@ int lbm_init(lbm_handle* h, const double* rho, const double* u, int on_device)
     }
     h->steps = 0;
     h->cur = 0;
-    lbm::launch_init(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, drho, du, h->grid,
+    lbm::launch_init(h->p.q, h->kprec, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, drho, du, h->grid,
                      h->block, h->stream);
     hipError_t e = hipGetLastError();
     if (staging) {
@@ -415,8 +422,12 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
             lbm::launch_step_mlp(h->p.precision, pat, h->walls, h->nt, h->buf[src], h->buf[dst], h->g, h->ph,
                                  h->mlp->packed, h->fb_partials, h->grid, h->block, h->stream);
         else
-            lbm::launch_step(h->p.q, h->p.moments == LBM_RAW_MOMENTS, h->p.precision, pat, h->walls, h->general, h->nt, h->buf[src], h->buf[dst], h->g,
-                             h->ph, h->step_grid, h->step_block, h->stream);
+        {
+            // stochastic rounding: a new key per step (seed and step count hashed)
+            if (h->kprec == lbm::PREC_BF16SR) h->ph.sr_key = lbm::hash32(h->p.seed ^ lbm::hash32((uint32_t)h->steps));
+            lbm::launch_step(h->p.q, h->p.moments == LBM_RAW_MOMENTS, h->kprec, pat, h->walls, h->general, h->nt,
+                             h->buf[src], h->buf[dst], h->g, h->ph, h->step_grid, h->step_block, h->stream);
+        }
         h->cur = dst;
         h->steps++;
         if (h->p.check_every > 0 && h->steps % h->p.check_every == 0) {
@@ -445,7 +456,7 @@ int lbm_moments(lbm_handle* h, double* rho, double* u, double* diag, int on_devi
         drho = rho ? staging : nullptr;
         du = u ? staging + N : nullptr;
     }
-    lbm::launch_moments(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, drho, du, h->partials,
+    lbm::launch_moments(h->p.q, h->kprec, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, drho, du, h->partials,
                         h->grid, h->block, h->stream);
     if (diag) lbm::launch_reduce(h->partials, h->nblocks, h->diag_dev, h->stream);
     hipError_t e = hipGetLastError();
@@ -469,7 +480,7 @@ int lbm_get_populations(lbm_handle* h, double* f, int on_device)
     const int64_t bytes = sizeof(double) * h->p.q * (int64_t)h->g.N;
     double* dst = f;
     if (!on_device) HIP_TRY(hipMalloc((void**)&dst, bytes));
-    lbm::launch_get_pops(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, dst, h->grid,
+    lbm::launch_get_pops(h->p.q, h->kprec, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, dst, h->grid,
                          h->block, h->stream);
     hipError_t e = hipGetLastError();
     if (!on_device) {
@@ -492,7 +503,7 @@ int lbm_set_populations(lbm_handle* h, const double* f, int on_device)
         HIP_TRY(hipMemcpyAsync(staging, f, bytes, hipMemcpyHostToDevice, h->stream));
         src = staging;
     }
-    lbm::launch_set_pops(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, src, h->grid,
+    lbm::launch_set_pops(h->p.q, h->kprec, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->p.rho0, src, h->grid,
                          h->block, h->stream);
     hipError_t e = hipGetLastError();
     if (staging) {
@@ -537,7 +548,7 @@ int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* bloc
     if (h->cp || h->mlp) return fail(LBM_EUNSUPPORTED, "the tuner sets up the plain step (no coupled lattice or network)");
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, h->device));
-    TuneEntry key{prop.gcnArchName, h->g.nx, h->g.ny, h->g.nz, h->p.q, h->p.moments, h->p.precision,
+    TuneEntry key{prop.gcnArchName, h->g.nx, h->g.ny, h->g.nz, h->p.q, h->p.moments, h->kprec,
                   h->p.streaming, h->walls ? 1 : 0, h->general ? 1 : 0, 0, 0, 0, 0};
     auto same = [&](const TuneEntry& e) {
         return e.arch == key.arch && e.nx == key.nx && e.ny == key.ny && e.nz == key.nz && e.q == key.q &&
@@ -735,6 +746,7 @@ int lbm_set_mlp(lbm_handle* h, const lbm_mlp* m)
         if (h->p.moments != LBM_CENTRAL_MOMENTS)
             return fail(LBM_EUNSUPPORTED, "learned rates act on central moments");
         if (h->p.precision == LBM_FP64) return fail(LBM_EUNSUPPORTED, "learned rates run with FP32 collision");
+        if (h->p.rounding != LBM_ROUND_NEAREST) return fail(LBM_EUNSUPPORTED, "learned rates store to nearest");
         if (!h->fb_partials) {
             HIP_TRY(hipMalloc((void**)&h->fb_partials, sizeof(uint32_t) * h->nblocks));
             h->bytes += sizeof(uint32_t) * h->nblocks;
@@ -926,7 +938,7 @@ extern "C" int lbm_moments_noalloc(lbm_handle* h, double* rho, double* u, double
     if (rc) return rc;
     const int64_t gz = std::min<int64_t>(h->grid.z, NOALLOC_MAX_PARTIALS / plane_groups);
     const dim3 grid(h->grid.x, h->grid.y, (unsigned)gz);
-    lbm::launch_moments(h->p.q, h->p.precision, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, rho, u, part, grid,
+    lbm::launch_moments(h->p.q, h->kprec, pattern_of(h), h->walls, h->buf[h->cur], h->g, h->ph, rho, u, part, grid,
                         h->block, h->stream);
     if (diag) lbm::launch_reduce(part, (int)(plane_groups * gz), diag, h->stream, 6);
     HIP_TRY(hipGetLastError());

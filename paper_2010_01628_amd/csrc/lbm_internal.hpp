@@ -6,7 +6,9 @@
 
 namespace lbm {
 
-enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16 = 2, PREC_BF16 = 3 };
+// kernel storage types; PREC_BF16SR: BF16 with stochastic rounding (plain
+// D3Q19 central-moment steps only)
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16 = 2, PREC_BF16 = 3, PREC_BF16SR = 4 };
 enum { FORCE_NONE = 0, FORCE_UNIFORM = 1, FORCE_FIELD = 2, FORCE_ROW_TABLE = 3 };
 
 struct Geom {
@@ -26,6 +28,7 @@ struct Phys {
     double force[3];
     const double* force_field; // device, double[3N]
     const double* row_table;   // device, double[ny]: F_x per y row
+    uint32_t sr_key;           // stochastic rounding: key of the current step
 };
 
 #define LBM_DECLARE_LAUNCHERS(SUFFIX)                                                                              \

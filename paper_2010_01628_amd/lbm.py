@@ -19,12 +19,13 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3
 LBM_AB, LBM_AA = 0, 1
 LBM_FORCE_NONE, LBM_FORCE_UNIFORM, LBM_FORCE_FIELD, LBM_FORCE_KOLMOGOROV = 0, 1, 2, 3
 LBM_CENTRAL_MOMENTS, LBM_RAW_MOMENTS = 0, 1
+LBM_ROUND_NEAREST, LBM_ROUND_STOCHASTIC = 0, 1
 
 PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16_SHIFTED, "bf16": LBM_BF16_SHIFTED}
 STREAMING = {"ab": LBM_AB, "aa": LBM_AA}
@@ -83,6 +84,8 @@ class lbm_params(ctypes.Structure):
         ("moments", ctypes.c_int32),
         ("shan_chen", lbm_shan_chen_params),
         ("colour", lbm_colour_params),
+        ("rounding", ctypes.c_int32),
+        ("seed", ctypes.c_uint32),
     ]
 
 
@@ -133,7 +136,7 @@ def lib():
         L.lbm_mlp_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.lbm_feature_rms.argtypes = [vp, dp]
         L.lbm_project_q27.argtypes = [vp, i64, vp, vp, vp]
-        L.lbm_stream_copy.argtypes = [vp, vp, i64, i32, i32, i32, vp]
+        L.lbm_stream_copy.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp]
         class _box(ctypes.Structure):
             _fields_ = [("n", ctypes.c_int32), ("omega", ctypes.c_double)]
 
@@ -316,10 +319,11 @@ def lbm_feature_rms(h):
     return out
 
 
-def lbm_stream_copy(src_ptr, dst_ptr, n, q, elem_bytes, nt=True, stream=None):
+def lbm_stream_copy(src_ptr, dst_ptr, n, q, elem_bytes, nt=True, stream=None, lane_bytes=0):
     """Copy q arrays of n elements (device pointers) with the step's access
-    pattern: a bandwidth reference for the step kernels."""
-    _check(lib().lbm_stream_copy(src_ptr, dst_ptr, int(n), int(q), int(elem_bytes), 1 if nt else 0,
+    pattern: a bandwidth reference for the step kernels.  lane_bytes: bytes
+    per thread and array (0: one element, as the step; 8 or 16: wider)."""
+    _check(lib().lbm_stream_copy(src_ptr, dst_ptr, int(n), int(q), int(elem_bytes), int(lane_bytes), 1 if nt else 0,
                                  ctypes.c_void_p(stream or 0)))
 
 
@@ -449,14 +453,16 @@ class Ensemble:
 def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_bulk=1.0, omega_hi=None,
                 rho0=1.0, force_mode=LBM_FORCE_NONE, force=(0.0, 0.0, 0.0), kolmogorov_amp=0.0,
                 force_field_ptr=None, walls_y=False, check_every=0, block=(0, 0), cache_policy=0,
-                q=19, phase=None, magnetic=None, moments="central", shan_chen=None, colour=None) -> lbm_params:
+                q=19, phase=None, magnetic=None, moments="central", shan_chen=None, colour=None,
+                rounding="nearest", seed=0) -> lbm_params:
     """phase: dict(rho_light, rho_heavy, sigma, width, mobility) makes a
     two-phase lattice (coupled = LBM_COUPLED_PHASE); magnetic: dict(eta,
     b_wall=(bx, by, bz)) a magnetic one (LBM_COUPLED_MAGNETIC); moments:
     "central" (the paper's scheme) or "raw" (its N = I variant); shan_chen:
     dict(G) a Shan-Chen two-phase lattice (LBM_COUPLED_SHAN_CHEN); colour:
     dict(alpha_red, alpha_blue=1/3, A=0, beta=0.7, gravity=(0,0,0), rho_ref=0)
-    a colour-gradient lattice (LBM_COUPLED_COLOUR)."""
+    a colour-gradient lattice (LBM_COUPLED_COLOUR); rounding: "nearest" or
+    "stochastic" (BF16 storage), with its random-bit key `seed`."""
     p = lbm_params_default()
     p.q = int(q)
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -478,6 +484,9 @@ def make_params(nx, ny, nz, precision="fp32", streaming="ab", omega=1.0, omega_b
     p.block_x, p.block_y = int(block[0]), int(block[1])
     p.cache_policy = int(cache_policy)
     p.moments = MOMENTS[moments] if isinstance(moments, str) else int(moments)
+    p.rounding = {"nearest": LBM_ROUND_NEAREST, "stochastic": LBM_ROUND_STOCHASTIC}[rounding] \
+        if isinstance(rounding, str) else int(rounding)
+    p.seed = int(seed) & 0xFFFFFFFF
     if magnetic is not None:
         p.coupled = LBM_COUPLED_MAGNETIC
         p.magnetic.eta = float(magnetic["eta"])

@@ -215,13 +215,15 @@ def test_colour_lattice_validation(lbm, kw, code):
     assert e.value.code == code, lbm.lib().lbm_last_error().decode()
 
 
-@pytest.mark.parametrize("src,n,q,eb", [(0, 16, 19, 4), (64, -1, 19, 4), (64, 16, 15, 4), (64, 16, 19, 3),
-                                         (64, (1 << 31) * 256 + 1, 19, 4)])
-def test_stream_copy_validation(lbm, src, n, q, eb):
+@pytest.mark.parametrize("src,n,q,eb,lane", [(0, 16, 19, 4, 0), (64, -1, 19, 4, 0), (64, 16, 15, 4, 0),
+                                              (64, 16, 19, 3, 0), (64, (1 << 31) * 256 + 1, 19, 4, 0),
+                                              (64, 16, 19, 8, 4), (64, 16, 19, 4, 32), (64, 3, 19, 2, 8),
+                                              (64, 16, 19, 8, 7)])
+def test_stream_copy_validation(lbm, src, n, q, eb, lane):
     """The bandwidth reference rejects bad arguments before any device use
     (the pointers here are never dereferenced)."""
     with pytest.raises(lbm.LbmError) as e:
-        lbm.lbm_stream_copy(src, 64, n, q, eb)
+        lbm.lbm_stream_copy(src, 64, n, q, eb, lane_bytes=lane)
     assert e.value.code == lbm.LBM_EINVAL
     assert "lbm_stream_copy" in lbm.lib().lbm_last_error().decode()
 

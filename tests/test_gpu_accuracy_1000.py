@@ -23,7 +23,9 @@ storage format costs by itself; the GPU adds its FP32 collision arithmetic.
         covering rounding decisions that differ between the GPU's FP32 values
         and the oracle's FP64 ones.  FP16 also meets 1e-3 on u; BF16 cannot
         (its storage alone costs 2.8e-2 on u at 64^3 -- reading recorded with
-        the measurements).
+        the measurements).  BF16 with stochastic rounding against the
+        storage-only run with stochastic rounding (other random bits, the same
+        statistics).
 """
 import json
 import os
@@ -52,8 +54,11 @@ def _gpu():
     L.lib()
 
 
-# the sizes whose storage-only errors have been measured for every precision (64 and 128)
-SIZES = sorted(int(k) for k, v in COND.items() if all(p in v for p in ("fp32", "fp16", "bf16")))
+# storage variants: (lbm precision, rounding, conditioning entry)
+VARIANTS = {"fp32": ("fp32", "nearest", "fp32"), "fp16": ("fp16", "nearest", "fp16"),
+            "bf16": ("bf16", "nearest", "bf16"), "bf16sr": ("bf16", "stochastic", "bf16_sr")}
+# the sizes whose storage-only errors have been measured for every variant (64 and 128)
+SIZES = sorted(int(k) for k, v in COND.items() if all(e in v for _, _, e in VARIANTS.values()))
 
 
 @pytest.fixture(scope="module", params=SIZES)
@@ -68,15 +73,16 @@ def reference(orc, request):
     return N, rho, u, r, v
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("precision", list(VARIANTS))
 @pytest.mark.parametrize("streaming", ["ab", "aa"])
 def test_long_run_error(reference, precision, streaming):
     N, rho, u, ro, uo = reference
-    cond = COND[str(N)][precision][str(STEPS)]
+    storage, rounding, entry = VARIANTS[precision]
+    cond = COND[str(N)][entry][str(STEPS)]
     say(f"{precision} {streaming}: {N}^3, {STEPS} steps; storage alone: u {cond['u']:.3e}, "
         f"rho - mean(rho) {cond['rho_fluct']:.3e}")
-    g = gpu_run(N, N, N, rho, u, STEPS, precision, streaming, omega=inputs.omega_from_nu(NU),
-                force_mode=L.LBM_FORCE_KOLMOGOROV, kolmogorov_amp=1e-6, want_pops=False)
+    g = gpu_run(N, N, N, rho, u, STEPS, storage, streaming, omega=inputs.omega_from_nu(NU),
+                force_mode=L.LBM_FORCE_KOLMOGOROV, kolmogorov_amp=1e-6, want_pops=False, rounding=rounding)
     err = {"u": rel_l2(g["u"], uo), "rho_fluct": rel_l2_fluct(g["rho"], ro)}
     say(f"  rel L2 u = {err['u']:.3e} ({err['u'] / cond['u']:.2f} x storage alone), rho - mean(rho) = "
         f"{err['rho_fluct']:.3e} ({err['rho_fluct'] / cond['rho_fluct']:.2f} x)")

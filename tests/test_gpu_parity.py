@@ -348,11 +348,13 @@ def test_64bit_addressing_is_bitwise_identical(precision, streaming, walls, q, m
     assert np.array_equal(a["f"], b["f"])
 
 
-@pytest.mark.parametrize("q,eb,nt", [(19, 4, True), (19, 2, False), (19, 2, True), (27, 8, True), (19, 8, False)])
-def test_stream_copy_is_exact(q, eb, nt):
+@pytest.mark.parametrize("q,eb,nt,lane", [(19, 4, True, 0), (19, 2, False, 0), (19, 2, True, 0), (27, 8, True, 0),
+                                          (19, 8, False, 0), (19, 4, True, 8), (19, 4, True, 16), (19, 2, True, 16),
+                                          (27, 8, False, 16)])
+def test_stream_copy_is_exact(q, eb, nt, lane):
     """The bandwidth reference (the step's loads and stores without its
-    arithmetic) copies every element of all q arrays; n = 1000 leaves a
-    ragged last work-group."""
+    arithmetic, one element or 8 / 16 bytes per thread and array) copies every
+    element of all q arrays; n = 1000 leaves a ragged last work-group."""
     import torch
 
     n = 1000
@@ -361,6 +363,7 @@ def test_stream_copy_is_exact(q, eb, nt):
     gen = torch.Generator().manual_seed(5)
     src = torch.randint(-(1 << 15), 1 << 15, (q * n,), generator=gen, dtype=torch.int64).to(dt).cuda()
     dst = torch.zeros_like(src)
-    L.lbm_stream_copy(src.data_ptr(), dst.data_ptr(), n, q, eb, nt, torch.cuda.current_stream().cuda_stream)
+    L.lbm_stream_copy(src.data_ptr(), dst.data_ptr(), n, q, eb, nt, torch.cuda.current_stream().cuda_stream,
+                      lane_bytes=lane)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
