@@ -374,7 +374,9 @@ int lbm_abi_version(void);
 typedef struct lbm_mlp lbm_mlp;
 
 /* params: host float[LBM_MLP_NPARAM] or NULL (all zero: the paper's rates);
- * scales: host float[11], all > 0.  All calls are ordered on `stream`. */
+ * scales: host float[11], all > 0.  All calls are ordered on `stream`.
+ * Errors: LBM_EINVAL (NULL out or scales, a scale <= 0, a non-finite
+ * parameter), LBM_EDEVICE (no HIP device), LBM_ENOMEM (device buffers). */
 int lbm_mlp_create(const float *params, const float *scales, void *stream, lbm_mlp **out);
 int lbm_mlp_set_params(lbm_mlp *m, const float *params);   /* host; resets Adam moments */
 int lbm_mlp_get_params(const lbm_mlp *m, float *params);   /* host */

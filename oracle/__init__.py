@@ -18,7 +18,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIBRARY names another build of the same sources (the sanitized one)
+_SO = os.environ.get("ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["d3q19_oracle.c", "d3q27_oracle.c", "mlp_oracle.c", "phase_oracle.c", "mhd_oracle.c",
             "shan_chen_oracle.c", "colour_gradient_oracle.c"]
 
@@ -28,17 +29,24 @@ RM_DEFINITION = 2   # raw-moment variant of App. C (N = I): f* = M^-1 k* by a de
 Q = 19
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no HIP, no GPU headers)."""
-    if not force and os.path.exists(_SO):
-        return _SO
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+def build(force: bool = True, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no HIP, no GPU headers).  ``sanitize``
+    builds it with AddressSanitizer and UndefinedBehaviorSanitizer instead of
+    -O3 (load it with gcc's libasan preloaded)."""
+    so = out or _SO
+    if not force and os.path.exists(so):
+        return so
     srcs = [os.path.join(_HERE, s) for s in _SOURCES]
-    tmp = _SO + ".tmp"
-    cmd = ["gcc", "-std=c11", "-O3", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", tmp] + srcs + ["-lm"]
+    tmp = so + ".tmp"
+    opt = SANITIZE if sanitize else ["-O3"]
+    cmd = ["gcc", "-std=c11"] + opt + ["-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+                                       "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _SO)
-    return _SO
+    os.replace(tmp, so)
+    return so
 
 
 _lib = None

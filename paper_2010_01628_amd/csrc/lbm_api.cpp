@@ -664,6 +664,8 @@ int lbm_mlp_create(const float* params, const float* scales, void* stream, lbm_m
     if (params)
         for (int p = 0; p < LBM_MLP_NPARAM; ++p)
             if (!std::isfinite(params[p])) return fail(LBM_EINVAL, "non-finite parameter %d", p);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(LBM_EDEVICE, "no HIP device");
     lbm_mlp* m = new lbm_mlp();
     m->stream = (hipStream_t)stream;
     const size_t pb = sizeof(float) * LBM_MLP_NPARAM;

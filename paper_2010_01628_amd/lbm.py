@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "liblbm.so")
+# LBM_LIBRARY names another build of the same library (the host-sanitized one)
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_PKG, "liblbm.so")
 
 ABI_VERSION = 6
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5

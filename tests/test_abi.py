@@ -244,3 +244,38 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         L.lib()
     with pytest.raises(ImportError):
         L.Lattice(L.make_params(8, 8, 8))
+
+
+def test_without_a_device_every_create_fails_cleanly(lbm):
+    """Valid parameters on a host with no GPU: each create call reports
+    LBM_EDEVICE and hands back no handle (nothing is left half-built)."""
+    import numpy as np
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    extras = [{}, dict(phase=dict(rho_light=1.0, rho_heavy=10.0, sigma=1e-3, width=4.0, mobility=0.1)),
+              dict(magnetic=dict(eta=0.1)), dict(shan_chen=dict(G=-5.0)), dict(colour=dict(alpha_red=7.0 / 9.0))]
+    for extra in extras:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_create(lbm.make_params(16, 16, 16, precision="fp32", **extra), None)
+        assert e.value.code == lbm.LBM_EDEVICE
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_mlp_create(None, np.ones(11))
+    assert e.value.code == lbm.LBM_EDEVICE
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_ensemble_create([(8, 1.5), (12, 1.2)])
+    assert e.value.code == lbm.LBM_EDEVICE
+
+
+def test_null_handles(lbm):
+    """NULL handles: destroy is a no-op, queries report an error."""
+    lbm.lbm_destroy(0)
+    lbm.lbm_mlp_destroy(0)
+    assert lbm.lbm_step_count(0) == -1
+    for call in (lambda: lbm.lbm_step(0, 1), lambda: lbm.lbm_init(0, 0, 0, False),
+                 lambda: lbm.lbm_moments(0, 0, 0, 0, False), lambda: lbm.lbm_moments_noalloc(0, 0, 0, 0),
+                 lambda: lbm.lbm_get_populations(0, 0, False), lambda: lbm.lbm_set_populations(0, 0, False)):
+        with pytest.raises(lbm.LbmError) as e:
+            call()
+        assert e.value.code == lbm.LBM_EINVAL
