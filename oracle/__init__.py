@@ -516,6 +516,34 @@ class mlp:
         return a, total
 
     @staticmethod
+    def moments10(f):
+        """The 10 raw moments of the training loss (rho, j, Pi) of populations
+        f (19, nz, ny, nx): component k = sum_i f_i times the monomial k of c_i."""
+        c, _, _ = tables()
+        mono = np.stack([np.ones(Q), c[:, 0], c[:, 1], c[:, 2], c[:, 0] ** 2, c[:, 1] ** 2, c[:, 2] ** 2,
+                         c[:, 0] * c[:, 1], c[:, 0] * c[:, 2], c[:, 1] * c[:, 2]]).astype(np.float64)
+        return np.tensordot(mono, _f64(f), axes=(1, 0))
+
+    @staticmethod
+    def rollout_loss(f, targets, omega, P, scales, sigma, bf16=False):
+        """Rollout loss: `len(targets)` learned steps from the pre-collision
+        populations f (periodic, no force); after step k the squared misfit
+        of the 10 moments against targets[k-1] in units of sigma, averaged
+        over nodes and summed over the moments; the mean over the steps.
+        Returns (loss, fallbacks)."""
+        a = _f64(f).copy()
+        b = np.empty_like(a)
+        sig = _f64(sigma).reshape(10, 1, 1, 1)
+        total, fbs = 0.0, 0
+        for tk in targets:
+            _, fb = mlp.step(a, omega, P, scales, bf16=bf16, out=b)
+            fbs += fb
+            a, b = b, a
+            r = (mlp.moments10(a) - _f64(tk)) / sig
+            total += float(np.sum(r * r)) / (a.size // Q)
+        return total / len(targets), fbs
+
+    @staticmethod
     def loss_grad(f, target, omega, P, scales, sigma, bf16=False, want_grad=True):
         f = _f64(f)
         _, nz, ny, nx = f.shape

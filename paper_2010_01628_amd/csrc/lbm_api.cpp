@@ -638,8 +638,8 @@ int lbm_mlp_destroy(lbm_mlp* m)
 {
     if (!m) return LBM_OK;
     hipStreamSynchronize(m->stream);
-    void* bufs[] = {m->theta, m->m1, m->m2, m->grad, m->inv_scale, m->packed, m->inv_sigma, m->gbuf, m->grad_parts,
-                    m->loss_parts, m->loss_dev};
+    void* bufs[] = {m->theta, m->m1, m->m2, m->grad, m->inv_scale, m->packed, m->inv_sigma, m->gbuf, m->traj,
+                    m->grad_parts, m->loss_parts, m->loss_dev};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (m->loss_host) hipHostFree(m->loss_host);
@@ -794,21 +794,30 @@ static int grow(void** p, int64_t& have, int64_t need, size_t elem)
     return LBM_OK;
 }
 
+// Shared checks of the training entry points; fills the inverse moment scales
+// (each sigma_k times sqrt(steps): the rollout loss is the mean over steps).
+static int training_checks(lbm_mlp* m, lbm_handle* h, const double sigma[10], int steps, float isig[10])
+{
+    if (h->mlp != m) return fail(LBM_EINVAL, "the network must be attached to the handle (lbm_set_mlp)");
+    if (h->p.q != 19 || h->p.precision != LBM_FP32 || h->p.streaming != LBM_AB || h->walls ||
+        h->p.force_mode != LBM_FORCE_NONE || h->p.moments != LBM_CENTRAL_MOMENTS)
+        return fail(LBM_EUNSUPPORTED, "training needs a periodic, force-free D3Q19 FP32 A-B lattice");
+    for (int k = 0; k < 10; ++k) {
+        if (!(std::isfinite(sigma[k]) && sigma[k] > 0.0)) return fail(LBM_EINVAL, "sigma must be positive");
+        isig[k] = (float)(1.0 / (sigma[k] * std::sqrt((double)steps)));
+    }
+    return LBM_OK;
+}
+
 int lbm_mlp_accumulate_grad(lbm_mlp* m, lbm_handle* h, const float* target, const double sigma[10], double* loss)
 {
     if (!m || !h || !target || !sigma) return fail(LBM_EINVAL, "NULL argument");
-    if (h->mlp != m) return fail(LBM_EINVAL, "the network must be attached to the handle (lbm_set_mlp)");
-    if (h->p.q != 19 || h->p.precision != LBM_FP32 || h->p.streaming != LBM_AB || h->walls ||
-        h->p.force_mode != LBM_FORCE_NONE)
-        return fail(LBM_EUNSUPPORTED, "training needs a periodic, force-free D3Q19 FP32 A-B lattice");
     float isig[10];
-    for (int k = 0; k < 10; ++k) {
-        if (!(std::isfinite(sigma[k]) && sigma[k] > 0.0)) return fail(LBM_EINVAL, "sigma must be positive");
-        isig[k] = (float)(1.0 / sigma[k]);
-    }
+    int rc = training_checks(m, h, sigma, 1, isig);
+    if (rc) return rc;
     const lbm::Geom& g = h->g;
     const int nwb = ((g.nx + 63) / 64) * g.ny * g.nz; // backward: one wavefront per block
-    int rc = grow((void**)&m->gbuf, m->gbuf_elems, (int64_t)19 * g.N, sizeof(float));
+    rc = grow((void**)&m->gbuf, m->gbuf_elems, (int64_t)2 * 19 * g.N, sizeof(float));
     if (!rc) rc = grow((void**)&m->grad_parts, m->grad_parts_n, (int64_t)nwb * LBM_MLP_NPARAM, sizeof(float));
     if (!rc) rc = grow((void**)&m->loss_parts, m->loss_parts_n, h->nblocks, sizeof(double));
     if (rc) return rc;
@@ -820,10 +829,62 @@ int lbm_mlp_accumulate_grad(lbm_mlp* m, lbm_handle* h, const float* target, cons
     lbm::launch_step_mlp(LBM_FP32, 0, false, false, state, post, g, h->ph, m->packed, h->fb_partials, h->grid, h->block,
                          h->stream);
     lbm::launch_train_loss((const float*)post, g, (float)h->p.rho0, target, m->inv_sigma, m->gbuf, m->loss_parts,
-                           h->grid, h->block, h->stream);
-    lbm::launch_train_backward((const float*)state, m->gbuf, g, (float)h->p.rho0, m->packed, m->grad_parts, h->stream);
+                           false, h->grid, h->block, h->stream);
+    lbm::launch_train_backward((const float*)state, m->gbuf, g, h->ph, m->packed, m->grad_parts, nullptr, h->stream);
     lbm::launch_reduce_grad(m->grad_parts, nwb, m->grad, h->stream);
     lbm::launch_sum_partials(m->loss_parts, h->nblocks, m->loss_dev, h->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(m->loss_host, m->loss_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (loss) *loss = *m->loss_host;
+    return LBM_OK;
+}
+
+int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targets, int32_t steps,
+                                    const double sigma[10], float* dstate, double* loss)
+{
+    if (!m || !h || !targets || !sigma) return fail(LBM_EINVAL, "NULL argument");
+    if (steps < 1 || steps > LBM_MLP_MAX_ROLLOUT)
+        return fail(LBM_EINVAL, "steps must be in [1, %d]", LBM_MLP_MAX_ROLLOUT);
+    float isig[10];
+    int rc = training_checks(m, h, sigma, steps, isig);
+    if (rc) return rc;
+    const lbm::Geom& g = h->g;
+    const int64_t state_elems = (int64_t)19 * g.stride;
+    const int nwb = ((g.nx + 63) / 64) * g.ny * g.nz;
+    rc = grow((void**)&m->gbuf, m->gbuf_elems, (int64_t)2 * 19 * g.N, sizeof(float));
+    if (!rc) rc = grow((void**)&m->traj, m->traj_elems, (int64_t)steps * state_elems, sizeof(float));
+    if (!rc) rc = grow((void**)&m->grad_parts, m->grad_parts_n, (int64_t)nwb * LBM_MLP_NPARAM, sizeof(float));
+    if (!rc) rc = grow((void**)&m->loss_parts, m->loss_parts_n, (int64_t)steps * h->nblocks, sizeof(double));
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    HIP_TRY(hipMemcpyAsync(m->inv_sigma, isig, sizeof isig, hipMemcpyHostToDevice, h->stream));
+    // forward: P_0 = h's state, P_k = m->traj + (k - 1) * state_elems
+    auto P = [&](int k) -> float* {
+        return k == 0 ? (float*)h->buf[h->cur] : m->traj + (int64_t)(k - 1) * state_elems;
+    };
+    for (int k = 0; k < steps; ++k)
+        lbm::launch_step_mlp(LBM_FP32, 0, false, false, P(k), P(k + 1), g, h->ph, m->packed, h->fb_partials, h->grid,
+                             h->block, h->stream);
+    // backward: A holds dL/df(t0 + k + 1); the step from P_k turns it into
+    // dL/df(t0 + k) (in B, or in dstate for k = 0), to which the loss after k
+    // steps adds its own gradient
+    float* A = m->gbuf;
+    float* B = m->gbuf + (int64_t)19 * g.N;
+    const float* tk = targets + (int64_t)(steps - 1) * 10 * g.N;
+    lbm::launch_train_loss(P(steps), g, (float)h->p.rho0, tk, m->inv_sigma, A,
+                           m->loss_parts + (int64_t)(steps - 1) * h->nblocks, false, h->grid, h->block, h->stream);
+    for (int k = steps - 1; k >= 0; --k) {
+        float* out = k > 0 ? B : dstate;
+        lbm::launch_train_backward(P(k), A, g, h->ph, m->packed, m->grad_parts, out, h->stream);
+        lbm::launch_reduce_grad(m->grad_parts, nwb, m->grad, h->stream);
+        if (k > 0) {
+            lbm::launch_train_loss(P(k), g, (float)h->p.rho0, targets + (int64_t)(k - 1) * 10 * g.N, m->inv_sigma, B,
+                                   m->loss_parts + (int64_t)(k - 1) * h->nblocks, true, h->grid, h->block, h->stream);
+            std::swap(A, B);
+        }
+    }
+    lbm::launch_sum_partials(m->loss_parts, steps * h->nblocks, m->loss_dev, h->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(m->loss_host, m->loss_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));

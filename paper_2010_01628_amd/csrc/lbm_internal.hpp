@@ -96,9 +96,10 @@ constexpr int MLP_PARAMS = 1737;
 void launch_step_mlp(int precision, int pattern, bool walls, bool nt, const void* src, void* dst, const Geom& g,
                      const Phys& ph, const void* net, uint32_t* fb_partials, dim3 grid, dim3 block, hipStream_t st);
 void launch_train_loss(const float* post, const Geom& g, float rho0, const float* target, const float* inv_sigma,
-                       float* gbuf, double* loss_partials, dim3 grid, dim3 block, hipStream_t st);
-void launch_train_backward(const float* state, const float* gbuf, const Geom& g, float rho0, const void* net,
-                           float* grad_partials, hipStream_t st);
+                       float* gbuf, double* loss_partials, bool accumulate, dim3 grid, dim3 block, hipStream_t st);
+// gout != nullptr: also write dL/df(t) (rollout back-propagation)
+void launch_train_backward(const float* state, const float* gbuf, const Geom& g, const Phys& ph, const void* net,
+                           float* grad_partials, float* gout, hipStream_t st);
 void launch_reduce_grad(const float* partials, int nparts, double* grad, hipStream_t st);
 void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
 void launch_adam(float* theta, float* m1, float* m2, const double* grad, float lr, float b1, float b2, float eps,
@@ -128,8 +129,10 @@ struct lbm_mlp {
     float* inv_sigma = nullptr; // 10 floats
     int64_t adam_t = 0;
     // training scratch, grown on demand
-    float* gbuf = nullptr;
+    float* gbuf = nullptr; // two adjoint buffers of 19 N floats (rollouts alternate them)
     int64_t gbuf_elems = 0;
+    float* traj = nullptr; // rollout states after steps 1..s (19 x stride floats each)
+    int64_t traj_elems = 0;
     float* grad_parts = nullptr;
     int64_t grad_parts_n = 0;
     double* loss_parts = nullptr;

@@ -1,5 +1,6 @@
 // Learned-rate D3Q19 step, its training kernels, and the D3Q27 -> D3Q19
 // projection that produces training data.
+#include "dual.hpp"
 #include "lattice_kernels.hpp"
 #include "mlp_device.hpp"
 
@@ -7,11 +8,11 @@ namespace lbm {
 
 // Raw features of reading L1 from the pre-collision state (the kernels scale
 // them by MlpPacked::inv_scale).
-__device__ inline void mlp_features(const CMState<float>& st, float x[MLP_NIN])
+template <class R> __device__ inline void mlp_features(const CMState<R>& st, R x[MLP_NIN])
 {
-    const float ir = 1.0f / st.rho;
-    const RawMoments<float>& n = st.n;
-    x[0] = st.rho - 1.0f;
+    const R ir = R(1) / st.rho;
+    const RawMoments<R>& n = st.n;
+    x[0] = st.rho - R(1);
     x[1] = st.k4 * ir;
     x[2] = n.m210 * ir;
     x[3] = n.m120 * ir;
@@ -108,11 +109,13 @@ __global__ __launch_bounds__(256) void k_step_mlp(const S* src, S* dst, Geom g, 
 // Training, reading L5: loss on the 10 raw moments of f(t+1) after one A-B
 // step from f(t) (periodic, no force).  post: post-collision buffer written by
 // k_step_mlp (A-B).  Writes dL/df_i(y, t+1) to gbuf (SoA floats, stride N) and
-// one FP64 loss partial per block.
+// one FP64 loss partial per block; with `accumulate` the gradient is added to
+// what gbuf holds (the adjoint carried back from later steps of a rollout).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_train_loss(const float* __restrict__ post, Geom g, float rho0,
                                                     const float* __restrict__ target, const float* __restrict__ inv_sigma,
-                                                    float* __restrict__ gbuf, double* __restrict__ loss_partials)
+                                                    float* __restrict__ gbuf, double* __restrict__ loss_partials,
+                                                    int accumulate)
 {
     __shared__ double red[4];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -152,8 +155,10 @@ __global__ __launch_bounds__(256) void k_train_loss(const float* __restrict__ po
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             const float cx = LatD3Q19::cx(i), cy = LatD3Q19::cy(i), cz = LatD3Q19::cz(i);
-            gbuf[(int64_t)i * g.N + n] = dm[0] + cx * dm[1] + cy * dm[2] + cz * dm[3] + cx * cx * dm[4] + cy * cy * dm[5] +
-                                         cz * cz * dm[6] + cx * cy * dm[7] + cx * cz * dm[8] + cy * cz * dm[9];
+            const float gi = dm[0] + cx * dm[1] + cy * dm[2] + cz * dm[3] + cx * cx * dm[4] + cy * cy * dm[5] +
+                             cz * cz * dm[6] + cx * cy * dm[7] + cx * cz * dm[8] + cy * cz * dm[9];
+            float* gp = gbuf + (int64_t)i * g.N + n;
+            *gp = accumulate ? *gp + gi : gi;
         }
     }
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
@@ -174,10 +179,22 @@ __global__ __launch_bounds__(256) void k_train_loss(const float* __restrict__ po
 // dL/domega_j = kbar_{10+j} (-(k_{10+j} - k_eq) - R_{10+j}/2) with
 // kbar = S(+u)^T M^-T gbar, then back-propagate through the network.  Writes
 // this wavefront's 1737 gradient entries to grad_partials[wave].
+//
+// PROP (rollouts): also dL/df_j(x, t), written to gout[j N + x].  It has two
+// parts: the collision's own dependence on the populations at fixed rates,
+// and the dependence through the rates (features -> network -> rates).  The
+// first is the directional derivative of the collision along each of the 19
+// unit vectors, by evaluating it on dual numbers, contracted with gbar; the
+// second contracts the same directional derivatives of the 11 raw features
+// with xbar = dL/dx, which the network's backward pass gives (ReLU masks,
+// W1^T, the input scales).  Nodes that fall back use rates 1 that do not
+// depend on the state, and take only the first part.
+template <bool PROP>
 __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__ state, const float* __restrict__ gbuf,
-                                                       Geom g, float rho0, const MlpPacked* __restrict__ net,
-                                                       float* __restrict__ grad_partials)
+                                                       Geom g, Phys ph, const MlpPacked* __restrict__ net,
+                                                       float* __restrict__ grad_partials, float* __restrict__ gout)
 {
+    const float rho0 = (float)ph.rho0;
     __shared__ MlpPacked snet;
     __shared__ uint16_t tx[MLP_TILE], th1[MLP_TILE], th2[MLP_TILE], tdz[MLP_TILE], tdh[MLP_TILE];
     __shared__ float tz[64 * MLP_NOUT];
@@ -276,6 +293,41 @@ __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__
         float sb = 0.0f;
         for (int q = 0; q < 64; ++q) sb += bf16_to_f32(tdz[q * MLP_LDS_STRIDE + l]);
         gp[MLP_OFF_B1 + l] = sb;
+    }
+    if constexpr (PROP) {
+        // xbar = (W1^T dh1) * inv_scale: dh1 of this lane's node is row l of tdz
+        float xbar[MLP_NIN];
+#pragma unroll
+        for (int i = 0; i < MLP_NIN; ++i) xbar[i] = 0.0f;
+        for (int o = 0; o < 32; ++o) {
+            const float dh = bf16_to_f32(tdz[l * MLP_LDS_STRIDE + o]);
+#pragma unroll
+            for (int i = 0; i < MLP_NIN; ++i) xbar[i] += dh * bf16_to_f32(snet.w1[o * 16 + i]);
+        }
+#pragma unroll
+        for (int i = 0; i < MLP_NIN; ++i) xbar[i] *= snet.inv_scale[i];
+        Rates<Dual> rt = rates_of<Dual>(ph);
+#pragma unroll
+        for (int j = 0; j < MLP_NOUT; ++j) rt.omega_hi[j] = Dual(rates[j], 0.0f);
+#pragma unroll 1
+        for (int j = 0; j < 19; ++j) {
+            Dual sd[19];
+#pragma unroll
+            for (int i = 0; i < 19; ++i) sd[i] = Dual(s[i], i == j ? 1.0f : 0.0f);
+            CMState<Dual> sdt;
+            pre_collide<Dual, true>(sd, Dual(rho0, 0.0f), Dual(0.0), Dual(0.0), Dual(0.0), sdt);
+            Dual xd[MLP_NIN];
+            mlp_features(sdt, xd);
+            RawMoments<Dual> pd;
+            relax<Dual, true>(sdt, rt, pd);
+            post_collide_increment(sdt, pd, sd);
+            float acc = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 19; ++i) acc += gbar[i] * sd[i].d;
+#pragma unroll
+            for (int k = 0; k < MLP_NIN; ++k) acc += xbar[k] * xd[k].d;
+            if (valid) gout[(int64_t)j * g.N + nb(d, 0, 0, 0)] = acc;
+        }
     }
 }
 
@@ -509,17 +561,22 @@ void launch_step_mlp(int precision, int pattern, bool walls, bool nt, const void
 }
 
 void launch_train_loss(const float* post, const Geom& g, float rho0, const float* target, const float* inv_sigma,
-                       float* gbuf, double* loss_partials, dim3 grid, dim3 block, hipStream_t st)
+                       float* gbuf, double* loss_partials, bool accumulate, dim3 grid, dim3 block, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_train_loss, grid, block, 0, st, post, g, rho0, target, inv_sigma, gbuf, loss_partials);
+    hipLaunchKernelGGL(k_train_loss, grid, block, 0, st, post, g, rho0, target, inv_sigma, gbuf, loss_partials,
+                       (int)accumulate);
 }
 
-void launch_train_backward(const float* state, const float* gbuf, const Geom& g, float rho0, const void* net,
-                           float* grad_partials, hipStream_t st)
+void launch_train_backward(const float* state, const float* gbuf, const Geom& g, const Phys& ph, const void* net,
+                           float* grad_partials, float* gout, hipStream_t st)
 {
     const dim3 grid((g.nx + 63) / 64, g.ny, g.nz);
-    hipLaunchKernelGGL(k_train_backward, grid, dim3(64), 0, st, state, gbuf, g, rho0, (const MlpPacked*)net,
-                       grad_partials);
+    if (gout)
+        hipLaunchKernelGGL(k_train_backward<true>, grid, dim3(64), 0, st, state, gbuf, g, ph, (const MlpPacked*)net,
+                           grad_partials, gout);
+    else
+        hipLaunchKernelGGL(k_train_backward<false>, grid, dim3(64), 0, st, state, gbuf, g, ph, (const MlpPacked*)net,
+                           grad_partials, gout);
 }
 
 void launch_reduce_grad(const float* partials, int nparts, double* grad, hipStream_t st)

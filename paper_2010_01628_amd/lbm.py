@@ -133,6 +133,7 @@ def lib():
         L.lbm_fallback_count.restype = i64
         L.lbm_mlp_zero_grad.argtypes = [vp]
         L.lbm_mlp_accumulate_grad.argtypes = [vp, vp, vp, dp, dp]
+        L.lbm_mlp_accumulate_rollout_grad.argtypes = [vp, vp, vp, i32, dp, vp, dp]
         L.lbm_mlp_get_grad.argtypes = [vp, dp]
         L.lbm_mlp_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.lbm_feature_rms.argtypes = [vp, dp]
@@ -180,7 +181,8 @@ def lib():
         for name in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_moments_noalloc", "lbm_get_populations",
                      "lbm_set_populations", "lbm_destroy", "lbm_mlp_create", "lbm_mlp_set_params",
                      "lbm_mlp_get_params", "lbm_mlp_set_scales", "lbm_mlp_destroy", "lbm_set_mlp",
-                     "lbm_mlp_zero_grad", "lbm_mlp_accumulate_grad", "lbm_mlp_get_grad", "lbm_mlp_adam_step",
+                     "lbm_mlp_zero_grad", "lbm_mlp_accumulate_grad", "lbm_mlp_accumulate_rollout_grad",
+                     "lbm_mlp_get_grad", "lbm_mlp_adam_step",
                      "lbm_feature_rms", "lbm_project_q27", "lbm_stream_copy"):
             getattr(L, name).restype = i32
         if L.lbm_abi_version() != ABI_VERSION:
@@ -246,6 +248,7 @@ def lbm_destroy(h: int) -> None:
 
 
 MLP_NPARAM = 1737
+MLP_MAX_ROLLOUT = 64
 
 
 def _fptr(a):
@@ -301,6 +304,13 @@ def lbm_mlp_accumulate_grad(m, h, target_ptr, sigma) -> float:
     sig = np.ascontiguousarray(sigma, dtype=np.float64)
     loss = np.zeros(1)
     _check(lib().lbm_mlp_accumulate_grad(m, h, target_ptr, _dptr(sig), _dptr(loss)))
+    return float(loss[0])
+
+
+def lbm_mlp_accumulate_rollout_grad(m, h, targets_ptr, steps, sigma, dstate_ptr=None) -> float:
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    loss = np.zeros(1)
+    _check(lib().lbm_mlp_accumulate_rollout_grad(m, h, targets_ptr, int(steps), _dptr(sig), dstate_ptr, _dptr(loss)))
     return float(loss[0])
 
 
@@ -599,6 +609,18 @@ class Lattice:
         t = target.contiguous()
         assert t.dtype == self.torch.float32 and t.numel() == 10 * self.N
         return lbm_mlp_accumulate_grad(mlp.m, self.h, t.data_ptr(), sigma)
+
+    def accumulate_rollout_grad(self, mlp, targets, sigma, want_dstate=False):
+        """targets: device float32 tensor (steps, 10, nz, ny, nx), the moments
+        after each step.  Returns the loss, and with want_dstate also
+        dL/df (device float32 (19, nz, ny, nx)) of the current populations."""
+        t = targets.contiguous()
+        assert t.dtype == self.torch.float32 and t.numel() % (10 * self.N) == 0
+        steps = t.numel() // (10 * self.N)
+        ds = self.torch.empty((19,) + self.shape, dtype=self.torch.float32, device=t.device) if want_dstate else None
+        loss = lbm_mlp_accumulate_rollout_grad(mlp.m, self.h, t.data_ptr(), steps, sigma,
+                                               ds.data_ptr() if ds is not None else None)
+        return (loss, ds) if want_dstate else loss
 
     @property
     def step_count(self):

@@ -178,3 +178,40 @@ def test_step_info_flip_effects(orc, M):
     _, _, ez, mz = M.step_info(f, 1.8, Z, scales, tie_ulps=4096.0)
     assert np.all(ez == 0.0)
     assert np.allclose(mz, np.min(np.minimum(1 + Z[-9:], 1 - Z[-9:])), atol=1e-15)
+
+
+def test_rollout_loss_reduces_to_the_one_step_loss(orc, M):
+    """One step: the rollout loss (oracle steps + numpy moments) equals the
+    C one-step loss; several steps: the mean over steps of the one-step
+    losses of the states the learned scheme reaches."""
+    nx, ny, nz = 4, 4, 3
+    rng = np.random.default_rng(3)
+    rho, u, _ = inputs.random_lattice_fields(nx, ny, nz, seed=4, umax=0.06, drho=0.03)
+    f = orc.init(rho, u) * (1 + 0.03 * rng.uniform(-1, 1, (19, nz, ny, nx)))
+    P = small_params(M, 5, 0.2)
+    scales = rng.uniform(0.2, 0.5, 11)
+    sigma = rng.uniform(0.01, 0.05, 10)
+    targets = M.moments10(f)[None] + 0.01 * rng.normal(size=(3, 10, nz, ny, nx))
+    for bf16 in (False, True):
+        l1, fb = M.rollout_loss(f, targets[:1], 1.6, P, scales, sigma, bf16=bf16)
+        lc, _, _ = M.loss_grad(f, targets[0], 1.6, P, scales, sigma, bf16=bf16, want_grad=False)
+        assert fb == 0
+        assert abs(l1 - lc) <= 1e-13 * lc
+    l3, _ = M.rollout_loss(f, targets, 1.6, P, scales, sigma)
+    parts, a = [], f
+    for k in range(3):
+        parts.append(M.loss_grad(a, targets[k], 1.6, P, scales, sigma, want_grad=False)[0])
+        a, _ = M.step(a, 1.6, P, scales)
+    assert abs(l3 - np.mean(parts)) <= 1e-13 * l3
+
+
+def test_moments10_are_the_raw_moments(orc, M):
+    """rho, j and Pi of populations built from known moments (the Hermite
+    equilibrium's second moments: rho (u u + I/3))."""
+    rho, u, _ = inputs.random_lattice_fields(3, 3, 3, seed=12, umax=0.07, drho=0.04)
+    m = M.moments10(orc.init(rho, u))
+    assert np.allclose(m[0], rho, rtol=0, atol=1e-14)
+    assert np.allclose(m[1:4], rho * u, rtol=0, atol=1e-14)
+    for k, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+        want = rho * u[a] * u[b] + (rho / 3.0 if a == b else 0.0)
+        assert np.allclose(m[4 + k], want, rtol=0, atol=1e-14)
