@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 6
+#define LBM_ABI_VERSION 7
 
 typedef enum {
     LBM_OK = 0,
@@ -404,22 +404,26 @@ int lbm_mlp_accumulate_grad(lbm_mlp *m, lbm_handle *h, const float *target, cons
 
 /* Rollout training: the loss of lbm_mlp_accumulate_grad taken after each of
  * `steps` learned steps from h's current state f(t) (step k against target
- * k, k = 1..steps) and averaged over the steps:
- *   L = (1/steps) sum_k mean_nodes sum_j ((m_j(f(t+k)) - target_kj) / sigma_j)^2.
+ * k, k = 1..steps) and averaged over the steps with weights w_k:
+ *   L = (1/steps) sum_k w_k L_k,
+ *   L_k = mean_nodes sum_j ((m_j(f(t+k)) - target_kj) / sigma_j)^2.
  * The gradient is back-propagated through every step, including the way each
  * step's rates depend on the state it starts from, and added to m's
- * accumulator (steps = 1 gives lbm_mlp_accumulate_grad's result).
+ * accumulator (steps = 1 with w = 1 gives lbm_mlp_accumulate_grad's result).
  * targets: device float[steps][10][N] (target k, component j at
- * [((k-1)*10 + j)*N + n], n = x + nx (y + ny z)); dstate: device float[19*N]
- * or NULL, receives dL/df_i(x, t) at [i*N + n]; *loss (host, may be NULL)
- * receives L.  h as for lbm_mlp_accumulate_grad; its state and step counter
- * are unchanged.  m keeps steps states of h's size as scratch (grown on
- * demand, freed by lbm_mlp_destroy).  Errors: LBM_EINVAL (NULL argument,
- * steps outside [1, LBM_MLP_MAX_ROLLOUT], sigma <= 0, m not attached to h),
+ * [((k-1)*10 + j)*N + n], n = x + nx (y + ny z)); step_weight: host
+ * double[steps], each > 0, or NULL (all 1); dstate: device float[19*N] or
+ * NULL, receives dL/df_i(x, t) at [i*N + n]; step_loss: host double[steps]
+ * or NULL, receives L_1..L_steps; *loss (host, may be NULL) receives L.  h as
+ * for lbm_mlp_accumulate_grad; its state and step counter are unchanged.  m
+ * keeps `steps` states of h's size as scratch (grown on demand, freed by
+ * lbm_mlp_destroy).  Errors: LBM_EINVAL (NULL argument, steps outside
+ * [1, LBM_MLP_MAX_ROLLOUT], sigma or a weight <= 0, m not attached to h),
  * LBM_EUNSUPPORTED (h not as required), LBM_ENOMEM. */
-#define LBM_MLP_MAX_ROLLOUT 64
+#define LBM_MLP_MAX_ROLLOUT 128
 int lbm_mlp_accumulate_rollout_grad(lbm_mlp *m, lbm_handle *h, const float *targets, int32_t steps,
-                                    const double sigma[10], float *dstate, double *loss);
+                                    const double sigma[10], const double *step_weight, float *dstate,
+                                    double *step_loss, double *loss);
 int lbm_mlp_get_grad(const lbm_mlp *m, double *grad);      /* host double[LBM_MLP_NPARAM] */
 /* One Adam update of the FP32 master parameters with the accumulated gradient. */
 int lbm_mlp_adam_step(lbm_mlp *m, double lr, double beta1, double beta2, double eps);

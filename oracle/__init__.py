@@ -525,23 +525,31 @@ class mlp:
         return np.tensordot(mono, _f64(f), axes=(1, 0))
 
     @staticmethod
-    def rollout_loss(f, targets, omega, P, scales, sigma, bf16=False):
-        """Rollout loss: `len(targets)` learned steps from the pre-collision
-        populations f (periodic, no force); after step k the squared misfit
-        of the 10 moments against targets[k-1] in units of sigma, averaged
-        over nodes and summed over the moments; the mean over the steps.
-        Returns (loss, fallbacks)."""
+    def rollout_step_losses(f, targets, omega, P, scales, sigma, bf16=False):
+        """`len(targets)` learned steps from the pre-collision populations f
+        (periodic, no force); after step k the squared misfit of the 10
+        moments against targets[k-1] in units of sigma, averaged over nodes
+        and summed over the moments.  Returns (per-step losses, fallbacks)."""
         a = _f64(f).copy()
         b = np.empty_like(a)
         sig = _f64(sigma).reshape(10, 1, 1, 1)
-        total, fbs = 0.0, 0
+        out, fbs = [], 0
         for tk in targets:
             _, fb = mlp.step(a, omega, P, scales, bf16=bf16, out=b)
             fbs += fb
             a, b = b, a
             r = (mlp.moments10(a) - _f64(tk)) / sig
-            total += float(np.sum(r * r)) / (a.size // Q)
-        return total / len(targets), fbs
+            out.append(float(np.sum(r * r)) / (a.size // Q))
+        return np.array(out), fbs
+
+    @staticmethod
+    def rollout_loss(f, targets, omega, P, scales, sigma, bf16=False, weights=None):
+        """Rollout loss: the per-step losses (rollout_step_losses) averaged
+        over the steps with weights (default all 1): sum_k w_k L_k / steps.
+        Returns (loss, fallbacks)."""
+        per, fbs = mlp.rollout_step_losses(f, targets, omega, P, scales, sigma, bf16=bf16)
+        w = np.ones(len(per)) if weights is None else _f64(weights)
+        return float(np.sum(w * per)) / len(per), fbs
 
     @staticmethod
     def loss_grad(f, target, omega, P, scales, sigma, bf16=False, want_grad=True):

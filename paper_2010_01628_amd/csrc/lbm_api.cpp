@@ -639,10 +639,11 @@ int lbm_mlp_destroy(lbm_mlp* m)
     if (!m) return LBM_OK;
     hipStreamSynchronize(m->stream);
     void* bufs[] = {m->theta, m->m1, m->m2, m->grad, m->inv_scale, m->packed, m->inv_sigma, m->gbuf, m->traj,
-                    m->grad_parts, m->loss_parts, m->loss_dev};
+                    m->grad_parts, m->loss_parts, m->loss_dev, m->red_tmp, m->isig_steps, m->loss_steps};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (m->loss_host) hipHostFree(m->loss_host);
+    if (m->loss_steps_host) hipHostFree(m->loss_steps_host);
     delete m;
     return LBM_OK;
 }
@@ -676,6 +677,7 @@ int lbm_mlp_create(const float* params, const float* scales, void* stream, lbm_m
         hipMalloc(&m->packed, lbm::mlp_packed_bytes()) != hipSuccess ||
         hipMalloc((void**)&m->inv_sigma, sizeof(float) * 10) != hipSuccess ||
         hipMalloc((void**)&m->loss_dev, sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&m->red_tmp, lbm::reduce_grad_tmp_bytes()) != hipSuccess ||
         hipHostMalloc((void**)&m->loss_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
         lbm_mlp_destroy(m);
         return fail(LBM_ENOMEM, "network buffers");
@@ -830,8 +832,9 @@ int lbm_mlp_accumulate_grad(lbm_mlp* m, lbm_handle* h, const float* target, cons
                          h->stream);
     lbm::launch_train_loss((const float*)post, g, (float)h->p.rho0, target, m->inv_sigma, m->gbuf, m->loss_parts,
                            false, h->grid, h->block, h->stream);
-    lbm::launch_train_backward((const float*)state, m->gbuf, g, h->ph, m->packed, m->grad_parts, nullptr, h->stream);
-    lbm::launch_reduce_grad(m->grad_parts, nwb, m->grad, h->stream);
+    lbm::launch_train_backward((const float*)state, m->gbuf, g, h->ph, m->packed, m->grad_parts, nullptr, false,
+                               h->stream);
+    lbm::launch_reduce_grad(m->grad_parts, nwb, m->grad, m->red_tmp, h->stream);
     lbm::launch_sum_partials(m->loss_parts, h->nblocks, m->loss_dev, h->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(m->loss_host, m->loss_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -841,14 +844,27 @@ int lbm_mlp_accumulate_grad(lbm_mlp* m, lbm_handle* h, const float* target, cons
 }
 
 int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targets, int32_t steps,
-                                    const double sigma[10], float* dstate, double* loss)
+                                    const double sigma[10], const double* step_weight, float* dstate,
+                                    double* step_loss, double* loss)
 {
     if (!m || !h || !targets || !sigma) return fail(LBM_EINVAL, "NULL argument");
     if (steps < 1 || steps > LBM_MLP_MAX_ROLLOUT)
         return fail(LBM_EINVAL, "steps must be in [1, %d]", LBM_MLP_MAX_ROLLOUT);
     float isig[10];
-    int rc = training_checks(m, h, sigma, steps, isig);
+    int rc = training_checks(m, h, sigma, 1, isig);
     if (rc) return rc;
+    // step k's loss enters as (w_k / steps) loss_k: its inverse scales carry sqrt(w_k / steps)
+    std::vector<float> isk((size_t)steps * 10);
+    std::vector<double> wk((size_t)steps, 1.0);
+    for (int k = 0; k < steps; ++k) {
+        if (step_weight) {
+            if (!(std::isfinite(step_weight[k]) && step_weight[k] > 0.0))
+                return fail(LBM_EINVAL, "step weights must be positive");
+            wk[k] = step_weight[k];
+        }
+        const double f = std::sqrt(wk[k] / steps);
+        for (int j = 0; j < 10; ++j) isk[(size_t)k * 10 + j] = (float)(f / sigma[j]);
+    }
     const lbm::Geom& g = h->g;
     const int64_t state_elems = (int64_t)19 * g.stride;
     const int nwb = ((g.nx + 63) / 64) * g.ny * g.nz;
@@ -856,9 +872,17 @@ int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targ
     if (!rc) rc = grow((void**)&m->traj, m->traj_elems, (int64_t)steps * state_elems, sizeof(float));
     if (!rc) rc = grow((void**)&m->grad_parts, m->grad_parts_n, (int64_t)nwb * LBM_MLP_NPARAM, sizeof(float));
     if (!rc) rc = grow((void**)&m->loss_parts, m->loss_parts_n, (int64_t)steps * h->nblocks, sizeof(double));
+    if (!rc) rc = grow((void**)&m->isig_steps, m->isig_steps_n, (int64_t)steps * 10, sizeof(float));
+    if (!rc && m->loss_steps_n < LBM_MLP_MAX_ROLLOUT) {
+        if (hipMalloc((void**)&m->loss_steps, sizeof(double) * LBM_MLP_MAX_ROLLOUT) != hipSuccess ||
+            hipHostMalloc((void**)&m->loss_steps_host, sizeof(double) * LBM_MLP_MAX_ROLLOUT, hipHostMallocDefault) !=
+                hipSuccess)
+            return fail(LBM_ENOMEM, "rollout loss buffers");
+        m->loss_steps_n = LBM_MLP_MAX_ROLLOUT;
+    }
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(m->stream));
-    HIP_TRY(hipMemcpyAsync(m->inv_sigma, isig, sizeof isig, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(m->isig_steps, isk.data(), sizeof(float) * isk.size(), hipMemcpyHostToDevice, h->stream));
     // forward: P_0 = h's state, P_k = m->traj + (k - 1) * state_elems
     auto P = [&](int k) -> float* {
         return k == 0 ? (float*)h->buf[h->cur] : m->traj + (int64_t)(k - 1) * state_elems;
@@ -871,24 +895,33 @@ int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targ
     // steps adds its own gradient
     float* A = m->gbuf;
     float* B = m->gbuf + (int64_t)19 * g.N;
-    const float* tk = targets + (int64_t)(steps - 1) * 10 * g.N;
-    lbm::launch_train_loss(P(steps), g, (float)h->p.rho0, tk, m->inv_sigma, A,
-                           m->loss_parts + (int64_t)(steps - 1) * h->nblocks, false, h->grid, h->block, h->stream);
+    auto loss_at = [&](int k, float* adj, bool acc) { // loss after k steps (k = 1..steps)
+        lbm::launch_train_loss(P(k), g, (float)h->p.rho0, targets + (int64_t)(k - 1) * 10 * g.N,
+                               m->isig_steps + (int64_t)(k - 1) * 10, adj,
+                               m->loss_parts + (int64_t)(k - 1) * h->nblocks, acc, h->grid, h->block, h->stream);
+    };
+    loss_at(steps, A, false);
     for (int k = steps - 1; k >= 0; --k) {
         float* out = k > 0 ? B : dstate;
-        lbm::launch_train_backward(P(k), A, g, h->ph, m->packed, m->grad_parts, out, h->stream);
-        lbm::launch_reduce_grad(m->grad_parts, nwb, m->grad, h->stream);
+        // the partials of all steps add up in place; one reduction at the end
+        lbm::launch_train_backward(P(k), A, g, h->ph, m->packed, m->grad_parts, out, k < steps - 1, h->stream);
         if (k > 0) {
-            lbm::launch_train_loss(P(k), g, (float)h->p.rho0, targets + (int64_t)(k - 1) * 10 * g.N, m->inv_sigma, B,
-                                   m->loss_parts + (int64_t)(k - 1) * h->nblocks, true, h->grid, h->block, h->stream);
+            loss_at(k, B, true);
             std::swap(A, B);
         }
     }
-    lbm::launch_sum_partials(m->loss_parts, steps * h->nblocks, m->loss_dev, h->stream);
+    lbm::launch_reduce_grad(m->grad_parts, nwb, m->grad, m->red_tmp, h->stream);
+    for (int k = 0; k < steps; ++k)
+        lbm::launch_sum_partials(m->loss_parts + (int64_t)k * h->nblocks, h->nblocks, m->loss_steps + k, h->stream);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(m->loss_host, m->loss_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(m->loss_steps_host, m->loss_steps, sizeof(double) * steps, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    if (loss) *loss = *m->loss_host;
+    double total = 0.0;
+    for (int k = 0; k < steps; ++k) {
+        total += m->loss_steps_host[k];
+        if (step_loss) step_loss[k] = m->loss_steps_host[k] * steps / wk[k];
+    }
+    if (loss) *loss = total;
     return LBM_OK;
 }
 

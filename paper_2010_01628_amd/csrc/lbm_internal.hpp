@@ -97,10 +97,13 @@ void launch_step_mlp(int precision, int pattern, bool walls, bool nt, const void
                      const Phys& ph, const void* net, uint32_t* fb_partials, dim3 grid, dim3 block, hipStream_t st);
 void launch_train_loss(const float* post, const Geom& g, float rho0, const float* target, const float* inv_sigma,
                        float* gbuf, double* loss_partials, bool accumulate, dim3 grid, dim3 block, hipStream_t st);
-// gout != nullptr: also write dL/df(t) (rollout back-propagation)
+// gout != nullptr: also write dL/df(t) (rollout back-propagation);
+// accumulate: add to grad_partials instead of overwriting them
 void launch_train_backward(const float* state, const float* gbuf, const Geom& g, const Phys& ph, const void* net,
-                           float* grad_partials, float* gout, hipStream_t st);
-void launch_reduce_grad(const float* partials, int nparts, double* grad, hipStream_t st);
+                           float* grad_partials, float* gout, bool accumulate, hipStream_t st);
+// tmp: reduce_grad_tmp_bytes() of device scratch
+size_t reduce_grad_tmp_bytes();
+void launch_reduce_grad(const float* partials, int nparts, double* grad, double* tmp, hipStream_t st);
 void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
 void launch_adam(float* theta, float* m1, float* m2, const double* grad, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t st);
@@ -139,6 +142,12 @@ struct lbm_mlp {
     int64_t loss_parts_n = 0;
     double* loss_dev = nullptr;
     double* loss_host = nullptr;
+    double* red_tmp = nullptr; // gradient reduction slices
+    float* isig_steps = nullptr; // rollouts: 10 inverse moment scales per step
+    int64_t isig_steps_n = 0;
+    double* loss_steps = nullptr; // rollouts: loss of each step (device, and its host copy)
+    int64_t loss_steps_n = 0;
+    double* loss_steps_host = nullptr;
 };
 
 

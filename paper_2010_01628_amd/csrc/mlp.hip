@@ -192,7 +192,8 @@ __global__ __launch_bounds__(256) void k_train_loss(const float* __restrict__ po
 template <bool PROP>
 __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__ state, const float* __restrict__ gbuf,
                                                        Geom g, Phys ph, const MlpPacked* __restrict__ net,
-                                                       float* __restrict__ grad_partials, float* __restrict__ gout)
+                                                       float* __restrict__ grad_partials, float* __restrict__ gout,
+                                                       int accumulate)
 {
     const float rho0 = (float)ph.rho0;
     __shared__ MlpPacked snet;
@@ -232,20 +233,22 @@ __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__
     for (int k = 0; k < 32; ++k) tdz[l * MLP_LDS_STRIDE + k] = (k < MLP_NOUT && active) ? f32_to_bf16(dz[k]) : 0;
     __syncthreads();
     float* gp = grad_partials + (int64_t)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) * MLP_NPARAM;
+    // accumulate: add to the partials of earlier steps of a rollout
+    auto put = [accumulate](float* q, float v) { *q = accumulate ? *q + v : v; };
     // dW3[o][h] = sum_n dz[n][o] h2[n][h]
     {
         const f32x16_t acc = mfma_AtB(tdz, th2);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int o = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-            if (o < MLP_NOUT) gp[MLP_OFF_W3 + o * 32 + (l & 31)] = acc[r];
+            if (o < MLP_NOUT) put(gp + MLP_OFF_W3 + o * 32 + (l & 31), acc[r]);
         }
     }
     // db3, and dh2 = (dz W3) * relu'(h2)
     if (l < MLP_NOUT) {
         float sb = 0.0f;
         for (int q = 0; q < 64; ++q) sb += bf16_to_f32(tdz[q * MLP_LDS_STRIDE + l]);
-        gp[MLP_OFF_B3 + l] = sb;
+        put(gp + MLP_OFF_B3 + l, sb);
     }
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
@@ -262,12 +265,12 @@ __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__
     {
         const f32x16_t acc = mfma_AtB(tdh, th1);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) gp[MLP_OFF_W2 + (8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * 32 + (l & 31)] = acc[r];
+        for (int r = 0; r < 16; ++r) put(gp + MLP_OFF_W2 + (8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * 32 + (l & 31), acc[r]);
     }
     if (l < 32) {
         float sb = 0.0f;
         for (int q = 0; q < 64; ++q) sb += bf16_to_f32(tdh[q * MLP_LDS_STRIDE + l]);
-        gp[MLP_OFF_B2 + l] = sb;
+        put(gp + MLP_OFF_B2 + l, sb);
     }
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
@@ -286,13 +289,13 @@ __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int i = l & 31;
-            if (i < MLP_NIN) gp[MLP_OFF_W1 + (8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * MLP_NIN + i] = acc[r];
+            if (i < MLP_NIN) put(gp + MLP_OFF_W1 + (8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * MLP_NIN + i, acc[r]);
         }
     }
     if (l < 32) {
         float sb = 0.0f;
         for (int q = 0; q < 64; ++q) sb += bf16_to_f32(tdz[q * MLP_LDS_STRIDE + l]);
-        gp[MLP_OFF_B1 + l] = sb;
+        put(gp + MLP_OFF_B1 + l, sb);
     }
     if constexpr (PROP) {
         // xbar = (W1^T dh1) * inv_scale: dh1 of this lane's node is row l of tdz
@@ -331,13 +334,33 @@ __global__ __launch_bounds__(64) void k_train_backward(const float* __restrict__
     }
 }
 
-// grad[p] += sum over partials (FP64, fixed order); one thread per parameter.
-__global__ __launch_bounds__(256) void k_reduce_grad(const float* __restrict__ partials, int nparts, double* __restrict__ grad)
+// grad[p] += sum over the per-wavefront partials, in FP64 and a fixed order
+// (repeatable bit for bit).  Stage 1: block (x, y) sums slice y of the
+// partials for 64 parameters, four lanes per parameter over interleaved
+// partials (each wavefront reads 64 consecutive floats per partial), into
+// tmp[y][p]; stage 2 adds the slices.
+constexpr int MLP_RED_SLICES = 32;
+__global__ __launch_bounds__(256) void k_reduce_grad_slices(const float* __restrict__ partials, int nparts,
+                                                            double* __restrict__ tmp)
+{
+    __shared__ double red[4][64];
+    const int l = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + l;
+    const int chunk = (nparts + MLP_RED_SLICES - 1) / MLP_RED_SLICES;
+    const int w0 = blockIdx.y * chunk, w1 = min(nparts, w0 + chunk);
+    double s = 0.0;
+    if (p < MLP_NPARAM)
+        for (int w = w0 + sub; w < w1; w += 4) s += (double)partials[(int64_t)w * MLP_NPARAM + p];
+    red[sub][l] = s;
+    __syncthreads();
+    if (sub == 0 && p < MLP_NPARAM) tmp[(int64_t)blockIdx.y * MLP_NPARAM + p] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
+}
+__global__ __launch_bounds__(256) void k_reduce_grad(const double* __restrict__ tmp, double* __restrict__ grad)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= MLP_NPARAM) return;
     double s = 0.0;
-    for (int w = 0; w < nparts; ++w) s += (double)partials[(int64_t)w * MLP_NPARAM + p];
+    for (int y = 0; y < MLP_RED_SLICES; ++y) s += tmp[(int64_t)y * MLP_NPARAM + p];
     grad[p] += s;
 }
 
@@ -568,20 +591,24 @@ void launch_train_loss(const float* post, const Geom& g, float rho0, const float
 }
 
 void launch_train_backward(const float* state, const float* gbuf, const Geom& g, const Phys& ph, const void* net,
-                           float* grad_partials, float* gout, hipStream_t st)
+                           float* grad_partials, float* gout, bool accumulate, hipStream_t st)
 {
     const dim3 grid((g.nx + 63) / 64, g.ny, g.nz);
     if (gout)
         hipLaunchKernelGGL(k_train_backward<true>, grid, dim3(64), 0, st, state, gbuf, g, ph, (const MlpPacked*)net,
-                           grad_partials, gout);
+                           grad_partials, gout, (int)accumulate);
     else
         hipLaunchKernelGGL(k_train_backward<false>, grid, dim3(64), 0, st, state, gbuf, g, ph, (const MlpPacked*)net,
-                           grad_partials, gout);
+                           grad_partials, gout, (int)accumulate);
 }
 
-void launch_reduce_grad(const float* partials, int nparts, double* grad, hipStream_t st)
+size_t reduce_grad_tmp_bytes() { return sizeof(double) * MLP_RED_SLICES * MLP_NPARAM; }
+
+void launch_reduce_grad(const float* partials, int nparts, double* grad, double* tmp, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_grad, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, partials, nparts, grad);
+    hipLaunchKernelGGL(k_reduce_grad_slices, dim3((MLP_NPARAM + 63) / 64, MLP_RED_SLICES), dim3(256), 0, st, partials,
+                       nparts, tmp);
+    hipLaunchKernelGGL(k_reduce_grad, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, tmp, grad);
 }
 
 void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st)

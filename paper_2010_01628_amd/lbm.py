@@ -20,7 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 # LBM_LIBRARY names another build of the same library (the host-sanitized one)
 LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_PKG, "liblbm.so")
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3
 LBM_AB, LBM_AA = 0, 1
@@ -133,7 +133,7 @@ def lib():
         L.lbm_fallback_count.restype = i64
         L.lbm_mlp_zero_grad.argtypes = [vp]
         L.lbm_mlp_accumulate_grad.argtypes = [vp, vp, vp, dp, dp]
-        L.lbm_mlp_accumulate_rollout_grad.argtypes = [vp, vp, vp, i32, dp, vp, dp]
+        L.lbm_mlp_accumulate_rollout_grad.argtypes = [vp, vp, vp, i32, dp, dp, vp, dp, dp]
         L.lbm_mlp_get_grad.argtypes = [vp, dp]
         L.lbm_mlp_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.lbm_feature_rms.argtypes = [vp, dp]
@@ -248,7 +248,7 @@ def lbm_destroy(h: int) -> None:
 
 
 MLP_NPARAM = 1737
-MLP_MAX_ROLLOUT = 64
+MLP_MAX_ROLLOUT = 128
 
 
 def _fptr(a):
@@ -307,11 +307,18 @@ def lbm_mlp_accumulate_grad(m, h, target_ptr, sigma) -> float:
     return float(loss[0])
 
 
-def lbm_mlp_accumulate_rollout_grad(m, h, targets_ptr, steps, sigma, dstate_ptr=None) -> float:
+def lbm_mlp_accumulate_rollout_grad(m, h, targets_ptr, steps, sigma, step_weight=None, dstate_ptr=None):
+    """Returns (loss, per-step losses)."""
     sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    w = None if step_weight is None else np.ascontiguousarray(step_weight, dtype=np.float64)
+    if w is not None and w.size != int(steps):
+        raise ValueError("one weight per step")
     loss = np.zeros(1)
-    _check(lib().lbm_mlp_accumulate_rollout_grad(m, h, targets_ptr, int(steps), _dptr(sig), dstate_ptr, _dptr(loss)))
-    return float(loss[0])
+    per = np.zeros(int(steps))
+    _check(lib().lbm_mlp_accumulate_rollout_grad(m, h, targets_ptr, int(steps), _dptr(sig),
+                                                 None if w is None else _dptr(w), dstate_ptr, _dptr(per),
+                                                 _dptr(loss)))
+    return float(loss[0]), per
 
 
 def lbm_mlp_get_grad(m):
@@ -610,17 +617,24 @@ class Lattice:
         assert t.dtype == self.torch.float32 and t.numel() == 10 * self.N
         return lbm_mlp_accumulate_grad(mlp.m, self.h, t.data_ptr(), sigma)
 
-    def accumulate_rollout_grad(self, mlp, targets, sigma, want_dstate=False):
+    def accumulate_rollout_grad(self, mlp, targets, sigma, step_weight=None, want_dstate=False, want_steps=False):
         """targets: device float32 tensor (steps, 10, nz, ny, nx), the moments
-        after each step.  Returns the loss, and with want_dstate also
-        dL/df (device float32 (19, nz, ny, nx)) of the current populations."""
+        after each step; step_weight: one positive weight per step or None.
+        Returns the loss; with want_steps also the per-step losses, with
+        want_dstate also dL/df (device float32 (19, nz, ny, nx)) of the
+        current populations."""
         t = targets.contiguous()
         assert t.dtype == self.torch.float32 and t.numel() % (10 * self.N) == 0
         steps = t.numel() // (10 * self.N)
         ds = self.torch.empty((19,) + self.shape, dtype=self.torch.float32, device=t.device) if want_dstate else None
-        loss = lbm_mlp_accumulate_rollout_grad(mlp.m, self.h, t.data_ptr(), steps, sigma,
-                                               ds.data_ptr() if ds is not None else None)
-        return (loss, ds) if want_dstate else loss
+        loss, per = lbm_mlp_accumulate_rollout_grad(mlp.m, self.h, t.data_ptr(), steps, sigma, step_weight,
+                                                    ds.data_ptr() if ds is not None else None)
+        out = (loss,)
+        if want_steps:
+            out += (per,)
+        if want_dstate:
+            out += (ds,)
+        return out if len(out) > 1 else loss
 
     @property
     def step_count(self):

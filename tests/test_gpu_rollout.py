@@ -89,6 +89,13 @@ class Case:
             return out[0], g, out[1].cpu().numpy().astype(np.float64)
         return out, g
 
+    def gpu_weighted(self, w):
+        self.mlp.zero_grad()
+        loss, per = self.lat.accumulate_rollout_grad(self.mlp, self.tgt, SIGMA, step_weight=w, want_steps=True)
+        g = self.mlp.grad()
+        self.mlp.zero_grad()
+        return loss, per, g
+
     def loss(self, orc, P=None, f=None, bf16=False):
         P = self.Pg if P is None else P
         f = self.f0 if f is None else f
@@ -194,4 +201,40 @@ def test_rollout_state_gradient(orc, steps):
         fd = c.fd_state(orc, U, 1e-7 * scale)
         say(f"    entry {np.unravel_index(k, ds.shape)}: gpu {ds.flat[k]:+.6e} fd {fd:+.6e}")
         assert abs(fd - ds.flat[k]) <= GRAD_TOL * flat.max()
+    c.close()
+
+
+def test_step_weights_and_per_step_losses(orc):
+    """Per-step losses equal the oracle's (BF16 emulated); weights scale
+    each step's loss and its gradient: weights w give sum_k w_k L_k / steps,
+    and the gradient is linear in w (the gradient with w = e_1 + 3 e_3 is
+    that of e_1 plus three times that of e_3, up to the BF16 rounding of the
+    back-propagated errors), which the oracle's weighted loss confirms by
+    central differences along the weighted gradient."""
+    steps = 3
+    c = Case(orc, steps)
+    loss, per, g = c.gpu_weighted(None)
+    assert abs(loss - per.mean()) <= 1e-12 * loss
+    want, _ = orc.mlp.rollout_step_losses(c.f0, c.targets, OMEGA, c.Pg, SCALES, SIGMA, bf16=True)
+    say(f"  per-step loss gpu {per} oracle {want}")
+    assert np.all(np.abs(per - want) <= 1e-4 * want)
+    tiny = 1e-30
+    w1 = np.array([1.0, tiny, tiny])
+    w3 = np.array([tiny, tiny, 1.0])
+    _, p1, g1 = c.gpu_weighted(w1)
+    _, p3, g3 = c.gpu_weighted(w3)
+    w = w1 + 3 * w3
+    lw, pw, gw = c.gpu_weighted(w)
+    assert np.allclose(pw, per, rtol=1e-6) and np.allclose(p1, per, rtol=1e-6)
+    assert abs(lw - (per[0] + 3 * per[2]) / steps) <= 1e-6 * lw
+    # linear up to the BF16 rounding of the back-propagated errors (one BF16
+    # step, 2^-8 relative, is the bound: measured 5.6e-4)
+    assert np.linalg.norm(gw - (g1 + 3 * g3)) <= 2.0 ** -8 * np.linalg.norm(gw)
+    h = 1e-5
+    v = gw / np.linalg.norm(gw)
+    lp, _ = orc.mlp.rollout_loss(c.f0, c.targets, OMEGA, c.Pg + h * v, SCALES, SIGMA, weights=w)
+    lm, _ = orc.mlp.rollout_loss(c.f0, c.targets, OMEGA, c.Pg - h * v, SCALES, SIGMA, weights=w)
+    d = (lp - lm) / (2 * h)
+    say(f"  weighted: |g| {np.linalg.norm(gw):.6e}, fd {d:.6e}")
+    assert abs(d - np.linalg.norm(gw)) <= GRAD_TOL * np.linalg.norm(gw)
     c.close()
