@@ -78,6 +78,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                       uint32_t* __restrict__ fb_counts)
 {
     __shared__ uint32_t wave_fb[4];
+    __shared__ __align__(16) uint32_t net_lds[MLP_INFER_WORDS];
+    load_net(net_lds, net, MLP_INFER_WORDS);
     const int w = threadIdx.x >> 6;
     uint32_t my_fb = 0;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -109,14 +111,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             xin[9] = st0.n.m202 * ir;
             xin[10] = st0.n.m022 * ir;
         }
-        // the network is re-read every tile (L1/L2 hits) rather than held in
-        // registers across the loop: hoisting its loads costs ~70 registers
-        // (pinned as a global-address-space pointer: the loads stay global,
-        // not flat, instructions)
-        typedef __attribute__((address_space(1))) const MlpPacked gnet_t;
-        gnet_t* netg = (gnet_t*)net;
-        asm volatile("" : "+s"(netg));
-        mlp_forward_regs(*(const MlpPacked*)netg, xin, zout);
+        // the network, staged in LDS once per work-group, is re-read every
+        // tile rather than held in registers across the loop (hoisting its
+        // loads costs ~70 registers): an offset the compiler cannot see
+        // keeps the reads inside the loop, and LDS reads
+        int zoff = 0;
+        asm volatile("" : "+s"(zoff));
+        mlp_forward_regs(*reinterpret_cast<const MlpPacked*>(reinterpret_cast<const char*>(net_lds) + zoff), xin, zout);
         const bool fb = mlp_rates(zout, rates);
         // recomputed rather than kept live across the network: with the tile
         // loop's own state, keeping it would spill at four waves per SIMD;

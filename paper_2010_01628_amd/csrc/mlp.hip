@@ -25,17 +25,6 @@ template <class R> __device__ inline void mlp_features(const CMState<R>& st, R x
     x[10] = n.m022 * ir;
 }
 
-// Cooperative copy of the first `words` 32-bit words of the packed network
-// into LDS (all threads of the block).
-__device__ inline void load_net(uint32_t* d, const MlpPacked* __restrict__ src, int words)
-{
-    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-    const int nthr = blockDim.x * blockDim.y;
-    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
-    for (int i = tid; i < words; i += nthr) d[i] = s[i];
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // Step with learned rates (FP32 collision; FP32/FP16/BF16 storage).  Every
 // lane of every wavefront takes part in the network (lanes past the lattice
@@ -46,6 +35,12 @@ template <class S, Pattern P, bool WALLS, bool NT, bool O32 = false>
 __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const Phys& ph,
                                      const MlpPacked* __restrict__ net, uint32_t* __restrict__ fb_partials)
 {
+    // the inference part of the network, once per work-group in LDS: each
+    // wavefront reads its MFMA weight operands and bias accumulators from
+    // there instead of from memory (~17 KB per wavefront)
+    __shared__ __align__(16) uint32_t net_lds[MLP_INFER_WORDS];
+    load_net(net_lds, net, MLP_INFER_WORDS);
+    const MlpPacked* snet = reinterpret_cast<const MlpPacked*>(net_lds);
     const int xr = blockIdx.x * blockDim.x + threadIdx.x;
     const int yr = blockIdx.y * blockDim.y + threadIdx.y;
     const bool valid = xr < g.nx && yr < g.ny;
@@ -63,7 +58,7 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
     pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
     mlp_features(st, xin);
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-    mlp_forward_regs(*net, xin, zout);
+    mlp_forward_regs(*snet, xin, zout);
     const bool fb = mlp_rates(zout, rates);
     Rates<float> rt = rates_of<float>(ph);
 #pragma unroll

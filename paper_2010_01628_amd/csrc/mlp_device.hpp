@@ -45,6 +45,17 @@ struct MlpPacked {
 };
 constexpr int MLP_INFER_WORDS = (int)(__builtin_offsetof(MlpPacked, w2t) / 4);
 
+// Cooperative copy of the first `words` 32-bit words of the packed network
+// into LDS (all threads of the block).
+__device__ inline void load_net(uint32_t* d, const MlpPacked* __restrict__ src, int words)
+{
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int nthr = blockDim.x * blockDim.y;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    for (int i = tid; i < words; i += nthr) d[i] = s[i];
+    __syncthreads();
+}
+
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
