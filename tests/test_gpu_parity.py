@@ -1,9 +1,13 @@
 """GPU (HIP, gfx950) parity with the FP64 oracle, through the C ABI.
 
 Tolerances (relative L2 on rho and u after the stated steps): 1e-12 for FP64
-storage, 1e-5 for FP32, 1e-3 for FP16/BF16 shifted storage; populations are
-also compared element by element where the precision allows.
+storage, 1e-5 for FP32, 1e-3 for FP16 shifted storage and 1.5 times the
+storage-only error for BF16 (HALF_U_TOL); populations are also compared
+element by element where the precision allows.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -118,9 +122,14 @@ def test_fp32_parity_config2_recipe(orc, streaming):
 
 
 # Relative-L2 bound on u per storage precision.  The target for 16-bit storage
-# is 1e-3.  FP16 meets it.  BF16 (8-bit significand: 2^-9 relative rounding of
-# s_i ~ 1e-2 per store) does not: 3.0e-3 was measured for this case.
-HALF_U_TOL = {"fp16": 1e-3, "bf16": 5e-3}
+# is 1e-3, which FP16 meets.  BF16 cannot on this recipe with any arithmetic:
+# its storage rounding alone (the FP64 oracle with the stored deviations
+# rounded to BF16 after every step, tests/golden/conditioning.py) costs
+# 2.96e-3 on u after 200 steps at 32^3.  BF16 is held to 1.5 times that (the
+# margin covers rounding decisions that differ between the GPU's FP32 values
+# and the oracle's FP64 ones; 3.0e-3 measured).
+_COND = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "conditioning_config2.json")))
+HALF_U_TOL = {"fp16": 1e-3, "bf16": 1.5 * _COND["32"]["bf16"]["200"]["u"]}
 
 
 @pytest.mark.parametrize("precision", ["fp16", "bf16"])
