@@ -344,6 +344,12 @@ int lbm_tune(lbm_handle *h, int32_t trial_steps, int32_t *block_x, int32_t *bloc
 /* Number of steps taken since lbm_init. */
 int64_t lbm_step_count(const lbm_handle *h);
 
+/* Which plain step kernel lbm_step launches (not the learned or coupled
+ * ones): 0 = one node per thread, 1 = x-moving populations staged through LDS
+ * along whole rows (the default wherever possible; lbm_tune may choose
+ * either); -1 for a NULL handle. */
+int32_t lbm_step_variant(const lbm_handle *h);
+
 /* Device bytes held by the handle (population buffers and tables). */
 int64_t lbm_device_bytes(const lbm_handle *h);
 

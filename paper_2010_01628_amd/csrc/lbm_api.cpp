@@ -516,6 +516,12 @@ int lbm_set_populations(lbm_handle* h, const double* f, int on_device)
 
 int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }
 
+int32_t lbm_step_variant(const lbm_handle* h)
+{
+    if (!h) return -1;
+    return h->g.row_stage ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // Autotuner of the plain step: work-group shape x cache policy
 // ---------------------------------------------------------------------------
@@ -589,6 +595,7 @@ int lbm_tune(lbm_handle* h, int32_t trial_steps, int32_t* block_x, int32_t* bloc
                 cands.push_back({bx, sh[1], nt, h->g.row_stage ? 1 : 0, 1e30f});
             }
         }
+
         hipEvent_t a, b;
         HIP_TRY(hipEventCreate(&a));
         HIP_TRY(hipEventCreate(&b));

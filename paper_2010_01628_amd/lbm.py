@@ -117,6 +117,8 @@ def lib():
         L.lbm_set_populations.argtypes = [vp, vp, i32]
         L.lbm_step_count.argtypes = [vp]
         L.lbm_step_count.restype = i64
+        L.lbm_step_variant.argtypes = [vp]
+        L.lbm_step_variant.restype = i32
         L.lbm_device_bytes.argtypes = [vp]
         L.lbm_device_bytes.restype = i64
         L.lbm_destroy.argtypes = [vp]
@@ -237,6 +239,10 @@ def lbm_set_populations(h: int, f_ptr: int, on_device: bool) -> None:
 
 def lbm_step_count(h: int) -> int:
     return lib().lbm_step_count(h)
+
+
+def lbm_step_variant(h: int) -> int:
+    return lib().lbm_step_variant(h)
 
 
 def lbm_device_bytes(h: int) -> int:
@@ -639,6 +645,11 @@ class Lattice:
     @property
     def step_count(self):
         return lbm_step_count(self.h)
+
+    @property
+    def step_variant(self):
+        """0: one node per thread, 1: x-moving populations staged through LDS."""
+        return lbm_step_variant(self.h)
 
     def tune(self, trial_steps=10):
         """Pick the step kernel's work-group shape, cache policy and row

@@ -273,6 +273,7 @@ def test_null_handles(lbm):
     lbm.lbm_destroy(0)
     lbm.lbm_mlp_destroy(0)
     assert lbm.lbm_step_count(0) == -1
+    assert lbm.lbm_step_variant(0) == -1
     for call in (lambda: lbm.lbm_step(0, 1), lambda: lbm.lbm_init(0, 0, 0, False),
                  lambda: lbm.lbm_moments(0, 0, 0, 0, False), lambda: lbm.lbm_moments_noalloc(0, 0, 0, 0),
                  lambda: lbm.lbm_get_populations(0, 0, False), lambda: lbm.lbm_set_populations(0, 0, False)):
