@@ -430,6 +430,14 @@ int lbm_mlp_accumulate_grad(lbm_mlp *m, lbm_handle *h, const float *target, cons
 int lbm_mlp_accumulate_rollout_grad(lbm_mlp *m, lbm_handle *h, const float *targets, int32_t steps,
                                     const double sigma[10], const double *step_weight, float *dstate,
                                     double *step_loss, double *loss);
+
+/* Weight w_E >= 0 (default 0) of a kinetic-energy term in m's later rollout
+ * losses: L gains (w_E / steps) sum_k ((E_k - T_k) / T_k)^2, with E_k =
+ * 1/2 sum over the lattice of |j|^2 / rho of the populations after step k and
+ * T_k the same of target k's moments (rho, j); its gradient is
+ * back-propagated with the rest.  step_loss keeps reporting the moment terms
+ * L_k only.  Not used by lbm_mlp_accumulate_grad. */
+int lbm_mlp_set_energy_weight(lbm_mlp *m, double w);
 int lbm_mlp_get_grad(const lbm_mlp *m, double *grad);      /* host double[LBM_MLP_NPARAM] */
 /* One Adam update of the FP32 master parameters with the accumulated gradient. */
 int lbm_mlp_adam_step(lbm_mlp *m, double lr, double beta1, double beta2, double eps);

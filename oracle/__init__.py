@@ -543,13 +543,32 @@ class mlp:
         return np.array(out), fbs
 
     @staticmethod
-    def rollout_loss(f, targets, omega, P, scales, sigma, bf16=False, weights=None):
+    def kinetic_energy(rho, j):
+        """1/2 sum over the lattice of |j|^2 / rho."""
+        return float(0.5 * np.sum((j[0] ** 2 + j[1] ** 2 + j[2] ** 2) / rho))
+
+    @staticmethod
+    def rollout_loss(f, targets, omega, P, scales, sigma, bf16=False, weights=None, energy_weight=0.0):
         """Rollout loss: the per-step losses (rollout_step_losses) averaged
-        over the steps with weights (default all 1): sum_k w_k L_k / steps.
-        Returns (loss, fallbacks)."""
+        over the steps with weights (default all 1): sum_k w_k L_k / steps;
+        with energy_weight w_E > 0 also (w_E / steps) sum_k ((E_k - T_k) /
+        T_k)^2, E_k the kinetic energy of the populations after step k and
+        T_k that of target k's moments.  Returns (loss, fallbacks)."""
         per, fbs = mlp.rollout_step_losses(f, targets, omega, P, scales, sigma, bf16=bf16)
         w = np.ones(len(per)) if weights is None else _f64(weights)
-        return float(np.sum(w * per)) / len(per), fbs
+        loss = float(np.sum(w * per)) / len(per)
+        if energy_weight:
+            a = _f64(f).copy()
+            b = np.empty_like(a)
+            for tk in targets:
+                mlp.step(a, omega, P, scales, bf16=bf16, out=b)
+                a, b = b, a
+                m = mlp.moments10(a)
+                tk = _f64(tk)
+                E = mlp.kinetic_energy(m[0], m[1:4])
+                T = mlp.kinetic_energy(tk[0], tk[1:4])
+                loss += energy_weight / len(per) * ((E - T) / T) ** 2
+        return loss, fbs
 
     @staticmethod
     def loss_grad(f, target, omega, P, scales, sigma, bf16=False, want_grad=True):

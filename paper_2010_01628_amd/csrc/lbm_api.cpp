@@ -646,7 +646,8 @@ int lbm_mlp_destroy(lbm_mlp* m)
     if (!m) return LBM_OK;
     hipStreamSynchronize(m->stream);
     void* bufs[] = {m->theta, m->m1, m->m2, m->grad, m->inv_scale, m->packed, m->inv_sigma, m->gbuf, m->traj,
-                    m->grad_parts, m->loss_parts, m->loss_dev, m->red_tmp, m->isig_steps, m->loss_steps};
+                    m->grad_parts, m->loss_parts, m->loss_dev, m->red_tmp, m->isig_steps, m->loss_steps,
+                    m->energies, m->energy_parts};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (m->loss_host) hipHostFree(m->loss_host);
@@ -838,7 +839,7 @@ int lbm_mlp_accumulate_grad(lbm_mlp* m, lbm_handle* h, const float* target, cons
     lbm::launch_step_mlp(LBM_FP32, 0, false, false, state, post, g, h->ph, m->packed, h->fb_partials, h->grid, h->block,
                          h->stream);
     lbm::launch_train_loss((const float*)post, g, (float)h->p.rho0, target, m->inv_sigma, m->gbuf, m->loss_parts,
-                           false, h->grid, h->block, h->stream);
+                           false, nullptr, 0.0f, h->grid, h->block, h->stream);
     lbm::launch_train_backward((const float*)state, m->gbuf, g, h->ph, m->packed, m->grad_parts, nullptr, false,
                                h->stream);
     lbm::launch_reduce_grad(m->grad_parts, nwb, m->grad, m->red_tmp, h->stream);
@@ -880,6 +881,9 @@ int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targ
     if (!rc) rc = grow((void**)&m->grad_parts, m->grad_parts_n, (int64_t)nwb * LBM_MLP_NPARAM, sizeof(float));
     if (!rc) rc = grow((void**)&m->loss_parts, m->loss_parts_n, (int64_t)steps * h->nblocks, sizeof(double));
     if (!rc) rc = grow((void**)&m->isig_steps, m->isig_steps_n, (int64_t)steps * 10, sizeof(float));
+    const bool energy = m->energy_weight > 0.0;
+    if (!rc && energy) rc = grow((void**)&m->energies, m->energies_n, (int64_t)2 * steps, sizeof(double));
+    if (!rc && energy) rc = grow((void**)&m->energy_parts, m->energy_parts_n, (int64_t)2 * h->nblocks, sizeof(double));
     if (!rc && m->loss_steps_n < LBM_MLP_MAX_ROLLOUT) {
         if (hipMalloc((void**)&m->loss_steps, sizeof(double) * LBM_MLP_MAX_ROLLOUT) != hipSuccess ||
             hipHostMalloc((void**)&m->loss_steps_host, sizeof(double) * LBM_MLP_MAX_ROLLOUT, hipHostMallocDefault) !=
@@ -897,6 +901,15 @@ int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targ
     for (int k = 0; k < steps; ++k)
         lbm::launch_step_mlp(LBM_FP32, 0, false, false, P(k), P(k + 1), g, h->ph, m->packed, h->fb_partials, h->grid,
                              h->block, h->stream);
+    // kinetic energies of every state and target (energy term)
+    if (energy)
+        for (int k = 1; k <= steps; ++k) {
+            lbm::launch_train_energy(P(k), g, (float)h->p.rho0, targets + (int64_t)(k - 1) * 10 * g.N, m->energy_parts,
+                                     h->grid, h->block, h->stream);
+            lbm::launch_sum_partials(m->energy_parts, h->nblocks, m->energies + 2 * (k - 1), h->stream);
+            lbm::launch_sum_partials(m->energy_parts + h->nblocks, h->nblocks, m->energies + 2 * (k - 1) + 1, h->stream);
+        }
+    const float ew = (float)(m->energy_weight / steps);
     // backward: A holds dL/df(t0 + k + 1); the step from P_k turns it into
     // dL/df(t0 + k) (in B, or in dstate for k = 0), to which the loss after k
     // steps adds its own gradient
@@ -905,7 +918,8 @@ int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targ
     auto loss_at = [&](int k, float* adj, bool acc) { // loss after k steps (k = 1..steps)
         lbm::launch_train_loss(P(k), g, (float)h->p.rho0, targets + (int64_t)(k - 1) * 10 * g.N,
                                m->isig_steps + (int64_t)(k - 1) * 10, adj,
-                               m->loss_parts + (int64_t)(k - 1) * h->nblocks, acc, h->grid, h->block, h->stream);
+                               m->loss_parts + (int64_t)(k - 1) * h->nblocks, acc,
+                               energy ? m->energies + 2 * (k - 1) : nullptr, ew, h->grid, h->block, h->stream);
     };
     loss_at(steps, A, false);
     for (int k = steps - 1; k >= 0; --k) {
@@ -922,13 +936,28 @@ int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targ
         lbm::launch_sum_partials(m->loss_parts + (int64_t)k * h->nblocks, h->nblocks, m->loss_steps + k, h->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(m->loss_steps_host, m->loss_steps, sizeof(double) * steps, hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> en(energy ? 2 * (size_t)steps : 0);
+    if (energy)
+        HIP_TRY(hipMemcpyAsync(en.data(), m->energies, sizeof(double) * en.size(), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     double total = 0.0;
     for (int k = 0; k < steps; ++k) {
         total += m->loss_steps_host[k];
         if (step_loss) step_loss[k] = m->loss_steps_host[k] * steps / wk[k];
+        if (energy) {
+            const double r = (en[2 * k] - en[2 * k + 1]) / en[2 * k + 1];
+            total += m->energy_weight / steps * r * r;
+        }
     }
     if (loss) *loss = total;
+    return LBM_OK;
+}
+
+int lbm_mlp_set_energy_weight(lbm_mlp* m, double w)
+{
+    if (!m) return fail(LBM_EINVAL, "NULL argument");
+    if (!(std::isfinite(w) && w >= 0.0)) return fail(LBM_EINVAL, "the energy weight must be finite and >= 0");
+    m->energy_weight = w;
     return LBM_OK;
 }
 

@@ -95,8 +95,13 @@ void launch_reduce(const double* partials, int nblocks, double* out, hipStream_t
 constexpr int MLP_PARAMS = 1737;
 void launch_step_mlp(int precision, int pattern, bool walls, bool nt, const void* src, void* dst, const Geom& g,
                      const Phys& ph, const void* net, uint32_t* fb_partials, dim3 grid, dim3 block, hipStream_t st);
+// energy (device, [E, E_target]) or nullptr: adds the energy term ew ((E - E_t) / E_t)^2
 void launch_train_loss(const float* post, const Geom& g, float rho0, const float* target, const float* inv_sigma,
-                       float* gbuf, double* loss_partials, bool accumulate, dim3 grid, dim3 block, hipStream_t st);
+                       float* gbuf, double* loss_partials, bool accumulate, const double* energy, float ew, dim3 grid,
+                       dim3 block, hipStream_t st);
+// per-block partial kinetic energies of post (pulled) and of the target moments: partials[b], partials[nblocks + b]
+void launch_train_energy(const float* post, const Geom& g, float rho0, const float* target, double* partials,
+                         dim3 grid, dim3 block, hipStream_t st);
 // gout != nullptr: also write dL/df(t) (rollout back-propagation);
 // accumulate: add to grad_partials instead of overwriting them
 void launch_train_backward(const float* state, const float* gbuf, const Geom& g, const Phys& ph, const void* net,
@@ -148,6 +153,11 @@ struct lbm_mlp {
     double* loss_steps = nullptr; // rollouts: loss of each step (device, and its host copy)
     int64_t loss_steps_n = 0;
     double* loss_steps_host = nullptr;
+    double energy_weight = 0.0; // rollouts: weight of the kinetic-energy term
+    double* energies = nullptr; // rollouts: [E, E_target] per step (device)
+    int64_t energies_n = 0;
+    double* energy_parts = nullptr; // per-block partial energies of one step
+    int64_t energy_parts_n = 0;
 };
 
 

@@ -107,10 +107,15 @@ __global__ __launch_bounds__(256) void k_step_mlp(const S* src, S* dst, Geom g, 
 // one FP64 loss partial per block; with `accumulate` the gradient is added to
 // what gbuf holds (the adjoint carried back from later steps of a rollout).
 // ---------------------------------------------------------------------------
+// Energy term (rollouts, `energy` != nullptr): the gradient of
+// ew ((E - E_t) / E_t)^2, with the kinetic energies E = 1/2 sum |j|^2 / rho of
+// the populations and E_t of the target moments (energy[0] = E, energy[1] =
+// E_t, from k_train_energy), is added per node: 2 ew (E - E_t) / E_t^2
+// (c_i . u - |u|^2 / 2).  The term's value is formed by the host.
 __global__ __launch_bounds__(256) void k_train_loss(const float* __restrict__ post, Geom g, float rho0,
                                                     const float* __restrict__ target, const float* __restrict__ inv_sigma,
                                                     float* __restrict__ gbuf, double* __restrict__ loss_partials,
-                                                    int accumulate)
+                                                    int accumulate, const double* __restrict__ energy, float ew)
 {
     __shared__ double red[4];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -147,11 +152,21 @@ __global__ __launch_bounds__(256) void k_train_loss(const float* __restrict__ po
             l2 += (double)r * (double)r;
             dm[k] = two_over_n * r * inv_sigma[k];
         }
+        float ce = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f, u2 = 0.0f;
+        if (energy) {
+            ce = (float)(2.0 * ew * (energy[0] - energy[1]) / (energy[1] * energy[1]));
+            const float ir = 1.0f / m[0];
+            ux = m[1] * ir;
+            uy = m[2] * ir;
+            uz = m[3] * ir;
+            u2 = 0.5f * (ux * ux + uy * uy + uz * uz);
+        }
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             const float cx = LatD3Q19::cx(i), cy = LatD3Q19::cy(i), cz = LatD3Q19::cz(i);
-            const float gi = dm[0] + cx * dm[1] + cy * dm[2] + cz * dm[3] + cx * cx * dm[4] + cy * cy * dm[5] +
-                             cz * cz * dm[6] + cx * cy * dm[7] + cx * cz * dm[8] + cy * cz * dm[9];
+            float gi = dm[0] + cx * dm[1] + cy * dm[2] + cz * dm[3] + cx * cx * dm[4] + cy * cy * dm[5] +
+                       cz * cz * dm[6] + cx * cy * dm[7] + cx * cz * dm[8] + cy * cz * dm[9];
+            if (energy) gi += ce * (cx * ux + cy * uy + cz * uz - u2);
             float* gp = gbuf + (int64_t)i * g.N + n;
             *gp = accumulate ? *gp + gi : gi;
         }
@@ -166,6 +181,60 @@ __global__ __launch_bounds__(256) void k_train_loss(const float* __restrict__ po
         double t = 0.0;
         for (int i = 0; i < (int)((blockDim.x * blockDim.y + 63) / 64); ++i) t += red[i];
         loss_partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t / (double)g.N;
+    }
+}
+
+// Per-block FP64 partial kinetic energies 1/2 |j|^2 / rho of the populations
+// pulled from post (no force) and of the target moments (rho, j): out[b] and
+// out[nblocks + b].
+__global__ __launch_bounds__(256) void k_train_energy(const float* __restrict__ post, Geom g, float rho0,
+                                                      const float* __restrict__ target, double* __restrict__ out)
+{
+    __shared__ double red[2][4];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double e = 0.0, et = 0.0;
+    if (x < g.nx && y < g.ny) {
+        NodeIdx d;
+        node_idx(g, x, y, z, d);
+        const int n = nb(d, 0, 0, 0);
+        float s[19];
+        gather<LatD3Q19, float, AB, false>(post, g.stride, d, s);
+        double r = rho0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            r += s[i];
+            jx += LatD3Q19::cx(i) * (double)s[i];
+            jy += LatD3Q19::cy(i) * (double)s[i];
+            jz += LatD3Q19::cz(i) * (double)s[i];
+        }
+        e = 0.5 * (jx * jx + jy * jy + jz * jz) / r;
+        const double rt = target[n], tx = target[(int64_t)g.N + n], ty = target[2 * (int64_t)g.N + n],
+                     tz = target[3 * (int64_t)g.N + n];
+        et = 0.5 * (tx * tx + ty * ty + tz * tz) / rt;
+    }
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e += __shfl_xor(e, o, 64);
+        et += __shfl_xor(et, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = e;
+        red[1][tid >> 6] = et;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < (int)((blockDim.x * blockDim.y + 63) / 64); ++i) {
+            a += red[0][i];
+            b += red[1][i];
+        }
+        const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        const int nb_ = gridDim.x * gridDim.y * gridDim.z;
+        out[bid] = a;
+        out[nb_ + bid] = b;
     }
 }
 
@@ -579,10 +648,17 @@ void launch_step_mlp(int precision, int pattern, bool walls, bool nt, const void
 }
 
 void launch_train_loss(const float* post, const Geom& g, float rho0, const float* target, const float* inv_sigma,
-                       float* gbuf, double* loss_partials, bool accumulate, dim3 grid, dim3 block, hipStream_t st)
+                       float* gbuf, double* loss_partials, bool accumulate, const double* energy, float ew, dim3 grid,
+                       dim3 block, hipStream_t st)
 {
     hipLaunchKernelGGL(k_train_loss, grid, block, 0, st, post, g, rho0, target, inv_sigma, gbuf, loss_partials,
-                       (int)accumulate);
+                       (int)accumulate, energy, ew);
+}
+
+void launch_train_energy(const float* post, const Geom& g, float rho0, const float* target, double* partials,
+                         dim3 grid, dim3 block, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_train_energy, grid, block, 0, st, post, g, rho0, target, partials);
 }
 
 void launch_train_backward(const float* state, const float* gbuf, const Geom& g, const Phys& ph, const void* net,

@@ -136,6 +136,7 @@ def lib():
         L.lbm_mlp_zero_grad.argtypes = [vp]
         L.lbm_mlp_accumulate_grad.argtypes = [vp, vp, vp, dp, dp]
         L.lbm_mlp_accumulate_rollout_grad.argtypes = [vp, vp, vp, i32, dp, dp, vp, dp, dp]
+        L.lbm_mlp_set_energy_weight.argtypes = [vp, ctypes.c_double]
         L.lbm_mlp_get_grad.argtypes = [vp, dp]
         L.lbm_mlp_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.lbm_feature_rms.argtypes = [vp, dp]
@@ -184,6 +185,7 @@ def lib():
                      "lbm_set_populations", "lbm_destroy", "lbm_mlp_create", "lbm_mlp_set_params",
                      "lbm_mlp_get_params", "lbm_mlp_set_scales", "lbm_mlp_destroy", "lbm_set_mlp",
                      "lbm_mlp_zero_grad", "lbm_mlp_accumulate_grad", "lbm_mlp_accumulate_rollout_grad",
+                     "lbm_mlp_set_energy_weight",
                      "lbm_mlp_get_grad", "lbm_mlp_adam_step",
                      "lbm_feature_rms", "lbm_project_q27", "lbm_stream_copy"):
             getattr(L, name).restype = i32
@@ -327,6 +329,10 @@ def lbm_mlp_accumulate_rollout_grad(m, h, targets_ptr, steps, sigma, step_weight
     return float(loss[0]), per
 
 
+def lbm_mlp_set_energy_weight(m, w):
+    _check(lib().lbm_mlp_set_energy_weight(m, float(w)))
+
+
 def lbm_mlp_get_grad(m):
     out = np.zeros(MLP_NPARAM)
     _check(lib().lbm_mlp_get_grad(m, _dptr(out)))
@@ -388,6 +394,10 @@ class Mlp:
 
     def grad(self):
         return lbm_mlp_get_grad(self.m)
+
+    def set_energy_weight(self, w):
+        """Weight of the kinetic-energy term of later rollout losses (0: none)."""
+        lbm_mlp_set_energy_weight(self.m, w)
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         lbm_mlp_adam_step(self.m, lr, beta1, beta2, eps)

@@ -268,6 +268,13 @@ def test_without_a_device_every_create_fails_cleanly(lbm):
     assert e.value.code == lbm.LBM_EDEVICE
 
 
+def test_energy_weight_validation(lbm):
+    for w in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_mlp_set_energy_weight(0, w)
+        assert e.value.code == lbm.LBM_EINVAL
+
+
 def test_null_handles(lbm):
     """NULL handles: destroy is a no-op, queries report an error."""
     lbm.lbm_destroy(0)

@@ -99,9 +99,16 @@ class Case:
     def loss(self, orc, P=None, f=None, bf16=False):
         P = self.Pg if P is None else P
         f = self.f0 if f is None else f
-        lo, fb = orc.mlp.rollout_loss(f, self.targets, OMEGA, P, SCALES, SIGMA, bf16=bf16)
+        lo, fb = orc.mlp.rollout_loss(f, self.targets, OMEGA, P, SCALES, SIGMA, bf16=bf16,
+                                      energy_weight=self.energy_weight)
         assert fb == 0
         return lo
+
+    energy_weight = 0.0
+
+    def set_energy_weight(self, w):
+        self.energy_weight = w
+        self.mlp.set_energy_weight(w)
 
     def fd_theta(self, orc, v, h=1e-5):
         v = v / np.linalg.norm(v)
@@ -237,4 +244,36 @@ def test_step_weights_and_per_step_losses(orc):
     d = (lp - lm) / (2 * h)
     say(f"  weighted: |g| {np.linalg.norm(gw):.6e}, fd {d:.6e}")
     assert abs(d - np.linalg.norm(gw)) <= GRAD_TOL * np.linalg.norm(gw)
+    c.close()
+
+
+def test_energy_term(orc):
+    """The kinetic-energy term of the rollout loss: value against the oracle
+    (BF16 emulated), parameter gradient and initial-state gradient against
+    central differences of the exact model's loss.  The targets' energies
+    differ from the scheme's by the noise added to them, and the weight makes
+    the term a sizeable part of the loss."""
+    steps = 3
+    c = Case(orc, steps)
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(L.LbmError):
+            c.mlp.set_energy_weight(bad)
+    c.set_energy_weight(2e5)
+    lo_gpu, g, ds = c.gpu(want_dstate=True)
+    lo = c.loss(orc, bf16=True)
+    c.set_energy_weight(0.0)
+    lo_moments = c.loss(orc, bf16=True)
+    c.set_energy_weight(2e5)
+    say(f"  loss gpu {lo_gpu:.8e} oracle {lo:.8e} (moment terms alone {lo_moments:.6e})")
+    assert lo > 1.2 * lo_moments
+    assert abs(lo_gpu - lo) / lo < 1e-4
+    gn = np.linalg.norm(g)
+    d = c.fd_theta(orc, g)
+    say(f"  |g| {gn:.6e}, d/dh L(theta + h g/|g|) {d:.6e}")
+    assert abs(d - gn) <= GRAD_TOL * gn
+    n2 = float(np.sum(ds * ds))
+    h = 1e-7 * np.abs(c.f0).max() / np.abs(ds).max()
+    dsd = c.fd_state(orc, ds, h)
+    say(f"  |dL/df|^2 {n2:.6e}, fd along dL/df {dsd:.6e}")
+    assert abs(dsd - n2) <= GRAD_TOL * n2
     c.close()
