@@ -50,8 +50,8 @@ __host__ __device__ constexpr double w19(int i)
 }
 
 // ---------------------------------------------------------------------------
-// Storage codecs.  FP16 uses the hardware round-to-nearest-even conversion;
-// BF16 is rounded to nearest even on the bit pattern (NaN kept quiet).
+// Storage codecs.  FP16 and BF16 use the hardware round-to-nearest-even
+// conversions.
 // ---------------------------------------------------------------------------
 struct bf16_t {
     uint16_t bits;
@@ -97,12 +97,12 @@ template <> struct Codec<bf16_t> {
     static constexpr bool increment = false;
     using R = float;
     __device__ static inline float dec(bf16_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
+    // gfx950's conversion instruction (v_cvt_pk_bf16_f32): round to nearest
+    // even, one instruction instead of the bit-pattern rounding's six
     __device__ static inline bf16_t enc(float v)
     {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return bf16_t{(uint16_t)((u >> 16) | 0x40u)};
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return bf16_t{(uint16_t)(u >> 16)};
+        const __bf16 b = (__bf16)v;
+        return bf16_t{__builtin_bit_cast(uint16_t, b)};
     }
 };
 
