@@ -805,7 +805,7 @@ static int grow(void** p, int64_t& have, int64_t need, size_t elem)
 }
 
 // Shared checks of the training entry points; fills the inverse moment scales
-// (each sigma_k times sqrt(steps): the rollout loss is the mean over steps).
+// 1 / (sigma_k sqrt(steps)).
 static int training_checks(lbm_mlp* m, lbm_handle* h, const double sigma[10], int steps, float isig[10])
 {
     if (h->mlp != m) return fail(LBM_EINVAL, "the network must be attached to the handle (lbm_set_mlp)");
@@ -885,10 +885,16 @@ int lbm_mlp_accumulate_rollout_grad(lbm_mlp* m, lbm_handle* h, const float* targ
     if (!rc && energy) rc = grow((void**)&m->energies, m->energies_n, (int64_t)2 * steps, sizeof(double));
     if (!rc && energy) rc = grow((void**)&m->energy_parts, m->energy_parts_n, (int64_t)2 * h->nblocks, sizeof(double));
     if (!rc && m->loss_steps_n < LBM_MLP_MAX_ROLLOUT) {
-        if (hipMalloc((void**)&m->loss_steps, sizeof(double) * LBM_MLP_MAX_ROLLOUT) != hipSuccess ||
-            hipHostMalloc((void**)&m->loss_steps_host, sizeof(double) * LBM_MLP_MAX_ROLLOUT, hipHostMallocDefault) !=
-                hipSuccess)
+        // both buffers or neither: a partial allocation is released, so a
+        // later call starts from nothing again
+        double *dev = nullptr, *host = nullptr;
+        if (hipMalloc((void**)&dev, sizeof(double) * LBM_MLP_MAX_ROLLOUT) != hipSuccess ||
+            hipHostMalloc((void**)&host, sizeof(double) * LBM_MLP_MAX_ROLLOUT, hipHostMallocDefault) != hipSuccess) {
+            if (dev) hipFree(dev);
             return fail(LBM_ENOMEM, "rollout loss buffers");
+        }
+        m->loss_steps = dev;
+        m->loss_steps_host = host;
         m->loss_steps_n = LBM_MLP_MAX_ROLLOUT;
     }
     if (rc) return rc;
