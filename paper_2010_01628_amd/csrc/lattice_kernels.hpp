@@ -409,14 +409,21 @@ __global__ __launch_bounds__(W) void k_step_ab_rows(const S* __restrict__ src, S
     NodeIdx d;
     node_idx(g, x, y, z, d);
     const int row0 = threadIdx.y * blockDim.x;
+    // every load is issued before the barrier: the populations that stay in
+    // x go straight to registers, the others to LDS
+    S direct[L::Q];
     {
         int k = 0;
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i)
+        for (int i = 0; i < L::Q; ++i) {
+            const S v = ld<S, NT>(pop_at<S, O32, true>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i))));
             if (L::cx(i) != 0) {
-                rows[k][row0 + x] = ld<S, NT>(pop_at<S, O32, true>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i))));
+                rows[k][row0 + x] = v;
                 ++k;
+            } else {
+                direct[i] = v;
             }
+        }
     }
     __syncthreads();
     R s[L::Q];
@@ -430,7 +437,7 @@ __global__ __launch_bounds__(W) void k_step_ab_rows(const S* __restrict__ src, S
                 s[i] = Codec<S>::dec(rows[k][row0 + xs]);
                 ++k;
             } else {
-                s[i] = Codec<S>::dec(ld<S, NT>(pop_at<S, O32, true>(src, g.stride, i, nb(d, 0, -L::cy(i), -L::cz(i)))));
+                s[i] = Codec<S>::dec(direct[i]);
             }
         }
     }
@@ -474,15 +481,20 @@ __global__ __launch_bounds__(W) void k_step_aa_odd_rows(S* __restrict__ buf, Geo
     NodeIdx d;
     node_idx(g, x, y, z, d);
     const int row0 = threadIdx.y * blockDim.x;
+    // every load is issued before the barrier (as in k_step_ab_rows)
+    S direct[L::Q];
     {
         int k = 0;
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i)
+        for (int i = 0; i < L::Q; ++i) {
+            const S v = ld<S, NT>(pop_at<S, O32, true>(buf, g.stride, L::opp(i), nb(d, 0, -L::cy(i), -L::cz(i))));
             if (L::cx(i) != 0) {
-                rows[k][row0 + x] =
-                    ld<S, NT>(pop_at<S, O32, true>(buf, g.stride, L::opp(i), nb(d, 0, -L::cy(i), -L::cz(i))));
+                rows[k][row0 + x] = v;
                 ++k;
+            } else {
+                direct[i] = v;
             }
+        }
     }
     __syncthreads();
     R s[L::Q];
@@ -496,8 +508,7 @@ __global__ __launch_bounds__(W) void k_step_aa_odd_rows(S* __restrict__ buf, Geo
                 s[i] = Codec<S>::dec(rows[k][row0 + xs]);
                 ++k;
             } else {
-                s[i] = Codec<S>::dec(
-                    ld<S, NT>(pop_at<S, O32, true>(buf, g.stride, L::opp(i), nb(d, 0, -L::cy(i), -L::cz(i)))));
+                s[i] = Codec<S>::dec(direct[i]);
             }
         }
     }
