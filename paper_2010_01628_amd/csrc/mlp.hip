@@ -37,9 +37,10 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
 {
     // the inference part of the network, once per work-group in LDS: each
     // wavefront reads its MFMA weight operands and bias accumulators from
-    // there instead of from memory (~17 KB per wavefront)
+    // there instead of from memory (~17 KB per wavefront).  Its loads are
+    // issued first, the populations' next, so both are in flight together.
     __shared__ __align__(16) uint32_t net_lds[MLP_INFER_WORDS];
-    load_net(net_lds, net, MLP_INFER_WORDS);
+    const NetCopy netcopy = net_copy_begin(net, MLP_INFER_WORDS);
     const MlpPacked* snet = reinterpret_cast<const MlpPacked*>(net_lds);
     const int xr = blockIdx.x * blockDim.x + threadIdx.x;
     const int yr = blockIdx.y * blockDim.y + threadIdx.y;
@@ -51,6 +52,7 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
     node_idx(g, x, y, z, d);
     float s[19];
     gather<LatD3Q19, S, P, WALLS, NT, O32>(src, g.stride, d, s);
+    net_copy_finish(netcopy, net, MLP_INFER_WORDS, net_lds);
     float Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];

@@ -6,15 +6,18 @@
 // paper's rates.  Inputs: rho - 1, (k4 - rho)/rho, k10..k15/rho and
 // (k16..k18 - rho/9)/rho, each times a fixed inverse scale.
 //
-// One wavefront evaluates the network for its 64 nodes (one per lane) with
-// v_mfma_f32_32x32x8bf16_1k.  MFMA operand layout (lane l, v = 0..3):
+// One wavefront evaluates the network for its 64 nodes (one per lane) on
+// 32 x 32 MFMA products.  Inference (the step kernels, mlp_forward_regs)
+// keeps the activations in registers and uses the 16-deep
+// v_mfma_f32_32x32x16bf16 (its layout is described there); training
+// (mlp_forward_wave) moves them through per-wavefront LDS tiles (rows =
+// nodes, bf16), which its weight-gradient products need, and uses the 8-deep
+// v_mfma_f32_32x32x8bf16_1k, operand layout (lane l, v = 0..3):
 //   A[l % 32][4 (l / 32) + v],  B[4 (l / 32) + v][l % 32],
-//   D: acc[r] = D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-// Inference (the step kernels) keeps the activations in registers
-// (mlp_forward_regs); training (mlp_forward_wave) moves them through
-// per-wavefront LDS tiles (rows = nodes, bf16), which its weight-gradient
-// products need.  Products take BF16 operands and accumulate in FP32; biases
-// and the rates are FP32; ReLU is applied to the bf16 activations.
+//   D: acc[r] = D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
+// (the same D layout for both depths).  Products take BF16 operands and
+// accumulate in FP32; biases and the rates are FP32; ReLU is applied to the
+// bf16 activations.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,7 +35,7 @@ static_assert(MLP_OFF_B3 + MLP_NOUT == MLP_NPARAM, "parameter layout");
 // Packed network as the kernels read it (built by k_mlp_pack from the FP32
 // master parameters).  Matrices are bf16 [row][col], zero padded to 32 x 32
 // (W1 to 32 x 16); the transposed copies serve the backward products.
-struct MlpPacked {
+struct alignas(16) MlpPacked {
     // inference part (what the step kernels read)
     uint16_t w1[32 * 16]; // [out][in]
     uint16_t w2[32 * 32]; // [out][in]
@@ -44,16 +47,51 @@ struct MlpPacked {
     uint16_t w3t[32 * 32]; // [in][out (9 used)]
 };
 constexpr int MLP_INFER_WORDS = (int)(__builtin_offsetof(MlpPacked, w2t) / 4);
+static_assert(MLP_INFER_WORDS % 4 == 0 && sizeof(MlpPacked) % 16 == 0, "16-byte network copies");
 
-// Cooperative copy of the first `words` 32-bit words of the packed network
-// into LDS (all threads of the block).
-__device__ inline void load_net(uint32_t* d, const MlpPacked* __restrict__ src, int words)
+// Cooperative copy of the first `words` 32-bit words (a multiple of four) of
+// the packed network into 16-byte aligned LDS, in two parts so that a kernel
+// can issue its own memory reads in between: net_copy_begin issues each
+// thread's two 16-byte loads, net_copy_finish writes them, copies what is
+// left (work-groups of fewer than words / 8 threads) and waits for the
+// work-group.  All threads of the block take part.  The loads and stores
+// are unconditional, so that the compiler keeps the loads where they are
+// issued: a thread with no chunk of its own copies chunk min(tid, n4 - 1)
+// again (the same value to the same place as the thread that owns it).
+struct NetCopy {
+    uint4 r0, r1;
+    int i0, i1;
+};
+__device__ __attribute__((always_inline)) inline NetCopy net_copy_begin(const MlpPacked* __restrict__ src, int words)
 {
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int nthr = blockDim.x * blockDim.y;
-    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
-    for (int i = tid; i < words; i += nthr) d[i] = s[i];
+    const int n4 = words / 4;
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    NetCopy c;
+    c.i0 = tid < n4 ? tid : n4 - 1;
+    c.i1 = tid + nthr < n4 ? tid + nthr : c.i0;
+    c.r0 = s[c.i0];
+    c.r1 = s[c.i1];
+    return c;
+}
+__device__ __attribute__((always_inline)) inline void net_copy_finish(const NetCopy& c, const MlpPacked* __restrict__ src,
+                                                                      int words, uint32_t* d)
+{
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int nthr = blockDim.x * blockDim.y;
+    const int n4 = words / 4;
+    uint4* d4 = reinterpret_cast<uint4*>(d);
+    d4[c.i0] = c.r0;
+    d4[c.i1] = c.r1;
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    for (int i = tid + 2 * nthr; i < n4; i += nthr) d4[i] = s[i];
     __syncthreads();
+}
+
+__device__ inline void load_net(uint32_t* d, const MlpPacked* __restrict__ src, int words)
+{
+    net_copy_finish(net_copy_begin(src, words), src, words, d);
 }
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
@@ -157,27 +195,31 @@ __device__ inline void mlp_forward_wave(const MlpPacked& W, uint16_t* tx, uint16
 }
 
 // ---------------------------------------------------------------------------
-// Inference with the activations kept in registers.  Each layer is computed
+// Inference with the activations kept in registers, on the 16-deep product
+// v_mfma_f32_32x32x16bf16 (lane l holds eight k of each operand: A[l % 32][k],
+// B[k][l % 32] for the k of slots v = 0..7).  Each layer is computed
 // transposed, Y^T[out][node] = W[out][k] X^T[k][node], as two 32-node column
-// blocks.  With A = W (lane l: W[l % 32][k0 + 4 (l / 32) + v]) and B = X^T
-// (lane l: X^T[k0 + 4 (l / 32) + v][node l % 32]), the accumulator of one
-// layer, acc[r] = Y^T[8 (r / 4) + 4 (l / 32) + r % 4][l % 32], holds in
-// acc[4m .. 4m+3] exactly the B operand of k-step k0 = 8m of the next layer:
-// hidden layers chain without data movement.  Only the input (lane = node,
+// blocks.  The contraction pairs the slots of A and B, so any assignment of
+// k to (half-wave, slot) that both operands share is valid; this one takes
+// what the previous layer's accumulator already holds, acc[r] =
+// Y^T[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]: for k-step m (16 hidden
+// units) slots 0..3 are units 16 m + 4 (l / 32) + 0..3 and slots 4..7 units
+// 16 m + 8 + 4 (l / 32) + 0..3, i.e. acc[8m .. 8m+7].  Hidden layers chain
+// without data movement; the weight operand reads the two matching 8-byte
+// runs of the row.  The input layer takes features 8 (l / 32) + v (one
+// 16-byte run of the zero-padded W1 row).  Only the input (lane = node,
 // features split over the two half-waves) and the output (rates back to the
 // node's lane) cross half-waves, by v_permlane32_swap.
 // ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
 // Round to nearest even, two floats per conversion instruction.
 __device__ inline uint32_t pack2_bf16(float a, float b)
 {
     typedef float f32x2_t __attribute__((ext_vector_type(2)));
     typedef __bf16 b16x2_t __attribute__((ext_vector_type(2)));
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, b16x2_t));
-}
-__device__ inline bf16x4_t pack_bf16(float a, float b, float c, float d)
-{
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    return __builtin_bit_cast(bf16x4_t, (u32x2){pack2_bf16(a, b), pack2_bf16(c, d)});
 }
 
 // swap: a <- [a.lo | b.lo], b <- [a.hi | b.hi] (half-waves of 32 lanes)
@@ -186,20 +228,6 @@ __device__ inline void swap_halves(uint32_t& a, uint32_t& b)
     const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
     a = r[0];
     b = r[1];
-}
-__device__ inline void swap_halves(bf16x4_t& a, bf16x4_t& b)
-{
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    u32x2 ua = __builtin_bit_cast(u32x2, a), ub = __builtin_bit_cast(u32x2, b);
-    uint32_t a0 = ua[0], a1 = ua[1], b0 = ub[0], b1 = ub[1];
-    swap_halves(a0, b0);
-    swap_halves(a1, b1);
-    ua[0] = a0;
-    ua[1] = a1;
-    ub[0] = b0;
-    ub[1] = b1;
-    a = __builtin_bit_cast(bf16x4_t, ua);
-    b = __builtin_bit_cast(bf16x4_t, ub);
 }
 __device__ inline void swap_halves(float& a, float& b)
 {
@@ -238,37 +266,47 @@ __device__ inline uint32_t relu_bf16x2(uint32_t p)
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, (s16x2_t){0, 0}));
 }
 
-// bf16 and ReLU of an accumulator: the next layer's four B operands
-__device__ inline void act_to_operands(const f32x16_t& acc, bf16x4_t op[4])
+// bf16 and ReLU of an accumulator: the next layer's two B operands
+// (k-step m from acc[8m .. 8m+7])
+__device__ inline void act_to_operands(const f32x16_t& acc, bf16x8_t op[2])
 {
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-        op[m] = __builtin_bit_cast(bf16x4_t, (u32x2){relu_bf16x2(pack2_bf16(acc[4 * m], acc[4 * m + 1])),
-                                                    relu_bf16x2(pack2_bf16(acc[4 * m + 2], acc[4 * m + 3]))});
+    for (int m = 0; m < 2; ++m) {
+        u32x4_t w;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = relu_bf16x2(pack2_bf16(acc[8 * m + 2 * q], acc[8 * m + 2 * q + 1]));
+        op[m] = __builtin_bit_cast(bf16x8_t, w);
+    }
+}
+
+// weight operand of a hidden layer's k-step m: row l % 32 of the 32 x 32
+// matrix, units 16 m + 4 (l / 32) + 0..3 and 16 m + 8 + 4 (l / 32) + 0..3
+__device__ inline bf16x8_t w_hidden(const uint16_t* w, int row, int kh, int m)
+{
+    typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+    const u32x2_t a = *reinterpret_cast<const u32x2_t*>(w + row * 32 + 16 * m + kh);
+    const u32x2_t b = *reinterpret_cast<const u32x2_t*>(w + row * 32 + 16 * m + 8 + kh);
+    return __builtin_bit_cast(bf16x8_t, (u32x4_t){a[0], a[1], b[0], b[1]});
 }
 
 // One 32-node column block through the three layers; o[q] = accumulator
 // rows q (q < 5) of the output layer.
-__device__ inline void mlp_block_regs(const MlpPacked& W, const bf16x4_t in[2], float o[5])
+__device__ inline void mlp_block_regs(const MlpPacked& W, const bf16x8_t in, float o[5])
 {
     const int l = lane_id();
     const int row = l & 31, kh = 4 * (l >> 5);
     f32x16_t acc = bias_acc(W.b1);
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w1 + row * 16 + 8 * s + kh), in[s], acc, 0, 0, 0);
-    bf16x4_t h[4];
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+        __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(W.w1 + row * 16 + 2 * kh)), in, acc, 0, 0, 0);
+    bf16x8_t h[2];
     act_to_operands(acc, h);
     acc = bias_acc(W.b2);
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w2 + row * 32 + 8 * m + kh), h[m], acc, 0, 0, 0);
+    for (int m = 0; m < 2; ++m) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w_hidden(W.w2, row, kh, m), h[m], acc, 0, 0, 0);
     act_to_operands(acc, h);
     acc = bias_acc(W.b3);
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds4(W.w3 + row * 32 + 8 * m + kh), h[m], acc, 0, 0, 0);
+    for (int m = 0; m < 2; ++m) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w_hidden(W.w3, row, kh, m), h[m], acc, 0, 0, 0);
 #pragma unroll
     for (int q = 0; q < 5; ++q) o[q] = acc[q];
 }
@@ -278,23 +316,31 @@ __device__ inline void mlp_block_regs(const MlpPacked& W, const bf16x4_t in[2], 
 // Must be called by all 64 lanes.
 __device__ inline void mlp_forward_regs(const MlpPacked& W, const float x[MLP_NIN], float z[MLP_NOUT])
 {
-    // layer-1 B operands: features scaled and rounded; after the swap, in0
-    // feeds block 0 (nodes 0..31) and in1 block 1 (nodes 32..63)
+    // input operands: features scaled and rounded, lo = features 0..7 and
+    // hi = 8..15 of this lane's node; after the swap lo feeds block 0
+    // (nodes 0..31: features 0..7 in lanes < 32, 8..15 in lanes >= 32) and
+    // hi block 1 (nodes 32..63)
     float xs[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) xs[k] = k < MLP_NIN ? x[k] * W.inv_scale[k] : 0.0f;
-    bf16x4_t in0[2], in1[2];
+    u32x4_t lo, hi;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        in0[s] = pack_bf16(xs[8 * s], xs[8 * s + 1], xs[8 * s + 2], xs[8 * s + 3]);
-        in1[s] = pack_bf16(xs[8 * s + 4], xs[8 * s + 5], xs[8 * s + 6], xs[8 * s + 7]);
-        swap_halves(in0[s], in1[s]);
+    for (int q = 0; q < 4; ++q) {
+        lo[q] = pack2_bf16(xs[2 * q], xs[2 * q + 1]);
+        hi[q] = pack2_bf16(xs[8 + 2 * q], xs[8 + 2 * q + 1]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t a = lo[q], b = hi[q];
+        swap_halves(a, b);
+        lo[q] = a;
+        hi[q] = b;
     }
     // o_b[q]: output q (lanes < 32) or 4 + q (lanes >= 32) of node 32 b + l % 32;
     // o_b[4]: output 8 (lanes < 32)
     float o0[5], o1[5];
-    mlp_block_regs(W, in0, o0);
-    mlp_block_regs(W, in1, o1);
+    mlp_block_regs(W, __builtin_bit_cast(bf16x8_t, lo), o0);
+    mlp_block_regs(W, __builtin_bit_cast(bf16x8_t, hi), o1);
 #pragma unroll
     for (int q = 0; q < 5; ++q) swap_halves(o0[q], o1[q]);
 #pragma unroll
@@ -306,19 +352,25 @@ __device__ inline void mlp_forward_regs(const MlpPacked& W, const float x[MLP_NI
 }
 
 // rates 1 + z, or the paper's rates (all 1) when any leaves (0, 2); returns
-// true on fallback.
+// true on fallback.  As unsigned integers the FP32 patterns of (0, 2) are
+// exactly 1 .. 0x3fffffff (+0 is 0, negative values and NaNs have the sign
+// bit or lie above 2.0 = 0x40000000), so one unsigned maximum of pattern - 1
+// tests all nine rates, NaN included.  The rates are reset only in
+// wavefronts that hold a fallen-back node.
 __device__ inline bool mlp_rates(const float z[MLP_NOUT], float rates[MLP_NOUT])
 {
-    bool bad = false;
+    uint32_t worst = 0;
 #pragma unroll
     for (int j = 0; j < MLP_NOUT; ++j) {
         const float w = 1.0f + z[j];
-        bad = bad || !(w > 0.0f && w < 2.0f);
         rates[j] = w;
+        const uint32_t k = __builtin_bit_cast(uint32_t, w) - 1u;
+        worst = k > worst ? k : worst;
     }
-    if (bad)
+    const bool bad = worst >= 0x3fffffffu;
+    if (__builtin_amdgcn_ballot_w64(bad) != 0)
 #pragma unroll
-        for (int j = 0; j < MLP_NOUT; ++j) rates[j] = 1.0f;
+        for (int j = 0; j < MLP_NOUT; ++j) rates[j] = bad ? 1.0f : rates[j];
     return bad;
 }
 
