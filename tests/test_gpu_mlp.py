@@ -173,6 +173,29 @@ def test_mlp_64bit_addressing_is_bitwise_identical(orc, monkeypatch):
     assert np.array_equal(out[0], out[1])
 
 
+def test_mlp_row_staging_is_bitwise_identical(orc, monkeypatch):
+    """The learned A-B step with the x-moving populations staged through
+    LDS (work-groups of whole rows, the default where possible) and with
+    direct reads gives the same populations, bit for bit."""
+    nx, ny, nz = 64, 10, 6
+    rng = np.random.default_rng(3)
+    P = 0.08 * rng.normal(size=L.MLP_NPARAM)
+    f0 = noneq_state(orc, nx, ny, nz, 11)
+    mlp = L.Mlp(P, SCALES)
+    out = []
+    for staging in ("1", "0"):
+        monkeypatch.setenv("LBM_ROW_STAGING", staging)
+        lat = make_lattice(nx, ny, nz, f0, 1.8)
+        assert lat.step_variant == (1 if staging == "1" else 0)
+        lat.attach_mlp(mlp)
+        lat.step(4)
+        out.append(lat.get_populations().cpu().numpy())
+        assert lat.fallback_count() == 0
+        lat.close()
+    mlp.close()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_fallback_is_plain_scheme_bitwise(orc):
     nx, ny, nz = 20, 9, 7
     f0 = noneq_state(orc, nx, ny, nz, 5)
