@@ -661,7 +661,7 @@ static void step_mlp_s(int pattern, bool walls, bool nt, const void* src, void* 
     const bool rows = sizeof(S) >= 4 && g.row_stage && (int)block.x == g.nx && grid.x == 1 && block.x * block.y <= 256;
 #define LBM_MLP_STEP(P, W, NT_)                                                                       \
     do {                                                                                              \
-        if constexpr (P == AB && !W) {                                                                \
+        if constexpr (P == AB && !W && sizeof(S) >= 4) {                                              \
             if (rows && g.off32) hipLaunchKernelGGL((k_step_mlp_ab<S, W, NT_, true, true>), grid, block, 0, st, a, b, g, ph, w, fb); \
             else if (rows) hipLaunchKernelGGL((k_step_mlp_ab<S, W, NT_, false, true>), grid, block, 0, st, a, b, g, ph, w, fb); \
             else if (g.off32) hipLaunchKernelGGL((k_step_mlp_ab<S, W, NT_, true>), grid, block, 0, st, a, b, g, ph, w, fb); \
