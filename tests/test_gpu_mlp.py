@@ -109,6 +109,49 @@ def test_mlp_step_matches_oracle(orc, streaming, walls):
     mlp.close()
 
 
+@pytest.mark.parametrize("precision,unit_roundoff", [("fp16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_mlp_step_16bit_storage_matches_oracle(orc, precision, unit_roundoff):
+    """One learned A-B step with FP16- or BF16-shifted storage (the deviation
+    s = f - w rho0 stored, rounded to nearest even; the collision in FP32) from
+    the decoded start state both sides share: each population agrees with
+    the oracle to the FP32 test's bound, plus the stored deviation's
+    rounding, at most the unit roundoff u times |s| (plus half the smallest
+    FP16 subnormal spacing, 2^-25, for deviations below FP16's normal
+    range).  A value within the FP32 bound of a rounding tie may round
+    either way; the bound covers that: |fl(x') - x| <= u |x'| + |x' - x|."""
+    nx, ny, nz = 16, 12, 8
+    say(f"mlp step parity {precision} storage")
+    rng = np.random.default_rng(1)
+    P = 0.08 * rng.normal(size=L.MLP_NPARAM)
+    f0 = noneq_state(orc, nx, ny, nz, 3)
+    om = 1.85
+    mlp = L.Mlp(P, SCALES)
+    lat = L.Lattice(L.make_params(nx, ny, nz, precision=precision, omega=om))
+    lat.init(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    lat.set_populations(f0)
+    f0r = lat.get_populations().cpu().numpy()  # the stored start, decoded
+    assert np.abs(f0r - f0).max() > 0  # the start was rounded to the storage type
+    lat.attach_mlp(mlp)
+    Pg = gpu_weights(orc, P)
+    lat.step(1)
+    g = lat.get_populations().cpu().numpy()
+    o, fb, flip, margin = orc.mlp.step_info(f0r, om, Pg, SCALES, tie_ulps=TIE_ULPS)
+    _, w, _ = orc.tables()
+    dev = np.abs(o - w[:, None, None, None])  # rho0 = 1
+    fp32_part = STRICT + from_source(orc, flip, False)
+    bound = fp32_part * (1 + unit_roundoff) + unit_roundoff * (dev + fp32_part) + 2.0 ** -25
+    d = np.abs(g - o)
+    say(f"  max |f_gpu - f_oracle| {d.max():.3e}; max over bound {(d / bound).max():.3f}; "
+        f"largest stored deviation {dev.max():.2e}; oracle fallbacks {fb}")
+    assert fb == 0 and margin.min() > 1e-2
+    assert np.all(d <= bound)
+    # the rounding is really there: the error is of the storage's size, not FP32's
+    assert d.max() > 10 * STRICT
+    assert lat.fallback_count() == 0
+    lat.close()
+    mlp.close()
+
+
 @pytest.mark.parametrize("bound", ["upper", "lower"])
 def test_fallback_decision_near_the_rate_bounds(orc, bound):
     """Output 0 is driven to a rate just inside or just outside 2 (or 0) at
