@@ -228,7 +228,10 @@ typedef struct lbm_handle lbm_handle;
  *                       consecutive rows;
  *   LBM_COUPLED_FLAT=0  the 3-D grid of row work-groups instead of the flat
  *                       1-D grid for the two-phase, Shan-Chen and
- *                       colour-gradient step kernels.
+ *                       colour-gradient step kernels;
+ *   LBM_AA_EVEN_CACHED=0/1  with 16-bit storage, the AA even step's loads
+ *                       with / without the streaming hint (default: without
+ *                       up to 2^25 nodes).
  * None of them changes results: every path is tested bit for bit against the
  * default one. */
 

@@ -155,6 +155,12 @@ template <bool WALLS> __device__ inline bool beyond(const NodeIdx& d, int dy)
 // Population loads and stores, with or without the non-temporal (streaming)
 // hint.  Each population value is touched once per step, so the hint keeps it
 // from displacing reusable lines.
+//
+// The AA even step with 16-bit storage may read without the hint while its
+// stores keep it (Geom::even_cached, set by the host for lattices of up to
+// 2^25 nodes).  Measured, FP16 / BF16 AA against the hint on both: +4-7 % at
+// 128^3, 256^3 and 512x256x128 (0.72 -> 0.75-0.76 of 8 TB/s), within 1 % at
+// 192^3, 256x256x512 and 512x512x128, -3 to -4 % at 256x256x1024 and 512^3.
 template <class S, bool NT> __device__ inline S ld(const S* p)
 {
     if constexpr (!NT) {
@@ -351,7 +357,8 @@ __device__ inline void block_coords(const Geom& g, int chunk, int& bxi, int& byi
     }
 }
 
-template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT, bool O32>
+// NTL: the streaming hint on the loads (NT: on the stores)
+template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT, bool O32, bool NTL = NT>
 __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys& ph)
 {
     using R = typename Codec<S>::R;
@@ -363,7 +370,7 @@ __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys
     NodeIdx d;
     node_idx(g, x, y, z, d);
     R s[L::Q];
-    gather<L, S, P, WALLS, NT, O32>(src, g.stride, d, s);
+    gather<L, S, P, WALLS, NTL, O32>(src, g.stride, d, s);
     R Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
@@ -450,10 +457,10 @@ __global__ __launch_bounds__(W) void k_step_ab_rows(const S* __restrict__ src, S
 }
 
 // AA: one buffer, each node rewrites exactly the locations it read.
-template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT, bool O32>
+template <class L, class S, Pattern P, bool WALLS, bool GENERAL, bool NT, bool O32, bool NTL = NT>
 __global__ __launch_bounds__(256) void k_step_aa(S* buf, Geom g, Phys ph)
 {
-    step_node<L, S, P, WALLS, GENERAL, NT, O32>(buf, buf, g, ph);
+    step_node<L, S, P, WALLS, GENERAL, NT, O32, NTL>(buf, buf, g, ph);
 }
 
 // AA odd step, periodic, with work-groups of whole x rows (blockDim.x == nx).
@@ -757,6 +764,10 @@ template <class L, class S> struct Launch {
                 else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph);     \
             } else if (g.row_stage) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O>), grid, block, 0, st, b, g, ph); \
             else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);               \
+        } else if constexpr (P == AA_EVEN && sizeof(S) == 2 && NT) {                                       \
+            const dim3 gr = wide ? grid256 : grid, bl = wide ? block256 : block;                            \
+            if (g.even_cached) hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O, false>), gr, bl, 0, st, b, g, ph); \
+            else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), gr, bl, 0, st, b, g, ph);              \
         } else if (wide) hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph); \
         else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);                   \
     } while (0)

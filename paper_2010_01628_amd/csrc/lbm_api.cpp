@@ -251,6 +251,14 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
         const char* env = std::getenv("LBM_OFF32");
         h->g.off32 = h->g.stride * eb < ((int64_t)1 << 32) && !(env && env[0] == '0');
     }
+    // AA even step with 16-bit storage: loads without the streaming hint up
+    // to 2^25 nodes (measured faster there, slower beyond); LBM_AA_EVEN_CACHED
+    // =0/1 forces either
+    {
+        const char* env = std::getenv("LBM_AA_EVEN_CACHED");
+        const bool want = env ? env[0] == '1' : h->g.N <= (1 << 25);
+        h->g.even_cached = eb == 2 && want;
+    }
     h->walls = p->walls_y != 0;
     // default: streaming hints for A-B with 4- and 8-byte storage and for
     // every staged step (set below), ordinary accesses otherwise -- the

@@ -19,6 +19,7 @@ struct Geom {
     int row_stage = 0; // periodic A-B / AA odd step with whole-row work-groups: x-moving populations via LDS
     int flat = 0;      // kernels that use thread_node(): 1-D grid over all nodes in index order
     int off32 = 0;     // every population array is below 4 GiB (32-bit element byte offsets)
+    int even_cached = 0; // AA even step with 16-bit storage: population loads without the streaming hint
 };
 
 struct Phys {

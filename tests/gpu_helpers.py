@@ -27,7 +27,8 @@ def rel_l2_fluct(rho_a, rho_b):
 
 def gpu_run(nx, ny, nz, rho, u, steps, precision="fp64", streaming="ab", omega=1.0, omega_bulk=1.0,
             omega_hi=None, force=None, force_mode=L.LBM_FORCE_NONE, kolmogorov_amp=0.0, walls=False,
-            uniform=(0.0, 0.0, 0.0), block=(0, 0), want_pops=True, q=19, moments="central", rounding="nearest"):
+            uniform=(0.0, 0.0, 0.0), block=(0, 0), want_pops=True, q=19, moments="central", rounding="nearest",
+            cache_policy=0):
     """Run the GPU library; returns dict(rho, u, f, diag) as numpy float64."""
     import torch
 
@@ -38,7 +39,7 @@ def gpu_run(nx, ny, nz, rho, u, steps, precision="fp64", streaming="ab", omega=1
     p = L.make_params(nx, ny, nz, precision=precision, streaming=streaming, omega=omega, omega_bulk=omega_bulk,
                       omega_hi=omega_hi, force_mode=force_mode, force=uniform, kolmogorov_amp=kolmogorov_amp,
                       force_field_ptr=None if ff is None else ff.data_ptr(), walls_y=walls, block=block,
-                      moments=moments, rounding=rounding, seed=20101628)
+                      moments=moments, rounding=rounding, seed=20101628, cache_policy=cache_policy)
     p.q = q
     lat = L.Lattice(p, force_field=ff)
     try:

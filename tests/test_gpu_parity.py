@@ -339,6 +339,24 @@ def test_wide_row_staged_step_is_bitwise_identical(nx, precision, streaming, q, 
     assert np.array_equal(staged["f"], direct["f"])
 
 
+@pytest.mark.parametrize("precision,walls,moments", [("fp16", False, "central"), ("bf16", False, "central"),
+                                                     ("fp16", True, "central"), ("bf16", True, "central"),
+                                                     ("fp16", False, "raw")])
+def test_aa_even_load_hint_is_bitwise_identical(precision, walls, moments, monkeypatch):
+    """With 16-bit storage the AA even step's loads go with or without the
+    streaming hint (chosen by lattice size; LBM_AA_EVEN_CACHED forces either);
+    the values are the same, bit for bit.  Streaming hints on (cache policy
+    1); an odd step count ends on an odd AA step."""
+    nx, ny, nz = 64, 20, 9
+    rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=45, umax=0.05, fmax=1e-3)
+    kw = dict(omega=1.8, omega_hi=[1.4] * 9, force=F, walls=walls, moments=moments, cache_policy=1)
+    monkeypatch.setenv("LBM_AA_EVEN_CACHED", "1")
+    a = gpu_run(nx, ny, nz, rho, u, 7, precision, "aa", **kw)
+    monkeypatch.setenv("LBM_AA_EVEN_CACHED", "0")
+    b = gpu_run(nx, ny, nz, rho, u, 7, precision, "aa", **kw)
+    assert np.array_equal(a["f"], b["f"])
+
+
 @pytest.mark.parametrize("precision,streaming,walls,q", [
     ("fp32", "ab", False, 19), ("fp16", "aa", True, 19), ("fp64", "ab", True, 19), ("bf16", "ab", True, 19),
     ("fp32", "aa", False, 19), ("fp32", "ab", True, 27), ("fp64", "aa", True, 27)])
