@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         node_idx(g, x, y, z, d);
         float s[19];
         gather<LatD3Q19, S, AB, false, true, O32>(src_all + bd.off, g.stride, d, s);
-        float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];
+        float xin[MLP_NIN], zout[MLP_NOUT];
         {
             CMState<float> st0;
             pre_collide<float, true>(s, rho0, 0.0f, 0.0f, 0.0f, st0);
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         int zoff = 0;
         asm volatile("" : "+s"(zoff));
         mlp_forward_regs(*reinterpret_cast<const MlpPacked*>(reinterpret_cast<const char*>(net_lds) + zoff), xin, zout);
-        const bool fb = mlp_rates(zout, rates);
+        const bool fb = mlp_fallback(zout);
         // recomputed rather than kept live across the network: with the tile
         // loop's own state, keeping it would spill at four waves per SIMD;
         // kept at three waves per SIMD (15 % fewer VALU instructions) the
@@ -130,13 +130,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         Rates<float> rt;
         rt.omega = (float)bd.omega;
         rt.omega_bulk = 1.0f;
-#pragma unroll
-        for (int j = 0; j < MLP_NOUT; ++j) rt.omega_hi[j] = rates[j];
         RawMoments<float> p;
         if (fb)
             relax<float, false>(st, rt, p);
         else
-            relax<float, true>(st, rt, p);
+            relax_learned(st, rt, zout, p);
         if constexpr (Codec<S>::increment)
             post_collide_increment(st, p, s);
         else

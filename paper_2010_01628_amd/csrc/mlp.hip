@@ -93,21 +93,19 @@ __device__ inline void step_mlp_body(const S* src, S* dst, const Geom& g, const 
     }
     float Fx, Fy, Fz;
     node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
-    float xin[MLP_NIN], zout[MLP_NOUT], rates[MLP_NOUT];
+    float xin[MLP_NIN], zout[MLP_NOUT];
     CMState<float> st;
     pre_collide<float, true>(s, (float)ph.rho0, Fx, Fy, Fz, st);
     mlp_features(st, xin);
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     mlp_forward_regs(*snet, xin, zout);
-    const bool fb = mlp_rates(zout, rates);
-    Rates<float> rt = rates_of<float>(ph);
-#pragma unroll
-    for (int j = 0; j < MLP_NOUT; ++j) rt.omega_hi[j] = rates[j];
+    const bool fb = mlp_fallback(zout);
+    const Rates<float> rt = rates_of<float>(ph);
     RawMoments<float> p;
     if (fb && ph.omega_bulk == 1.0)
         relax<float, false>(st, rt, p); // the paper's rates: the plain step's arithmetic, bit for bit
     else
-        relax<float, true>(st, rt, p);
+        relax_learned(st, rt, zout, p);
     if constexpr (Codec<S>::increment)
         post_collide_increment(st, p, s);
     else

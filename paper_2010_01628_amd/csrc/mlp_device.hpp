@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "d3q19_cm.hpp"
+
 namespace lbm {
 
 constexpr int MLP_NIN = 11, MLP_NH = 32, MLP_NOUT = 9;
@@ -372,6 +374,62 @@ __device__ inline bool mlp_rates(const float z[MLP_NOUT], float rates[MLP_NOUT])
 #pragma unroll
         for (int j = 0; j < MLP_NOUT; ++j) rates[j] = bad ? 1.0f : rates[j];
     return bad;
+}
+
+// The step kernels' form of the same test and of the relaxation, on the
+// outputs z = omega_hi - 1 themselves: omega = 1 + z lies in (0, 2) exactly
+// when |z| < 1, and as unsigned integers the FP32 patterns with the sign bit
+// cleared are below 0x3f800000 (1.0) exactly for |z| < 1 (NaNs lie above),
+// so one unsigned maximum tests the nine.  A fallen-back node's z are set to
+// 0 (rates 1), in wavefronts that hold one.  Returns true on fallback.
+__device__ inline bool mlp_fallback(float z[MLP_NOUT])
+{
+    uint32_t worst = 0;
+#pragma unroll
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        const uint32_t k = __builtin_bit_cast(uint32_t, z[j]) & 0x7fffffffu;
+        worst = k > worst ? k : worst;
+    }
+    const bool bad = worst >= 0x3f800000u;
+    if (__builtin_amdgcn_ballot_w64(bad) != 0)
+#pragma unroll
+        for (int j = 0; j < MLP_NOUT; ++j) z[j] = bad ? 0.0f : z[j];
+    return bad;
+}
+
+// Post-collision non-equilibrium CMs with the learned higher-order rates
+// omega_hi = 1 + z (eq. posColl0, as relax<R, true>): 1 - omega = -z and
+// 1 - omega / 2 = (1 - z) / 2 are formed from z directly, without rounding
+// 1 + z first.
+__device__ inline void relax_learned(const CMState<float>& st, const Rates<float>& rt, const float z[MLP_NOUT],
+                                     RawMoments<float>& p)
+{
+    const float third = 1.0f / 3.0f, cs2 = third;
+    const RawMoments<float>& n = st.n;
+    const float Fx = st.Fx, Fy = st.Fy, Fz = st.Fz;
+    const float w1 = 1.0f - rt.omega;
+    const float s5 = w1 * st.k5, s6 = w1 * st.k6;
+    const float s4 = (1.0f - rt.omega_bulk) * st.k4;
+    const float hx = 0.5f * cs2 * Fx, hy = 0.5f * cs2 * Fy, hz = 0.5f * cs2 * Fz;
+    p.m000 = 0.0f;
+    p.m100 = 0.5f * Fx;
+    p.m010 = 0.5f * Fy;
+    p.m001 = 0.5f * Fz;
+    p.m110 = w1 * n.m110;
+    p.m101 = w1 * n.m101;
+    p.m011 = w1 * n.m011;
+    p.m210 = (1.0f - z[0]) * hy - z[0] * n.m210;
+    p.m120 = (1.0f - z[1]) * hx - z[1] * n.m120;
+    p.m201 = (1.0f - z[2]) * hz - z[2] * n.m201;
+    p.m102 = (1.0f - z[3]) * hx - z[3] * n.m102;
+    p.m021 = (1.0f - z[4]) * hz - z[4] * n.m021;
+    p.m012 = (1.0f - z[5]) * hy - z[5] * n.m012;
+    p.m220 = -z[6] * n.m220;
+    p.m202 = -z[7] * n.m202;
+    p.m022 = -z[8] * n.m022;
+    p.m200 = third * (s4 + 2.0f * s5 + s6);
+    p.m020 = third * (s4 - s5 + s6);
+    p.m002 = third * (s4 - s5 - 2.0f * s6);
 }
 
 // Weight-gradient product over the 64 nodes of the wavefront:
