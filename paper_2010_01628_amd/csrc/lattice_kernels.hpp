@@ -736,13 +736,18 @@ template <class L, class S> struct Launch {
         // wide work-groups (one per row of 257..1024 nodes; kernels for rows
         // up to 512 or up to 1024) exist only for the staged kernels; every
         // other step kernel of such a launch (the AA even step, and any kernel
-        // whose staging rows would not fit in 64 KB of LDS) runs on 256-wide
+        // whose staging rows would not fit in 64 KB of LDS) runs on 256-thread
         // work-groups over the same rows
         const bool wide = block.x > 256;
         constexpr bool wide_fits = moving_x_count<L>() * 512 * sizeof(S) <= 65536;
         constexpr bool fits1024 = moving_x_count<L>() * 1024 * sizeof(S) <= 65536;
-        const dim3 block256(wide ? 256 : block.x, wide ? 1 : block.y, 1);
-        const dim3 grid256(wide ? (g.nx + 255) / 256 : grid.x, wide ? g.ny : grid.y, grid.z);
+        // those 256-thread work-groups take an x width that divides the row
+        // where one does (256, 128, 64 or 32 x-values by 1, 2, 4 or 8 rows),
+        // so that no lane idles at the row's end
+        const int wx = g.nx % 256 == 0 ? 256 : g.nx % 128 == 0 ? 128 : g.nx % 64 == 0 ? 64 : g.nx % 32 == 0 ? 32 : 256;
+        const dim3 block256(wide ? wx : block.x, wide ? 256 / wx : block.y, 1);
+        const dim3 grid256(wide ? (g.nx + wx - 1) / wx : grid.x, wide ? (g.ny + 256 / wx - 1) / (256 / wx) : grid.y,
+                           grid.z);
 #define LBM_STEP_O(P, W, G, O)                                                                                      \
     do {                                                                                                            \
         if constexpr (P == AB && !W) {                                                                              \

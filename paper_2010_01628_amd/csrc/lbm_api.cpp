@@ -134,8 +134,12 @@ void default_block(const lbm_params* p, int& bx, int& by)
         by = p->block_y;
         return;
     }
-    // one block per x-row (up to 256 nodes): measured fastest at 256^3
-    bx = p->nx >= 256 ? 256 : next_pow2(p->nx);
+    // one block per x-row (up to 256 nodes): measured fastest at 256^3; rows
+    // longer than 256 nodes take an x width that divides them where one does
+    // (256, 128, 64 or 32), so that no lane idles at the row's end
+    const int nx = p->nx;
+    bx = nx <= 256 ? next_pow2(nx)
+                   : (nx % 256 == 0 ? 256 : nx % 128 == 0 ? 128 : nx % 64 == 0 ? 64 : nx % 32 == 0 ? 32 : 256);
     if (bx < 8) bx = 8;
     by = 256 / bx;
     const int ny2 = next_pow2(p->ny);
@@ -158,10 +162,13 @@ void set_row_stage(lbm_handle* h)
     const bool want = (env && env[0] == '1') || h->row_stage_pref < 0 || h->row_stage_pref == 1;
     h->g.row_stage = allowed && want;
     // a 512-wide step work-group exists only for the staged kernels: without
-    // staging the step falls back to 256-wide work-groups over the rows
+    // staging the step falls back to 256-thread work-groups over the rows,
+    // with an x width that divides the row where one does (no idle lanes)
     if (h->step_block.x > 256 && !h->g.row_stage) {
-        h->step_block = dim3(256, 1, 1);
-        h->step_grid = dim3((h->g.nx + 255) / 256, h->g.ny, h->g.nz);
+        const int nx = h->g.nx;
+        const int wx = nx % 256 == 0 ? 256 : nx % 128 == 0 ? 128 : nx % 64 == 0 ? 64 : nx % 32 == 0 ? 32 : 256;
+        h->step_block = dim3(wx, 256 / wx, 1);
+        h->step_grid = dim3((nx + wx - 1) / wx, (h->g.ny + 256 / wx - 1) / (256 / wx), h->g.nz);
     }
 }
 
@@ -298,14 +305,12 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
         h->step_block = h->block;
         set_row_stage(h);
         // rows of 257..1024 nodes: one work-group of nx threads per row,
-        // staged (unless LBM_ROW_STAGING=0), except A-B with 16-bit storage,
-        // where 256-wide work-groups with direct cached accesses measured
-        // faster (512 and 1024 wide rows: FP16 65.4 / 67.2 GLUPS against
-        // 57.4 / 60.2 staged); AA stages at every width
+        // staged (unless LBM_ROW_STAGING=0).  FP16 A-B against direct reads
+        // on 256-thread work-groups: 0.685 / 0.49 of 8 TB/s at 320^3, 0.68 /
+        // 0.51 at 384^3, 0.70 / 0.62 at 512^3, 0.66 / 0.65 at 1024 x 128^2
         if (!remap && wide_rows_possible(h)) {
             const char* rs = std::getenv("LBM_ROW_STAGING");
-            const bool want = (rs && rs[0] == '1') ||
-                              (!(rs && rs[0] == '0') && (eb >= 4 || p->streaming == LBM_AA));
+            const bool want = !(rs && rs[0] == '0');
             if (want) {
                 h->step_block = dim3(h->g.nx, 1, 1);
                 h->step_grid = dim3(1, h->g.ny, h->g.nz);
