@@ -138,6 +138,16 @@ void default_block(const lbm_params* p, int& bx, int& by)
     // longer than 256 nodes take an x width that divides them where one does
     // (256, 128, 64 or 32), so that no lane idles at the row's end
     const int nx = p->nx;
+    // a row shorter than 256 nodes whose length is not a power of two: whole
+    // rows per work-group when some number of them fills whole wavefronts
+    // (48 x 4, 96 x 2, 192 x 1: no idle lane, and the rows can be staged)
+    if (nx < 256 && (nx & (nx - 1)) != 0)
+        for (int k = 256 / nx; k >= 1; --k)
+            if (nx * k % 64 == 0) {
+                bx = nx;
+                by = k;
+                return;
+            }
     bx = nx <= 256 ? next_pow2(nx)
                    : (nx % 256 == 0 ? 256 : nx % 128 == 0 ? 128 : nx % 64 == 0 ? 64 : nx % 32 == 0 ? 32 : 256);
     if (bx < 8) bx = 8;

@@ -73,9 +73,12 @@ def from_source(orc, v, walls):
     return out
 
 
-@pytest.mark.parametrize("streaming,walls", [("ab", False), ("aa", True)])
-def test_mlp_step_matches_oracle(orc, streaming, walls):
-    nx, ny, nz = 16, 12, 8
+@pytest.mark.parametrize("streaming,walls,dims", [("ab", False, (16, 12, 8)), ("aa", True, (16, 12, 8)),
+                                                  ("ab", False, (96, 5, 3))])
+def test_mlp_step_matches_oracle(orc, streaming, walls, dims):
+    """(96, 5, 3): two 96-node rows per 192-thread work-group, the x-moving
+    populations staged through LDS."""
+    nx, ny, nz = dims
     say(f"mlp step parity {streaming} walls={walls}")
     rng = np.random.default_rng(1)
     P = 0.08 * rng.normal(size=L.MLP_NPARAM)

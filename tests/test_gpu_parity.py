@@ -55,6 +55,10 @@ CASES = [
     (70, 3, 2, False, "aa", 6),   # x spans two wavefronts plus a tail
     (1, 1, 8, False, "ab", 5),    # degenerate x, y (every x/y link wraps to itself)
     (2, 9, 1, True, "aa", 7),
+    (96, 5, 3, False, "ab", 7),   # rows of 96: two rows per 192-thread work-group, staged
+    (48, 6, 4, False, "aa", 7),   # four rows of 48 per work-group, the odd step staged
+    (192, 3, 2, False, "ab", 5),  # one 192-node row per work-group
+    (320, 2, 2, False, "aa", 5),  # a 320-node row: staged odd step, even step on 64 x 4 work-groups
 ]
 
 
