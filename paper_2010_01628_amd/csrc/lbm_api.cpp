@@ -199,8 +199,12 @@ int64_t pad_stride(int64_t N, int eb)
 {
     // Separate the starts of consecutive population arrays by a non-power-of-two
     // number of 256-byte blocks so the streams of one step spread over channels.
+    // 68 x 256 B for 4- and 8-byte elements, 102 x 256 B for 2-byte ones
+    // (256^3, alternating runs on one machine: FP16 A-B 0.724 -> 0.737 of
+    // 8 TB/s, BF16 A-B 0.725 -> 0.731, AA within noise; FP32 A-B with
+    // 102 x 256 B: 0.732 against 0.740)
     const char* env = std::getenv("LBM_PAD_BYTES");
-    int64_t pad_bytes = env ? std::atoll(env) : 17408;  // 68 * 256 B
+    int64_t pad_bytes = env ? std::atoll(env) : (eb == 2 ? 26112 : 17408);
     int64_t base = round_up(N * eb, 4096);
     return (base + pad_bytes) / eb;
 }
