@@ -232,6 +232,9 @@ typedef struct lbm_handle lbm_handle;
  *   LBM_AA_EVEN_CACHED=0/1  with 16-bit storage, the AA even step's loads
  *                       with / without the streaming hint (default: without
  *                       up to 2^25 nodes).
+ *   LBM_WAVES_PER_SIMD=n cap on the step kernels' resident wavefronts per
+ *                       SIMD, set through their LDS allocation (default: 5
+ *                       for 4- and 8-byte storage, none for 2-byte; 0: none).
  * None of them changes results: every path is tested bit for bit against the
  * default one. */
 

@@ -392,6 +392,22 @@ __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* _
 // once, into LDS, and node x takes element x - c_x (wrapped) from there;
 // reading it straight from memory would start each wavefront's load four
 // bytes off a line boundary.  Same values as k_step_ab, bit for bit.
+// Dynamic LDS for a step launch that caps the resident wavefronts per SIMD at
+// g.occ_waves (0: no cap): a work-group of T threads places ceil(T / 64)
+// wavefronts spread over the compute unit's four SIMDs, so at most
+// 4 occ_waves / ceil(T / 64) work-groups may share the unit's LDS; each one
+// is given that share (at most 64 KB) less the static LDS it already uses.
+inline unsigned occ_pad(const Geom& g, unsigned static_lds, dim3 b)
+{
+    if (g.occ_waves <= 0) return 0;
+    const unsigned waves = (b.x * b.y * b.z + 63) / 64;
+    unsigned wgs = 4u * (unsigned)g.occ_waves / waves;
+    if (wgs < 1) wgs = 1;
+    unsigned total = (unsigned)g.lds_per_cu / wgs;
+    if (total > 65536u) total = 65536u;
+    return total > static_lds ? total - static_lds : 0;
+}
+
 template <class L> __host__ __device__ constexpr int moving_x_count()
 {
     int k = 0;
@@ -748,33 +764,40 @@ template <class L, class S> struct Launch {
         const dim3 block256(wide ? wx : block.x, wide ? 256 / wx : block.y, 1);
         const dim3 grid256(wide ? (g.nx + wx - 1) / wx : grid.x, wide ? (g.ny + 256 / wx - 1) / (256 / wx) : grid.y,
                            grid.z);
+        // dynamic LDS that caps the resident wavefronts per SIMD (g.occ_waves)
+        constexpr unsigned rows256 = moving_x_count<L>() * 256 * sizeof(S);
+        constexpr unsigned rows512 = moving_x_count<L>() * 512 * sizeof(S);
+        constexpr unsigned rows1024 = moving_x_count<L>() * 1024 * sizeof(S);
+        const unsigned pad_r = occ_pad(g, rows256, block), pad_0 = occ_pad(g, 0, block);
+        const unsigned pad_w512 = occ_pad(g, rows512, block), pad_w1024 = occ_pad(g, rows1024, block);
+        const unsigned pad_256 = occ_pad(g, 0, block256);
 #define LBM_STEP_O(P, W, G, O)                                                                                      \
     do {                                                                                                            \
         if constexpr (P == AB && !W) {                                                                              \
             if (g.row_stage && wide) {                                                                              \
                 if (block.x > 512) {                                                                                \
-                    if constexpr (fits1024) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O, 1024>), grid, block, 0, st, a, b, g, ph); \
-                    else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid256, block256, 0, st, a, b, g, ph); \
-                } else if constexpr (wide_fits) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O, 512>), grid, block, 0, st, a, b, g, ph); \
-                else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid256, block256, 0, st, a, b, g, ph);     \
-            } else if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
-            else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph);              \
-        } else if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, 0, st, a, b, g, ph); \
+                    if constexpr (fits1024) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O, 1024>), grid, block, pad_w1024, st, a, b, g, ph); \
+                    else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid256, block256, pad_256, st, a, b, g, ph); \
+                } else if constexpr (wide_fits) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O, 512>), grid, block, pad_w512, st, a, b, g, ph); \
+                else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid256, block256, pad_256, st, a, b, g, ph);     \
+            } else if (g.row_stage) hipLaunchKernelGGL((k_step_ab_rows<L, S, G, NT, O>), grid, block, pad_r, st, a, b, g, ph); \
+            else hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, pad_0, st, a, b, g, ph);              \
+        } else if constexpr (P == AB) hipLaunchKernelGGL((k_step_ab<L, S, W, G, NT, O>), grid, block, pad_0, st, a, b, g, ph); \
         else if constexpr (P == AA_ODD && !W) {                                                                     \
             if (g.row_stage && wide) {                                                                              \
                 if (block.x > 512) {                                                                                \
-                    if constexpr (fits1024) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O, 1024>), grid, block, 0, st, b, g, ph); \
-                    else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph); \
-                } else if constexpr (wide_fits) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O, 512>), grid, block, 0, st, b, g, ph); \
-                else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph);     \
-            } else if (g.row_stage) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O>), grid, block, 0, st, b, g, ph); \
-            else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);               \
+                    if constexpr (fits1024) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O, 1024>), grid, block, pad_w1024, st, b, g, ph); \
+                    else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, pad_256, st, b, g, ph); \
+                } else if constexpr (wide_fits) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O, 512>), grid, block, pad_w512, st, b, g, ph); \
+                else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, pad_256, st, b, g, ph);     \
+            } else if (g.row_stage) hipLaunchKernelGGL((k_step_aa_odd_rows<L, S, G, NT, O>), grid, block, pad_r, st, b, g, ph); \
+            else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, pad_0, st, b, g, ph);               \
         } else if constexpr (P == AA_EVEN && sizeof(S) == 2 && NT) {                                       \
             const dim3 gr = wide ? grid256 : grid, bl = wide ? block256 : block;                            \
-            if (g.even_cached) hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O, false>), gr, bl, 0, st, b, g, ph); \
-            else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), gr, bl, 0, st, b, g, ph);              \
-        } else if (wide) hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, 0, st, b, g, ph); \
-        else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, 0, st, b, g, ph);                   \
+            if (g.even_cached) hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O, false>), gr, bl, wide ? pad_256 : pad_0, st, b, g, ph); \
+            else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), gr, bl, wide ? pad_256 : pad_0, st, b, g, ph);              \
+        } else if (wide) hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid256, block256, pad_256, st, b, g, ph); \
+        else hipLaunchKernelGGL((k_step_aa<L, S, P, W, G, NT, O>), grid, block, pad_0, st, b, g, ph);                   \
     } while (0)
 #define LBM_STEP(P, W, G)                        \
     do {                                         \

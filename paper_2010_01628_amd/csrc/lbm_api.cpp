@@ -280,6 +280,21 @@ int lbm_create(const lbm_params* p, void* stream, lbm_handle** out)
         const bool want = env ? env[0] == '1' : h->g.N <= (1 << 25);
         h->g.even_cached = eb == 2 && want;
     }
+    // step kernels with 4- and 8-byte storage: at most five resident
+    // wavefronts per SIMD (by LDS allocation).  At 256^3, A-B, one machine:
+    // FP32 0.737 -> 0.769 of 8 TB/s (seven waves -> five; four the same,
+    // three 0.762), raw moments 0.723 -> 0.745, FP64 0.707 -> 0.722 (six
+    // waves -> five); 16-bit storage keeps every wave it can hold (eight:
+    // FP16 0.734, with five 0.67).  LBM_WAVES_PER_SIMD=n sets the cap (0:
+    // none).
+    {
+        const char* env = std::getenv("LBM_WAVES_PER_SIMD");
+        h->g.occ_waves = env ? std::atoi(env) : (eb >= 4 ? 5 : 0);
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, h->device) == hipSuccess &&
+            lds > 0)
+            h->g.lds_per_cu = lds;
+    }
     h->walls = p->walls_y != 0;
     // default: streaming hints for A-B with 4- and 8-byte storage and for
     // every staged step (set below), ordinary accesses otherwise -- the

@@ -20,6 +20,8 @@ struct Geom {
     int flat = 0;      // kernels that use thread_node(): 1-D grid over all nodes in index order
     int off32 = 0;     // every population array is below 4 GiB (32-bit element byte offsets)
     int even_cached = 0; // AA even step with 16-bit storage: population loads without the streaming hint
+    int occ_waves = 0;   // step kernels: cap on resident wavefronts per SIMD (0: none), by LDS allocation
+    int lds_per_cu = 163840; // bytes of LDS per compute unit
 };
 
 struct Phys {
