@@ -243,9 +243,13 @@ __global__ __launch_bounds__(256) void k_ens_box_sums(const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// lds_pad: dynamic LDS of the plain step's work-groups (a cap on resident
+// wavefronts per SIMD, as for the single lattice); the learned step runs at
+// four wavefronts per SIMD by its registers and takes none
 template <bool O32>
 static void ens_step_o(int q, int precision, bool mlp, const void* src, void* dst, const BoxDesc* bd, const int* tile_box,
-                       int ntiles, float rho0, const void* net, uint32_t* fb, int grid, int block, hipStream_t st)
+                       int ntiles, float rho0, const void* net, uint32_t* fb, int grid, int block, unsigned lds_pad,
+                       hipStream_t st)
 {
     if (mlp) {
         hipLaunchKernelGGL((k_ens_step_mlp<float, O32>), dim3(grid), dim3(block), 0, st, (const float*)src, (float*)dst,
@@ -254,30 +258,31 @@ static void ens_step_o(int q, int precision, bool mlp, const void* src, void* ds
     }
     if (q == 27) {
         if (precision == PREC_FP64)
-            hipLaunchKernelGGL((k_ens_step<LatD3Q27, double, O32>), dim3(grid), dim3(block), 0, st, (const double*)src,
+            hipLaunchKernelGGL((k_ens_step<LatD3Q27, double, O32>), dim3(grid), dim3(block), lds_pad, st, (const double*)src,
                                (double*)dst, bd, tile_box, ntiles, rho0);
         else
-            hipLaunchKernelGGL((k_ens_step<LatD3Q27, float, O32>), dim3(grid), dim3(block), 0, st, (const float*)src,
+            hipLaunchKernelGGL((k_ens_step<LatD3Q27, float, O32>), dim3(grid), dim3(block), lds_pad, st, (const float*)src,
                                (float*)dst, bd, tile_box, ntiles, rho0);
     } else {
         if (precision == PREC_FP64)
-            hipLaunchKernelGGL((k_ens_step<LatD3Q19, double, O32>), dim3(grid), dim3(block), 0, st, (const double*)src,
+            hipLaunchKernelGGL((k_ens_step<LatD3Q19, double, O32>), dim3(grid), dim3(block), lds_pad, st, (const double*)src,
                                (double*)dst, bd, tile_box, ntiles, rho0);
         else
-            hipLaunchKernelGGL((k_ens_step<LatD3Q19, float, O32>), dim3(grid), dim3(block), 0, st, (const float*)src,
+            hipLaunchKernelGGL((k_ens_step<LatD3Q19, float, O32>), dim3(grid), dim3(block), lds_pad, st, (const float*)src,
                                (float*)dst, bd, tile_box, ntiles, rho0);
     }
 }
 
 void launch_ens_step(int q, int precision, bool mlp, bool off32, const void* src, void* dst, const void* boxes,
                      const int* tile_box, int ntiles, float rho0, const void* net, uint32_t* fb, int grid, int block,
-                     hipStream_t st)
+                     int occ_waves, int lds_per_cu, hipStream_t st)
 {
     const BoxDesc* bd = (const BoxDesc*)boxes;
+    const unsigned pad = occ_pad(occ_waves, lds_per_cu, 0, dim3(block));
     if (off32)
-        ens_step_o<true>(q, precision, mlp, src, dst, bd, tile_box, ntiles, rho0, net, fb, grid, block, st);
+        ens_step_o<true>(q, precision, mlp, src, dst, bd, tile_box, ntiles, rho0, net, fb, grid, block, pad, st);
     else
-        ens_step_o<false>(q, precision, mlp, src, dst, bd, tile_box, ntiles, rho0, net, fb, grid, block, st);
+        ens_step_o<false>(q, precision, mlp, src, dst, bd, tile_box, ntiles, rho0, net, fb, grid, block, pad, st);
 }
 
 void launch_ens_energy(int q, int precision, const void* buf, const void* boxes, const int* tile_box, int ntiles,

@@ -69,6 +69,9 @@ struct lbm_ensemble {
     hipGraphExec_t exec = nullptr;
     int graph_steps = 0;
     const void* graph_net = nullptr; // network weights the captured launches read (NULL: plain rates)
+    // plain step: at most occ_waves resident wavefronts per SIMD (by LDS
+    // allocation; 0: no cap), as for the single lattice
+    int occ_waves = 5, lds_per_cu = 163840;
 };
 
 namespace {
@@ -78,7 +81,7 @@ void launch_one(lbm_ensemble* e)
     const int src = e->cur, dst = 1 - e->cur;
     lbm::launch_ens_step(e->q, e->precision == LBM_FP64 ? 0 : 1, e->mlp != nullptr, e->off32, e->buf[src], e->buf[dst],
                          e->boxes_dev, e->tile_box_dev, e->ntiles, 1.0f, e->mlp ? e->mlp->packed : nullptr, e->fb,
-                         e->grid, TILE, e->stream);
+                         e->grid, TILE, e->occ_waves, e->lds_per_cu, e->stream);
     e->cur = dst;
 }
 
@@ -173,6 +176,16 @@ int lbm_ensemble_create(const lbm_box* boxes, int32_t nboxes, int32_t q, int32_t
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return cleanup(efail(LBM_EDEVICE, "no HIP device"));
+    // five wavefronts per SIMD for the plain step: 64-box workload, one
+    // machine, D3Q19 5.42 -> 5.58 TB/s, D3Q27 5.16 -> 5.27 (four: the same
+    // for D3Q19, six: 5.51); LBM_WAVES_PER_SIMD=n sets the cap (0: none)
+    {
+        const char* env = std::getenv("LBM_WAVES_PER_SIMD");
+        if (env) e->occ_waves = std::atoi(env);
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && lds > 0)
+            e->lds_per_cu = lds;
+    }
     // default: one work-group per tile (the tuner's choice on MI355X for the
     // 64-box workload); lbm_ensemble_tune also tries 2..64 persistent
     // work-groups per CU

@@ -397,15 +397,19 @@ __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* _
 // wavefronts spread over the compute unit's four SIMDs, so at most
 // 4 occ_waves / ceil(T / 64) work-groups may share the unit's LDS; each one
 // is given that share (at most 64 KB) less the static LDS it already uses.
-inline unsigned occ_pad(const Geom& g, unsigned static_lds, dim3 b)
+inline unsigned occ_pad(int occ_waves, int lds_per_cu, unsigned static_lds, dim3 b)
 {
-    if (g.occ_waves <= 0) return 0;
     const unsigned waves = (b.x * b.y * b.z + 63) / 64;
-    unsigned wgs = 4u * (unsigned)g.occ_waves / waves;
+    if (occ_waves <= 0 || waves == 0) return 0; // no cap, or no launch (an empty block shape)
+    unsigned wgs = 4u * (unsigned)occ_waves / waves;
     if (wgs < 1) wgs = 1;
-    unsigned total = (unsigned)g.lds_per_cu / wgs;
+    unsigned total = (unsigned)lds_per_cu / wgs;
     if (total > 65536u) total = 65536u;
     return total > static_lds ? total - static_lds : 0;
+}
+inline unsigned occ_pad(const Geom& g, unsigned static_lds, dim3 b)
+{
+    return occ_pad(g.occ_waves, g.lds_per_cu, static_lds, b);
 }
 
 template <class L> __host__ __device__ constexpr int moving_x_count()

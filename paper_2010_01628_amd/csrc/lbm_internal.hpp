@@ -169,7 +169,7 @@ namespace lbm {
 // off32: every box's population arrays are below 4 GiB (32-bit element offsets)
 void launch_ens_step(int q, int precision, bool mlp, bool off32, const void* src, void* dst, const void* boxes,
                      const int* tile_box, int ntiles, float rho0, const void* net, uint32_t* fb, int grid, int block,
-                     hipStream_t st);
+                     int occ_waves, int lds_per_cu, hipStream_t st);
 void launch_ens_energy(int q, int precision, const void* buf, const void* boxes, const int* tile_box, int ntiles,
                        int nboxes, const int* tile_count, double rho0, double* tile_out, double* box_out, int grid,
                        hipStream_t st);
