@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 
 #include "lattice_kernels.hpp"
 #include "lbm.h"
@@ -55,33 +56,49 @@ __global__ __launch_bounds__(256) void k_stream_copy_wide(const char* __restrict
     }
 }
 
+// The step kernels' cap on resident wavefronts per SIMD (by LDS allocation;
+// LBM_WAVES_PER_SIMD, default five for 4- and 8-byte elements, none for
+// 2-byte ones), applied to the reference too: dynamic LDS per work-group.
+static unsigned copy_lds(int elem_bytes)
+{
+    const char* env = std::getenv("LBM_WAVES_PER_SIMD");
+    const int waves = env ? std::atoi(env) : (elem_bytes >= 4 ? 5 : 0);
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || lds <= 0)
+        lds = 163840;
+    return occ_pad(waves, lds, 0, dim3(256));
+}
+
 template <class T>
 static void stream_copy_t(const void* src, void* dst, int64_t n, int q, bool nt, hipStream_t st)
 {
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    const unsigned pad = copy_lds((int)sizeof(T));
     const T* a = (const T*)src;
     T* b = (T*)dst;
     if (q == 19) {
-        if (nt) hipLaunchKernelGGL((k_stream_copy<T, 19, true>), grid, block, 0, st, a, b, n);
-        else hipLaunchKernelGGL((k_stream_copy<T, 19, false>), grid, block, 0, st, a, b, n);
+        if (nt) hipLaunchKernelGGL((k_stream_copy<T, 19, true>), grid, block, pad, st, a, b, n);
+        else hipLaunchKernelGGL((k_stream_copy<T, 19, false>), grid, block, pad, st, a, b, n);
     } else {
-        if (nt) hipLaunchKernelGGL((k_stream_copy<T, 27, true>), grid, block, 0, st, a, b, n);
-        else hipLaunchKernelGGL((k_stream_copy<T, 27, false>), grid, block, 0, st, a, b, n);
+        if (nt) hipLaunchKernelGGL((k_stream_copy<T, 27, true>), grid, block, pad, st, a, b, n);
+        else hipLaunchKernelGGL((k_stream_copy<T, 27, false>), grid, block, pad, st, a, b, n);
     }
 }
 
 template <int W>
-static void stream_copy_w(const void* src, void* dst, int64_t nb, int q, bool nt, hipStream_t st)
+static void stream_copy_w(const void* src, void* dst, int64_t nb, int q, bool nt, int elem_bytes, hipStream_t st)
 {
     const dim3 grid((unsigned)((nb / W + 255) / 256)), block(256);
+    const unsigned pad = copy_lds(elem_bytes);
     const char* a = (const char*)src;
     char* b = (char*)dst;
     if (q == 19) {
-        if (nt) hipLaunchKernelGGL((k_stream_copy_wide<W, 19, true>), grid, block, 0, st, a, b, nb);
-        else hipLaunchKernelGGL((k_stream_copy_wide<W, 19, false>), grid, block, 0, st, a, b, nb);
+        if (nt) hipLaunchKernelGGL((k_stream_copy_wide<W, 19, true>), grid, block, pad, st, a, b, nb);
+        else hipLaunchKernelGGL((k_stream_copy_wide<W, 19, false>), grid, block, pad, st, a, b, nb);
     } else {
-        if (nt) hipLaunchKernelGGL((k_stream_copy_wide<W, 27, true>), grid, block, 0, st, a, b, nb);
-        else hipLaunchKernelGGL((k_stream_copy_wide<W, 27, false>), grid, block, 0, st, a, b, nb);
+        if (nt) hipLaunchKernelGGL((k_stream_copy_wide<W, 27, true>), grid, block, pad, st, a, b, nb);
+        else hipLaunchKernelGGL((k_stream_copy_wide<W, 27, false>), grid, block, pad, st, a, b, nb);
     }
 }
 
@@ -115,9 +132,9 @@ int lbm_stream_copy(const void* src, void* dst, int64_t n, int32_t q, int32_t el
         default: lbm::stream_copy_t<uint64_t>(src, dst, n, q, nt != 0, st); break;
         }
     } else if (lane_bytes == 8) {
-        lbm::stream_copy_w<8>(src, dst, n * elem_bytes, q, nt != 0, st);
+        lbm::stream_copy_w<8>(src, dst, n * elem_bytes, q, nt != 0, elem_bytes, st);
     } else {
-        lbm::stream_copy_w<16>(src, dst, n * elem_bytes, q, nt != 0, st);
+        lbm::stream_copy_w<16>(src, dst, n * elem_bytes, q, nt != 0, elem_bytes, st);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
