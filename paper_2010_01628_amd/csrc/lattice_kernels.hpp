@@ -386,12 +386,6 @@ __global__ __launch_bounds__(256) void k_step_ab(const S* __restrict__ src, S* _
     step_node<L, S, AB, WALLS, GENERAL, NT, O32>(src, dst, g, ph);
 }
 
-// A-B, periodic, with work-groups of whole x rows (blockDim.x == nx): the
-// populations that move along x are staged through LDS.  Each such
-// population's source row (y - c_y, z - c_z) is read aligned, each element
-// once, into LDS, and node x takes element x - c_x (wrapped) from there;
-// reading it straight from memory would start each wavefront's load four
-// bytes off a line boundary.  Same values as k_step_ab, bit for bit.
 // Dynamic LDS for a step launch that caps the resident wavefronts per SIMD at
 // g.occ_waves (0: no cap): a work-group of T threads places ceil(T / 64)
 // wavefronts spread over the compute unit's four SIMDs, so at most
@@ -412,6 +406,12 @@ inline unsigned occ_pad(const Geom& g, unsigned static_lds, dim3 b)
     return occ_pad(g.occ_waves, g.lds_per_cu, static_lds, b);
 }
 
+// A-B, periodic, with work-groups of whole x rows (blockDim.x == nx): the
+// populations that move along x are staged through LDS.  Each such
+// population's source row (y - c_y, z - c_z) is read aligned, each element
+// once, into LDS, and node x takes element x - c_x (wrapped) from there;
+// reading it straight from memory would start each wavefront's load four
+// bytes off a line boundary.  Same values as k_step_ab, bit for bit.
 template <class L> __host__ __device__ constexpr int moving_x_count()
 {
     int k = 0;
@@ -762,9 +762,8 @@ template <class L, class S> struct Launch {
         constexpr bool wide_fits = moving_x_count<L>() * 512 * sizeof(S) <= 65536;
         constexpr bool fits1024 = moving_x_count<L>() * 1024 * sizeof(S) <= 65536;
         // those 256-thread work-groups take an x width that divides the row
-        // where one does (256, 128, 64 or 32 x-values by 1, 2, 4 or 8 rows),
-        // so that no lane idles at the row's end
-        const int wx = g.nx % 256 == 0 ? 256 : g.nx % 128 == 0 ? 128 : g.nx % 64 == 0 ? 64 : g.nx % 32 == 0 ? 32 : 256;
+        // where one does (256, 128, 64 or 32 x-values by 1, 2, 4 or 8 rows)
+        const int wx = row_width(g.nx);
         const dim3 block256(wide ? wx : block.x, wide ? 256 / wx : block.y, 1);
         const dim3 grid256(wide ? (g.nx + wx - 1) / wx : grid.x, wide ? (g.ny + 256 / wx - 1) / (256 / wx) : grid.y,
                            grid.z);

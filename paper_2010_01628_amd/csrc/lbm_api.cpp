@@ -134,13 +134,12 @@ void default_block(const lbm_params* p, int& bx, int& by)
         by = p->block_y;
         return;
     }
-    // one block per x-row (up to 256 nodes): measured fastest at 256^3; rows
-    // longer than 256 nodes take an x width that divides them where one does
-    // (256, 128, 64 or 32), so that no lane idles at the row's end
-    const int nx = p->nx;
-    // a row shorter than 256 nodes whose length is not a power of two: whole
+    // one block per x-row (up to 256 nodes): measured fastest at 256^3.  A
+    // row shorter than 256 nodes whose length is not a power of two: whole
     // rows per work-group when some number of them fills whole wavefronts
-    // (48 x 4, 96 x 2, 192 x 1: no idle lane, and the rows can be staged)
+    // (48 x 4, 96 x 2, 192 x 1: no idle lane, and the rows can be staged);
+    // rows longer than 256 nodes: row_width
+    const int nx = p->nx;
     if (nx < 256 && (nx & (nx - 1)) != 0)
         for (int k = 256 / nx; k >= 1; --k)
             if (nx * k % 64 == 0) {
@@ -148,8 +147,7 @@ void default_block(const lbm_params* p, int& bx, int& by)
                 by = k;
                 return;
             }
-    bx = nx <= 256 ? next_pow2(nx)
-                   : (nx % 256 == 0 ? 256 : nx % 128 == 0 ? 128 : nx % 64 == 0 ? 64 : nx % 32 == 0 ? 32 : 256);
+    bx = nx <= 256 ? next_pow2(nx) : lbm::row_width(nx);
     if (bx < 8) bx = 8;
     by = 256 / bx;
     const int ny2 = next_pow2(p->ny);
@@ -175,8 +173,7 @@ void set_row_stage(lbm_handle* h)
     // staging the step falls back to 256-thread work-groups over the rows,
     // with an x width that divides the row where one does (no idle lanes)
     if (h->step_block.x > 256 && !h->g.row_stage) {
-        const int nx = h->g.nx;
-        const int wx = nx % 256 == 0 ? 256 : nx % 128 == 0 ? 128 : nx % 64 == 0 ? 64 : nx % 32 == 0 ? 32 : 256;
+        const int nx = h->g.nx, wx = lbm::row_width(nx);
         h->step_block = dim3(wx, 256 / wx, 1);
         h->step_grid = dim3((nx + wx - 1) / wx, (h->g.ny + 256 / wx - 1) / (256 / wx), h->g.nz);
     }

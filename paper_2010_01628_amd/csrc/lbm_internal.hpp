@@ -24,6 +24,14 @@ struct Geom {
     int lds_per_cu = 163840; // bytes of LDS per compute unit
 };
 
+// x width of a 256-thread work-group over rows longer than 256 nodes that no
+// single work-group spans: the widest of 256, 128, 64 and 32 that divides the
+// row (no lane idles at the row's end), else 256
+inline int row_width(int nx)
+{
+    return nx % 256 == 0 ? 256 : nx % 128 == 0 ? 128 : nx % 64 == 0 ? 64 : nx % 32 == 0 ? 32 : 256;
+}
+
 struct Phys {
     double omega, omega_bulk, omega_hi[9];
     double rho0;
