@@ -116,6 +116,23 @@ def test_64bit_addressing_is_bitwise_identical(q, learned, monkeypatch):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("q", [19, 27])
+def test_wavefront_cap_is_bitwise_identical(q, monkeypatch):
+    """The plain step's cap on resident wavefronts per SIMD (an LDS
+    allocation; LBM_WAVES_PER_SIMD) changes no value, bit for bit."""
+    boxes = [(12, 1.85), (7, 1.7), (10, 1.9)]
+    out = []
+    for cap in ("5", "0", "2"):
+        monkeypatch.setenv("LBM_WAVES_PER_SIMD", cap)
+        ens = make_ensemble(boxes, q=q, precision="fp32")
+        ens.step(9)
+        out.append([ens.get_populations(b) for b in range(len(boxes))])
+        ens.close()
+    for run in out[1:]:
+        for a, b in zip(out[0], run):
+            assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("chunk", ["2", "16", "0", "3", "17"])
 def test_graph_replay_equals_single_steps(chunk, monkeypatch):
     """Stepping through captured graphs of `chunk` steps (0: no graph; odd

@@ -343,6 +343,25 @@ def test_wide_row_staged_step_is_bitwise_identical(nx, precision, streaming, q, 
     assert np.array_equal(staged["f"], direct["f"])
 
 
+@pytest.mark.parametrize("precision,streaming,walls,q", [
+    ("fp32", "ab", False, 19), ("fp32", "aa", False, 19), ("fp64", "aa", True, 19), ("fp32", "ab", False, 27),
+    ("fp16", "ab", False, 19)])
+def test_wavefront_cap_is_bitwise_identical(precision, streaming, walls, q, monkeypatch):
+    """The step kernels' cap on resident wavefronts per SIMD (an LDS
+    allocation; LBM_WAVES_PER_SIMD, default five for 4- and 8-byte storage)
+    changes no value, bit for bit: the default against no cap and against a
+    cap of two (FP16 storage: no cap by default, against five).  An odd step
+    count ends on an odd AA step."""
+    nx, ny, nz = 64, 20, 9
+    rho, u, F = inputs.random_lattice_fields(nx, ny, nz, seed=46, umax=0.05, fmax=1e-3)
+    kw = dict(omega=1.8, omega_hi=[1.4] * 9 if q == 19 else None, force=F, walls=walls, q=q)
+    a = gpu_run(nx, ny, nz, rho, u, 7, precision, streaming, **kw)
+    for cap in ("0", "2", "5"):
+        monkeypatch.setenv("LBM_WAVES_PER_SIMD", cap)
+        b = gpu_run(nx, ny, nz, rho, u, 7, precision, streaming, **kw)
+        assert np.array_equal(a["f"], b["f"])
+
+
 @pytest.mark.parametrize("precision,walls,moments", [("fp16", False, "central"), ("bf16", False, "central"),
                                                      ("fp16", True, "central"), ("bf16", True, "central"),
                                                      ("fp16", False, "raw")])

@@ -62,6 +62,18 @@ def test_row_staged_step_is_bitwise_identical(shape, precision, monkeypatch):
     assert np.array_equal(a["g"], b["g"]) and np.array_equal(a["h"], b["h"])
 
 
+@pytest.mark.parametrize("shape", [(17, 9, 5), (192, 6, 4)])
+def test_wavefront_cap_is_bitwise_identical(shape, monkeypatch):
+    """The step's cap on resident wavefronts per SIMD (an LDS allocation;
+    LBM_WAVES_PER_SIMD) changes no value, bit for bit (flat and staged
+    launches)."""
+    phi, p, u = case(shape, 23)
+    a = gpu_phase(shape, PRMS[1], phi, p, u, 7, "fp32")
+    monkeypatch.setenv("LBM_WAVES_PER_SIMD", "0")
+    b = gpu_phase(shape, PRMS[1], phi, p, u, 7, "fp32")
+    assert np.array_equal(a["g"], b["g"]) and np.array_equal(a["h"], b["h"])
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_flat_and_3d_grids_are_bitwise_identical(precision, monkeypatch):
     """The density launch (and, with staging off, the step) runs on a flat

@@ -113,6 +113,18 @@ def test_64bit_addressing_is_bitwise_identical(precision, monkeypatch):
     assert np.array_equal(a["f"], b["f"])
 
 
+def test_wavefront_cap_is_bitwise_identical(monkeypatch):
+    """The steps' cap on resident wavefronts per SIMD (an LDS allocation;
+    LBM_WAVES_PER_SIMD) changes no population, bit for bit."""
+    shape = (23, 17, 11)
+    rho = droplet_rho(shape, 5.0)
+    _, u, _ = inputs.random_lattice_fields(*shape, seed=8, umax=0.02)
+    a = gpu_sc(shape, rho, u, 7, "fp32")
+    monkeypatch.setenv("LBM_WAVES_PER_SIMD", "0")
+    b = gpu_sc(shape, rho, u, 7, "fp32")
+    assert np.array_equal(a["f"], b["f"])
+
+
 def test_flat_and_3d_grids_are_bitwise_identical(monkeypatch):
     """Flat 1-D grid (default) and 3-D grid (LBM_COUPLED_FLAT=0) of the
     coupled step: same populations, bit for bit."""
