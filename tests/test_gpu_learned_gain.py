@@ -8,7 +8,7 @@ The held-out one-step and eight-step moment losses are reported and
 guarded: matching the energy decay costs some local moment accuracy
 (training on the moments alone lowers those losses but raises the small
 boxes' decay error).  Over six training seeds of this recipe the learned
-losses are 1.11-1.30 (one step) and 1.03-1.51 (eight steps) times the
+losses are 1.01-1.41 (one step) and 1.12-1.47 (eight steps) times the
 paper's; the guard, 1.5 and 2 times, catches the runs that trade local
 accuracy wholesale (half the energy weight gave eight-step losses of 4.6
 and 7.0 times the paper's on two of six seeds, three times the learning
