@@ -304,6 +304,49 @@ __device__ inline void place_state(S* __restrict__ buf, int64_t stride, const No
     }
 }
 
+// The force at a node in two parts: force_load issues the loads a node's
+// force needs (a row table or field entry; issued ahead of the population
+// loads), force_value converts where the collision needs it, so that the
+// conversion does not make the wavefront wait for the load early (the
+// components force_load does not read stay 0 and are not used).
+struct ForceRaw {
+    double x, y, z;
+};
+__device__ inline ForceRaw force_load(const Phys& ph, const Geom& g, int n, int y)
+{
+    ForceRaw f{0.0, 0.0, 0.0};
+    if (ph.force_mode == FORCE_FIELD) {
+        f.x = ph.force_field[n];
+        f.y = ph.force_field[g.N + n];
+        f.z = ph.force_field[2 * (int64_t)g.N + n];
+    } else if (ph.force_mode == FORCE_ROW_TABLE) {
+        f.x = ph.row_table[y];
+    }
+    return f;
+}
+template <class R> __device__ inline void force_value(const Phys& ph, const ForceRaw& f, R& Fx, R& Fy, R& Fz)
+{
+    switch (ph.force_mode) {
+    case FORCE_UNIFORM:
+        Fx = (R)ph.force[0];
+        Fy = (R)ph.force[1];
+        Fz = (R)ph.force[2];
+        break;
+    case FORCE_FIELD:
+        Fx = (R)f.x;
+        Fy = (R)f.y;
+        Fz = (R)f.z;
+        break;
+    case FORCE_ROW_TABLE:
+        Fx = (R)f.x;
+        Fy = R(0);
+        Fz = R(0);
+        break;
+    default:
+        Fx = Fy = Fz = R(0);
+    }
+}
+// The same in one part, converted where it is read.
 template <class R> __device__ inline void node_force(const Phys& ph, const Geom& g, int n, int y, R& Fx, R& Fy, R& Fz)
 {
     switch (ph.force_mode) {
@@ -326,6 +369,14 @@ template <class R> __device__ inline void node_force(const Phys& ph, const Geom&
         Fx = Fy = Fz = R(0);
     }
 }
+
+// Whether a step issues the force's load ahead of the population loads
+// (force_load / force_value) or reads it after them (node_force).  Ahead
+// measured faster for the AA steps with 2- and 8-byte storage (FP16 / BF16
+// AA +1.5-2 %, FP64 AA within noise) and slower with 4-byte storage (FP32
+// AA -0.5 %); the staged A-B step keeps its load after the barrier for
+// every storage type (ahead: FP32 -0.7 %, FP16 / BF16 -1 to -2 %).
+template <class S> constexpr bool early_force() { return sizeof(S) != 4; }
 
 // One fused step at one node.  Block (bx, by, 1) covers bx x-values of by
 // rows; blockIdx.z is the z plane.
@@ -369,10 +420,15 @@ __device__ inline void step_node(const S* src, S* dst, const Geom& g, const Phys
     if (x >= g.nx || y >= g.ny) return;
     NodeIdx d;
     node_idx(g, x, y, z, d);
+    ForceRaw fr{0.0, 0.0, 0.0};
+    if constexpr (early_force<S>()) fr = force_load(ph, g, nb(d, 0, 0, 0), y);
     R s[L::Q];
     gather<L, S, P, WALLS, NTL, O32>(src, g.stride, d, s);
     R Fx, Fy, Fz;
-    node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
+    if constexpr (early_force<S>())
+        force_value(ph, fr, Fx, Fy, Fz);
+    else
+        node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
     L::template collide<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
     if constexpr (Codec<S>::stochastic) dither_bf16(s, ph.sr_key, (uint32_t)nb(d, 0, 0, 0));
@@ -436,8 +492,9 @@ __global__ __launch_bounds__(W) void k_step_ab_rows(const S* __restrict__ src, S
     NodeIdx d;
     node_idx(g, x, y, z, d);
     const int row0 = threadIdx.y * blockDim.x;
-    // every load is issued before the barrier: the populations that stay in
-    // x go straight to registers, the others to LDS
+    // every population load is issued before the barrier: the populations
+    // that stay in x go straight to registers, the others to LDS (the
+    // force's load follows the barrier; see early_force)
     S direct[L::Q];
     {
         int k = 0;
@@ -508,7 +565,10 @@ __global__ __launch_bounds__(W) void k_step_aa_odd_rows(S* __restrict__ buf, Geo
     NodeIdx d;
     node_idx(g, x, y, z, d);
     const int row0 = threadIdx.y * blockDim.x;
-    // every load is issued before the barrier (as in k_step_ab_rows)
+    // every population load is issued before the barrier (as in
+    // k_step_ab_rows), the force's ahead of them where early_force says so
+    ForceRaw fr{0.0, 0.0, 0.0};
+    if constexpr (early_force<S>()) fr = force_load(ph, g, nb(d, 0, 0, 0), y);
     S direct[L::Q];
     {
         int k = 0;
@@ -540,7 +600,10 @@ __global__ __launch_bounds__(W) void k_step_aa_odd_rows(S* __restrict__ buf, Geo
         }
     }
     R Fx, Fy, Fz;
-    node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
+    if constexpr (early_force<S>())
+        force_value(ph, fr, Fx, Fy, Fz);
+    else
+        node_force(ph, g, nb(d, 0, 0, 0), y, Fx, Fy, Fz);
     NodeMacro<R> mac;
     L::template collide<R, GENERAL, Codec<S>::increment>(s, (R)ph.rho0, Fx, Fy, Fz, ph, mac);
     if constexpr (Codec<S>::stochastic) dither_bf16(s, ph.sr_key, (uint32_t)nb(d, 0, 0, 0));
