@@ -154,7 +154,8 @@ template <class R> __device__ inline void dither_bf16(R s[19], uint32_t key, uin
             if (i < 19) {
                 const uint32_t u = __float_as_uint(s[i]);
                 const uint32_t r = k ? (h >> 16) : (h & 0xffffu);
-                if ((u & 0x7f800000u) != 0x7f800000u) s[i] = __uint_as_float((u + r) & 0xffff0000u);
+                // finite: the exponent field is not all ones (one class test)
+                if (__builtin_isfinite(s[i])) s[i] = __uint_as_float((u + r) & 0xffff0000u);
             }
         }
     }
